@@ -1,0 +1,628 @@
+/*
+ * FP64 CPU oracle of the CRK-HACC short-range step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library or its binding may link,
+ * load or call this file; only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark do.  It shares no code with the GPU path.
+ *
+ * Plain, slow and obviously correct: one target particle at a time, its
+ * neighbours found either by brute force over all particles or by a
+ * periodic linked-cell list, every sum accumulated in double precision in a
+ * fixed order.  Inputs are the float32 values the GPU path consumes,
+ * widened to double.
+ *
+ * What each function computes (the paper names the method, CRKSPH, and the
+ * long/short gravity split, but prints none of the formulas, so each is the
+ * standard definition of the named method, with the readings listed in the
+ * design notes):
+ *   - cubic-spline (M4) kernel W(r,h) with support 2h;
+ *   - orc_density: V_i = 1/sum_j W(r_ij,h_i), rho~_i = sum_j m_j W(r_ij,h_i),
+ *     gathered over gas j including j = i (pairwise sums of the form of
+ *     Eq. (1), Sec. IV-B.2);
+ *   - orc_coefficients: reproducing-kernel moments and the correction
+ *     coefficients A, B, grad A, grad B that make the corrected kernel
+ *     A(1 + B.x)W reproduce constant and linear fields exactly (CRKSPH,
+ *     Sec. IV-A), then rho = A (rho~ + B.M1), ideal-gas P and c;
+ *   - orc_hydro: the antisymmetric CRKSPH pair force F_ij = -F_ji (Eq. (2)
+ *     and its (anti)symmetry, Sec. IV-B.2) and the work-split du/dt, which
+ *     conserve momentum and energy (Sec. IV-A);
+ *   - orc_gravity: the short-range remainder of Newtonian gravity inside the
+ *     handover scale r_c (Sec. IV-A): Plummer-softened 1/r^2 minus the force
+ *     between two S2 clouds of diameter r_c (Hockney & Eastwood), zero
+ *     beyond r_c.
+ * Parity-pinned by the tests under tests/ (normalisation, reproducing
+ * conditions, lattice symmetry, conservation, closed forms, quadrature,
+ * brute force versus cells).  The viscosity form and constants are a
+ * reading: parity unpinned beyond conservation and Galilean invariance.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* periodic geometry                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* minimum-image separation along one axis in the unit periodic box */
+static double min_image(double d)
+{
+    if (d > 0.5) d -= 1.0;
+    else if (d < -0.5) d += 1.0;
+    return d;
+}
+
+/* ------------------------------------------------------------------------ */
+/* cubic-spline kernel                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* W(r, h) and dW/dr of the M4 cubic spline with support 2h, normalised to 1
+ * in three dimensions. */
+void orc_kernel(double r, double h, double *W, double *dWdr)
+{
+    double q = r / h;
+    double s = 1.0 / (M_PI * h * h * h);
+    if (q < 1.0) {
+        *W = s * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
+        *dWdr = s / h * (-3.0 * q + 2.25 * q * q);
+    } else if (q < 2.0) {
+        double t = 2.0 - q;
+        *W = s * 0.25 * t * t * t;
+        *dWdr = -s / h * 0.75 * t * t;
+    } else {
+        *W = 0.0;
+        *dWdr = 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* short-range gravity                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Force between two unit-mass S2 clouds of diameter a at separation r
+ * (Hockney & Eastwood's S2 shape: density falling linearly to zero at
+ * radius a/2).  Equals 1/r^2 for r >= a. */
+double orc_s2_force(double r, double a)
+{
+    double xi = 2.0 * r / a;
+    double c = 1.0 / (35.0 * a * a);
+    if (xi < 1.0) {
+        double x2 = xi * xi, x3 = x2 * xi, x4 = x3 * xi, x5 = x4 * xi,
+               x6 = x5 * xi;
+        return c * (224.0 * xi - 224.0 * x3 + 70.0 * x4 + 48.0 * x5 - 21.0 * x6);
+    }
+    if (xi < 2.0) {
+        double t = 2.0 - xi;
+        double t5 = t * t * t * t * t;
+        return 1.0 / (r * r)
+               - c * t5 * (7.0 * xi * xi * xi + 22.0 * xi * xi + 10.0 * xi + 4.0)
+                     / (xi * xi);
+    }
+    return 1.0 / (r * r);
+}
+
+/* Short-range force magnitude g(r) per unit mass pair: Plummer-softened
+ * Newtonian force minus the S2 long-range part, cut at r_c. */
+double orc_grav_g(double r, double r_c, double eps)
+{
+    if (r >= r_c) return 0.0;
+    double s = r * r + eps * eps;
+    return r / (s * sqrt(s)) - orc_s2_force(r, r_c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* neighbour search                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* A periodic linked-cell list over n points of the unit box with cells of
+ * width >= w.  With fewer than three cells per side the search falls back
+ * to brute force over all points. */
+typedef struct {
+    int64_t n;
+    int nc;            /* cells per side, 0 = brute force */
+    int64_t *head;     /* nc^3 + 1 offsets */
+    int64_t *items;    /* n point indices, grouped by cell, ascending */
+} cells_t;
+
+static int cell_of(double x, int nc)
+{
+    int c = (int)floor((x - 1.0) * nc);
+    if (c < 0) c = 0;
+    if (c >= nc) c = nc - 1;
+    return c;
+}
+
+static int cells_build(cells_t *cl, int64_t n, const double *x,
+                       const double *y, const double *z, double w, int brute)
+{
+    cl->n = n;
+    cl->head = NULL;
+    cl->items = NULL;
+    int nc = (w > 0.0) ? (int)floor(1.0 / w) : 0;
+    if (nc > 512) nc = 512;
+    if (brute || nc < 3) {
+        cl->nc = 0;
+        return 0;
+    }
+    cl->nc = nc;
+    int64_t ncell = (int64_t)nc * nc * nc;
+    cl->head = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    cl->items = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *cid = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!cl->head || !cl->items || !cid) {
+        free(cl->head); free(cl->items); free(cid);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = ((int64_t)cell_of(x[i], nc) * nc + cell_of(y[i], nc)) * nc
+                    + cell_of(z[i], nc);
+        cid[i] = c;
+        cl->head[c + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) cl->head[c + 1] += cl->head[c];
+    int64_t *fill = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+    if (!fill) { free(cl->head); free(cl->items); free(cid); return -1; }
+    memcpy(fill, cl->head, (size_t)ncell * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) cl->items[fill[cid[i]]++] = i;
+    free(fill);
+    free(cid);
+    return 0;
+}
+
+static void cells_free(cells_t *cl)
+{
+    free(cl->head);
+    free(cl->items);
+}
+
+/* Neighbour candidates of one target: indices j, in a fixed order (cell by
+ * cell, ascending index within a cell), whose minimum-image separation
+ * x_i - x_j satisfies r^2 < R2. */
+typedef struct {
+    int64_t n, cap;
+    int64_t *j;
+    double *d; /* dx, dy, dz, r2 per entry */
+} nbr_t;
+
+static void nbr_push(nbr_t *nb, int64_t j, double dx, double dy, double dz,
+                     double r2)
+{
+    if (nb->n == nb->cap) {
+        nb->cap = nb->cap ? 2 * nb->cap : 256;
+        nb->j = (int64_t *)realloc(nb->j, (size_t)nb->cap * sizeof(int64_t));
+        nb->d = (double *)realloc(nb->d, (size_t)nb->cap * 4 * sizeof(double));
+        if (!nb->j || !nb->d) abort();
+    }
+    nb->j[nb->n] = j;
+    nb->d[4 * nb->n + 0] = dx;
+    nb->d[4 * nb->n + 1] = dy;
+    nb->d[4 * nb->n + 2] = dz;
+    nb->d[4 * nb->n + 3] = r2;
+    nb->n++;
+}
+
+static void nbr_free(nbr_t *nb)
+{
+    free(nb->j);
+    free(nb->d);
+}
+
+static void test_point(nbr_t *nb, int64_t j, const double *X, const double *Y,
+                       const double *Z, double px, double py, double pz,
+                       double R2)
+{
+    double dx = min_image(px - X[j]);
+    double dy = min_image(py - Y[j]);
+    double dz = min_image(pz - Z[j]);
+    double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < R2) nbr_push(nb, j, dx, dy, dz, r2);
+}
+
+static void find_neighbours(const cells_t *cl, const double *X,
+                            const double *Y, const double *Z, double px,
+                            double py, double pz, double R2, nbr_t *nb)
+{
+    nb->n = 0;
+    if (cl->nc == 0) {
+        for (int64_t j = 0; j < cl->n; ++j)
+            test_point(nb, j, X, Y, Z, px, py, pz, R2);
+        return;
+    }
+    int nc = cl->nc;
+    int cx = cell_of(px, nc), cy = cell_of(py, nc), cz = cell_of(pz, nc);
+    for (int ox = -1; ox <= 1; ++ox)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int oz = -1; oz <= 1; ++oz) {
+                int ax = (cx + ox + nc) % nc;
+                int ay = (cy + oy + nc) % nc;
+                int az = (cz + oz + nc) % nc;
+                int64_t c = ((int64_t)ax * nc + ay) * nc + az;
+                for (int64_t k = cl->head[c]; k < cl->head[c + 1]; ++k)
+                    test_point(nb, cl->items[k], X, Y, Z, px, py, pz, R2);
+            }
+}
+
+static double max_of(int64_t n, const double *a)
+{
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        if (a[i] > m) m = a[i];
+    return m;
+}
+
+static int64_t target_index(const int64_t *targets, int64_t k)
+{
+    return targets ? targets[k] : k;
+}
+
+/* ------------------------------------------------------------------------ */
+/* neighbour lists (used by the tests to expand sampled targets)              */
+/* ------------------------------------------------------------------------ */
+
+/* For each target i: the gas j with r_ij < 2 h_i (mode 0, the gather range
+ * of the density and coefficient sums) or r_ij < 2 max(h_i, h_j) (mode 1,
+ * the range of the force sums), j = i included.  With idx == NULL only the
+ * counts are written; otherwise idx receives the concatenated lists
+ * (offsets = running sum of counts). */
+int orc_neighbours(int64_t n, const double *x, const double *y,
+                   const double *z, const double *h, int mode, int64_t nt,
+                   const int64_t *targets, int brute, int64_t *counts,
+                   const int64_t *offsets, int64_t *idx)
+{
+    double hmax = max_of(n, h);
+    cells_t cl;
+    if (cells_build(&cl, n, x, y, z, 2.0 * hmax, brute)) return -1;
+#pragma omp parallel
+    {
+    nbr_t nb = {0, 0, NULL, NULL};
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = target_index(targets, k);
+        double hi = h[i];
+        double R = mode ? 2.0 * hmax : 2.0 * hi;
+        int64_t c = 0;
+        find_neighbours(&cl, x, y, z, x[i], y[i], z[i], R * R, &nb);
+        for (int64_t q = 0; q < nb.n; ++q) {
+            int64_t j = nb.j[q];
+            double r2 = nb.d[4 * q + 3];
+            double lim = mode ? 2.0 * (hi > h[j] ? hi : h[j]) : 2.0 * hi;
+            if (r2 < lim * lim) {
+                if (idx) idx[offsets[k] + c] = j;
+                c++;
+            }
+        }
+        counts[k] = c;
+    }
+    nbr_free(&nb);
+    }
+    cells_free(&cl);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* density / volume                                                           */
+/* ------------------------------------------------------------------------ */
+
+int orc_density(int64_t n, const double *x, const double *y, const double *z,
+                const double *h, const double *m, int64_t nt,
+                const int64_t *targets, int brute, double *V,
+                double *rho_tilde)
+{
+    double hmax = max_of(n, h);
+    cells_t cl;
+    if (cells_build(&cl, n, x, y, z, 2.0 * hmax, brute)) return -1;
+#pragma omp parallel
+    {
+    nbr_t nb = {0, 0, NULL, NULL};
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = target_index(targets, k);
+        double hi = h[i];
+        double sw = 0.0, smw = 0.0;
+        double R = 2.0 * hi;
+        find_neighbours(&cl, x, y, z, x[i], y[i], z[i], R * R, &nb);
+        for (int64_t q = 0; q < nb.n; ++q) {
+            int64_t j = nb.j[q];
+            double r2 = nb.d[4 * q + 3];
+            double W, dW;
+            orc_kernel(sqrt(r2), hi, &W, &dW);
+            sw += W;
+            smw += m[j] * W;
+        }
+        V[k] = 1.0 / sw;
+        rho_tilde[k] = smw;
+    }
+    nbr_free(&nb);
+    }
+    cells_free(&cl);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* reproducing-kernel correction coefficients                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Solve the reproducing conditions at one particle from its moments.
+ * m2 is symmetric; inverted through its adjugate.  Returns 1 when m2 is
+ * singular (then B = grad B = 0, A = 1/m0, grad A = -grad m0 / m0^2). */
+static int solve_coefficients(double m0, const double m1[3],
+                              const double m2[3][3], const double dm0[3],
+                              const double dm1[3][3] /* [g][a] */,
+                              const double dm2[3][3][3] /* [g][a][b] */,
+                              double *A, double B[3], double dA[3],
+                              double dB[3][3] /* [g][a] */)
+{
+    double c00 = m2[1][1] * m2[2][2] - m2[1][2] * m2[2][1];
+    double c01 = m2[1][2] * m2[2][0] - m2[1][0] * m2[2][2];
+    double c02 = m2[1][0] * m2[2][1] - m2[1][1] * m2[2][0];
+    double det = m2[0][0] * c00 + m2[0][1] * c01 + m2[0][2] * c02;
+    double tr = m2[0][0] + m2[1][1] + m2[2][2];
+    if (!(fabs(det) > 1e-12 * tr * tr * tr / 27.0) || !(tr > 0.0)) {
+        *A = 1.0 / m0;
+        for (int g = 0; g < 3; ++g) {
+            B[g] = 0.0;
+            dA[g] = -dm0[g] / (m0 * m0);
+            for (int a = 0; a < 3; ++a) dB[g][a] = 0.0;
+        }
+        return 1;
+    }
+    double inv[3][3];
+    inv[0][0] = c00 / det;
+    inv[0][1] = (m2[0][2] * m2[2][1] - m2[0][1] * m2[2][2]) / det;
+    inv[0][2] = (m2[0][1] * m2[1][2] - m2[0][2] * m2[1][1]) / det;
+    inv[1][0] = c01 / det;
+    inv[1][1] = (m2[0][0] * m2[2][2] - m2[0][2] * m2[2][0]) / det;
+    inv[1][2] = (m2[0][2] * m2[1][0] - m2[0][0] * m2[1][2]) / det;
+    inv[2][0] = c02 / det;
+    inv[2][1] = (m2[0][1] * m2[2][0] - m2[0][0] * m2[2][1]) / det;
+    inv[2][2] = (m2[0][0] * m2[1][1] - m2[0][1] * m2[1][0]) / det;
+
+    /* B = -m2^{-1} m1 */
+    for (int a = 0; a < 3; ++a) {
+        B[a] = 0.0;
+        for (int b = 0; b < 3; ++b) B[a] -= inv[a][b] * m1[b];
+    }
+    /* A = 1 / (m0 + B.m1) */
+    double Bm1 = B[0] * m1[0] + B[1] * m1[1] + B[2] * m1[2];
+    *A = 1.0 / (m0 + Bm1);
+    for (int g = 0; g < 3; ++g) {
+        /* d_g B = -m2^{-1} (d_g m1 + d_g m2 . B) */
+        double rhs[3];
+        for (int a = 0; a < 3; ++a) {
+            rhs[a] = dm1[g][a];
+            for (int b = 0; b < 3; ++b) rhs[a] += dm2[g][a][b] * B[b];
+        }
+        for (int a = 0; a < 3; ++a) {
+            dB[g][a] = 0.0;
+            for (int b = 0; b < 3; ++b) dB[g][a] -= inv[a][b] * rhs[b];
+        }
+        /* d_g A = -A^2 (d_g m0 + d_g B . m1 + B . d_g m1) */
+        double s = dm0[g];
+        for (int a = 0; a < 3; ++a) s += dB[g][a] * m1[a] + B[a] * dm1[g][a];
+        dA[g] = -(*A) * (*A) * s;
+    }
+    return 0;
+}
+
+/* For each target: A, B[3], gradA[3], gradB[9] (gradB[3g+a] = d_g B^a),
+ * corrected density rho, pressure P and sound speed cs; degenerate[k] = 1
+ * when the moment matrix was singular. */
+int orc_coefficients(int64_t n, const double *x, const double *y,
+                     const double *z, const double *h, const double *m,
+                     const double *V, const double *u, double gamma,
+                     int64_t nt, const int64_t *targets, int brute, double *A,
+                     double *B, double *gradA, double *gradB, double *rho,
+                     double *P, double *cs, int *degenerate)
+{
+    double hmax = max_of(n, h);
+    cells_t cl;
+    if (cells_build(&cl, n, x, y, z, 2.0 * hmax, brute)) return -1;
+#pragma omp parallel
+    {
+    nbr_t nb = {0, 0, NULL, NULL};
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = target_index(targets, k);
+        double hi = h[i];
+        double m0 = 0.0, m1[3] = {0, 0, 0}, m2[3][3] = {{0}}, dm0[3] = {0, 0, 0};
+        double sxdw[3][3] = {{0}};        /* sum V x^a d_g W   [g][a]    */
+        double sxxdw[3][3][3] = {{{0}}};  /* sum V x^a x^b d_g W [g][a][b] */
+        double M1[3] = {0, 0, 0}, rt = 0.0;
+        double R = 2.0 * hi;
+        find_neighbours(&cl, x, y, z, x[i], y[i], z[i], R * R, &nb);
+        for (int64_t q = 0; q < nb.n; ++q) {
+            int64_t j = nb.j[q];
+            double dx = nb.d[4 * q], dy = nb.d[4 * q + 1];
+            double dz = nb.d[4 * q + 2], r2 = nb.d[4 * q + 3];
+            double r = sqrt(r2);
+            double W, dW;
+            orc_kernel(r, hi, &W, &dW);
+            double xv[3] = {dx, dy, dz};
+            double gW[3];
+            for (int g = 0; g < 3; ++g) gW[g] = (r > 0.0) ? dW * xv[g] / r : 0.0;
+            double Vj = V[j];
+            m0 += Vj * W;
+            rt += m[j] * W;
+            for (int a = 0; a < 3; ++a) {
+                m1[a] += Vj * xv[a] * W;
+                M1[a] += m[j] * xv[a] * W;
+                dm0[a] += Vj * gW[a];
+                for (int b = 0; b < 3; ++b) m2[a][b] += Vj * xv[a] * xv[b] * W;
+            }
+            for (int g = 0; g < 3; ++g)
+                for (int a = 0; a < 3; ++a) {
+                    sxdw[g][a] += Vj * xv[a] * gW[g];
+                    for (int b = 0; b < 3; ++b)
+                        sxxdw[g][a][b] += Vj * xv[a] * xv[b] * gW[g];
+                }
+        }
+        double dm1[3][3], dm2[3][3][3];
+        for (int g = 0; g < 3; ++g)
+            for (int a = 0; a < 3; ++a) {
+                dm1[g][a] = (a == g ? m0 : 0.0) + sxdw[g][a];
+                for (int b = 0; b < 3; ++b)
+                    dm2[g][a][b] = (a == g ? m1[b] : 0.0) + (b == g ? m1[a] : 0.0)
+                                   + sxxdw[g][a][b];
+            }
+        double a_, b_[3], da_[3], db_[3][3];
+        int deg = solve_coefficients(m0, m1, m2, dm0, dm1, dm2, &a_, b_, da_, db_);
+        A[k] = a_;
+        for (int g = 0; g < 3; ++g) {
+            B[3 * k + g] = b_[g];
+            gradA[3 * k + g] = da_[g];
+            for (int a = 0; a < 3; ++a) gradB[9 * k + 3 * g + a] = db_[g][a];
+        }
+        double r_ = a_ * (rt + b_[0] * M1[0] + b_[1] * M1[1] + b_[2] * M1[2]);
+        rho[k] = r_;
+        P[k] = (gamma - 1.0) * r_ * u[i];
+        cs[k] = sqrt(gamma * (gamma - 1.0) * u[i]);
+        if (degenerate) degenerate[k] = deg;
+    }
+    nbr_free(&nb);
+    }
+    cells_free(&cl);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* CRKSPH pair forces                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Gradient of particle k's corrected kernel at separation y (= x_k - x_other),
+ * with the kernel at k's own smoothing length. */
+static void grad_rk(const double y[3], double hk, double Ak, const double *Bk,
+                    const double *dAk, const double *dBk, double out[3])
+{
+    double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    double W, dW;
+    orc_kernel(r, hk, &W, &dW);
+    double By = Bk[0] * y[0] + Bk[1] * y[1] + Bk[2] * y[2];
+    for (int g = 0; g < 3; ++g) {
+        double gW = (r > 0.0) ? dW * y[g] / r : 0.0;
+        double dBy = dBk[3 * g + 0] * y[0] + dBk[3 * g + 1] * y[1]
+                     + dBk[3 * g + 2] * y[2];
+        out[g] = dAk[g] * (1.0 + By) * W + Ak * (dBy + Bk[g]) * W
+                 + Ak * (1.0 + By) * gW;
+    }
+}
+
+int orc_hydro(int64_t n, const double *x, const double *y, const double *z,
+              const double *vx, const double *vy, const double *vz,
+              const double *h, const double *m, const double *V,
+              const double *rho, const double *P, const double *cs,
+              const double *A, const double *B, const double *gradA,
+              const double *gradB, double Cl, double Cq, double epsQ,
+              int64_t nt, const int64_t *targets, int brute, double *ax,
+              double *ay, double *az, double *dudt)
+{
+    double hmax = max_of(n, h);
+    cells_t cl;
+    if (cells_build(&cl, n, x, y, z, 2.0 * hmax, brute)) return -1;
+#pragma omp parallel
+    {
+    nbr_t nb = {0, 0, NULL, NULL};
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = target_index(targets, k);
+        double hi = h[i];
+        double f[3] = {0, 0, 0}, work = 0.0;
+        double R = 2.0 * hmax;
+        find_neighbours(&cl, x, y, z, x[i], y[i], z[i], R * R, &nb);
+        for (int64_t q = 0; q < nb.n; ++q) {
+            int64_t j = nb.j[q];
+            double dx = nb.d[4 * q], dy = nb.d[4 * q + 1];
+            double dz = nb.d[4 * q + 2], r2 = nb.d[4 * q + 3];
+            double lim = 2.0 * (hi > h[j] ? hi : h[j]);
+            if (j != i && r2 < lim * lim) {
+                double xij[3] = {dx, dy, dz};
+                double xji[3] = {-dx, -dy, -dz};
+                double gi[3], gj[3];
+                grad_rk(xij, hi, A[i], &B[3 * i], &gradA[3 * i], &gradB[9 * i], gi);
+                grad_rk(xji, h[j], A[j], &B[3 * j], &gradA[3 * j], &gradB[9 * j], gj);
+                double vij[3] = {vx[i] - vx[j], vy[i] - vy[j], vz[i] - vz[j]};
+                double vdx = vij[0] * dx + vij[1] * dy + vij[2] * dz;
+                double mui = hi * vdx / (r2 + epsQ * hi * hi);
+                double muj = h[j] * vdx / (r2 + epsQ * h[j] * h[j]);
+                if (mui > 0.0) mui = 0.0;
+                if (muj > 0.0) muj = 0.0;
+                double Qi = rho[i] * (-Cl * cs[i] * mui + Cq * mui * mui);
+                double Qj = rho[j] * (-Cl * cs[j] * muj + Cq * muj * muj);
+                double pp = P[i] + P[j];
+                double Fij[3];
+                for (int g = 0; g < 3; ++g)
+                    Fij[g] = -0.5 * V[i] * V[j]
+                             * (pp * (gi[g] - gj[g]) + Qi * gi[g] - Qj * gj[g]);
+                for (int g = 0; g < 3; ++g) f[g] += Fij[g];
+                work += vij[0] * Fij[0] + vij[1] * Fij[1] + vij[2] * Fij[2];
+            }
+        }
+        ax[k] = f[0] / m[i];
+        ay[k] = f[1] / m[i];
+        az[k] = f[2] / m[i];
+        dudt[k] = -0.5 * work / m[i];
+    }
+    nbr_free(&nb);
+    }
+    cells_free(&cl);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* short-range gravity                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* a_i = -G sum_{j != i, r < r_c} m_j g(r) x_ij / r over all particles of the
+ * box (both species, concatenated by the caller). */
+int orc_gravity(int64_t n, const double *x, const double *y, const double *z,
+                const double *m, double r_c, double eps, double G, int64_t nt,
+                const int64_t *targets, int brute, double *ax, double *ay,
+                double *az)
+{
+    cells_t cl;
+    if (cells_build(&cl, n, x, y, z, r_c, brute)) return -1;
+#pragma omp parallel
+    {
+    nbr_t nb = {0, 0, NULL, NULL};
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = target_index(targets, k);
+        double a[3] = {0, 0, 0};
+        find_neighbours(&cl, x, y, z, x[i], y[i], z[i], r_c * r_c, &nb);
+        for (int64_t q = 0; q < nb.n; ++q) {
+            int64_t j = nb.j[q];
+            double dx = nb.d[4 * q], dy = nb.d[4 * q + 1];
+            double dz = nb.d[4 * q + 2], r2 = nb.d[4 * q + 3];
+            if (j != i && r2 > 0.0) {
+                double r = sqrt(r2);
+                double s = -G * m[j] * orc_grav_g(r, r_c, eps) / r;
+                a[0] += s * dx;
+                a[1] += s * dy;
+                a[2] += s * dz;
+            }
+        }
+        ax[k] = a[0];
+        ay[k] = a[1];
+        az[k] = a[2];
+    }
+    nbr_free(&nb);
+    }
+    cells_free(&cl);
+    return 0;
+}
+
+/* Number of threads the parallel loops above use. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,326 @@
+"""ctypes front end of the FP64 C oracle (test infrastructure only).
+
+Every function takes numpy arrays (any float dtype; widened to float64,
+which is exact for the float32 inputs of the GPU path) and returns float64
+results.  ``targets`` selects the particles whose outputs are computed; the
+sums still run over every particle of the box.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_SRC = _HERE / "crk_oracle.c"
+_LIB = _HERE / "libcrk_oracle.so"
+
+# Constants of the step (readings of the method; the paper prints none):
+# ideal gas gamma = 5/3, Monaghan viscosity C_l = 1, C_q = 2 with eps_Q = 0.01,
+# gravitational constant G = 1.
+PARAMS = dict(gamma=5.0 / 3.0, Cl=1.0, Cq=2.0, epsQ=0.01, G=1.0)
+
+_lib = None
+
+
+def build(force: bool = True) -> Path:
+    """Compile the oracle with gcc (plain C, -O2, OpenMP)."""
+    if force or not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+        tmp = _LIB.with_suffix(".so.tmp%d" % os.getpid())
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                        "-std=c11", "-o", str(tmp), str(_SRC), "-lm"],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+            build(force=True)
+        _lib = ctypes.CDLL(str(_LIB))
+        _lib.orc_s2_force.restype = ctypes.c_double
+        _lib.orc_s2_force.argtypes = [ctypes.c_double, ctypes.c_double]
+        _lib.orc_grav_g.restype = ctypes.c_double
+        _lib.orc_grav_g.argtypes = [ctypes.c_double] * 3
+        _lib.orc_num_threads.restype = ctypes.c_int
+    return _lib
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _targets(targets, n):
+    if targets is None:
+        return n, None
+    t = np.ascontiguousarray(targets, dtype=np.int64)
+    return t.shape[0], t
+
+
+def _i64(v):
+    return ctypes.c_int64(int(v))
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def kernel(r, h):
+    """Cubic spline W(r, h) and dW/dr (scalar)."""
+    W = ctypes.c_double()
+    dW = ctypes.c_double()
+    _load().orc_kernel(ctypes.c_double(r), ctypes.c_double(h),
+                       ctypes.byref(W), ctypes.byref(dW))
+    return W.value, dW.value
+
+
+def s2_force(r, a):
+    return _load().orc_s2_force(float(r), float(a))
+
+
+def grav_g(r, r_c, eps):
+    return _load().orc_grav_g(float(r), float(r_c), float(eps))
+
+
+def neighbours(x, y, z, h, mode, targets=None, brute=False):
+    """Lists of gas neighbours of each target (mode 0: r < 2 h_i; mode 1:
+    r < 2 max(h_i, h_j)); returns (offsets, indices)."""
+    lib = _load()
+    x, y, z, h = _d(x), _d(y), _d(z), _d(h)
+    n = x.shape[0]
+    nt, t = _targets(targets, n)
+    counts = np.zeros(nt, np.int64)
+    if lib.orc_neighbours(_i64(n), _p(x), _p(y), _p(z), _p(h),
+                          ctypes.c_int(mode), _i64(nt), _p(t),
+                          ctypes.c_int(int(brute)), _p(counts), None, None):
+        raise MemoryError("oracle neighbour search failed")
+    off = np.zeros(nt + 1, np.int64)
+    np.cumsum(counts, out=off[1:])
+    idx = np.zeros(int(off[-1]), np.int64)
+    if lib.orc_neighbours(_i64(n), _p(x), _p(y), _p(z), _p(h),
+                          ctypes.c_int(mode), _i64(nt), _p(t),
+                          ctypes.c_int(int(brute)), _p(counts), _p(off),
+                          _p(idx)):
+        raise MemoryError("oracle neighbour search failed")
+    return off, idx
+
+
+def density(x, y, z, h, m, targets=None, brute=False):
+    lib = _load()
+    x, y, z, h, m = _d(x), _d(y), _d(z), _d(h), _d(m)
+    nt, t = _targets(targets, x.shape[0])
+    V = np.zeros(nt)
+    rt = np.zeros(nt)
+    if lib.orc_density(_i64(x.shape[0]), _p(x), _p(y), _p(z), _p(h), _p(m),
+                       _i64(nt), _p(t), ctypes.c_int(int(brute)), _p(V),
+                       _p(rt)):
+        raise MemoryError("oracle density failed")
+    return V, rt
+
+
+def coefficients(x, y, z, h, m, V, u, gamma=PARAMS["gamma"], targets=None,
+                 brute=False):
+    """A, B (n,3), gradA (n,3), gradB (n,3,3) with gradB[:, g, a] = d_g B^a,
+    rho, P, cs and the degenerate-moment flags."""
+    lib = _load()
+    x, y, z, h, m, V, u = (_d(a) for a in (x, y, z, h, m, V, u))
+    nt, t = _targets(targets, x.shape[0])
+    out = dict(A=np.zeros(nt), B=np.zeros((nt, 3)), gradA=np.zeros((nt, 3)),
+               gradB=np.zeros((nt, 3, 3)), rho=np.zeros(nt), P=np.zeros(nt),
+               cs=np.zeros(nt))
+    deg = np.zeros(nt, np.int32)
+    if lib.orc_coefficients(_i64(x.shape[0]), _p(x), _p(y), _p(z), _p(h),
+                            _p(m), _p(V), _p(u), ctypes.c_double(gamma),
+                            _i64(nt), _p(t), ctypes.c_int(int(brute)),
+                            _p(out["A"]), _p(out["B"]), _p(out["gradA"]),
+                            _p(out["gradB"]), _p(out["rho"]), _p(out["P"]),
+                            _p(out["cs"]), _p(deg)):
+        raise MemoryError("oracle coefficients failed")
+    out["degenerate"] = deg
+    return out
+
+
+def hydro(x, y, z, vx, vy, vz, h, m, V, rho, P, cs, A, B, gradA, gradB,
+          Cl=PARAMS["Cl"], Cq=PARAMS["Cq"], epsQ=PARAMS["epsQ"],
+          targets=None, brute=False):
+    """a_hydro (3 arrays) and du/dt at the targets."""
+    lib = _load()
+    arrs = [_d(a) for a in (x, y, z, vx, vy, vz, h, m, V, rho, P, cs, A)]
+    B = _d(np.reshape(B, (-1, 3)))
+    gradA = _d(np.reshape(gradA, (-1, 3)))
+    gradB = _d(np.reshape(gradB, (-1, 3, 3)))
+    n = arrs[0].shape[0]
+    nt, t = _targets(targets, n)
+    ax, ay, az, du = (np.zeros(nt) for _ in range(4))
+    if lib.orc_hydro(_i64(n), *[_p(a) for a in arrs], _p(B), _p(gradA),
+                     _p(gradB), ctypes.c_double(Cl), ctypes.c_double(Cq),
+                     ctypes.c_double(epsQ), _i64(nt), _p(t),
+                     ctypes.c_int(int(brute)), _p(ax), _p(ay), _p(az),
+                     _p(du)):
+        raise MemoryError("oracle hydro failed")
+    return ax, ay, az, du
+
+
+def gravity(x, y, z, m, r_c, eps, G=PARAMS["G"], targets=None, brute=False):
+    lib = _load()
+    x, y, z, m = _d(x), _d(y), _d(z), _d(m)
+    nt, t = _targets(targets, x.shape[0])
+    ax, ay, az = (np.zeros(nt) for _ in range(3))
+    if lib.orc_gravity(_i64(x.shape[0]), _p(x), _p(y), _p(z), _p(m),
+                       ctypes.c_double(r_c), ctypes.c_double(eps),
+                       ctypes.c_double(G), _i64(nt), _p(t),
+                       ctypes.c_int(int(brute)), _p(ax), _p(ay), _p(az)):
+        raise MemoryError("oracle gravity failed")
+    return ax, ay, az
+
+
+def integrate(dt, x, v, u, a_grav, a_hydro=None, dudt=None):
+    """One FP64 kick-drift: v += dt a, x += dt v (wrapped into [1, 2)),
+    u += dt du/dt.  x, v, a_* are (3, n) arrays."""
+    x = np.array(x, dtype=np.float64)
+    v = np.array(v, dtype=np.float64)
+    a = np.array(a_grav, dtype=np.float64)
+    if a_hydro is not None:
+        a = a + np.asarray(a_hydro, dtype=np.float64)
+    v = v + dt * a
+    x = x + dt * v
+    x = np.where(x >= 2.0, x - 1.0, x)
+    x = np.where(x < 1.0, x + 1.0, x)
+    out = dict(x=x, v=v)
+    if u is not None:
+        out["u"] = np.asarray(u, np.float64) + dt * np.asarray(dudt, np.float64)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# whole step and sampled step over a workload (duck-typed: any object with
+# gas/dm species, per-box offsets, r_c and eps)
+# ----------------------------------------------------------------------------
+
+def _box_slices(wl):
+    for b in range(wl.n_boxes):
+        yield (b, slice(int(wl.gas_off[b]), int(wl.gas_off[b + 1])),
+               slice(int(wl.dm_off[b]), int(wl.dm_off[b + 1])))
+
+
+def step(wl, params=PARAMS, brute=False, passes=("density", "coefficients",
+                                                   "hydro", "gravity")):
+    """Every output of the short-range step for every particle, box by box,
+    each pass fed with the previous passes' FP64 results."""
+    g, d = wl.gas, wl.dm
+    ng, nd = g.n, d.n
+    out = {k: np.zeros(ng) for k in ("V", "rho_tilde", "A", "rho", "P", "cs",
+                                     "dudt")}
+    out.update(B=np.zeros((ng, 3)), gradA=np.zeros((ng, 3)),
+               gradB=np.zeros((ng, 3, 3)), a_hydro=np.zeros((3, ng)),
+               a_grav_gas=np.zeros((3, ng)), a_grav_dm=np.zeros((3, nd)),
+               degenerate=np.zeros(ng, np.int32))
+    for b, gs, ds in _box_slices(wl):
+        if "density" in passes and gs.stop > gs.start:
+            V, rt = density(g.x[gs], g.y[gs], g.z[gs], g.h[gs], g.m[gs],
+                            brute=brute)
+            out["V"][gs], out["rho_tilde"][gs] = V, rt
+        if "coefficients" in passes and gs.stop > gs.start:
+            c = coefficients(g.x[gs], g.y[gs], g.z[gs], g.h[gs], g.m[gs],
+                             out["V"][gs], g.u[gs], params["gamma"],
+                             brute=brute)
+            for k in ("A", "B", "gradA", "gradB", "rho", "P", "cs",
+                      "degenerate"):
+                out[k][gs] = c[k]
+        if "hydro" in passes and gs.stop > gs.start:
+            ax, ay, az, du = hydro(
+                g.x[gs], g.y[gs], g.z[gs], g.vx[gs], g.vy[gs], g.vz[gs],
+                g.h[gs], g.m[gs], out["V"][gs], out["rho"][gs], out["P"][gs],
+                out["cs"][gs], out["A"][gs], out["B"][gs], out["gradA"][gs],
+                out["gradB"][gs], params["Cl"], params["Cq"], params["epsQ"],
+                brute=brute)
+            out["a_hydro"][:, gs] = (ax, ay, az)
+            out["dudt"][gs] = du
+        if "gravity" in passes:
+            X = np.concatenate([g.x[gs], d.x[ds]])
+            Y = np.concatenate([g.y[gs], d.y[ds]])
+            Z = np.concatenate([g.z[gs], d.z[ds]])
+            M = np.concatenate([g.m[gs], d.m[ds]])
+            if X.shape[0]:
+                ax, ay, az = gravity(X, Y, Z, M, float(wl.r_c[b]),
+                                     float(wl.eps[b]), params["G"],
+                                     brute=brute)
+                k = gs.stop - gs.start
+                out["a_grav_gas"][:, gs] = (ax[:k], ay[:k], az[:k])
+                out["a_grav_dm"][:, ds] = (ax[k:], ay[k:], az[k:])
+    return out
+
+
+def step_sampled(wl, gas_targets, dm_targets, params=PARAMS):
+    """The step's outputs at sampled particles only (global indices into the
+    gas and dm arrays).  Each sampled gas particle pulls in the
+    neighbourhoods its outputs depend on: coefficients at its force
+    neighbours, and volumes at their gather neighbours."""
+    g, d = wl.gas, wl.dm
+    gas_targets = np.asarray(gas_targets, np.int64)
+    dm_targets = np.asarray(dm_targets, np.int64)
+    res = dict(gas_idx=gas_targets, dm_idx=dm_targets)
+    nt = gas_targets.shape[0]
+    res.update(V=np.zeros(nt), rho_tilde=np.zeros(nt), A=np.zeros(nt),
+               rho=np.zeros(nt), P=np.zeros(nt), cs=np.zeros(nt),
+               dudt=np.zeros(nt), B=np.zeros((nt, 3)), gradA=np.zeros((nt, 3)),
+               gradB=np.zeros((nt, 3, 3)), a_hydro=np.zeros((3, nt)),
+               a_grav_gas=np.zeros((3, nt)),
+               a_grav_dm=np.zeros((3, dm_targets.shape[0])))
+    for b, gs, ds in _box_slices(wl):
+        sel = np.nonzero((gas_targets >= gs.start) & (gas_targets < gs.stop))[0]
+        dsel = np.nonzero((dm_targets >= ds.start) & (dm_targets < ds.stop))[0]
+        if sel.size == 0 and dsel.size == 0:
+            continue
+        gx, gy, gz = g.x[gs], g.y[gs], g.z[gs]
+        gh, gm = g.h[gs], g.m[gs]
+        n = gs.stop - gs.start
+        if sel.size:
+            T = gas_targets[sel] - gs.start
+            off, idx = neighbours(gx, gy, gz, gh, 1, targets=T)
+            S1 = np.unique(np.concatenate([T, idx]))
+            off2, idx2 = neighbours(gx, gy, gz, gh, 0, targets=S1)
+            S2 = np.unique(np.concatenate([S1, idx2]))
+            V = np.full(n, np.nan)
+            rt = np.full(n, np.nan)
+            V[S2], rt[S2] = density(gx, gy, gz, gh, gm, targets=S2)
+            c = coefficients(gx, gy, gz, gh, gm, V, g.u[gs], params["gamma"],
+                             targets=S1)
+            full = {}
+            for k in ("A", "rho", "P", "cs"):
+                full[k] = np.full(n, np.nan)
+                full[k][S1] = c[k]
+            for k, shp in (("B", (3,)), ("gradA", (3,)), ("gradB", (3, 3))):
+                full[k] = np.full((n,) + shp, np.nan)
+                full[k][S1] = c[k]
+            ax, ay, az, du = hydro(
+                gx, gy, gz, g.vx[gs], g.vy[gs], g.vz[gs], gh, gm, V,
+                full["rho"], full["P"], full["cs"], full["A"], full["B"],
+                full["gradA"], full["gradB"], params["Cl"], params["Cq"],
+                params["epsQ"], targets=T)
+            res["V"][sel], res["rho_tilde"][sel] = V[T], rt[T]
+            for k in ("A", "rho", "P", "cs", "B", "gradA", "gradB"):
+                res[k][sel] = full[k][T]
+            res["a_hydro"][:, sel] = (ax, ay, az)
+            res["dudt"][sel] = du
+        X = np.concatenate([gx, d.x[ds]])
+        Y = np.concatenate([gy, d.y[ds]])
+        Z = np.concatenate([gz, d.z[ds]])
+        M = np.concatenate([gm, d.m[ds]])
+        tg = np.concatenate([gas_targets[sel] - gs.start,
+                             dm_targets[dsel] - ds.start + n])
+        ax, ay, az = gravity(X, Y, Z, M, float(wl.r_c[b]), float(wl.eps[b]),
+                             params["G"], targets=tg)
+        k = sel.size
+        res["a_grav_gas"][:, sel] = (ax[:k], ay[:k], az[:k])
+        res["a_grav_dm"][:, dsel] = (ax[k:], ay[k:], az[k:])
+    return res
