@@ -1,0 +1,219 @@
+#!/usr/bin/env python
+"""Throughput of one full short-range step (build_tree, lists, density,
+coefficients, hydro forces, gravity, integrate) on one MI355X.
+
+Workload (default): 128^3 dm + 128^3 gas particles, Zel'dovich displacements
+of a Gaussian random field with P(k) ~ k^-2 (rms 0.5 grid spacing),
+~64 hydro neighbours, r_c = 3/128, leaf size <= 128; synthetic, seeded.
+
+value = particles / s of the float32 path (pair sums in float32 with
+compensated accumulation, double moment solve and integration), replayed as
+one HIP graph per step.  The plain float64 path (same kernels in double,
+launched eagerly) is timed beside it and reported as fp64_plain; the
+speedup is their ratio.  The roofline entry covers the pass kernel with
+the largest average duration, timed with HIP events on the library's stream.
+The CPU baseline is the FP64 oracle (C, OpenMP) on the same workload.
+Progress goes to stderr; stdout carries one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# FLOP per in-range ordered pair of each pass kernel, counted from its
+# arithmetic (FMA = 2, rsqrt/rcp = 1, compares and selects not counted).
+# gravity: 33 for r < r_c/2, 39 beyond; 38 is the uniform-density mean.
+FLOP_PER_PAIR = {"density": 20, "coefficients": 89, "hydro": 178,
+                 "gravity": 38}
+PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector, published (packed)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+KERNEL_NAMES = {"density": "pair_kernel<float, DensityPass<float>>",
+                "coefficients": "pair_kernel<float, CoeffPass<float>>",
+                "hydro": "pair_kernel<float, HydroPass<float>>",
+                "gravity": "pair_kernel<float, GravityPass<float>>"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("passes.hip", "crk_internal.h"):
+        with open(os.path.join(ROOT, "paper_2510_03557_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(pass_name: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"{pass_name}_pmc_zeldovich128.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_steps(fn, sync, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="zeldovich128")
+    ap.add_argument("--leaf-max", type=int, default=128)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--dt", type=float, default=1e-5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the short-range step of one "
+              "box set runs on a single MI355X here; multi-GPU runs are not "
+              "part of this build (see DESIGN.md for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2510_03557_amd import workloads
+    from paper_2510_03557_amd.step import ShortRangeStep
+
+    torch.cuda.set_device(0)
+    log(f"[bench] generating {args.workload}")
+    wl = workloads.make(args.workload)
+    n = wl.n_total
+    tuning = dict(leaf_max=args.leaf_max)
+
+    # ---------------- float32 path: graph replay of the whole step ---------
+    log("[bench] fp32 path: eager warm-up, kernel timing")
+    st = ShortRangeStep(wl, precision="fp32", tuning=tuning, dt=args.dt)
+    st.run(integrate=True)
+    st.sync()
+    pairs = st.ctx.count_pairs(st.tree)
+    info = st.tree.info()
+    # per-kernel HIP-event timing over eager steps on the library stream
+    st.ctx.timing(True)
+    n_eager = max(args.steps // 4, 3)
+    for _ in range(n_eager):
+        st.run(integrate=True)
+    pass_ms, kern_ms, launches = st.ctx.pass_times()
+    st.ctx.timing(False)
+    st.sync()
+    log("[bench] fp32 path: graph capture and timed replays")
+    st.capture(integrate=True)
+    sec = time_steps(st.replay, lambda: (torch.cuda.synchronize(),
+                                         st.ctx.stream.synchronize()),
+                     args.steps, args.warmup)
+    st.sync()
+    value = n / sec
+
+    # ---------------- float64 plain path (eager) -----------------------------
+    fp64 = None
+    if not args.no_fp64:
+        log("[bench] fp64 plain path")
+        st64 = ShortRangeStep(wl, precision="fp64", tuning=dict(leaf_max=64),
+                              dt=args.dt)
+        sec64 = time_steps(lambda: st64.run(integrate=True),
+                           lambda: st64.ctx.stream.synchronize(),
+                           args.fp64_steps, 1)
+        st64.sync()
+        fp64 = {"value": n / sec64, "ms_per_step": sec64 * 1e3,
+                "dtype": "f64", "launch": "eager", "leaf_max": 64}
+        st64.close()
+
+    # ---------------- roofline of the dominant pass kernel -------------------
+    pair_of = {"density": pairs[0], "coefficients": pairs[0],
+               "hydro": pairs[1], "gravity": pairs[2]}
+    kern = {}
+    for p in ("density", "coefficients", "hydro", "gravity"):
+        if launches[p]:
+            avg = kern_ms[p] / launches[p]
+            flop = pair_of[p] * FLOP_PER_PAIR[p]
+            kern[p] = {"avg_ms": avg, "pairs": pair_of[p],
+                       "flop_per_pair": FLOP_PER_PAIR[p],
+                       "tflops": flop / (avg * 1e-3) / 1e12}
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"])
+    ach = kern[dom]["tflops"]
+    traffic = measured_traffic(dom)
+    roofline = {"bound": "alu", "achieved": round(ach, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                "traffic": traffic, "kernel": KERNEL_NAMES[dom],
+                "avg_launch_ms": round(kern[dom]["avg_ms"], 4),
+                "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                "frac_unpacked": round(ach / PEAK_FP32_UNPACKED_TFLOPS, 4)}
+
+    # ---------------- CPU baseline: the FP64 oracle ---------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline: FP64 oracle, whole workload, one step")
+        import oracle
+        oracle.build(force=False)
+        t0 = time.perf_counter()
+        oracle.step(wl)
+        tc = time.perf_counter() - t0
+        cpu = {"value": n / tc, "unit": "particles/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"the whole {args.workload} workload ({n} particles),"
+                         " one step of the four passes, FP64 C oracle with "
+                         "OpenMP", "seconds": round(tc, 2)}
+
+    out = {
+        "metric": "particles/s per full short-range step (grav+CRKSPH), "
+                  "FP32-batched vs FP64 plain",
+        "value": value, "unit": "particles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload,
+                   "description": "128^3 dm + 128^3 gas, Zel'dovich P(k)~k^-2,"
+                                  " r_c=3/128, ~64 hydro neighbours, periodic"
+                   if args.workload == "zeldovich128" else wl.name,
+                   "n_particles": n, "boxes": wl.n_boxes,
+                   "leaf_max": args.leaf_max, "launch": "hip_graph",
+                   "leaves": info["n_leaves"],
+                   "list_entries": {"gravity": info["grav_entries"],
+                                    "hydro": info["hydro_entries"]}},
+        "fp64_plain": fp64,
+        "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "pairs": {"gather": pairs[0], "hydro": pairs[1], "gravity": pairs[2]},
+        "pass_ms": {k: round(v / n_eager, 4) for k, v in pass_ms.items()},
+        "kernels": kern,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "context": "paper: 46.6e9 particles/s on 9,000 Frontier nodes for the"
+                   " whole solver per PM step (not like-for-like)",
+    }
+    st.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,273 @@
+/*
+ * crk.h -- C ABI of the MI355X short-range step of CRK-HACC
+ * (Frontiere et al., "Cosmological Hydrodynamics at Exascale: A
+ * Trillion-Particle Leap in Capability").
+ *
+ * The step evaluates, for particles in periodic unit boxes, the short-range
+ * gravitational force inside the handover scale r_c (Sec. IV-A: the force
+ * is split into a spectral long-range part and a local short-range part)
+ * and the CRKSPH hydrodynamics passes (Sec. IV-A: conservative
+ * reproducing-kernel SPH), all as pairwise sums phi_i = sum_j phi_ij
+ * (Eq. (1)) over leaf-leaf interaction lists of chaining-mesh bins and
+ * per-bin k-d base leaves (Sec. IV-B.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every particle pointer is a DEVICE pointer owned by the caller, in the
+ *   caller's particle order.  Arrays hold float (context precision
+ *   CRK_FP32) or double (CRK_FP64), except where a type is stated.
+ * - Positions lie in [1, 2) (unit periodic box shifted by one).  In float32
+ *   any two such values share one exponent, so their difference is exact.
+ * - Vector fields are stored as planes: B and gradA hold 3 planes of n
+ *   values (plane a at offset a*n), gradB holds 9 planes with plane
+ *   (3*g + a) = d B^a / d x^g.
+ * - Particles are grouped into n_boxes independent periodic boxes by the
+ *   per-box offsets of the gas and dm arrays; boxes do not interact.
+ * - All work is enqueued asynchronously on the context's stream; no entry
+ *   point synchronises except build_tree / build_interaction_lists outside
+ *   graph capture (they read back sizes) and crk_sync.
+ * - Return value: CRK_OK or a negative crk_status; the message of the last
+ *   failure on the calling thread is returned by crk_last_error().
+ *   Argument errors are detected on the host before anything is enqueued.
+ *   Errors found on the device (non-finite or out-of-range inputs, a
+ *   capacity fixed at graph capture being exceeded) are latched in the
+ *   context and returned by crk_sync.
+ * - The library never aborts, never throws across this boundary and keeps
+ *   no global state besides the last-error message.
+ */
+#ifndef CRK_H
+#define CRK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CRK_OK = 0,
+    CRK_EINVAL = -1,    /* bad argument (host side) or bad input value      */
+    CRK_ECAPACITY = -2, /* a capacity fixed at graph capture was exceeded    */
+    CRK_EDEVICE = -3,   /* HIP runtime error                                 */
+    CRK_ESTATE = -4     /* call out of order (e.g. lists before tree)        */
+} crk_status;
+
+typedef enum {
+    CRK_FP64 = 0, /* plain double precision everywhere                       */
+    CRK_FP32 = 1  /* float pair sums with compensated accumulation; double
+                     moment-matrix solve and double integration             */
+} crk_precision;
+
+typedef struct crk_ctx crk_ctx;   /* opaque, library-owned */
+typedef struct crk_tree crk_tree; /* opaque, library-owned */
+
+/* Physical constants of the step.  The paper fixes none of them; these are
+ * the method's usual choices: ideal gas gamma, Monaghan viscosity C_l, C_q
+ * with denominator guard eps_Q, gravitational constant G. */
+typedef struct {
+    double gamma; /* adiabatic index (5/3)                 */
+    double Cl;    /* linear viscosity coefficient (1)      */
+    double Cq;    /* quadratic viscosity coefficient (2)   */
+    double epsQ;  /* viscosity guard, times h^2 (0.01)     */
+    double G;     /* gravitational constant (1)            */
+} crk_params;
+
+/* Host-side description of the boxes (all arrays are HOST memory, read
+ * during build_tree only). */
+typedef struct {
+    int32_t n_boxes;       /* >= 1                                          */
+    const int64_t *gas_off; /* n_boxes + 1 offsets into the gas arrays       */
+    const int64_t *dm_off;  /* n_boxes + 1 offsets into the dm arrays        */
+    const double *r_c;      /* per box: gravity cutoff, 0 < r_c < 0.5        */
+    const double *eps;      /* per box: Plummer softening, 0 <= eps < r_c    */
+    const double *h_max;    /* per box: upper bound of the gas smoothing
+                               lengths, 0 < 2 h_max < 0.5 (checked on the
+                               device; a larger h raises CRK_EINVAL at
+                               crk_sync)                                     */
+} crk_boxes;
+
+/* Tunables of the tree and launch shape (results do not depend on them
+ * beyond floating-point rounding order). */
+typedef struct {
+    int32_t leaf_max;   /* k-d leaf size bound, 16..256 (default 64)         */
+    double cm_factor;   /* chaining-mesh bin width / max(r_c, 2 h_max) >= 1
+                           (default 1.0)                                     */
+    int32_t grid_mult;  /* persistent grid = grid_mult x CU count; 0 = one
+                           workgroup per leaf (default 0)                    */
+} crk_tuning;
+
+/* ------------------------------------------------------------------------ */
+/* context                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Creates a context on the current HIP device.  stream: a hipStream_t (or
+ * NULL for the default stream) on which all work is enqueued.  params may
+ * be NULL for the defaults above. */
+int crk_ctx_create(crk_ctx **out, int precision, void *stream,
+                   const crk_params *params);
+int crk_ctx_destroy(crk_ctx *ctx);
+int crk_set_tuning(crk_ctx *ctx, const crk_tuning *t);
+int crk_get_tuning(const crk_ctx *ctx, crk_tuning *t);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *crk_last_error(void);
+
+/* Waits for the context's stream and returns the first latched device-side
+ * error (CRK_EINVAL for bad input values, CRK_ECAPACITY when a capacity
+ * fixed at capture was exceeded), then clears it.  *required (may be NULL)
+ * receives the list capacity, in entries, that the last build needed. */
+int crk_sync(crk_ctx *ctx, int64_t *required);
+
+/* ------------------------------------------------------------------------ */
+/* the six operations of the short-range step                               */
+/* ------------------------------------------------------------------------ */
+
+/* Chaining-mesh bins and per-bin k-d base leaves (Sec. IV-B.1).
+ * Each box is cut into n_cm^3 bins with n_cm = floor(1 / (cm_factor *
+ * max(r_c, 2 h_max))), so every interaction of a particle lies in its bin
+ * or one of the 26 neighbours.  Particles are sorted by (species, box,
+ * bin); inside each bin a k-d tree splits the widest extent at the median
+ * (ties by caller index) until leaves hold <= leaf_max particles; only the
+ * leaves are kept.
+ * gx, gy, gz, gh: gas positions and smoothing lengths (n_gas values);
+ * dx, dy, dz: dark-matter positions (n_dm values); n_gas = gas_off[n_boxes],
+ * n_dm = dm_off[n_boxes].  The positions and h are copied into the tree (in
+ * tree order); later calls use the copies.  *tree is created on first use
+ * and reused (grown as needed) when non-NULL. */
+int build_tree(crk_ctx *ctx, const crk_boxes *boxes, const void *gx,
+               const void *gy, const void *gz, const void *gh,
+               const void *dx, const void *dy, const void *dz,
+               crk_tree **tree);
+
+/* Leaf-leaf interaction lists (Sec. IV-B.1): for every leaf, the leaves of
+ * its own and the 26 neighbouring bins whose periodic bounding boxes come
+ * closer than the interaction range, with the periodic image shift of each.
+ * Gravity list: all species, range r_c.  Hydro list: gas leaves only, range
+ * 2 max(h_max of either leaf).  Ranges are widened by 1e-5 relative so that
+ * no pair accepted by float32 arithmetic is missed. */
+int build_interaction_lists(crk_ctx *ctx, crk_tree *tree);
+
+/* Volume and uncorrected density of every gas particle (CRKSPH, Sec. IV-A;
+ * a pairwise sum of the form of Eq. (1)):
+ *   V_i = 1 / sum_j W(r_ij, h_i),   rho~_i = sum_j m_j W(r_ij, h_i),
+ * over gas j with r_ij < 2 h_i, j = i included; W is the cubic spline.
+ * m: gas masses (n_gas); V, rho_tilde: outputs (n_gas). */
+int crk_density(crk_ctx *ctx, crk_tree *tree, const void *m, void *V,
+                void *rho_tilde);
+
+/* Reproducing-kernel correction coefficients (CRKSPH, Sec. IV-A; the
+ * paper's highest-throughput kernel, Sec. V-B).  Gathers the moments
+ * m0, m1, m2 of V_j W(r_ij, h_i) and their gradients, then solves, per
+ * particle in double precision,
+ *   B = -m2^-1 m1,  A = 1/(m0 + B.m1),
+ *   d_g B = -m2^-1 (d_g m1 + d_g m2 B),  d_g A = -A^2 (d_g m0 + d_g B.m1
+ *   + B.d_g m1),
+ * so that A(1 + B.x_ij) W reproduces constant and linear fields, then the
+ * corrected density rho = A (rho~ + B.M1) with M1 = sum m_j x_ij W_ij, the
+ * ideal-gas pressure P = (gamma - 1) rho u and sound speed
+ * cs = sqrt(gamma (gamma - 1) u).  A singular m2 falls back to B = grad B = 0,
+ * A = 1/m0, grad A = -grad m0 / m0^2.
+ * Inputs m, V, u (n_gas); outputs A, rho, P, cs (n_gas), B and gradA
+ * (3 planes), gradB (9 planes). */
+int crk_coefficients(crk_ctx *ctx, crk_tree *tree, const void *m,
+                     const void *V, const void *u, void *A, void *B,
+                     void *gradA, void *gradB, void *rho, void *P, void *cs);
+
+/* CRKSPH accelerations and specific-energy rates (Sec. IV-A; the
+ * antisymmetric pair terms of Eq. (2)).  With the corrected-kernel gradient
+ * g_k(y) = dA_k (1 + B_k.y) W_k + A_k (dB_k.y + B_k) W_k
+ *          + A_k (1 + B_k.y) grad W_k   (W_k at h_k),
+ * G_ij = g_i(x_ij) - g_j(x_ji) and the Monaghan viscosity
+ * Q_ij = rho_i (-C_l cs_i mu_ij + C_q mu_ij^2),
+ * mu_ij = min(0, h_i v_ij.x_ij / (r^2 + eps_Q h_i^2)), the pair force is
+ *   F_ij = -1/2 V_i V_j [(P_i + P_j) G_ij + Q_ij g_i(x_ij) - Q_ji g_j(x_ji)]
+ * = -F_ji, and a_i = sum_j F_ij / m_i, du_i/dt = -sum_j v_ij.F_ij / (2 m_i),
+ * over gas j != i with r_ij < 2 max(h_i, h_j).
+ * Inputs (n_gas each): m, vx, vy, vz, V, rho, P, cs, A; B, gradA (3 planes),
+ * gradB (9 planes).  Outputs ax, ay, az, dudt (n_gas). */
+int crk_hydro_forces(crk_ctx *ctx, crk_tree *tree, const void *m,
+                     const void *vx, const void *vy, const void *vz,
+                     const void *V, const void *rho, const void *P,
+                     const void *cs, const void *A, const void *B,
+                     const void *gradA, const void *gradB, void *ax,
+                     void *ay, void *az, void *dudt);
+
+/* Short-range gravity inside the handover scale (Sec. IV-A, with the
+ * long-range part left to a spectral particle-mesh solver):
+ *   a_i = -G sum_{j != i, r_ij < r_c} m_j g(r_ij) x_ij / r_ij,
+ *   g(r) = r / (r^2 + eps^2)^(3/2) - R_S2(r; r_c),
+ * where R_S2 is the force between two S2 clouds of diameter r_c (Hockney &
+ * Eastwood), over both species of the particle's box.
+ * m_gas (n_gas), m_dm (n_dm): masses; outputs ax/ay/az for gas (n_gas) and
+ * dm (n_dm). */
+int shortrange_gravity(crk_ctx *ctx, crk_tree *tree, const void *m_gas,
+                       const void *m_dm, void *ax_gas, void *ay_gas,
+                       void *az_gas, void *ax_dm, void *ay_dm, void *az_dm);
+
+/* One kick-drift in double precision (the mixed-precision pattern of
+ * Sec. IV-A: float short-range sums, double state):
+ *   v += dt (a_grav + a_hydro), x += dt v wrapped into [1, 2), u += dt dudt,
+ * then refreshes the context-precision copies of x, v and u.
+ * n particles; x64, v64: 3 planes of doubles (in/out); u64: doubles or NULL
+ * (dm); a_grav: 3 planes (context precision); a_hydro and dudt: 3 planes /
+ * n values or NULL; x, v: 3 pointers each to the context-precision copies
+ * (out); u: context-precision copy or NULL. */
+int crk_integrate(crk_ctx *ctx, int64_t n, double dt, double *x64,
+                  double *v64, double *u64, const void *const a_grav[3],
+                  const void *const a_hydro[3], const void *dudt,
+                  void *const x[3], void *const v[3], void *u);
+
+/* ------------------------------------------------------------------------ */
+/* tree queries, graph capture, release                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Sizes of a built tree (host values; valid after a synchronising build). */
+typedef struct {
+    int64_t n_gas, n_dm;
+    int64_t n_leaves, n_gas_leaves;
+    int64_t n_bins;                 /* chaining-mesh bins over all boxes     */
+    int64_t grav_entries, hydro_entries; /* list lengths (leaf pairs)        */
+    int32_t kd_levels;              /* k-d levels run                        */
+} crk_tree_info;
+int crk_tree_get_info(const crk_tree *tree, crk_tree_info *info);
+
+/* Exact numbers of in-range ordered pairs under each pass's own pair test
+ * (a diagnostic for throughput accounting; synchronises):
+ * totals[0]: gas pairs with r_ij < 2 h_i, i = j included (density and
+ * coefficients); totals[1]: gas pairs i != j with r_ij < 2 max(h_i, h_j)
+ * (hydro forces); totals[2]: pairs with 0 < r_ij < r_c (gravity). */
+int crk_count_pairs(crk_ctx *ctx, crk_tree *tree, int64_t totals[3]);
+
+/* Copies the tree-order permutation (caller index of each tree slot: gas
+ * index, or n_gas + dm index) and the leaf table (start, count; host int64
+ * arrays of n_leaves) to host memory; either pointer may be NULL. */
+int crk_tree_get_leaves(crk_ctx *ctx, const crk_tree *tree, int64_t *perm,
+                        int64_t *leaf_start, int64_t *leaf_count);
+
+/* Captures everything enqueued on the context's stream between begin and
+ * end into a HIP graph (build_tree and build_interaction_lists then use
+ * the capacities of the previous eager build and read nothing back);
+ * crk_graph_launch replays it.  Capacities exceeded during a replay are
+ * reported by crk_sync as CRK_ECAPACITY. */
+int crk_graph_begin(crk_ctx *ctx);
+int crk_graph_end(crk_ctx *ctx);
+int crk_graph_launch(crk_ctx *ctx);
+
+int crk_tree_free(crk_tree *tree);
+
+/* Timing with HIP events on the context's stream (outside graph capture).
+ * enable = 1 starts recording; crk_pass_times waits for the stream and
+ * returns, per operation since the last query, the summed milliseconds of
+ * the whole call (pass_ms) and of its main kernel alone (kernel_ms: the pair
+ * kernel of the four passes and the integrate kernel), and the number of
+ * main-kernel launches.  Index order: 0 build_tree, 1 lists, 2 density,
+ * 3 coefficients, 4 hydro, 5 gravity, 6 integrate.  Any array may be NULL. */
+int crk_timing_enable(crk_ctx *ctx, int enable);
+int crk_pass_times(crk_ctx *ctx, double pass_ms[7], double kernel_ms[7],
+                   int64_t launches[7]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRK_H */

@@ -1,0 +1,313 @@
+"""ctypes binding of libcrk.so (the C ABI declared in include/crk.h).
+
+Argument marshalling only: every step of the short-range step runs in the
+library's HIP kernels.  torch tensors serve as device buffers and the torch
+stream as the HIP stream.  The binding raises if the library is missing;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+LIB_PATH = Path(os.environ.get("CRK_LIB", _HERE / "libcrk.so"))
+
+CRK_OK, CRK_EINVAL, CRK_ECAPACITY, CRK_EDEVICE, CRK_ESTATE = 0, -1, -2, -3, -4
+CRK_FP64, CRK_FP32 = 0, 1
+PASS_NAMES = ("tree", "lists", "density", "coefficients", "hydro", "gravity",
+              "integrate")
+
+EXPORTS = (
+    "crk_ctx_create", "crk_ctx_destroy", "crk_set_tuning", "crk_get_tuning",
+    "crk_last_error", "crk_sync", "build_tree", "build_interaction_lists",
+    "crk_density", "crk_coefficients", "crk_hydro_forces",
+    "shortrange_gravity", "crk_integrate", "crk_tree_get_info",
+    "crk_tree_get_leaves", "crk_count_pairs", "crk_graph_begin", "crk_graph_end",
+    "crk_graph_launch", "crk_tree_free", "crk_timing_enable",
+    "crk_pass_times",
+)
+
+
+class CrkError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"crk status {status}: {msg}")
+        self.status = status
+
+
+class crk_params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("Cl", ctypes.c_double),
+                ("Cq", ctypes.c_double), ("epsQ", ctypes.c_double),
+                ("G", ctypes.c_double)]
+
+
+class crk_boxes(ctypes.Structure):
+    _fields_ = [("n_boxes", ctypes.c_int32),
+                ("gas_off", ctypes.POINTER(ctypes.c_int64)),
+                ("dm_off", ctypes.POINTER(ctypes.c_int64)),
+                ("r_c", ctypes.POINTER(ctypes.c_double)),
+                ("eps", ctypes.POINTER(ctypes.c_double)),
+                ("h_max", ctypes.POINTER(ctypes.c_double))]
+
+
+class crk_tuning(ctypes.Structure):
+    _fields_ = [("leaf_max", ctypes.c_int32), ("cm_factor", ctypes.c_double),
+                ("grid_mult", ctypes.c_int32)]
+
+
+class crk_tree_info(ctypes.Structure):
+    _fields_ = [("n_gas", ctypes.c_int64), ("n_dm", ctypes.c_int64),
+                ("n_leaves", ctypes.c_int64), ("n_gas_leaves", ctypes.c_int64),
+                ("n_bins", ctypes.c_int64), ("grav_entries", ctypes.c_int64),
+                ("hydro_entries", ctypes.c_int64), ("kd_levels", ctypes.c_int32)]
+
+
+_lib = None
+_exiting = False
+
+
+def _mark_exit():
+    # native objects still alive at interpreter exit are left to the process
+    # teardown: their streams may already be gone
+    global _exiting
+    _exiting = True
+
+
+import atexit  # noqa: E402
+
+atexit.register(_mark_exit)
+
+
+def load(path: Path | str | None = None):
+    """Loads libcrk.so; raises ImportError when it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = Path(path) if path else LIB_PATH
+    if not p.exists():
+        raise ImportError(f"{p} is missing: build it with "
+                          "`python -m paper_2510_03557_amd.build`")
+    lib = ctypes.CDLL(str(p))
+    vp = ctypes.c_void_p
+    lib.crk_last_error.restype = ctypes.c_char_p
+    lib.crk_last_error.argtypes = []
+    lib.crk_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp,
+                                   ctypes.POINTER(crk_params)]
+    lib.crk_ctx_destroy.argtypes = [vp]
+    lib.crk_set_tuning.argtypes = [vp, ctypes.POINTER(crk_tuning)]
+    lib.crk_get_tuning.argtypes = [vp, ctypes.POINTER(crk_tuning)]
+    lib.crk_sync.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.build_tree.argtypes = [vp, ctypes.POINTER(crk_boxes)] + [vp] * 7 + \
+        [ctypes.POINTER(vp)]
+    lib.build_interaction_lists.argtypes = [vp, vp]
+    lib.crk_density.argtypes = [vp, vp, vp, vp, vp]
+    lib.crk_coefficients.argtypes = [vp] * 12
+    lib.crk_hydro_forces.argtypes = [vp] * 18
+    lib.shortrange_gravity.argtypes = [vp] * 10
+    lib.crk_integrate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp, vp,
+                                  vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  vp]
+    lib.crk_tree_get_info.argtypes = [vp, ctypes.POINTER(crk_tree_info)]
+    lib.crk_tree_get_leaves.argtypes = [vp, vp, vp, vp, vp]
+    lib.crk_count_pairs.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.crk_graph_begin.argtypes = [vp]
+    lib.crk_graph_end.argtypes = [vp]
+    lib.crk_graph_launch.argtypes = [vp]
+    lib.crk_tree_free.argtypes = [vp]
+    lib.crk_timing_enable.argtypes = [vp, ctypes.c_int]
+    lib.crk_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64)]
+    for name in EXPORTS:
+        getattr(lib, name).restype = (ctypes.c_char_p if name == "crk_last_error"
+                                      else ctypes.c_int)
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().crk_last_error().decode()
+
+
+def check(status: int):
+    if status != CRK_OK:
+        raise CrkError(status, last_error())
+
+
+def _ptr(t):
+    """Device address of a torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _arr(ctype, vals):
+    a = (ctype * len(vals))(*vals)
+    return a
+
+
+class Context:
+    """A library context bound to one HIP stream."""
+
+    def __init__(self, precision: str = "fp32", stream=None, params=None):
+        import torch
+        self.lib = load()
+        self.precision = precision
+        self.torch = torch
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self._boxes_keep = None
+        h = ctypes.c_void_p()
+        p = None
+        if params is not None:
+            p = ctypes.byref(crk_params(**params))
+        check(self.lib.crk_ctx_create(
+            ctypes.byref(h), CRK_FP32 if precision == "fp32" else CRK_FP64,
+            ctypes.c_void_p(self.stream.cuda_stream), p))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and not _exiting:
+            self.lib.crk_ctx_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, leaf_max=64, cm_factor=1.0, grid_mult=0):
+        check(self.lib.crk_set_tuning(self.handle, ctypes.byref(
+            crk_tuning(int(leaf_max), float(cm_factor), int(grid_mult)))))
+
+    def sync(self):
+        req = ctypes.c_int64()
+        check(self.lib.crk_sync(self.handle, ctypes.byref(req)))
+        return req.value
+
+    def build_tree(self, tree, gas_off, dm_off, r_c, eps, h_max, gx, gy, gz,
+                   gh, dx, dy, dz):
+        """tree: a Tree object (created empty) whose handle is filled."""
+        go = np.ascontiguousarray(gas_off, np.int64)
+        do = np.ascontiguousarray(dm_off, np.int64)
+        rc = np.ascontiguousarray(r_c, np.float64)
+        ep = np.ascontiguousarray(eps, np.float64)
+        hm = np.ascontiguousarray(h_max, np.float64)
+        keep = (go, do, rc, ep, hm)
+        b = crk_boxes(len(go) - 1,
+                      go.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                      do.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                      rc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      ep.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      hm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self._boxes_keep = (keep, b)
+        check(self.lib.build_tree(self.handle, ctypes.byref(b), _ptr(gx),
+                                  _ptr(gy), _ptr(gz), _ptr(gh), _ptr(dx),
+                                  _ptr(dy), _ptr(dz),
+                                  ctypes.byref(tree.handle)))
+
+    def build_interaction_lists(self, tree):
+        check(self.lib.build_interaction_lists(self.handle, tree.handle))
+
+    def density(self, tree, m, V, rho_t):
+        check(self.lib.crk_density(self.handle, tree.handle, _ptr(m), _ptr(V),
+                                   _ptr(rho_t)))
+
+    def coefficients(self, tree, m, V, u, A, B, gA, gB, rho, P, cs):
+        check(self.lib.crk_coefficients(self.handle, tree.handle, _ptr(m),
+                                        _ptr(V), _ptr(u), _ptr(A), _ptr(B),
+                                        _ptr(gA), _ptr(gB), _ptr(rho), _ptr(P),
+                                        _ptr(cs)))
+
+    def hydro_forces(self, tree, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB,
+                     ax, ay, az, dudt):
+        check(self.lib.crk_hydro_forces(
+            self.handle, tree.handle, _ptr(m), _ptr(vx), _ptr(vy), _ptr(vz),
+            _ptr(V), _ptr(rho), _ptr(P), _ptr(cs), _ptr(A), _ptr(B), _ptr(gA),
+            _ptr(gB), _ptr(ax), _ptr(ay), _ptr(az), _ptr(dudt)))
+
+    def shortrange_gravity(self, tree, m_gas, m_dm, axg, ayg, azg, axd, ayd,
+                           azd):
+        check(self.lib.shortrange_gravity(
+            self.handle, tree.handle, _ptr(m_gas), _ptr(m_dm), _ptr(axg),
+            _ptr(ayg), _ptr(azg), _ptr(axd), _ptr(ayd), _ptr(azd)))
+
+    def integrate(self, n, dt, x64, v64, u64, a_grav, a_hydro, dudt, x, v, u):
+        P3 = ctypes.c_void_p * 3
+        ag = P3(*[t.data_ptr() for t in a_grav])
+        ah = P3(*[t.data_ptr() for t in a_hydro]) if a_hydro is not None else None
+        xo = P3(*[t.data_ptr() for t in x])
+        vo = P3(*[t.data_ptr() for t in v])
+        check(self.lib.crk_integrate(
+            self.handle, int(n), float(dt), _ptr(x64), _ptr(v64), _ptr(u64),
+            ag, ah, _ptr(dudt), xo, vo, _ptr(u)))
+
+    def count_pairs(self, tree):
+        """In-range ordered pairs: (gather, hydro, gravity)."""
+        a = (ctypes.c_int64 * 3)()
+        check(self.lib.crk_count_pairs(self.handle, tree.handle, a))
+        return tuple(int(v) for v in a)
+
+    def graph_begin(self):
+        check(self.lib.crk_graph_begin(self.handle))
+
+    def graph_end(self):
+        check(self.lib.crk_graph_end(self.handle))
+
+    def graph_launch(self):
+        check(self.lib.crk_graph_launch(self.handle))
+
+    def timing(self, enable=True):
+        check(self.lib.crk_timing_enable(self.handle, int(bool(enable))))
+
+    def pass_times(self):
+        a = (ctypes.c_double * 7)()
+        b = (ctypes.c_double * 7)()
+        c = (ctypes.c_int64 * 7)()
+        check(self.lib.crk_pass_times(self.handle, a, b, c))
+        return ({k: a[i] for i, k in enumerate(PASS_NAMES)},
+                {k: b[i] for i, k in enumerate(PASS_NAMES)},
+                {k: c[i] for i, k in enumerate(PASS_NAMES)})
+
+
+class Tree:
+    """An opaque tree handle (built by Context.build_tree)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self.handle = ctypes.c_void_p()
+
+    def info(self):
+        i = crk_tree_info()
+        check(self.ctx.lib.crk_tree_get_info(self.handle, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in crk_tree_info._fields_}
+
+    def leaves(self):
+        inf = self.info()
+        n = inf["n_gas"] + inf["n_dm"]
+        nl = inf["n_leaves"]
+        perm = np.zeros(n, np.int64)
+        st = np.zeros(nl, np.int64)
+        cn = np.zeros(nl, np.int64)
+        check(self.ctx.lib.crk_tree_get_leaves(
+            self.ctx.handle, self.handle, perm.ctypes.data_as(ctypes.c_void_p),
+            st.ctypes.data_as(ctypes.c_void_p),
+            cn.ctypes.data_as(ctypes.c_void_p)))
+        return perm, st, cn
+
+    def free(self):
+        if self.handle and not _exiting:
+            self.ctx.lib.crk_tree_free(self.handle)
+        self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

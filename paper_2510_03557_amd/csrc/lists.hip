@@ -1,0 +1,187 @@
+// build_interaction_lists: leaf-leaf interaction lists (Sec. IV-B.1).
+//
+// One wavefront per i-leaf walks the 27 chaining-mesh bins around the
+// leaf's bin (own box, periodic images), and tests the bounding box of every
+// candidate leaf against its own in double precision.  Accepted leaves are
+// compacted with a ballot, so each list is in a fixed order (stencil order,
+// species, leaf index) independent of scheduling.  Two passes: count, then
+// (after a prefix sum) fill.
+//   gravity: all species, range r_c of the box
+//   hydro:   gas i-leaves only, gas j-leaves, range 2 max(h_max_I, h_max_J)
+// Ranges are widened by a relative 1e-5 so that every pair a float32 pair
+// test could accept is in the list; the pass kernels apply the exact test.
+#include <algorithm>
+
+#include "crk_internal.h"
+
+namespace crk {
+
+namespace {
+
+constexpr int LB = 256;  // four wavefronts = four i-leaves per workgroup
+constexpr double RANGE_WIDEN = 1.0 + 1e-5;
+
+template <typename T>
+__global__ __launch_bounds__(LB) void lists_kernel(
+    int fill, const int32_t *__restrict__ nn_ptr, int64_t cap,
+    const int32_t *__restrict__ leaf_key, const int32_t *__restrict__ leaf_box,
+    const T *__restrict__ lo, const T *__restrict__ hi,
+    const T *__restrict__ lhmax, const int32_t *__restrict__ bin_leaf,
+    int64_t total_bins, const int *__restrict__ ncm,
+    const int64_t *__restrict__ bin_base, const double *__restrict__ rc,
+    int32_t *__restrict__ g_cnt, int32_t *__restrict__ h_cnt,
+    const int64_t *__restrict__ g_off, const int64_t *__restrict__ h_off,
+    uint32_t *__restrict__ g_list, uint32_t *__restrict__ h_list,
+    int64_t g_cap, int64_t h_cap, int *__restrict__ err) {
+    const int lane = threadIdx.x & 63;
+    const int64_t I = (int64_t)blockIdx.x * (LB / 64) + (threadIdx.x >> 6);
+    const int64_t nn = *nn_ptr;
+    if (I >= nn) return;  // whole wavefront leaves together
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int key = leaf_key[I];
+    const bool gasI = key < total_bins;
+    const int64_t gbin = gasI ? key : key - total_bins;
+    const int b = leaf_box[I];
+    const int nc = ncm[b];
+    const int64_t lb = gbin - bin_base[b];
+    const int cx = (int)(lb / ((int64_t)nc * nc));
+    const int cy = (int)((lb / nc) % nc);
+    const int cz = (int)(lb % nc);
+    double loI[3], hiI[3];
+    for (int a = 0; a < 3; ++a) {
+        loI[a] = (double)lo[a * cap + I];
+        hiI[a] = (double)hi[a * cap + I];
+    }
+    const double hmI = (double)lhmax[I];
+    const double Rg = rc[b] * RANGE_WIDEN;
+    const double Rg2 = Rg * Rg;
+    int64_t gpos = fill ? g_off[I] : 0;
+    int64_t hpos = fill ? h_off[I] : 0;
+    int32_t gc = 0, hc = 0;
+    for (int ox = -1; ox <= 1; ++ox)
+    for (int oy = -1; oy <= 1; ++oy)
+    for (int oz = -1; oz <= 1; ++oz) {
+        int nx = cx + ox, ny = cy + oy, nz = cz + oz;
+        int sx = 0, sy = 0, sz = 0;
+        if (nx < 0) { nx += nc; sx = -1; } else if (nx >= nc) { nx -= nc; sx = 1; }
+        if (ny < 0) { ny += nc; sy = -1; } else if (ny >= nc) { ny -= nc; sy = 1; }
+        if (nz < 0) { nz += nc; sz = -1; } else if (nz >= nc) { nz -= nc; sz = 1; }
+        const int64_t ngbin = bin_base[b] + ((int64_t)nx * nc + ny) * nc + nz;
+        const uint32_t code = (uint32_t)((sx + 1) * 9 + (sy + 1) * 3 + (sz + 1));
+        const double S[3] = {(double)sx, (double)sy, (double)sz};
+        for (int sp = 0; sp < 2; ++sp) {
+            const int64_t k = sp * total_bins + ngbin;
+            const int r0 = bin_leaf[k], r1 = bin_leaf[k + 1];
+            for (int base = r0; base < r1; base += 64) {
+                const int J = base + lane;
+                const bool valid = J < r1;
+                bool gok = false, hok = false;
+                if (valid) {
+                    double d2 = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        double l = (double)lo[a * cap + J] + S[a];
+                        double h = (double)hi[a * cap + J] + S[a];
+                        double g = fmax(0.0, fmax(l - hiI[a], loI[a] - h));
+                        d2 += g * g;
+                    }
+                    gok = d2 < Rg2;
+                    if (gasI && sp == 0) {
+                        double hm = fmax(hmI, (double)lhmax[J]);
+                        double Rh = 2.0 * hm * RANGE_WIDEN;
+                        hok = d2 < Rh * Rh;
+                    }
+                }
+                const uint64_t gm = __ballot(gok);
+                const uint64_t hm = __ballot(hok);
+                if (fill) {
+                    if (gok) {
+                        int64_t p = gpos + __popcll(gm & lt_mask);
+                        if (p < g_cap) g_list[p] = (uint32_t)J | (code << LIST_LEAF_BITS);
+                        else atomicOr(err, DEV_ERR_CAPACITY);
+                    }
+                    if (hok) {
+                        int64_t p = hpos + __popcll(hm & lt_mask);
+                        if (p < h_cap) h_list[p] = (uint32_t)J | (code << LIST_LEAF_BITS);
+                        else atomicOr(err, DEV_ERR_CAPACITY);
+                    }
+                }
+                gpos += __popcll(gm);
+                hpos += __popcll(hm);
+                gc += __popcll(gm);
+                hc += __popcll(hm);
+            }
+        }
+    }
+    if (!fill && lane == 0) {
+        g_cnt[I] = gc;
+        h_cnt[I] = hc;
+    }
+}
+
+template <typename T>
+int lists_impl(crk_ctx *ctx, crk_tree *t) {
+    hipStream_t s = ctx->stream;
+    const bool cap = ctx->capturing;
+    const int64_t lcap = t->leaf_cap;
+    const int cur = t->cur_nodes;
+    int32_t *cnt = t->counters.as<int32_t>();
+    int64_t *cnt64 = t->counters.as<int64_t>();
+    int *err = dev_err_word(ctx);
+    CRK_TRY(t->g_cnt.ensure((lcap + 1) * 4, cap));
+    CRK_TRY(t->h_cnt.ensure((lcap + 1) * 4, cap));
+    CRK_TRY(t->g_off.ensure((lcap + 1) * 8, cap));
+    CRK_TRY(t->h_off.ensure((lcap + 1) * 8, cap));
+    CRK_TRY(ctx->scratch.ensure(scan_tmp_bytes(lcap + 1), cap));
+    CRK_HIP(fill_i32(t->g_cnt.as<int32_t>(), 0, lcap + 1, s));
+    CRK_HIP(fill_i32(t->h_cnt.as<int32_t>(), 0, lcap + 1, s));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, (lcap + 3) / 4);
+    auto launch = [&](int fill) -> int {
+        hipLaunchKernelGGL((lists_kernel<T>), dim3(grid), dim3(LB), 0, s, fill,
+                           cnt + C_NN, lcap, t->nd_key[cur].as<int32_t>(),
+                           t->leaf_box.as<int32_t>(), t->leaf_lo.as<T>(),
+                           t->leaf_hi.as<T>(), t->leaf_hmax.as<T>(),
+                           t->bin_leaf.as<int32_t>(), t->total_bins,
+                           t->d_ncm.as<int>(), t->d_bin_base.as<int64_t>(),
+                           t->d_rc.as<double>(), t->g_cnt.as<int32_t>(),
+                           t->h_cnt.as<int32_t>(), t->g_off.as<int64_t>(),
+                           t->h_off.as<int64_t>(), t->g_list.as<uint32_t>(),
+                           t->h_list.as<uint32_t>(), t->grav_cap, t->hydro_cap,
+                           err);
+        CRK_HIP(hipGetLastError());
+        return CRK_OK;
+    };
+    CRK_TRY(launch(0));
+    CRK_HIP(exclusive_scan_i32_to_i64(t->g_cnt.as<int32_t>(), t->g_off.as<int64_t>(),
+                                      lcap + 1, cnt64 + C64_GTOT, ctx->scratch.p, s));
+    CRK_HIP(exclusive_scan_i32_to_i64(t->h_cnt.as<int32_t>(), t->h_off.as<int64_t>(),
+                                      lcap + 1, cnt64 + C64_HTOT, ctx->scratch.p, s));
+    if (!cap) {
+        int64_t *hb = ctx->err_host.as<int64_t>() + 8;
+        CRK_HIP(hipMemcpyAsync(hb, cnt64 + C64_GTOT, 16, hipMemcpyDeviceToHost, s));
+        CRK_HIP(hipStreamSynchronize(s));
+        t->grav_entries = hb[0];
+        t->hydro_entries = hb[1];
+        if (t->grav_entries > t->grav_cap) {
+            int64_t c = t->grav_entries + t->grav_entries / 8 + 1024;
+            CRK_TRY(t->g_list.ensure((size_t)c * 4, false));
+            t->grav_cap = c;
+        }
+        if (t->hydro_entries > t->hydro_cap) {
+            int64_t c = t->hydro_entries + t->hydro_entries / 8 + 1024;
+            CRK_TRY(t->h_list.ensure((size_t)c * 4, false));
+            t->hydro_cap = c;
+        }
+    }
+    CRK_TRY(launch(1));
+    t->lists_built = true;
+    return CRK_OK;
+}
+
+}  // namespace
+
+int lists_build(crk_ctx *ctx, crk_tree *t) {
+    if (ctx->precision == CRK_FP64) return lists_impl<double>(ctx, t);
+    return lists_impl<float>(ctx, t);
+}
+
+}  // namespace crk

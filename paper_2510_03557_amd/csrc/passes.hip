@@ -1,0 +1,1012 @@
+// The four pair passes of the short-range step: CRKSPH volume/density,
+// correction coefficients, hydro forces, and short-range gravity.  Each is a
+// per-particle sum phi_i = sum_j phi_ij over the leaf-leaf lists (Eq. (1)).
+//
+// Kernel shape (MI355X, wave64): one workgroup of BLOCK >= leaf_max threads
+// owns one i-leaf, one i-particle per lane.  For each j-leaf of the i-leaf's
+// list the workgroup stages the j-leaf's fields in LDS (one particle per
+// lane, coalesced global reads) and every lane sweeps the tile, reading each
+// j by LDS broadcast; per-particle sums stay in registers and each output is
+// written once (no atomics), which keeps results independent of scheduling.
+//
+// Precision.  Positions are float32 in [1, 2): they are recentred on the
+// i-leaf's first particle, e_i = x_i - x_ref and f_j = (x_j - x_ref) + S
+// (S the periodic image of the j-leaf), which are exact; so is every
+// in-range separation e_i - f_j.  The float32 path sums each tile in plain
+// float and folds the tile sum into a compensated (hi, lo) pair with
+// TwoSum; the moment-matrix solve runs in double.  The float64 path is
+// plain double throughout.
+#include <algorithm>
+#include <cmath>
+
+#include "crk_internal.h"
+
+namespace crk {
+
+namespace {
+
+// --------------------------------------------------------------------------
+// arithmetic helpers
+// --------------------------------------------------------------------------
+
+__device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsq(double x) { return 1.0 / sqrt(x); }
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp(double x) { return 1.0 / x; }
+
+// compensated running sum (float) / plain sum (double)
+template <typename T> struct Comp;
+template <> struct Comp<float> {
+    float hi, lo;
+    __device__ void zero() { hi = 0.f; lo = 0.f; }
+    __device__ void add(float t) {
+        float s = hi + t;
+        float bp = s - hi;
+        lo += (hi - (s - bp)) + (t - bp);
+        hi = s;
+    }
+    __device__ double value() const { return (double)hi + (double)lo; }
+};
+template <> struct Comp<double> {
+    double hi;
+    __device__ void zero() { hi = 0.0; }
+    __device__ void add(double t) { hi += t; }
+    __device__ double value() const { return hi; }
+};
+
+template <typename T, int N> struct CompArr {
+    Comp<T> c[N];
+    __device__ void zero() {
+#pragma unroll
+        for (int k = 0; k < N; ++k) c[k].zero();
+    }
+    __device__ void fold(T (&t)[N]) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            c[k].add(t[k]);
+            t[k] = T(0);
+        }
+    }
+};
+
+// Cubic spline in units of q = r/h: w(q) (times 1/(pi h^3) gives W) and
+// wq(q) = (dw/dq)/q; both vanish for q >= 2.  invq = 1/q (unused for q < 1).
+template <typename T>
+__device__ inline void spline(T q, T invq, T &w, T &wq) {
+    const T t = T(2) - q;
+    const T t2 = t * t;
+    const bool in = q < T(1);
+    const bool on = q < T(2);
+    const T w_in = fma(q * q, fma(T(0.75), q, T(-1.5)), T(1));
+    const T w_out = T(0.25) * t2 * t;
+    const T wq_in = fma(T(2.25), q, T(-3));
+    const T wq_out = T(-0.75) * t2 * invq;
+    w = in ? w_in : (on ? w_out : T(0));
+    wq = in ? wq_in : (on ? wq_out : T(0));
+}
+
+constexpr double PI_D = 3.14159265358979323846;
+
+// --------------------------------------------------------------------------
+// tree view shared by all passes
+// --------------------------------------------------------------------------
+
+template <typename T> struct TreeView {
+    const int32_t *leaf_start, *leaf_count, *leaf_box;
+    const int64_t *list_off;
+    const uint32_t *list;
+    const int32_t *n_items;  // device count of work items
+    const int32_t *n_leaves; // device count of all leaves
+    int64_t list_cap;        // allocated list entries
+    const int32_t *perm;
+    const T *px, *py, *pz, *h;
+    const double *rc, *eps;
+    int64_t n_gas;
+};
+
+__device__ inline void decode_shift(uint32_t code, int &sx, int &sy, int &sz) {
+    sx = (int)(code / 9u) - 1;
+    sy = (int)((code / 3u) % 3u) - 1;
+    sz = (int)(code % 3u) - 1;
+}
+
+// The common driver: P supplies the per-pass state and arithmetic.
+//   P::NJ        number of T fields staged per j particle
+//   P::I         per-lane i-state
+//   P::load_i(I&, args, tv, i, ex, ey, ez, box)
+//   P::load_j(T* dst, args, tv, j, fx, fy, fz)
+//   P::Tile / P::Acc  per-tile sums and compensated totals
+//   P::pair(Tile&, const I&, const T* jd, bool self)
+//   P::finish(const Acc&, const I&, args, tv, i)
+template <typename T, typename P, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
+                                                     const typename P::Args pa) {
+    __shared__ __attribute__((aligned(16))) T sj[BLOCK * P::NJ];
+    const int I = (int)blockIdx.x;
+    if (I >= *tv.n_items) return;
+    const int st = tv.leaf_start[I];
+    // a leaf above BLOCK exists only after a capacity error (already
+    // latched); clamping keeps every access inside the LDS tile
+    const int cnt = min(tv.leaf_count[I], BLOCK);
+    const int t = threadIdx.x;
+    const bool act = t < cnt;
+    const int i = st + (act ? t : 0);
+    const T rx = tv.px[st], ry = tv.py[st], rz = tv.pz[st];
+    const int box = tv.leaf_box[I];
+    typename P::I is;
+    P::load_i(is, pa, tv, i, tv.px[i] - rx, tv.py[i] - ry, tv.pz[i] - rz, box);
+    typename P::Tile tile;
+    tile.zero();
+    typename P::Acc acc;
+    acc.zero();
+    // after a capacity error (latched by the list builder) offsets may run
+    // past the allocation: clamp, and skip entries that were never written
+    const int64_t e0 = min(tv.list_off[I], tv.list_cap);
+    const int64_t e1 = min(tv.list_off[I + 1], tv.list_cap);
+    const int nl = *tv.n_leaves;
+    for (int64_t e = e0; e < e1; ++e) {
+        const uint32_t ent = tv.list[e];
+        const int J = (int)(ent & LIST_LEAF_MASK);
+        if (J >= nl) continue;
+        int sx, sy, sz;
+        decode_shift(ent >> LIST_LEAF_BITS, sx, sy, sz);
+        const int js = tv.leaf_start[J];
+        const int jc = min(tv.leaf_count[J], BLOCK);
+        __syncthreads();
+        if (t < jc) {
+            const int j = js + t;
+            P::load_j(&sj[t * P::NJ], pa, tv, j, (tv.px[j] - rx) + T(sx),
+                      (tv.py[j] - ry) + T(sy), (tv.pz[j] - rz) + T(sz));
+        }
+        __syncthreads();
+        if (act) {
+            for (int k = 0; k < jc; ++k)
+                P::pair(tile, is, &sj[k * P::NJ], js + k == i);
+        }
+        acc.fold(tile);
+    }
+    if (act) P::finish(acc, is, pa, tv, i);
+}
+
+// --------------------------------------------------------------------------
+// density / volume:  V_i = 1 / sum_j W_ij,  rho~_i = sum_j m_j W_ij
+// --------------------------------------------------------------------------
+
+template <typename T> struct DensityPass {
+    struct Args {
+        const T *m;       // tree order
+        T *V, *rho_t;     // caller order
+    };
+    static constexpr int NJ = 4;  // fx, fy, fz, m
+    struct I {
+        T ex, ey, ez, ih2, h;
+    };
+    struct Tile {
+        T s[2];
+        __device__ void zero() { s[0] = s[1] = T(0); }
+    };
+    struct Acc {
+        CompArr<T, 2> a;
+        __device__ void zero() { a.zero(); }
+        __device__ void fold(Tile &t) { a.fold(t.s); }
+    };
+    __device__ static void load_i(I &is, const Args &, const TreeView<T> &tv,
+                                  int i, T ex, T ey, T ez, int) {
+        is.ex = ex;
+        is.ey = ey;
+        is.ez = ez;
+        is.h = tv.h[i];
+        is.ih2 = T(1) / (is.h * is.h);
+    }
+    __device__ static void load_j(T *d, const Args &a, const TreeView<T> &,
+                                  int j, T fx, T fy, T fz) {
+        d[0] = fx;
+        d[1] = fy;
+        d[2] = fz;
+        d[3] = a.m[j];
+    }
+    __device__ static void pair(Tile &tl, const I &is, const T *jd, bool) {
+        const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
+        const T q2 = (dx * dx + dy * dy + dz * dz) * is.ih2;
+        if (q2 < T(4)) {
+            const T rq = rsq(q2);
+            const T q = q2 > T(0) ? q2 * rq : T(0);
+            const T t = T(2) - q;
+            const T w = q < T(1) ? fma(q * q, fma(T(0.75), q, T(-1.5)), T(1))
+                                 : T(0.25) * t * t * t;
+            tl.s[0] += w;
+            tl.s[1] = fma(jd[3], w, tl.s[1]);
+        }
+    }
+    __device__ static void finish(const Acc &ac, const I &is, const Args &a,
+                                  const TreeView<T> &tv, int i) {
+        const double h = (double)is.h;
+        const double ph3 = PI_D * h * h * h;
+        const int c = tv.perm[i];
+        a.V[c] = (T)(ph3 / ac.a.c[0].value());
+        a.rho_t[c] = (T)(ac.a.c[1].value() / ph3);
+    }
+};
+
+// --------------------------------------------------------------------------
+// correction coefficients
+// --------------------------------------------------------------------------
+// Sums, in units u = x_ij / h_i (a = V_j w, b = V_j wq, mw = m_j w):
+//   0      m0            sum a
+//   1..3   m1            sum a u_a
+//   4..9   m2 (ab)       sum a u_a u_b          (00 01 02 11 12 22)
+//   10..12 dm0           sum b u_g
+//   13..18 sxdw (ga)     sum b u_g u_a          (00 01 02 11 12 22)
+//   19..28 sxxdw (gab)   sum b u_g u_a u_b      (000 001 002 011 012 022
+//                                                111 112 122 222)
+//   29..31 M1            sum mw u_a
+//   32     rho~          sum mw
+template <typename T> struct CoeffPass {
+    struct Args {
+        const T *m, *V, *u;  // tree order
+        T *A, *B, *gA, *gB, *rho, *P, *cs;  // caller order (planes of n_gas)
+        int64_t n_gas;
+        double gamma;
+    };
+    static constexpr int NJ = 8;  // fx fy fz V m + pad
+    static constexpr int NS = 33;
+    struct I {
+        T ex, ey, ez, ih;
+        T h;
+    };
+    struct Tile {
+        T s[NS];
+        __device__ void zero() {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) s[k] = T(0);
+        }
+    };
+    struct Acc {
+        CompArr<T, NS> a;
+        __device__ void zero() { a.zero(); }
+        __device__ void fold(Tile &t) { a.fold(t.s); }
+    };
+    __device__ static void load_i(I &is, const Args &, const TreeView<T> &tv,
+                                  int i, T ex, T ey, T ez, int) {
+        is.ex = ex;
+        is.ey = ey;
+        is.ez = ez;
+        is.h = tv.h[i];
+        is.ih = T(1) / is.h;
+    }
+    __device__ static void load_j(T *d, const Args &a, const TreeView<T> &,
+                                  int j, T fx, T fy, T fz) {
+        d[0] = fx;
+        d[1] = fy;
+        d[2] = fz;
+        d[3] = a.V[j];
+        d[4] = a.m[j];
+        d[5] = T(0);
+        d[6] = T(0);
+        d[7] = T(0);
+    }
+    __device__ static void pair(Tile &tl, const I &is, const T *jd, bool) {
+        const T u0 = (is.ex - jd[0]) * is.ih;
+        const T u1 = (is.ey - jd[1]) * is.ih;
+        const T u2 = (is.ez - jd[2]) * is.ih;
+        const T q2 = u0 * u0 + u1 * u1 + u2 * u2;
+        if (q2 < T(4)) {
+            const T rq = rsq(q2);
+            const T q = q2 > T(0) ? q2 * rq : T(0);
+            T w, wq;
+            spline(q, rq, w, wq);
+            T *s = tl.s;
+            const T a = jd[3] * w;
+            const T b = jd[3] * wq;
+            const T mw = jd[4] * w;
+            const T au0 = a * u0, au1 = a * u1, au2 = a * u2;
+            s[0] += a;
+            s[1] += au0;
+            s[2] += au1;
+            s[3] += au2;
+            s[4] = fma(au0, u0, s[4]);
+            s[5] = fma(au0, u1, s[5]);
+            s[6] = fma(au0, u2, s[6]);
+            s[7] = fma(au1, u1, s[7]);
+            s[8] = fma(au1, u2, s[8]);
+            s[9] = fma(au2, u2, s[9]);
+            const T bu0 = b * u0, bu1 = b * u1, bu2 = b * u2;
+            s[10] += bu0;
+            s[11] += bu1;
+            s[12] += bu2;
+            const T p00 = bu0 * u0, p01 = bu0 * u1, p02 = bu0 * u2;
+            const T p11 = bu1 * u1, p12 = bu1 * u2, p22 = bu2 * u2;
+            s[13] += p00;
+            s[14] += p01;
+            s[15] += p02;
+            s[16] += p11;
+            s[17] += p12;
+            s[18] += p22;
+            s[19] = fma(p00, u0, s[19]);
+            s[20] = fma(p00, u1, s[20]);
+            s[21] = fma(p00, u2, s[21]);
+            s[22] = fma(p01, u1, s[22]);
+            s[23] = fma(p01, u2, s[23]);
+            s[24] = fma(p02, u2, s[24]);
+            s[25] = fma(p11, u1, s[25]);
+            s[26] = fma(p11, u2, s[26]);
+            s[27] = fma(p12, u2, s[27]);
+            s[28] = fma(p22, u2, s[28]);
+            s[29] = fma(mw, u0, s[29]);
+            s[30] = fma(mw, u1, s[30]);
+            s[31] = fma(mw, u2, s[31]);
+            s[32] += mw;
+        }
+    }
+    __device__ static void finish(const Acc &ac, const I &is, const Args &a,
+                                  const TreeView<T> &tv, int i) {
+        double S[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) S[k] = ac.a.c[k].value();
+        const double h = (double)is.h;
+        const double N = 1.0 / (PI_D * h * h * h);
+        // symmetric index maps
+        const int i2[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+        const int i3[3][3][3] = {{{0, 1, 2}, {1, 3, 4}, {2, 4, 5}},
+                                 {{1, 3, 4}, {3, 6, 7}, {4, 7, 8}},
+                                 {{2, 4, 5}, {4, 7, 8}, {5, 8, 9}}};
+        double m0 = N * S[0];
+        double m1[3], m2[3][3], dm0[3], dm1[3][3], dm2[3][3][3], M1[3];
+        for (int x = 0; x < 3; ++x) {
+            m1[x] = N * h * S[1 + x];
+            dm0[x] = N / h * S[10 + x];
+            M1[x] = N * h * S[29 + x];
+        }
+        for (int x = 0; x < 3; ++x)
+            for (int y = 0; y < 3; ++y) m2[x][y] = N * h * h * S[4 + i2[x][y]];
+        for (int g = 0; g < 3; ++g)
+            for (int x = 0; x < 3; ++x) {
+                dm1[g][x] = (x == g ? m0 : 0.0) + N * S[13 + i2[g][x]];
+                for (int y = 0; y < 3; ++y)
+                    dm2[g][x][y] = (x == g ? m1[y] : 0.0) + (y == g ? m1[x] : 0.0) +
+                                   N * h * S[19 + i3[g][x][y]];
+            }
+        const double rt = N * S[32];
+        // solve (double): B = -m2^-1 m1, A = 1/(m0 + B.m1), gradients
+        double c00 = m2[1][1] * m2[2][2] - m2[1][2] * m2[2][1];
+        double c01 = m2[1][2] * m2[2][0] - m2[1][0] * m2[2][2];
+        double c02 = m2[1][0] * m2[2][1] - m2[1][1] * m2[2][0];
+        double det = m2[0][0] * c00 + m2[0][1] * c01 + m2[0][2] * c02;
+        double tr = m2[0][0] + m2[1][1] + m2[2][2];
+        double A, B[3], dA[3], dB[3][3];
+        if (!(fabs(det) > 1e-12 * tr * tr * tr / 27.0) || !(tr > 0.0)) {
+            A = 1.0 / m0;
+            for (int g = 0; g < 3; ++g) {
+                B[g] = 0.0;
+                dA[g] = -dm0[g] / (m0 * m0);
+                for (int x = 0; x < 3; ++x) dB[g][x] = 0.0;
+            }
+        } else {
+            double inv[3][3];
+            const double id = 1.0 / det;
+            inv[0][0] = c00 * id;
+            inv[0][1] = (m2[0][2] * m2[2][1] - m2[0][1] * m2[2][2]) * id;
+            inv[0][2] = (m2[0][1] * m2[1][2] - m2[0][2] * m2[1][1]) * id;
+            inv[1][0] = c01 * id;
+            inv[1][1] = (m2[0][0] * m2[2][2] - m2[0][2] * m2[2][0]) * id;
+            inv[1][2] = (m2[0][2] * m2[1][0] - m2[0][0] * m2[1][2]) * id;
+            inv[2][0] = c02 * id;
+            inv[2][1] = (m2[0][1] * m2[2][0] - m2[0][0] * m2[2][1]) * id;
+            inv[2][2] = (m2[0][0] * m2[1][1] - m2[0][1] * m2[1][0]) * id;
+            for (int x = 0; x < 3; ++x) {
+                B[x] = 0.0;
+                for (int y = 0; y < 3; ++y) B[x] -= inv[x][y] * m1[y];
+            }
+            A = 1.0 / (m0 + B[0] * m1[0] + B[1] * m1[1] + B[2] * m1[2]);
+            for (int g = 0; g < 3; ++g) {
+                double rhs[3];
+                for (int x = 0; x < 3; ++x) {
+                    rhs[x] = dm1[g][x];
+                    for (int y = 0; y < 3; ++y) rhs[x] += dm2[g][x][y] * B[y];
+                }
+                for (int x = 0; x < 3; ++x) {
+                    dB[g][x] = 0.0;
+                    for (int y = 0; y < 3; ++y) dB[g][x] -= inv[x][y] * rhs[y];
+                }
+                double sg = dm0[g];
+                for (int x = 0; x < 3; ++x) sg += dB[g][x] * m1[x] + B[x] * dm1[g][x];
+                dA[g] = -A * A * sg;
+            }
+        }
+        const int c = tv.perm[i];
+        const int64_t n = a.n_gas;
+        a.A[c] = (T)A;
+        for (int g = 0; g < 3; ++g) {
+            a.B[g * n + c] = (T)B[g];
+            a.gA[g * n + c] = (T)dA[g];
+            for (int x = 0; x < 3; ++x) a.gB[(3 * g + x) * n + c] = (T)dB[g][x];
+        }
+        const double rho = A * (rt + B[0] * M1[0] + B[1] * M1[1] + B[2] * M1[2]);
+        const double uu = (double)a.u[i];
+        a.rho[c] = (T)rho;
+        a.P[c] = (T)((a.gamma - 1.0) * rho * uu);
+        a.cs[c] = (T)sqrt(a.gamma * (a.gamma - 1.0) * uu);
+    }
+};
+
+// --------------------------------------------------------------------------
+// hydro forces
+// --------------------------------------------------------------------------
+// Per-particle fields, precomputed by hydro_gather_kernel (tree order):
+//   0 vx 1 vy 2 vz 3 ih2=1/h^2 4 a=A N 5..7 da=dA N 8..10 B
+//   11..13 ab=A N B  14..22 adb=A N dB [g][x]  23 h  24 V  25 P  26 rho
+//   27 cs   (N = 1/(pi h^3))
+// The corrected-kernel gradient of particle k at separation y:
+//   g_k(y)_g = (1 + B.y)(da_g w + a wq ih2 y_g) + w (sum_x adb[g][x] y_x + ab_g)
+constexpr int HF = 28;
+
+template <typename T> struct HydroPass {
+    struct Args {
+        const T *f;       // HF planes of n_gas, tree order
+        int64_t n_gas;
+        T *ax, *ay, *az, *dudt;  // caller order
+        const T *m;       // tree order
+        T Cl, Cq, epsQ;
+    };
+    static constexpr int NJ = 32;  // fx fy fz + HF fields + pad
+    struct I {
+        T ex, ey, ez;
+        T Cl, Cq, epsQ;
+        T f[HF];
+    };
+    struct Tile {
+        T s[4];
+        __device__ void zero() { s[0] = s[1] = s[2] = s[3] = T(0); }
+    };
+    struct Acc {
+        CompArr<T, 4> a;
+        __device__ void zero() { a.zero(); }
+        __device__ void fold(Tile &t) { a.fold(t.s); }
+    };
+    __device__ static void load_i(I &is, const Args &a, const TreeView<T> &,
+                                  int i, T ex, T ey, T ez, int) {
+        is.ex = ex;
+        is.ey = ey;
+        is.ez = ez;
+        is.Cl = a.Cl;
+        is.Cq = a.Cq;
+        is.epsQ = a.epsQ;
+#pragma unroll
+        for (int k = 0; k < HF; ++k) is.f[k] = a.f[k * a.n_gas + i];
+    }
+    __device__ static void load_j(T *d, const Args &a, const TreeView<T> &,
+                                  int j, T fx, T fy, T fz) {
+        d[0] = fx;
+        d[1] = fy;
+        d[2] = fz;
+#pragma unroll
+        for (int k = 0; k < HF; ++k) d[3 + k] = a.f[k * a.n_gas + j];
+        d[31] = T(0);
+    }
+    // gradient of the corrected kernel of particle with fields f at y
+    __device__ static void grad_rk(const T *f, T y0, T y1, T y2, T r2, T out[3],
+                                   bool &on) {
+        const T q2 = r2 * f[3];
+        on = q2 < T(4);
+        const T rq = rsq(q2);
+        const T q = q2 > T(0) ? q2 * rq : T(0);
+        T w, wq;
+        spline(q, rq, w, wq);
+        const T by1 = T(1) + f[8] * y0 + f[9] * y1 + f[10] * y2;
+        const T c1 = f[4] * wq * f[3];
+        const T y[3] = {y0, y1, y2};
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const T dby = f[14 + 3 * g] * y0 + f[15 + 3 * g] * y1 + f[16 + 3 * g] * y2;
+            out[g] = by1 * fma(f[5 + g], w, c1 * y[g]) + w * (dby + f[11 + g]);
+        }
+    }
+    __device__ static void pair(Tile &tl, const I &is, const T *jd, bool self) {
+        const T x0 = is.ex - jd[0], x1 = is.ey - jd[1], x2 = is.ez - jd[2];
+        const T r2 = x0 * x0 + x1 * x1 + x2 * x2;
+        const T *fj = jd + 3;
+        const T *fi = is.f;
+        const bool near = (r2 * fi[3] < T(4)) || (r2 * fj[3] < T(4));
+        if (near && !self) {
+            T gi[3], gj[3];
+            bool oi, oj;
+            grad_rk(fi, x0, x1, x2, r2, gi, oi);
+            grad_rk(fj, -x0, -x1, -x2, r2, gj, oj);
+            const T v0 = fi[0] - fj[0], v1 = fi[1] - fj[1], v2 = fi[2] - fj[2];
+            const T vdx = v0 * x0 + v1 * x1 + v2 * x2;
+            const T hi_ = fi[23], hj_ = fj[23];
+            T mui = hi_ * vdx * rcp(fma(is.epsQ * hi_, hi_, r2));
+            T muj = hj_ * vdx * rcp(fma(is.epsQ * hj_, hj_, r2));
+            mui = mui < T(0) ? mui : T(0);
+            muj = muj < T(0) ? muj : T(0);
+            const T Qi = fi[26] * mui * fma(is.Cq, mui, -is.Cl * fi[27]);
+            const T Qj = fj[26] * muj * fma(is.Cq, muj, -is.Cl * fj[27]);
+            const T pp = fi[25] + fj[25];
+            const T ci = pp + Qi, cj = pp + Qj;
+            const T k = T(-0.5) * fi[24] * fj[24];
+            const T F0 = k * (ci * gi[0] - cj * gj[0]);
+            const T F1 = k * (ci * gi[1] - cj * gj[1]);
+            const T F2 = k * (ci * gi[2] - cj * gj[2]);
+            tl.s[0] += F0;
+            tl.s[1] += F1;
+            tl.s[2] += F2;
+            tl.s[3] = fma(v0, F0, fma(v1, F1, fma(v2, F2, tl.s[3])));
+        }
+    }
+    __device__ static void finish(const Acc &ac, const I &, const Args &a,
+                                  const TreeView<T> &tv, int i) {
+        const int c = tv.perm[i];
+        const double im = 1.0 / (double)a.m[i];
+        a.ax[c] = (T)(ac.a.c[0].value() * im);
+        a.ay[c] = (T)(ac.a.c[1].value() * im);
+        a.az[c] = (T)(ac.a.c[2].value() * im);
+        a.dudt[c] = (T)(-0.5 * ac.a.c[3].value() * im);
+    }
+};
+
+// --------------------------------------------------------------------------
+// short-range gravity
+// --------------------------------------------------------------------------
+// a_i = -G sum_j m_j g(r)/r x_ij with, for xi = 2r/r_c,
+//   g/r = (r^2+eps^2)^(-3/2) - (2/(35 r_c^3)) (224 - 224 xi^2 + 70 xi^3
+//         + 48 xi^4 - 21 xi^5)                                  xi < 1
+//   g/r = (r^2+eps^2)^(-3/2) + r^-3 ((2-xi)^5 (7 xi^3 + 22 xi^2 + 10 xi
+//         + 4) / 140 - 1)                                        1 <= xi < 2
+template <typename T> struct GravityPass {
+    struct Args {
+        const T *m;  // tree order, times G
+        T *ax_g, *ay_g, *az_g, *ax_d, *ay_d, *az_d;  // caller order
+        int64_t n_gas;
+    };
+    static constexpr int NJ = 4;  // fx fy fz Gm
+    struct I {
+        T ex, ey, ez;
+        T rc2, eps2, two_rc, cin;
+    };
+    struct Tile {
+        T s[3];
+        __device__ void zero() { s[0] = s[1] = s[2] = T(0); }
+    };
+    struct Acc {
+        CompArr<T, 3> a;
+        __device__ void zero() { a.zero(); }
+        __device__ void fold(Tile &t) { a.fold(t.s); }
+    };
+    __device__ static void load_i(I &is, const Args &, const TreeView<T> &tv,
+                                  int, T ex, T ey, T ez, int box) {
+        is.ex = ex;
+        is.ey = ey;
+        is.ez = ez;
+        const double rc = tv.rc[box], eps = tv.eps[box];
+        is.rc2 = (T)(rc * rc);
+        is.eps2 = (T)(eps * eps);
+        is.two_rc = (T)(2.0 / rc);
+        is.cin = (T)(2.0 / (35.0 * rc * rc * rc));
+    }
+    __device__ static void load_j(T *d, const Args &a, const TreeView<T> &,
+                                  int j, T fx, T fy, T fz) {
+        d[0] = fx;
+        d[1] = fy;
+        d[2] = fz;
+        d[3] = a.m[j];
+    }
+    __device__ static void pair(Tile &tl, const I &is, const T *jd, bool) {
+        const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const T rs = rsq(r2);
+        const T r = r2 * rs;
+        const T xi = r * is.two_rc;
+        const T ps = rsq(r2 + is.eps2);
+        const T plum = ps * ps * ps;
+        const T x2 = xi * xi;
+        T pin = fma(T(-21), xi, T(48));
+        pin = fma(pin, xi, T(70));
+        pin = fma(pin, xi, T(-224));
+        pin = fma(pin, x2, T(224));
+        const T gin = fma(-is.cin, pin, plum);
+        const T u = T(2) - xi;
+        const T u2 = u * u;
+        const T u5 = u2 * u2 * u;
+        T po = fma(T(7), xi, T(22));
+        po = fma(po, xi, T(10));
+        po = fma(po, xi, T(4));
+        const T val = fma(u5 * po, T(1.0 / 140.0), T(-1));
+        const T rs3 = rs * rs * rs;
+        const T gout = fma(rs3, val, plum);
+        const T gr = xi < T(1) ? gin : gout;
+        const bool on = (r2 > T(0)) && (r2 < is.rc2);
+        const T w = on ? jd[3] * gr : T(0);
+        tl.s[0] = fma(-w, dx, tl.s[0]);
+        tl.s[1] = fma(-w, dy, tl.s[1]);
+        tl.s[2] = fma(-w, dz, tl.s[2]);
+    }
+    __device__ static void finish(const Acc &ac, const I &, const Args &a,
+                                  const TreeView<T> &tv, int i) {
+        const int c = tv.perm[i];
+        const T x = (T)ac.a.c[0].value(), y = (T)ac.a.c[1].value(),
+                z = (T)ac.a.c[2].value();
+        if (c < a.n_gas) {
+            a.ax_g[c] = x;
+            a.ay_g[c] = y;
+            a.az_g[c] = z;
+        } else {
+            const int d = c - (int)a.n_gas;
+            a.ax_d[d] = x;
+            a.ay_d[d] = y;
+            a.az_d[d] = z;
+        }
+    }
+};
+
+// --------------------------------------------------------------------------
+// in-range pair counts (diagnostic; the exact pair conditions of the passes)
+// --------------------------------------------------------------------------
+// mode 0: gas j with r < 2 h_i, j = i included (density, coefficients)
+// mode 1: gas j != i with r < 2 max(h_i, h_j)          (hydro forces)
+// mode 2: any j with 0 < r < r_c                      (gravity)
+template <typename T> struct CountPass {
+    struct Args {
+        int mode;
+        int32_t *counts;  // tree order
+    };
+    static constexpr int NJ = 4;  // fx fy fz 1/h^2
+    struct I {
+        T ex, ey, ez, ih2, rc2;
+        int mode;
+    };
+    struct Tile {
+        int c;
+        __device__ void zero() { c = 0; }
+    };
+    struct Acc {
+        int c;
+        __device__ void zero() { c = 0; }
+        __device__ void fold(Tile &t) {
+            c += t.c;
+            t.c = 0;
+        }
+    };
+    __device__ static void load_i(I &is, const Args &a, const TreeView<T> &tv,
+                                  int i, T ex, T ey, T ez, int box) {
+        is.ex = ex;
+        is.ey = ey;
+        is.ez = ez;
+        const T h = tv.h[i];
+        is.ih2 = a.mode == 2 ? T(0) : T(1) / (h * h);
+        const double rc = tv.rc[box];
+        is.rc2 = (T)(rc * rc);
+        is.mode = a.mode;
+    }
+    __device__ static void load_j(T *d, const Args &a, const TreeView<T> &tv,
+                                  int j, T fx, T fy, T fz) {
+        d[0] = fx;
+        d[1] = fy;
+        d[2] = fz;
+        const T h = tv.h[j];
+        d[3] = a.mode == 1 ? T(1) / (h * h) : T(0);
+    }
+    __device__ static void pair(Tile &tl, const I &is, const T *jd, bool self) {
+        const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        bool in;
+        if (is.mode == 0) in = r2 * is.ih2 < T(4);
+        else if (is.mode == 1) in = !self && (r2 * is.ih2 < T(4) || r2 * jd[3] < T(4));
+        else in = r2 > T(0) && r2 < is.rc2;
+        tl.c += in ? 1 : 0;
+    }
+    __device__ static void finish(const Acc &ac, const I &, const Args &a,
+                                  const TreeView<T> &, int i) {
+        a.counts[i] = ac.c;
+    }
+};
+
+__global__ void sum_counts_kernel(const int32_t *__restrict__ c, int64_t n,
+                                  unsigned long long *__restrict__ total) {
+    __shared__ unsigned long long part[256];
+    unsigned long long s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        s += (unsigned long long)c[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(total, part[0]);
+}
+
+// --------------------------------------------------------------------------
+// gathers (caller order -> tree order, with derived per-particle fields)
+// --------------------------------------------------------------------------
+
+#define GRID_STRIDE(i, n)                                                     \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
+         i += (int64_t)gridDim.x * blockDim.x)
+
+inline unsigned grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 1048576) g = 1048576;
+    return (unsigned)g;
+}
+
+template <typename T>
+__global__ void gather1_kernel(const int32_t *__restrict__ perm,
+                               const T *__restrict__ a, int64_t n,
+                               T *__restrict__ out) {
+    GRID_STRIDE(p, n) out[p] = a[perm[p]];
+}
+
+// masses of all tree slots (gas, then dm), times G
+template <typename T>
+__global__ void gather_mass_kernel(const int32_t *__restrict__ perm,
+                                   const T *__restrict__ mg,
+                                   const T *__restrict__ md, int64_t n_gas,
+                                   int64_t n, T G, T *__restrict__ out) {
+    GRID_STRIDE(p, n) {
+        int c = perm[p];
+        out[p] = G * (c < n_gas ? mg[c] : md[c - n_gas]);
+    }
+}
+
+template <typename T>
+__global__ void hydro_gather_kernel(
+    const int32_t *__restrict__ perm, int64_t n, const T *__restrict__ h,
+    const T *__restrict__ m, const T *__restrict__ vx, const T *__restrict__ vy,
+    const T *__restrict__ vz, const T *__restrict__ V,
+    const T *__restrict__ rho, const T *__restrict__ P,
+    const T *__restrict__ cs, const T *__restrict__ A,
+    const T *__restrict__ B, const T *__restrict__ gA,
+    const T *__restrict__ gB, T *__restrict__ f, T *__restrict__ mt) {
+    GRID_STRIDE(p, n) {
+        const int c = perm[p];
+        const T hh = h[p];
+        const T N = (T)(1.0 / (PI_D * (double)hh * (double)hh * (double)hh));
+        const T a = A[c] * N;
+        f[0 * n + p] = vx[c];
+        f[1 * n + p] = vy[c];
+        f[2 * n + p] = vz[c];
+        f[3 * n + p] = T(1) / (hh * hh);
+        f[4 * n + p] = a;
+        for (int g = 0; g < 3; ++g) {
+            f[(5 + g) * n + p] = gA[g * n + c] * N;
+            f[(8 + g) * n + p] = B[g * n + c];
+            f[(11 + g) * n + p] = a * B[g * n + c];
+            for (int x = 0; x < 3; ++x)
+                f[(14 + 3 * g + x) * n + p] = a * gB[(3 * g + x) * n + c];
+        }
+        f[23 * n + p] = hh;
+        f[24 * n + p] = V[c];
+        f[25 * n + p] = P[c];
+        f[26 * n + p] = rho[c];
+        f[27 * n + p] = cs[c];
+        mt[p] = m[c];
+    }
+}
+
+// --------------------------------------------------------------------------
+// launch helpers
+// --------------------------------------------------------------------------
+
+template <typename T>
+TreeView<T> tree_view(crk_tree *t, bool hydro, const int32_t *n_items) {
+    TreeView<T> tv;
+    const int cur = t->cur_nodes;
+    tv.leaf_start = t->nd_start[cur].as<int32_t>();
+    tv.leaf_count = t->nd_count[cur].as<int32_t>();
+    tv.leaf_box = t->leaf_box.as<int32_t>();
+    tv.list_off = hydro ? t->h_off.as<int64_t>() : t->g_off.as<int64_t>();
+    tv.list = hydro ? t->h_list.as<uint32_t>() : t->g_list.as<uint32_t>();
+    tv.n_items = n_items;
+    tv.n_leaves = t->counters.as<int32_t>() + C_NN;
+    tv.list_cap = hydro ? t->hydro_cap : t->grav_cap;
+    tv.perm = t->perm.as<int32_t>();
+    tv.px = t->pos[0].as<T>();
+    tv.py = t->pos[1].as<T>();
+    tv.pz = t->pos[2].as<T>();
+    tv.h = t->hsm.as<T>();
+    tv.rc = t->d_rc.as<double>();
+    tv.eps = t->d_eps.as<double>();
+    tv.n_gas = t->n_gas;
+    return tv;
+}
+
+template <typename T, typename P>
+int launch_pair(crk_ctx *ctx, crk_tree *t, const TreeView<T> &tv,
+                const typename P::Args &pa, int64_t n_items_bound, int pass) {
+    const int L = t->leaf_max;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, n_items_bound);
+    hipEvent_t ev = nullptr;
+    if (pass >= 0) span_begin(ctx, pass, true, &ev);
+    if (L <= 64)
+        hipLaunchKernelGGL((pair_kernel<T, P, 64>), dim3(grid), dim3(64), 0,
+                           ctx->stream, tv, pa);
+    else if (L <= 128)
+        hipLaunchKernelGGL((pair_kernel<T, P, 128>), dim3(grid), dim3(128), 0,
+                           ctx->stream, tv, pa);
+    else
+        hipLaunchKernelGGL((pair_kernel<T, P, 256>), dim3(grid), dim3(256), 0,
+                           ctx->stream, tv, pa);
+    if (pass >= 0) span_end(ctx, pass, true, ev);
+    CRK_HIP(hipGetLastError());
+    return CRK_OK;
+}
+
+// number of gas leaves lives in bin_leaf[total_bins]; all leaves in C_NN
+inline const int32_t *gas_leaf_count(crk_tree *t) {
+    return t->bin_leaf.as<int32_t>() + t->total_bins;
+}
+inline const int32_t *all_leaf_count(crk_tree *t) {
+    return t->counters.as<int32_t>() + C_NN;
+}
+inline int64_t gas_bound(crk_ctx *ctx, crk_tree *t) {
+    return ctx->capturing ? t->leaf_cap : t->n_gas_leaves;
+}
+inline int64_t all_bound(crk_ctx *ctx, crk_tree *t) {
+    return ctx->capturing ? t->leaf_cap : t->n_leaves;
+}
+
+template <typename T>
+int density_impl(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
+                 void *rho_t) {
+    const int64_t ng = t->n_gas;
+    CRK_TRY(t->pf[4].ensure(std::max<int64_t>(ng, 1) * sizeof(T), ctx->capturing));
+    T *mt = t->pf[4].as<T>();
+    hipLaunchKernelGGL((gather1_kernel<T>), dim3(grid_for(ng)), dim3(256), 0,
+                       ctx->stream, t->perm.as<int32_t>(),
+                       static_cast<const T *>(m), ng, mt);
+    CRK_HIP(hipGetLastError());
+    typename DensityPass<T>::Args pa{mt, static_cast<T *>(V),
+                                     static_cast<T *>(rho_t)};
+    return launch_pair<T, DensityPass<T>>(ctx, t, tree_view<T>(t, true, gas_leaf_count(t)),
+                                          pa, gas_bound(ctx, t), P_DENSITY);
+}
+
+template <typename T>
+int coeff_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *V,
+               const void *u, void *A, void *B, void *gA, void *gB, void *rho,
+               void *P, void *cs) {
+    const int64_t ng = t->n_gas;
+    const size_t bytes = std::max<int64_t>(ng, 1) * sizeof(T);
+    for (int k = 4; k < 7; ++k) CRK_TRY(t->pf[k].ensure(bytes, ctx->capturing));
+    T *mt = t->pf[4].as<T>(), *Vt = t->pf[5].as<T>(), *ut = t->pf[6].as<T>();
+    const int32_t *perm = t->perm.as<int32_t>();
+    hipLaunchKernelGGL((gather1_kernel<T>), dim3(grid_for(ng)), dim3(256), 0,
+                       ctx->stream, perm, static_cast<const T *>(m), ng, mt);
+    hipLaunchKernelGGL((gather1_kernel<T>), dim3(grid_for(ng)), dim3(256), 0,
+                       ctx->stream, perm, static_cast<const T *>(V), ng, Vt);
+    hipLaunchKernelGGL((gather1_kernel<T>), dim3(grid_for(ng)), dim3(256), 0,
+                       ctx->stream, perm, static_cast<const T *>(u), ng, ut);
+    CRK_HIP(hipGetLastError());
+    typename CoeffPass<T>::Args pa{mt, Vt, ut,
+                                   static_cast<T *>(A), static_cast<T *>(B),
+                                   static_cast<T *>(gA), static_cast<T *>(gB),
+                                   static_cast<T *>(rho), static_cast<T *>(P),
+                                   static_cast<T *>(cs), ng, ctx->params.gamma};
+    return launch_pair<T, CoeffPass<T>>(ctx, t, tree_view<T>(t, true, gas_leaf_count(t)),
+                                        pa, gas_bound(ctx, t), P_COEFF);
+}
+
+template <typename T>
+int hydro_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
+               const void *vy, const void *vz, const void *V, const void *rho,
+               const void *P, const void *cs, const void *A, const void *B,
+               const void *gA, const void *gB, void *ax, void *ay, void *az,
+               void *dudt) {
+    const int64_t ng = t->n_gas;
+    const size_t n1 = std::max<int64_t>(ng, 1);
+    CRK_TRY(t->pf[7].ensure(n1 * HF * sizeof(T), ctx->capturing));
+    CRK_TRY(t->pf[4].ensure(n1 * sizeof(T), ctx->capturing));
+    T *f = t->pf[7].as<T>(), *mt = t->pf[4].as<T>();
+    hipLaunchKernelGGL((hydro_gather_kernel<T>), dim3(grid_for(ng)), dim3(256),
+                       0, ctx->stream, t->perm.as<int32_t>(), ng, t->hsm.as<T>(),
+                       static_cast<const T *>(m), static_cast<const T *>(vx),
+                       static_cast<const T *>(vy), static_cast<const T *>(vz),
+                       static_cast<const T *>(V), static_cast<const T *>(rho),
+                       static_cast<const T *>(P), static_cast<const T *>(cs),
+                       static_cast<const T *>(A), static_cast<const T *>(B),
+                       static_cast<const T *>(gA), static_cast<const T *>(gB), f,
+                       mt);
+    CRK_HIP(hipGetLastError());
+    typename HydroPass<T>::Args pa{f, ng, static_cast<T *>(ax),
+                                   static_cast<T *>(ay), static_cast<T *>(az),
+                                   static_cast<T *>(dudt), mt,
+                                   (T)ctx->params.Cl, (T)ctx->params.Cq,
+                                   (T)ctx->params.epsQ};
+    return launch_pair<T, HydroPass<T>>(ctx, t, tree_view<T>(t, true, gas_leaf_count(t)),
+                                        pa, gas_bound(ctx, t), P_HYDRO);
+}
+
+template <typename T>
+int gravity_impl(crk_ctx *ctx, crk_tree *t, const void *mg, const void *md,
+                 void *axg, void *ayg, void *azg, void *axd, void *ayd,
+                 void *azd) {
+    const int64_t n = t->n;
+    CRK_TRY(t->pf[8].ensure(std::max<int64_t>(n, 1) * sizeof(T), ctx->capturing));
+    T *mt = t->pf[8].as<T>();
+    hipLaunchKernelGGL((gather_mass_kernel<T>), dim3(grid_for(n)), dim3(256), 0,
+                       ctx->stream, t->perm.as<int32_t>(),
+                       static_cast<const T *>(mg), static_cast<const T *>(md),
+                       t->n_gas, n, (T)ctx->params.G, mt);
+    CRK_HIP(hipGetLastError());
+    typename GravityPass<T>::Args pa{mt,
+                                     static_cast<T *>(axg), static_cast<T *>(ayg),
+                                     static_cast<T *>(azg), static_cast<T *>(axd),
+                                     static_cast<T *>(ayd), static_cast<T *>(azd),
+                                     t->n_gas};
+    return launch_pair<T, GravityPass<T>>(ctx, t, tree_view<T>(t, false, all_leaf_count(t)),
+                                          pa, all_bound(ctx, t), P_GRAV);
+}
+
+template <typename T>
+int count_impl(crk_ctx *ctx, crk_tree *t, int64_t totals[3]) {
+    const int64_t n = t->n;
+    CRK_TRY(t->pf[9].ensure(std::max<int64_t>(n, 1) * 4, ctx->capturing));
+    int32_t *cnt = t->pf[9].as<int32_t>();
+    unsigned long long *tot =
+        reinterpret_cast<unsigned long long *>(t->counters.as<int64_t>() + 16);
+    CRK_HIP(fill_i64(reinterpret_cast<int64_t *>(tot), 0, 3, ctx->stream));
+    for (int mode = 0; mode < 3; ++mode) {
+        const bool gas = mode < 2;
+        CRK_HIP(fill_i32(cnt, 0, n, ctx->stream));
+        typename CountPass<T>::Args pa{mode, cnt};
+        CRK_TRY((launch_pair<T, CountPass<T>>(
+            ctx, t, tree_view<T>(t, mode == 1 || mode == 0, gas ? gas_leaf_count(t)
+                                                            : all_leaf_count(t)),
+            pa, gas ? gas_bound(ctx, t) : all_bound(ctx, t), -1)));
+        hipLaunchKernelGGL(sum_counts_kernel, dim3(256), dim3(256), 0, ctx->stream,
+                           cnt, gas ? t->n_gas : n, tot + mode);
+        CRK_HIP(hipGetLastError());
+    }
+    int64_t *hb = ctx->err_host.as<int64_t>() + 16;
+    CRK_HIP(hipMemcpyAsync(hb, tot, 24, hipMemcpyDeviceToHost, ctx->stream));
+    CRK_HIP(hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 3; ++k) totals[k] = hb[k];
+    return CRK_OK;
+}
+
+}  // namespace
+
+int pass_density(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
+                 void *rho_tilde) {
+    if (ctx->precision == CRK_FP64) return density_impl<double>(ctx, t, m, V, rho_tilde);
+    return density_impl<float>(ctx, t, m, V, rho_tilde);
+}
+
+int pass_coefficients(crk_ctx *ctx, crk_tree *t, const void *m, const void *V,
+                      const void *u, void *A, void *B, void *gradA,
+                      void *gradB, void *rho, void *P, void *cs) {
+    if (ctx->precision == CRK_FP64)
+        return coeff_impl<double>(ctx, t, m, V, u, A, B, gradA, gradB, rho, P, cs);
+    return coeff_impl<float>(ctx, t, m, V, u, A, B, gradA, gradB, rho, P, cs);
+}
+
+int pass_hydro(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
+               const void *vy, const void *vz, const void *V, const void *rho,
+               const void *P, const void *cs, const void *A, const void *B,
+               const void *gradA, const void *gradB, void *ax, void *ay,
+               void *az, void *dudt) {
+    if (ctx->precision == CRK_FP64)
+        return hydro_impl<double>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B,
+                                  gradA, gradB, ax, ay, az, dudt);
+    return hydro_impl<float>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gradA,
+                             gradB, ax, ay, az, dudt);
+}
+
+int count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[3]) {
+    if (ctx->precision == CRK_FP64) return count_impl<double>(ctx, t, totals);
+    return count_impl<float>(ctx, t, totals);
+}
+
+int pass_gravity(crk_ctx *ctx, crk_tree *t, const void *m_gas,
+                 const void *m_dm, void *ax_gas, void *ay_gas, void *az_gas,
+                 void *ax_dm, void *ay_dm, void *az_dm) {
+    if (ctx->precision == CRK_FP64)
+        return gravity_impl<double>(ctx, t, m_gas, m_dm, ax_gas, ay_gas, az_gas,
+                                    ax_dm, ay_dm, az_dm);
+    return gravity_impl<float>(ctx, t, m_gas, m_dm, ax_gas, ay_gas, az_gas,
+                               ax_dm, ay_dm, az_dm);
+}
+
+}  // namespace crk

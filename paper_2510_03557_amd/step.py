@@ -1,0 +1,162 @@
+"""One short-range step on the GPU for a workload: device buffers (torch
+tensors), the call sequence of the C ABI, and optional HIP-graph capture.
+
+Argument marshalling only; all arithmetic runs in libcrk.so.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .binding import Context, Tree
+
+OUTPUTS_GAS = ("V", "rho_tilde", "A", "B", "gradA", "gradB", "rho", "P", "cs",
+               "a_hydro", "dudt", "a_grav_gas")
+
+
+class ShortRangeStep:
+    """Device-resident inputs, outputs and double-precision state of one
+    workload.  ``run()`` enqueues build_tree, build_interaction_lists and the
+    four passes (and crk_integrate when ``integrate`` is set) on the
+    context's stream."""
+
+    def __init__(self, wl, precision: str = "fp32", tuning: dict | None = None,
+                 dt: float = 0.0, device: str = "cuda", params=None):
+        import torch
+        self.torch = torch
+        self.wl = wl
+        self.dt = float(dt)
+        self.ctx = Context(precision, params=params)
+        if tuning:
+            self.ctx.set_tuning(**tuning)
+        self.tree = Tree(self.ctx)
+        T = self.ctx.dtype
+        npT = np.float32 if precision == "fp32" else np.float64
+        g, d = wl.gas, wl.dm
+        self.ng, self.nd = g.n, d.n
+        ng, nd = self.ng, self.nd
+        # per-box h bound (host): the largest h of each box
+        hm = []
+        for b in range(wl.n_boxes):
+            s = slice(int(wl.gas_off[b]), int(wl.gas_off[b + 1]))
+            hm.append(float(np.max(g.h[s])) if s.stop > s.start else 1e-3)
+        self.h_max = np.array(hm, np.float64)
+
+        def up(a, dtype=None):
+            a = np.ascontiguousarray(a, dtype or npT)
+            return torch.from_numpy(a).to(device, non_blocking=False)
+
+        def zeros(n, dtype=T):
+            return torch.zeros(max(n, 1), dtype=dtype, device=device)
+
+        with torch.cuda.stream(self.ctx.stream):
+            self.gx, self.gy, self.gz = up(g.x), up(g.y), up(g.z)
+            self.gh, self.gm, self.gu = up(g.h), up(g.m), up(g.u)
+            self.gvx, self.gvy, self.gvz = up(g.vx), up(g.vy), up(g.vz)
+            self.dx, self.dy, self.dz = up(d.x), up(d.y), up(d.z)
+            self.dm = up(d.m)
+            self.dvx, self.dvy, self.dvz = up(d.vx), up(d.vy), up(d.vz)
+            f64 = np.float64
+            self.gx64 = up(np.concatenate([g.x, g.y, g.z]), f64)
+            self.gv64 = up(np.concatenate([g.vx, g.vy, g.vz]), f64)
+            self.gu64 = up(g.u, f64)
+            self.dx64 = up(np.concatenate([d.x, d.y, d.z]), f64)
+            self.dv64 = up(np.concatenate([d.vx, d.vy, d.vz]), f64)
+            self.V, self.rho_t = zeros(ng), zeros(ng)
+            self.A, self.rho, self.P, self.cs = (zeros(ng) for _ in range(4))
+            self.B, self.gA, self.gB = zeros(3 * ng), zeros(3 * ng), zeros(9 * ng)
+            self.ahx, self.ahy, self.ahz, self.dudt = (zeros(ng) for _ in range(4))
+            self.agx, self.agy, self.agz = (zeros(ng) for _ in range(3))
+            self.adx, self.ady, self.adz = (zeros(nd) for _ in range(3))
+        self.ctx.stream.synchronize()
+        self.graph = False
+
+    # --------------------------------------------------------------------
+    def run(self, integrate: bool = False, passes=("density", "coefficients",
+                                                    "hydro", "gravity")):
+        c, t, wl = self.ctx, self.tree, self.wl
+        c.build_tree(t, wl.gas_off, wl.dm_off, wl.r_c, wl.eps, self.h_max,
+                     self.gx, self.gy, self.gz, self.gh, self.dx, self.dy,
+                     self.dz)
+        c.build_interaction_lists(t)
+        if "density" in passes:
+            c.density(t, self.gm, self.V, self.rho_t)
+        if "coefficients" in passes:
+            c.coefficients(t, self.gm, self.V, self.gu, self.A, self.B,
+                           self.gA, self.gB, self.rho, self.P, self.cs)
+        if "hydro" in passes:
+            c.hydro_forces(t, self.gm, self.gvx, self.gvy, self.gvz, self.V,
+                           self.rho, self.P, self.cs, self.A, self.B, self.gA,
+                           self.gB, self.ahx, self.ahy, self.ahz, self.dudt)
+        if "gravity" in passes:
+            c.shortrange_gravity(t, self.gm, self.dm, self.agx, self.agy,
+                                 self.agz, self.adx, self.ady, self.adz)
+        if integrate:
+            self.integrate()
+
+    def integrate(self):
+        c = self.ctx
+        if self.ng:
+            c.integrate(self.ng, self.dt, self.gx64, self.gv64, self.gu64,
+                        (self.agx, self.agy, self.agz),
+                        (self.ahx, self.ahy, self.ahz), self.dudt,
+                        (self.gx, self.gy, self.gz),
+                        (self.gvx, self.gvy, self.gvz), self.gu)
+        if self.nd:
+            c.integrate(self.nd, self.dt, self.dx64, self.dv64, None,
+                        (self.adx, self.ady, self.adz), None, None,
+                        (self.dx, self.dy, self.dz),
+                        (self.dvx, self.dvy, self.dvz), None)
+
+    def capture(self, integrate: bool = True):
+        """Runs the step once eagerly (sizes), then captures it in a graph."""
+        self.run(integrate=integrate)
+        self.ctx.sync()
+        self.ctx.graph_begin()
+        try:
+            self.run(integrate=integrate)
+        finally:
+            self.ctx.graph_end()
+        self.graph = True
+
+    def replay(self):
+        self.ctx.graph_launch()
+
+    def sync(self):
+        return self.ctx.sync()
+
+    # --------------------------------------------------------------------
+    def set_inputs(self, **fields):
+        """Overwrites device inputs (numpy, caller order), e.g. V=..."""
+        T = self.ctx.dtype
+        for k, v in fields.items():
+            dst = getattr(self, k)
+            src = self.torch.from_numpy(np.ascontiguousarray(
+                v, np.float32 if T == self.torch.float32 else np.float64))
+            with self.torch.cuda.stream(self.ctx.stream):
+                dst.copy_(src.reshape(dst.shape).to(dst.device))
+        self.ctx.stream.synchronize()
+
+    def outputs(self) -> dict:
+        self.ctx.sync()
+        ng, nd = self.ng, self.nd
+
+        def h(t, n):
+            return t[:n].double().cpu().numpy() if n else np.zeros(0)
+
+        out = dict(V=h(self.V, ng), rho_tilde=h(self.rho_t, ng), A=h(self.A, ng),
+                   rho=h(self.rho, ng), P=h(self.P, ng), cs=h(self.cs, ng),
+                   dudt=h(self.dudt, ng))
+        out["B"] = h(self.B, 3 * ng).reshape(3, ng).T
+        out["gradA"] = h(self.gA, 3 * ng).reshape(3, ng).T
+        out["gradB"] = h(self.gB, 9 * ng).reshape(3, 3, ng).transpose(2, 0, 1)
+        out["a_hydro"] = np.stack([h(self.ahx, ng), h(self.ahy, ng),
+                                   h(self.ahz, ng)])
+        out["a_grav_gas"] = np.stack([h(self.agx, ng), h(self.agy, ng),
+                                      h(self.agz, ng)])
+        out["a_grav_dm"] = np.stack([h(self.adx, nd), h(self.ady, nd),
+                                     h(self.adz, nd)])
+        return out
+
+    def close(self):
+        self.tree.free()
+        self.ctx.close()

@@ -392,12 +392,26 @@ def plummer_spheres(n_total: int = 2 ** 26, seed: int = 5,
                         "n_spheres": n_spheres})
 
 
+def knn_smoothing_length(x01: np.ndarray, n_ngb: int) -> np.ndarray:
+    """h such that the 2h-sphere of every particle holds exactly n_ngb other
+    particles of the set (positions (3, n) in [0, 1), periodic): 2h is
+    midway between the n_ngb-th and (n_ngb+1)-th neighbour distances."""
+    from scipy.spatial import cKDTree
+    pts = np.ascontiguousarray(np.mod(x01.T, 1.0))
+    tree = cKDTree(pts, boxsize=1.0)
+    d, _ = tree.query(pts, k=n_ngb + 2)
+    return 0.25 * (d[:, n_ngb] + d[:, n_ngb + 1])
+
+
 def random_uniform(n_gas: int, n_dm: int, seed: int, n_ngb: float = 32.0,
                    r_c: float | None = None, h_spread: float = 0.3,
-                   clustered: bool = False) -> Workload:
+                   clustered: bool = False, h_rule: str = "knn") -> Workload:
     """Small random sets for parity cases: uniform (or two-blob clustered)
-    positions, unequal masses in [0.5, 1.5]/N, lognormal h around the value
-    for n_ngb neighbours, lognormal u, N(0, 0.1^2) velocities."""
+    positions, unequal masses in [0.5, 1.5]/N, lognormal u, N(0, 0.1^2)
+    velocities.  h_rule "knn" (default) gives every gas particle exactly
+    n_ngb neighbours inside 2h, as an adaptive smoothing length does;
+    "global" draws h lognormally (spread h_spread) around the value for
+    n_ngb neighbours at the mean density."""
     rng = np.random.default_rng(seed)
     n = n_gas + n_dm
 
@@ -416,7 +430,13 @@ def random_uniform(n_gas: int, n_dm: int, seed: int, n_ngb: float = 32.0,
     gp = draw(n_gas)
     dp = draw(n_dm)
     h0 = h_for_neighbours(float(max(n_gas, 1)), n_ngb)
-    h = h0 * np.exp(h_spread * rng.standard_normal(n_gas))
+    if h_rule == "knn" and n_gas > int(n_ngb) + 2:
+        # neighbours of the float32 positions actually used
+        g32 = np.stack([to_box32(c) for c in gp]).astype(np.float64) - 1.0
+        h = knn_smoothing_length(g32, int(n_ngb))
+        rng.standard_normal(n_gas)  # keep the random stream aligned
+    else:
+        h = h0 * np.exp(h_spread * rng.standard_normal(n_gas))
     h = np.minimum(h, 0.2)
     if r_c is None:
         r_c = min(3.0 / max(n, 1) ** (1.0 / 3.0) * 1.26, 0.4)
@@ -427,7 +447,7 @@ def random_uniform(n_gas: int, n_dm: int, seed: int, n_ngb: float = 32.0,
     dm = _species(dp, 0.1 * rng.standard_normal((3, n_dm)), dmm)
     return _single_box(f"random{n_gas}_{n_dm}_{seed}", gas, dm, r_c,
                        r_c / 60.0, {"kind": "random", "seed": seed,
-                                    "clustered": clustered})
+                                    "clustered": clustered, "h_rule": h_rule})
 
 
 def perfect_lattice(ng: int, n_ngb: float = 32.0, rc_cells: float = 3.0,

@@ -1,0 +1,62 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, it
+exports every function include/crk.h declares, and argument errors are
+caught on the host before any device work."""
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+from paper_2510_03557_amd import binding
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def header_functions():
+    text = (ROOT / "include" / "crk.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, re.M)
+    return sorted(set(n for n in names if n not in ("if", "return")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return binding.load()
+
+
+def test_header_declares_the_six_operations():
+    names = header_functions()
+    for op in ("build_tree", "build_interaction_lists", "crk_density",
+               "crk_coefficients", "crk_hydro_forces", "shortrange_gravity",
+               "crk_integrate"):
+        assert op in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in header_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(binding.EXPORTS) <= set(header_functions())
+
+
+def test_null_context_is_rejected_on_host(lib):
+    assert lib.crk_density(None, None, None, None, None) == binding.CRK_EINVAL
+    assert "context" in binding.last_error()
+    assert lib.build_interaction_lists(None, None) == binding.CRK_EINVAL
+    assert lib.crk_sync(None, None) == binding.CRK_EINVAL
+    assert lib.crk_graph_launch(None) == binding.CRK_EINVAL
+
+
+def test_bad_precision_is_rejected_on_host(lib):
+    h = ctypes.c_void_p()
+    assert lib.crk_ctx_create(ctypes.byref(h), 7, None, None) == binding.CRK_EINVAL
+    assert lib.crk_ctx_create(None, 1, None, None) == binding.CRK_EINVAL
+
+
+def test_context_without_device_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    st = lib.crk_ctx_create(ctypes.byref(h), binding.CRK_FP32, None, None)
+    assert st == binding.CRK_EDEVICE
+    assert not h.value

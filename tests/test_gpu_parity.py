@@ -1,0 +1,324 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerance: relative RMS <= 1e-5 per output for the float32 path (the bound
+the short-range step is specified to), 1e-10 for the float64 path (only
+summation order differs).  rel_rms(y) = sqrt(sum |y - y_ref|^2 / sum
+|y_ref|^2) with vectors and tensors compared by their Euclidean/Frobenius
+norms.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from paper_2510_03557_amd import workloads as W  # noqa: E402
+
+FP32_TOL = 1e-5
+FP64_TOL = 1e-10
+KEYS = ("V", "rho_tilde", "A", "B", "gradA", "gradB", "rho", "P", "cs",
+        "a_hydro", "dudt", "a_grav_gas", "a_grav_dm")
+
+
+def rel_rms(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.sqrt(np.sum(b * b))
+    num = np.sqrt(np.sum((a - b) ** 2))
+    return num / den if den > 0 else num
+
+
+def compare(got, ref, tol, keys=KEYS, sel=None):
+    errs = {}
+    for k in keys:
+        g, r = got[k], ref[k]
+        if sel is not None:
+            g = g[..., sel] if k.startswith("a_") else g[sel]
+        errs[k] = rel_rms(g, r)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert not bad, bad
+    return errs
+
+
+@pytest.fixture(scope="module")
+def step_cls():
+    from paper_2510_03557_amd.step import ShortRangeStep
+    assert torch.cuda.is_available()
+    return ShortRangeStep
+
+
+def run(step_cls, wl, precision="fp32", tuning=None):
+    st = step_cls(wl, precision=precision, tuning=tuning)
+    st.run()
+    out = st.outputs()
+    return st, out
+
+
+# ---------------------------------------------------------------------------
+# small cases, whole chain
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,ng,nd", [(101, 3000, 2500), (102, 777, 1301),
+                                        (103, 4096, 0)])
+def test_small_fp64_matches_oracle(orc, step_cls, seed, ng, nd):
+    print(f"case random_uniform({ng},{nd},{seed}) fp64", flush=True)
+    wl = W.random_uniform(ng, nd, seed, n_ngb=48.0, h_spread=0.15)
+    st, got = run(step_cls, wl, "fp64")
+    ref = orc.step(wl)
+    keys = KEYS if nd else KEYS[:-1]
+    compare(got, ref, FP64_TOL, keys)
+    st.close()
+
+
+@pytest.mark.parametrize("seed,ng,nd,clustered", [
+    (201, 3000, 2500, False), (202, 5000, 3000, True), (203, 1500, 4000, False)])
+def test_small_fp32_matches_oracle(orc, step_cls, seed, ng, nd, clustered):
+    print(f"case random_uniform({ng},{nd},{seed},clustered={clustered}) fp32",
+          flush=True)
+    wl = W.random_uniform(ng, nd, seed, n_ngb=48.0, h_spread=0.15,
+                          clustered=clustered)
+    st, got = run(step_cls, wl, "fp32")
+    ref = orc.step(wl)
+    compare(got, ref, FP32_TOL)
+    st.close()
+
+
+def test_dm_only_box(orc, step_cls):
+    print("case dm only", flush=True)
+    wl = W.random_uniform(0, 3000, 301)
+    st, got = run(step_cls, wl, "fp32")
+    ref = orc.step(wl)
+    compare(got, ref, FP32_TOL, ("a_grav_dm",))
+    st.close()
+
+
+# ---------------------------------------------------------------------------
+# each pass fed with the oracle's own inputs (isolates the pass)
+# ---------------------------------------------------------------------------
+
+def test_passes_with_oracle_inputs_fp32(orc, step_cls):
+    print("case per-pass random_uniform(4000,3000,401) fp32", flush=True)
+    wl = W.random_uniform(4000, 3000, 401, n_ngb=48.0, h_spread=0.15)
+    ref = orc.step(wl)
+    st = step_cls(wl, precision="fp32")
+    ng = wl.gas.n
+    # oracle intermediates rounded to float32 feed both sides
+    V32 = ref["V"].astype(np.float32)
+    g = wl.gas
+    coef = orc.coefficients(g.x, g.y, g.z, g.h, g.m, V32.astype(np.float64),
+                            g.u)
+    st.set_inputs(V=V32)
+    st.run(passes=("coefficients",))
+    got = st.outputs()
+    compare(got, coef, FP32_TOL, ("A", "B", "gradA", "gradB", "rho", "P", "cs"))
+    c32 = {k: np.asarray(coef[k], np.float32) for k in
+           ("A", "B", "gradA", "gradB", "rho", "P", "cs")}
+    st.set_inputs(A=c32["A"], B=c32["B"].T.ravel(), gA=c32["gradA"].T.ravel(),
+                  gB=c32["gradB"].transpose(1, 2, 0).ravel(), rho=c32["rho"],
+                  P=c32["P"], cs=c32["cs"])
+    st.run(passes=("hydro",))
+    got = st.outputs()
+    c64 = {k: v.astype(np.float64) for k, v in c32.items()}
+    ax, ay, az, du = orc.hydro(g.x, g.y, g.z, g.vx, g.vy, g.vz, g.h, g.m,
+                               V32, c64["rho"], c64["P"], c64["cs"], c64["A"],
+                               c64["B"], c64["gradA"], c64["gradB"])
+    compare(got, {"a_hydro": np.stack([ax, ay, az]), "dudt": du}, FP32_TOL,
+            ("a_hydro", "dudt"))
+    assert ng == got["V"].shape[0]
+    st.close()
+
+
+# ---------------------------------------------------------------------------
+# the benchmark configurations
+# ---------------------------------------------------------------------------
+
+def test_lattice32_fp64_and_fp32(orc, step_cls):
+    print("case lattice32 (65,536 particles)", flush=True)
+    wl = W.make("lattice32")
+    ref = orc.step(wl)
+    st, got = run(step_cls, wl, "fp64")
+    compare(got, ref, FP64_TOL)
+    st.close()
+    st, got = run(step_cls, wl, "fp32")
+    compare(got, ref, FP32_TOL)
+    st.close()
+
+
+def test_zeldovich128_fp32_full(orc, step_cls):
+    print("case zeldovich128 (4,194,304 particles) fp32, leaf 128", flush=True)
+    wl = W.make("zeldovich128")
+    st, got = run(step_cls, wl, "fp32", tuning=dict(leaf_max=128))
+    ref = orc.step(wl)
+    compare(got, ref, FP32_TOL)
+    st.close()
+
+
+# ---------------------------------------------------------------------------
+# invariances of the GPU path
+# ---------------------------------------------------------------------------
+
+def test_tree_structure(step_cls):
+    print("case tree structure", flush=True)
+    wl = W.random_uniform(5000, 4000, 501, n_ngb=48.0, h_spread=0.15,
+                          clustered=True)
+    st = step_cls(wl, precision="fp32", tuning=dict(leaf_max=32))
+    st.run(passes=())
+    info = st.tree.info()
+    perm, start, count = st.tree.leaves()
+    n = wl.n_total
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    assert (count >= 1).all() and (count <= 32).all()
+    assert start[0] == 0 and np.array_equal(start[1:], np.cumsum(count)[:-1])
+    assert start[-1] + count[-1] == n
+    # gas slots first, leaves never mix species
+    assert (perm[:wl.gas.n] < wl.gas.n).all()
+    ngl = info["n_gas_leaves"]
+    assert start[ngl] == wl.gas.n if ngl < len(start) else True
+    st.close()
+
+
+def test_results_independent_of_leaf_size(orc, step_cls):
+    print("case leaf-size independence", flush=True)
+    wl = W.random_uniform(4000, 3000, 601, n_ngb=48.0, h_spread=0.15,
+                          clustered=True)
+    outs = []
+    for L in (32, 64, 128, 256):
+        st, got = run(step_cls, wl, "fp32", tuning=dict(leaf_max=L))
+        outs.append(got)
+        st.close()
+    for o in outs[1:]:
+        compare(o, outs[0], 2e-6)
+
+
+def test_deterministic_and_graph_replay(step_cls):
+    print("case determinism + graph replay", flush=True)
+    wl = W.random_uniform(4000, 3000, 701, n_ngb=48.0, h_spread=0.15)
+    st, a = run(step_cls, wl, "fp32")
+    st.run()
+    b = st.outputs()
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k]), k
+    st.capture(integrate=False)
+    for rep in range(3):
+        st.replay()
+        c = st.outputs()
+        for k in KEYS:
+            assert np.array_equal(a[k], c[k]), (rep, k)
+    st.close()
+
+
+def test_batched_boxes(orc, step_cls):
+    print("case 6 uneven boxes", flush=True)
+    boxes = [W.random_uniform(n, m, 800 + k, n_ngb=48.0, h_spread=0.15)
+             for k, (n, m) in enumerate([(2000, 1500), (500, 700), (3000, 0),
+                                         (900, 2600), (1200, 1200),
+                                         (4000, 3500)])]
+    wl = W.concat_boxes("six", boxes)
+    st, got = run(step_cls, wl, "fp32")
+    ref = orc.step(wl)
+    compare(got, ref, FP32_TOL)
+    # box 3 alone gives bitwise the same results as inside the batch
+    alone, got3 = run(step_cls, boxes[3], "fp32")
+    gs = slice(int(wl.gas_off[3]), int(wl.gas_off[4]))
+    ds = slice(int(wl.dm_off[3]), int(wl.dm_off[4]))
+    for k in ("V", "A", "B", "gradB", "rho", "dudt"):
+        assert np.array_equal(got[k][gs], got3[k]), k
+    assert np.array_equal(got["a_hydro"][:, gs], got3["a_hydro"])
+    assert np.array_equal(got["a_grav_dm"][:, ds], got3["a_grav_dm"])
+    st.close()
+    alone.close()
+
+
+def test_integrate_matches_oracle(orc, step_cls):
+    print("case integrate", flush=True)
+    dt = 1e-3
+    wl = W.random_uniform(3000, 2000, 901, n_ngb=48.0, h_spread=0.15)
+    st = step_cls(wl, precision="fp32", dt=dt)
+    st.run(integrate=True)
+    st.sync()
+    ref = orc.step(wl)
+    g = wl.gas
+    x0 = np.stack([g.x, g.y, g.z]).astype(np.float64)
+    v0 = np.stack([g.vx, g.vy, g.vz]).astype(np.float64)
+    o = orc.integrate(dt, x0, v0, g.u, ref["a_grav_gas"], ref["a_hydro"],
+                      ref["dudt"])
+    x64 = st.gx64.cpu().numpy().reshape(3, -1)
+    v64 = st.gv64.cpu().numpy().reshape(3, -1)
+    u64 = st.gu64.cpu().numpy()
+    # increments carry the float32 accelerations: same bound as the passes
+    assert rel_rms(v64 - v0, o["v"] - v0) < FP32_TOL
+    assert rel_rms(u64 - g.u, o["u"] - g.u) < FP32_TOL
+    # the drift uses the new velocity, then wraps into [1, 2)
+    xd = x0 + dt * v64
+    xd = np.where(xd >= 2.0, xd - 1.0, xd)
+    xd = np.where(xd < 1.0, xd + 1.0, xd)
+    assert np.abs(x64 - xd).max() < 1e-15
+    # the float32 copies are the rounded doubles
+    x32 = x64[0].astype(np.float32)
+    x32[x32 >= 2.0] = 1.0
+    assert np.array_equal(st.gx.cpu().numpy()[:g.n], x32)
+    st.close()
+
+
+# ---------------------------------------------------------------------------
+# errors detected on the device and on the host
+# ---------------------------------------------------------------------------
+
+def test_device_input_errors(step_cls):
+    from paper_2510_03557_amd.binding import CrkError, CRK_EINVAL
+    print("case device-side input errors", flush=True)
+    wl = W.random_uniform(1000, 500, 1001)
+    st = step_cls(wl, precision="fp32")
+    st.h_max = st.h_max * 0.5  # declared bound below the real h
+    st.run(passes=())
+    with pytest.raises(CrkError) as e:
+        st.sync()
+    assert e.value.status == CRK_EINVAL
+    st.sync()  # the error is cleared
+    st.close()
+
+
+def test_host_argument_errors(step_cls):
+    from paper_2510_03557_amd.binding import CrkError, CRK_EINVAL, CRK_ESTATE
+    print("case host-side argument errors", flush=True)
+    wl = W.random_uniform(1000, 500, 1002)
+    st = step_cls(wl, precision="fp32")
+    c, t = st.ctx, st.tree
+    with pytest.raises(CrkError) as e:
+        c.density(t, st.gm, st.V, st.rho_t)  # tree not built yet
+    assert e.value.status in (CRK_EINVAL, CRK_ESTATE)
+    for bad in (dict(r_c=[0.6]), dict(r_c=[0.0]), dict(h_max=[0.3]),
+                dict(eps=[1.0])):
+        args = dict(r_c=wl.r_c, eps=wl.eps, h_max=st.h_max)
+        args.update({k: np.array(v) for k, v in bad.items()})
+        with pytest.raises(CrkError) as e:
+            c.build_tree(t, wl.gas_off, wl.dm_off, args["r_c"], args["eps"],
+                         args["h_max"], st.gx, st.gy, st.gz, st.gh, st.dx,
+                         st.dy, st.dz)
+        assert e.value.status == CRK_EINVAL
+    with pytest.raises(CrkError):
+        c.set_tuning(leaf_max=8)
+    with pytest.raises(CrkError):
+        c.build_tree(t, wl.gas_off, wl.dm_off, wl.r_c, wl.eps, st.h_max,
+                     None, st.gy, st.gz, st.gh, st.dx, st.dy, st.dz)
+    st.close()
+
+
+def test_capacity_overflow_in_graph_is_reported(step_cls):
+    from paper_2510_03557_amd.binding import CrkError, CRK_ECAPACITY
+    print("case graph capacity overflow", flush=True)
+    wl = W.random_uniform(3000, 2000, 1101, n_ngb=48.0, h_spread=0.15)
+    st = step_cls(wl, precision="fp32")
+    st.capture(integrate=False)
+    # clustering the particles after capture needs longer lists and deeper
+    # k-d trees than the captured capacities
+    g = wl.gas
+    st.set_inputs(gx=np.full(g.n, 1.5, np.float32) + np.float32(1e-4) *
+                  np.arange(g.n, dtype=np.float32) / g.n)
+    st.replay()
+    with pytest.raises(CrkError) as e:
+        st.sync()
+    assert e.value.status == CRK_ECAPACITY
+    st.close()
