@@ -15,7 +15,8 @@ from paper_2510_03557_amd import workloads  # noqa: E402
 
 
 def case():
-    return workloads.random_uniform(64, 48, 2024, n_ngb=40.0, h_spread=0.1)
+    return workloads.random_uniform(64, 48, 2024, n_ngb=40.0, h_spread=0.1,
+                                    h_rule="global")
 
 
 def main():
@@ -24,7 +25,7 @@ def main():
             if k != "degenerate"}
     with open(os.path.join(HERE, "tiny_step.json"), "w") as f:
         json.dump({"case": "random_uniform(64, 48, 2024, n_ngb=40, "
-                           "h_spread=0.1)", "outputs": keep}, f)
+                           "h_spread=0.1, h_rule=global)", "outputs": keep}, f)
 
 
 if __name__ == "__main__":

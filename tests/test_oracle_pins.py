@@ -40,8 +40,9 @@ def pair_table(x, y, z, i):
     return d, np.sqrt((d ** 2).sum(0))
 
 
-def small_gas(n=300, seed=11, n_ngb=48.0, spread=0.1):
-    w = wl_mod.random_uniform(n, 0, seed, n_ngb=n_ngb, h_spread=spread)
+def small_gas(n=300, seed=11, n_ngb=48.0, spread=0.1, h_rule="knn"):
+    w = wl_mod.random_uniform(n, 0, seed, n_ngb=n_ngb, h_spread=spread,
+                              h_rule=h_rule)
     g = w.gas
     return w, [np.asarray(a, np.float64) for a in
                (g.x, g.y, g.z, g.h, g.m, g.u, g.vx, g.vy, g.vz)]
@@ -407,7 +408,8 @@ def test_sampled_step_matches_full_step(orc):
 # ---------------------------------------------------------------------------
 
 def test_reduces_to_textbook_sph(orc):
-    w, (x, y, z, h, m, u, vx, vy, vz) = small_gas(250, 61, spread=0.0)
+    w, (x, y, z, h, m, u, vx, vy, vz) = small_gas(250, 61, spread=0.0,
+                                                  h_rule="global")
     n = x.size
     rho = np.abs(np.random.default_rng(1).normal(1.0, 0.1, n))
     P = (2.0 / 3.0) * rho * u
