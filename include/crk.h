@@ -90,8 +90,10 @@ typedef struct {
  * beyond floating-point rounding order). */
 typedef struct {
     int32_t leaf_max;   /* k-d leaf size bound, 16..256 (default 64)         */
-    double cm_factor;   /* chaining-mesh bin width / max(r_c, 2 h_max) >= 1
-                           (default 1.0)                                     */
+    double cm_factor;   /* chaining-mesh bin width / max(r_c, 2 h_max), in
+                           [1, 64]; 0 (default) widens the bins until each
+                           holds about 4 leaf_max particles of the denser
+                           species (never narrower than max(r_c, 2 h_max)) */
     int32_t grid_mult;  /* persistent grid = grid_mult x CU count; 0 = one
                            workgroup per leaf (default 0)                    */
 } crk_tuning;
@@ -123,11 +125,12 @@ int crk_sync(crk_ctx *ctx, int64_t *required);
 /* ------------------------------------------------------------------------ */
 
 /* Chaining-mesh bins and per-bin k-d base leaves (Sec. IV-B.1).
- * Each box is cut into n_cm^3 bins with n_cm = floor(1 / (cm_factor *
- * max(r_c, 2 h_max))), so every interaction of a particle lies in its bin
+ * Each box is cut into n_cm^3 bins of width >= max(r_c, 2 h_max) (see
+ * crk_tuning.cm_factor), so every interaction of a particle lies in its bin
  * or one of the 26 neighbours.  Particles are sorted by (species, box,
- * bin); inside each bin a k-d tree splits the widest extent at the median
- * (ties by caller index) until leaves hold <= leaf_max particles; only the
+ * bin); inside each bin a k-d tree splits the widest extent (ties by caller
+ * index) until leaves hold <= leaf_max particles, the left side taking
+ * ceil(k/2) of the k leaves a node needs (the median for even k); only the
  * leaves are kept.
  * gx, gy, gz, gh: gas positions and smoothing lengths (n_gas values);
  * dx, dy, dz: dark-matter positions (n_dm values); n_gas = gas_off[n_boxes],

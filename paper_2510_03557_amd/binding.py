@@ -182,7 +182,7 @@ class Context:
         except Exception:
             pass
 
-    def set_tuning(self, leaf_max=64, cm_factor=1.0, grid_mult=0):
+    def set_tuning(self, leaf_max=64, cm_factor=0.0, grid_mult=0):
         check(self.lib.crk_set_tuning(self.handle, ctypes.byref(
             crk_tuning(int(leaf_max), float(cm_factor), int(grid_mult)))))
 

@@ -161,7 +161,7 @@ int crk_ctx_create(crk_ctx **out, int precision, void *stream,
     c->stream = static_cast<hipStream_t>(stream);
     c->params = p;
     c->tuning.leaf_max = 64;
-    c->tuning.cm_factor = 1.0;
+    c->tuning.cm_factor = 0.0;
     c->tuning.grid_mult = 0;
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess)
@@ -210,8 +210,8 @@ int crk_set_tuning(crk_ctx *ctx, const crk_tuning *t) {
     if (!t) return set_error(CRK_EINVAL, "null tuning");
     if (t->leaf_max < 16 || t->leaf_max > 256)
         return set_error(CRK_EINVAL, "leaf_max must be in [16, 256]");
-    if (!(t->cm_factor >= 1.0) || !(t->cm_factor <= 64.0))
-        return set_error(CRK_EINVAL, "cm_factor must be in [1, 64]");
+    if (!(t->cm_factor == 0.0 || (t->cm_factor >= 1.0 && t->cm_factor <= 64.0)))
+        return set_error(CRK_EINVAL, "cm_factor must be 0 (auto) or in [1, 64]");
     if (t->grid_mult < 0 || t->grid_mult > 64)
         return set_error(CRK_EINVAL, "grid_mult must be in [0, 64]");
     if (ctx->capturing) return set_error(CRK_ESTATE, "tuning change during capture");

@@ -100,6 +100,8 @@ template <typename T> struct TreeView {
     int64_t list_cap;        // allocated list entries
     const int32_t *perm;
     const T *px, *py, *pz, *h;
+    const T *lo, *hi, *hmax;  // leaf boxes (3 planes of lcap) and h_max
+    int64_t lcap;
     const double *rc, *eps;
     int64_t n_gas;
 };
@@ -115,24 +117,45 @@ __device__ inline void decode_shift(uint32_t code, int &sx, int &sy, int &sz) {
 //   P::I         per-lane i-state
 //   P::load_i(I&, args, tv, i, ex, ey, ez, box)
 //   P::load_j(T* dst, args, tv, j, fx, fy, fz)
-//   P::Tile / P::Acc  per-tile sums and compensated totals
+//   P::range(args, tv, box, hmax_I, hmax_J)  interaction range of a leaf pair
+//   P::Tile / P::Acc  per-sweep sums and compensated totals
 //   P::pair(Tile&, const I&, const T* jd, bool self)
 //   P::finish(const Acc&, const I&, args, tv, i)
+//
+// Every j particle of a listed j-leaf is first tested against the i-leaf's
+// bounding box widened by the pair range; survivors are compacted (ballot +
+// prefix) into an LDS buffer of 2*BLOCK candidates that spans several
+// j-leaves.  A full buffer is swept by every lane and its partial sums are
+// folded into the compensated totals.  Culled particles are out of range of
+// every i, so the sums do not change beyond rounding order.
 template <typename T, typename P, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
                                                      const typename P::Args pa) {
-    __shared__ __attribute__((aligned(16))) T sj[BLOCK * P::NJ];
+    constexpr int CAP = 2 * BLOCK;
+    constexpr int NW = BLOCK / 64;
+    __shared__ __attribute__((aligned(16))) T sj[CAP * P::NJ];
+    __shared__ int sjid[CAP];
+    __shared__ int wcnt[NW];
     const int I = (int)blockIdx.x;
     if (I >= *tv.n_items) return;
     const int st = tv.leaf_start[I];
     // a leaf above BLOCK exists only after a capacity error (already
-    // latched); clamping keeps every access inside the LDS tile
+    // latched); clamping keeps every access inside the LDS buffer
     const int cnt = min(tv.leaf_count[I], BLOCK);
     const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const bool act = t < cnt;
     const int i = st + (act ? t : 0);
     const T rx = tv.px[st], ry = tv.py[st], rz = tv.pz[st];
     const int box = tv.leaf_box[I];
+    // i-leaf box relative to the reference particle (exact in float32)
+    const T blx = tv.lo[I] - rx, bly = tv.lo[tv.lcap + I] - ry,
+            blz = tv.lo[2 * tv.lcap + I] - rz;
+    const T bhx = tv.hi[I] - rx, bhy = tv.hi[tv.lcap + I] - ry,
+            bhz = tv.hi[2 * tv.lcap + I] - rz;
+    const T hmI = tv.hmax[I];
     typename P::I is;
     P::load_i(is, pa, tv, i, tv.px[i] - rx, tv.py[i] - ry, tv.pz[i] - rz, box);
     typename P::Tile tile;
@@ -144,6 +167,16 @@ __global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
     const int64_t e0 = min(tv.list_off[I], tv.list_cap);
     const int64_t e1 = min(tv.list_off[I + 1], tv.list_cap);
     const int nl = *tv.n_leaves;
+    int nbuf = 0;
+    auto sweep = [&](int n) {
+        __syncthreads();
+        if (act) {
+            for (int k = 0; k < n; ++k)
+                P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+        }
+        acc.fold(tile);
+        __syncthreads();
+    };
     for (int64_t e = e0; e < e1; ++e) {
         const uint32_t ent = tv.list[e];
         const int J = (int)(ent & LIST_LEAF_MASK);
@@ -152,20 +185,52 @@ __global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
         decode_shift(ent >> LIST_LEAF_BITS, sx, sy, sz);
         const int js = tv.leaf_start[J];
         const int jc = min(tv.leaf_count[J], BLOCK);
-        __syncthreads();
+        if (nbuf + jc > CAP) {
+            sweep(nbuf);
+            nbuf = 0;
+        }
+        const T R = P::range(pa, tv, box, hmI, tv.hmax[J]);
+        const T R2 = R * R;
+        bool keep = false;
+        T fx = T(0), fy = T(0), fz = T(0);
+        const int j = js + t;
         if (t < jc) {
-            const int j = js + t;
-            P::load_j(&sj[t * P::NJ], pa, tv, j, (tv.px[j] - rx) + T(sx),
-                      (tv.py[j] - ry) + T(sy), (tv.pz[j] - rz) + T(sz));
+            fx = (tv.px[j] - rx) + T(sx);
+            fy = (tv.py[j] - ry) + T(sy);
+            fz = (tv.pz[j] - rz) + T(sz);
+            const T dx = fmax(fmax(blx - fx, fx - bhx), T(0));
+            const T dy = fmax(fmax(bly - fy, fy - bhy), T(0));
+            const T dz = fmax(fmax(blz - fz, fz - bhz), T(0));
+            keep = dx * dx + dy * dy + dz * dz < R2;
         }
-        __syncthreads();
-        if (act) {
-            for (int k = 0; k < jc; ++k)
-                P::pair(tile, is, &sj[k * P::NJ], js + k == i);
+        const uint64_t m = __ballot(keep);
+        int off = __popcll(m & lt_mask);
+        int tot = __popcll(m);
+        if (NW > 1) {
+            if (lane == 0) wcnt[wave] = tot;
+            __syncthreads();
+            tot = 0;
+            for (int w = 0; w < NW; ++w) {
+                if (w < wave) off += wcnt[w];
+                tot += wcnt[w];
+            }
+            __syncthreads();
         }
-        acc.fold(tile);
+        if (keep) {
+            const int pos = nbuf + off;
+            P::load_j(&sj[pos * P::NJ], pa, tv, j, fx, fy, fz);
+            sjid[pos] = j;
+        }
+        nbuf += tot;
     }
+    sweep(nbuf);
     if (act) P::finish(acc, is, pa, tv, i);
+}
+
+// widened pair ranges (relative 1e-5 above the exact test, so that every
+// pair a float32 test accepts survives the culling)
+template <typename T> __device__ inline T widen(double r) {
+    return (T)(r * (1.0 + 1e-5));
 }
 
 // --------------------------------------------------------------------------
@@ -178,6 +243,9 @@ template <typename T> struct DensityPass {
         T *V, *rho_t;     // caller order
     };
     static constexpr int NJ = 4;  // fx, fy, fz, m
+    __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
+        return widen<T>(2.0 * (double)hI);
+    }
     struct I {
         T ex, ey, ez, ih2, h;
     };
@@ -250,6 +318,9 @@ template <typename T> struct CoeffPass {
     };
     static constexpr int NJ = 8;  // fx fy fz V m + pad
     static constexpr int NS = 33;
+    __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
+        return widen<T>(2.0 * (double)hI);
+    }
     struct I {
         T ex, ey, ez, ih;
         T h;
@@ -449,6 +520,9 @@ template <typename T> struct HydroPass {
         T Cl, Cq, epsQ;
     };
     static constexpr int NJ = 32;  // fx fy fz + HF fields + pad
+    __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T hJ) {
+        return widen<T>(2.0 * (double)(hI > hJ ? hI : hJ));
+    }
     struct I {
         T ex, ey, ez;
         T Cl, Cq, epsQ;
@@ -559,6 +633,9 @@ template <typename T> struct GravityPass {
         int64_t n_gas;
     };
     static constexpr int NJ = 4;  // fx fy fz Gm
+    __device__ static T range(const Args &, const TreeView<T> &tv, int box, T, T) {
+        return widen<T>(tv.rc[box]);
+    }
     struct I {
         T ex, ey, ez;
         T rc2, eps2, two_rc, cin;
@@ -650,6 +727,12 @@ template <typename T> struct CountPass {
         int32_t *counts;  // tree order
     };
     static constexpr int NJ = 4;  // fx fy fz 1/h^2
+    __device__ static T range(const Args &a, const TreeView<T> &tv, int box, T hI,
+                              T hJ) {
+        if (a.mode == 2) return widen<T>(tv.rc[box]);
+        if (a.mode == 1) return widen<T>(2.0 * (double)(hI > hJ ? hI : hJ));
+        return widen<T>(2.0 * (double)hI);
+    }
     struct I {
         T ex, ey, ez, ih2, rc2;
         int mode;
@@ -806,6 +889,10 @@ TreeView<T> tree_view(crk_tree *t, bool hydro, const int32_t *n_items) {
     tv.py = t->pos[1].as<T>();
     tv.pz = t->pos[2].as<T>();
     tv.h = t->hsm.as<T>();
+    tv.lo = t->leaf_lo.as<T>();
+    tv.hi = t->leaf_hi.as<T>();
+    tv.hmax = t->leaf_hmax.as<T>();
+    tv.lcap = t->leaf_cap;
     tv.rc = t->d_rc.as<double>();
     tv.eps = t->d_eps.as<double>();
     tv.n_gas = t->n_gas;

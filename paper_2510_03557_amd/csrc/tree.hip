@@ -5,8 +5,10 @@
 //     axis; three stable radix sorts give, for each axis a, the particles
 //     ordered by (bin, coordinate_a, caller index) -- the arrays S_a.
 //  2. every non-empty (species, bin) segment is a k-d node.  A level splits
-//     each node holding more than leaf_max particles at the median of its
-//     widest extent.  The extent is O(1) from the axis-sorted arrays (first
+//     each node holding more than leaf_max particles along its widest
+//     extent, at the quantile that gives the left side ceil(k/2) of the k
+//     leaves the node needs (the median when k is even), so leaves end up
+//     nearly full.  The extent is O(1) from the axis-sorted arrays (first
 //     and last element); the left half is the first ceil(c/2) elements of
 //     S_axis, and all three arrays are partitioned stably with one prefix
 //     sum each, so every array stays sorted inside every node.  A level
@@ -157,7 +159,8 @@ __global__ void node_counts_kernel(const int32_t *__restrict__ nd_start,
 }
 
 // Decide the split of every node: axis of widest extent (ties: lowest
-// axis), left part = ceil(count / 2).  On the last level of a captured
+// axis); the left part takes ceil(k/2) of the node's k leaves.  On the last
+// level of a captured
 // sequence a node that still needs a split raises the capacity error.
 template <typename T>
 __global__ void kd_plan_kernel(
@@ -194,7 +197,12 @@ __global__ void kd_plan_kernel(
                 }
                 if (ez > best) a = 2;
                 axis[k] = a;
-                left[k] = cnt - cnt / 2;
+                // the node needs nl = ceil(cnt / L) leaves; the left part
+                // takes ceil(nl / 2) of them, in proportion (the median when
+                // nl is even), so that leaves come out nearly full
+                const int nl = (cnt + L - 1) / L;
+                const int nleft = (nl + 1) / 2;
+                left[k] = (int)(((long long)cnt * nleft + nl / 2) / nl);
                 s = 1;
                 *any_split = 1;
             }
@@ -212,7 +220,9 @@ __global__ void kd_flag_kernel(const int32_t *__restrict__ elem_node,
                                const int32_t *__restrict__ S0,
                                const int32_t *__restrict__ S1,
                                const int32_t *__restrict__ S2, int64_t n,
+                               const int32_t *__restrict__ nn_next, int64_t cap,
                                int32_t *__restrict__ flag_c) {
+    if (*nn_next > cap) return;  // overflowing level: nothing splits
     GRID_STRIDE(p, n) {
         int k = elem_node[p];
         if (split[k]) {
@@ -227,8 +237,11 @@ __global__ void kd_part_flags_kernel(const int32_t *__restrict__ elem_node,
                                      const int32_t *__restrict__ split,
                                      const int32_t *__restrict__ S,
                                      const int32_t *__restrict__ flag_c,
-                                     int64_t n, int32_t *__restrict__ f) {
-    GRID_STRIDE(p, n) f[p] = split[elem_node[p]] ? flag_c[S[p]] : 1;
+                                     int64_t n,
+                                     const int32_t *__restrict__ nn_next,
+                                     int64_t cap, int32_t *__restrict__ f) {
+    const bool ovf = *nn_next > cap;
+    GRID_STRIDE(p, n) f[p] = (split[elem_node[p]] && !ovf) ? flag_c[S[p]] : 1;
 }
 
 __global__ void kd_part_scatter_kernel(
@@ -236,11 +249,13 @@ __global__ void kd_part_scatter_kernel(
     const int32_t *__restrict__ nd_count, const int32_t *__restrict__ split,
     const int32_t *__restrict__ left, const int32_t *__restrict__ f,
     const int32_t *__restrict__ sf, const int32_t *__restrict__ S, int64_t n,
+    const int32_t *__restrict__ nn_next, int64_t cap,
     int32_t *__restrict__ Snew) {
+    const bool ovf = *nn_next > cap;
     GRID_STRIDE(p, n) {
         int k = elem_node[p];
         int st = nd_start[k];
-        int lc = split[k] ? left[k] : nd_count[k];
+        int lc = (split[k] && !ovf) ? left[k] : nd_count[k];
         int rl = sf[p] - sf[st];
         int np = f[p] ? st + rl : st + lc + ((int)p - st - rl);
         Snew[np] = S[p];
@@ -251,14 +266,16 @@ __global__ void kd_children_kernel(
     const int32_t *__restrict__ nd_start, const int32_t *__restrict__ nd_count,
     const int32_t *__restrict__ nd_key, const int32_t *__restrict__ split,
     const int32_t *__restrict__ left, const int32_t *__restrict__ child,
-    const int32_t *__restrict__ nn_ptr, int64_t cap, int32_t *__restrict__ ns,
-    int32_t *__restrict__ nc, int32_t *__restrict__ nkey) {
+    const int32_t *__restrict__ nn_ptr, const int32_t *__restrict__ nn_next,
+    int64_t cap, int32_t *__restrict__ ns, int32_t *__restrict__ nc,
+    int32_t *__restrict__ nkey) {
     const int64_t nn = *nn_ptr;
+    const bool ovf = *nn_next > cap;
     GRID_STRIDE(k, cap) {
         if (k >= nn) break;
-        int cb = child[k];
+        int cb = ovf ? (int)k : child[k];
         int st = nd_start[k], cnt = nd_count[k], key = nd_key[k];
-        if (split[k]) {
+        if (split[k] && !ovf) {
             int l = left[k];
             ns[cb] = st;
             nc[cb] = l;
@@ -279,17 +296,28 @@ __global__ void kd_elem_node_kernel(const int32_t *__restrict__ elem_node,
                                     const int32_t *__restrict__ split,
                                     const int32_t *__restrict__ left,
                                     const int32_t *__restrict__ child,
-                                    int64_t n, int32_t *__restrict__ out) {
+                                    int64_t n,
+                                    const int32_t *__restrict__ nn_next,
+                                    int64_t cap, int32_t *__restrict__ out) {
+    const bool ovf = *nn_next > cap;
     GRID_STRIDE(p, n) {
         int k = elem_node[p];
+        if (ovf) {
+            out[p] = k;
+            continue;
+        }
         int cb = child[k];
         out[p] = cb + ((split[k] && (int)p - nd_start[k] >= left[k]) ? 1 : 0);
     }
 }
 
-__global__ void scalar_copy_kernel(const int32_t *__restrict__ a,
-                                   int32_t *__restrict__ b) {
-    *b = *a;
+// node count of the next level; a level that would exceed the node
+// capacity was run as an identity level and raises the capacity error
+__global__ void next_count_kernel(const int32_t *__restrict__ nn_next,
+                                  int64_t cap, int32_t *__restrict__ nn,
+                                  int *__restrict__ err) {
+    if (*nn_next > cap) atomicOr(err, DEV_ERR_CAPACITY);
+    else *nn = *nn_next;
 }
 
 template <typename T>
@@ -477,35 +505,38 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
         hipLaunchKernelGGL(kd_flag_kernel, dim3(grid_for(n)), dim3(TB), 0, s, en,
                            ns, t->nd_split.as<int32_t>(),
                            t->nd_left.as<int32_t>(), t->nd_axis.as<int32_t>(),
-                           S[0], S[1], S[2], n, t->flag_c.as<int32_t>());
+                           S[0], S[1], S[2], n, cnt + C_NN_NEXT, lcap,
+                           t->flag_c.as<int32_t>());
         CRK_HIP(hipGetLastError());
         for (int a = 0; a < 3; ++a) {
             hipLaunchKernelGGL(kd_part_flags_kernel, dim3(grid_for(n)), dim3(TB),
                                0, s, en, t->nd_split.as<int32_t>(), S[a],
-                               t->flag_c.as<int32_t>(), n, flags);
+                               t->flag_c.as<int32_t>(), n, cnt + C_NN_NEXT,
+                               lcap, flags);
             CRK_HIP(hipGetLastError());
             CRK_HIP(exclusive_scan_i32(flags, sf, n, nullptr, ctx->scratch.p, s));
             hipLaunchKernelGGL(kd_part_scatter_kernel, dim3(grid_for(n)),
                                dim3(TB), 0, s, en, ns, nc,
                                t->nd_split.as<int32_t>(),
                                t->nd_left.as<int32_t>(), flags, sf, S[a], n,
-                               Sn[a]);
+                               cnt + C_NN_NEXT, lcap, Sn[a]);
             CRK_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(kd_children_kernel, dim3(grid_for(lcap)), dim3(TB), 0,
                            s, ns, nc, nk, t->nd_split.as<int32_t>(),
                            t->nd_left.as<int32_t>(), t->nd_child.as<int32_t>(),
-                           cnt + C_NN, lcap, t->nd_start[cur ^ 1].as<int32_t>(),
+                           cnt + C_NN, cnt + C_NN_NEXT, lcap,
+                           t->nd_start[cur ^ 1].as<int32_t>(),
                            t->nd_count[cur ^ 1].as<int32_t>(),
                            t->nd_key[cur ^ 1].as<int32_t>());
         CRK_HIP(hipGetLastError());
         hipLaunchKernelGGL(kd_elem_node_kernel, dim3(grid_for(n)), dim3(TB), 0, s,
                            en, ns, t->nd_split.as<int32_t>(),
                            t->nd_left.as<int32_t>(), t->nd_child.as<int32_t>(),
-                           n, en2);
+                           n, cnt + C_NN_NEXT, lcap, en2);
         CRK_HIP(hipGetLastError());
-        hipLaunchKernelGGL(scalar_copy_kernel, dim3(1), dim3(1), 0, s,
-                           cnt + C_NN_NEXT, cnt + C_NN);
+        hipLaunchKernelGGL(next_count_kernel, dim3(1), dim3(1), 0, s,
+                           cnt + C_NN_NEXT, lcap, cnt + C_NN, err);
         CRK_HIP(hipGetLastError());
         for (int a = 0; a < 3; ++a) std::swap(S[a], Sn[a]);
         std::swap(en, en2);
@@ -573,7 +604,18 @@ int tree_build(crk_ctx *ctx, crk_tree *t, const crk_boxes *bx, const void *gx,
     std::vector<int64_t> base(nb + 1);
     base[0] = 0;
     for (int b = 0; b < nb; ++b) {
-        double w = std::max(bx->r_c[b], 2.0 * bx->h_max[b]) * ctx->tuning.cm_factor;
+        // a bin at least as wide as every interaction range, so the 27-bin
+        // stencil holds all partners; with cm_factor = 0 the bins are
+        // widened until they hold ~4 leaves of the denser species
+        const double w_min = std::max(bx->r_c[b], 2.0 * bx->h_max[b]);
+        double w = w_min;
+        if (ctx->tuning.cm_factor > 0.0) {
+            w = w_min * ctx->tuning.cm_factor;
+        } else {
+            const double nsp = (double)std::max(bx->gas_off[b + 1] - bx->gas_off[b],
+                                                bx->dm_off[b + 1] - bx->dm_off[b]);
+            if (nsp > 0) w = std::max(w_min, std::cbrt(4.0 * L / nsp));
+        }
         int64_t c = (int64_t)std::floor(1.0 / w);
         if (c < 1) c = 1;
         if (c > 1024) c = 1024;
@@ -596,9 +638,11 @@ int tree_build(crk_ctx *ctx, crk_tree *t, const crk_boxes *bx, const void *gx,
     if (cap && !same)
         return set_error(CRK_ESTATE,
                          "build_tree: boxes or tuning changed during capture");
-    // leaf upper bound: unsplit segments + halves of at least (L+1)/2
+    // leaf upper bound: unsplit segments + split leaves, which hold about
+    // L/2 particles or more (a quarter of L keeps a wide margin; a level
+    // that would still overflow is run as an identity level and reported)
     int64_t seg_bound = std::min<int64_t>(n, 2 * total_bins);
-    int64_t leaf_cap = seg_bound + n / std::max(1, (L + 1) / 2) + 1;
+    int64_t leaf_cap = seg_bound + n / std::max(1, L / 4) + 1;
     if (leaf_cap > n + 1) leaf_cap = n + 1;
     if (leaf_cap >= (int64_t)crk::LIST_LEAF_MASK)
         return set_error(CRK_EINVAL, "build_tree: too many leaves");
