@@ -83,11 +83,20 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zeldovich128")
-    ap.add_argument("--leaf-max", type=int, default=128)
+    # defaults: the fastest shape the tuner found for this workload on
+    # MI355X (--tune re-runs the search)
+    ap.add_argument("--leaf-max", type=int, default=64)
+    ap.add_argument("--grid-mult", type=int, default=0)
+    ap.add_argument("--xcd-remap", type=int, default=0)
+    ap.add_argument("--walk-mask", type=int, default=0)
+    ap.add_argument("--tune", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--dt", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB three times "
+                         "(reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -101,6 +110,17 @@ def main():
     import numpy as np
     import torch
 
+    if args.copy_calibration:
+        torch.cuda.set_device(0)
+        src = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 2 ** 30, "copy_bytes_written":
+                          2 ** 30, "launches": 3}), flush=True)
+        return
+
     from paper_2510_03557_amd import workloads
     from paper_2510_03557_amd.step import ShortRangeStep
 
@@ -108,11 +128,18 @@ def main():
     log(f"[bench] generating {args.workload}")
     wl = workloads.make(args.workload)
     n = wl.n_total
-    tuning = dict(leaf_max=args.leaf_max)
+    tuning = dict(leaf_max=args.leaf_max, grid_mult=args.grid_mult,
+                  xcd_remap=args.xcd_remap, walk_mask=args.walk_mask)
 
     # ---------------- float32 path: graph replay of the whole step ---------
-    log("[bench] fp32 path: eager warm-up, kernel timing")
     st = ShortRangeStep(wl, precision="fp32", tuning=tuning, dt=args.dt)
+    tuned = None
+    if args.tune:
+        from paper_2510_03557_amd import autotune
+        log("[bench] tuning leaf size and grid")
+        tuned = autotune.tune(st, log=log)
+        tuning = tuned["tuning"]
+    log(f"[bench] fp32 path with {tuning}: eager warm-up, kernel timing")
     st.run(integrate=True)
     st.sync()
     pairs = st.ctx.count_pairs(st.tree)
@@ -197,13 +224,19 @@ def main():
                                   " r_c=3/128, ~64 hydro neighbours, periodic"
                    if args.workload == "zeldovich128" else wl.name,
                    "n_particles": n, "boxes": wl.n_boxes,
-                   "leaf_max": args.leaf_max, "launch": "hip_graph",
+                   "leaf_max": tuning["leaf_max"],
+                   "grid_mult": tuning["grid_mult"],
+                   "xcd_remap": tuning.get("xcd_remap", 0),
+                   "walk_mask": tuning.get("walk_mask", 0), "launch": "hip_graph",
                    "leaves": info["n_leaves"],
                    "list_entries": {"gravity": info["grav_entries"],
                                     "hydro": info["hydro_entries"]}},
         "fp64_plain": fp64,
         "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "pairs": {"gather": pairs[0], "hydro": pairs[1], "gravity": pairs[2]},
+        "swept_pairs": {"gather": pairs[3], "hydro": pairs[4],
+                        "gravity": pairs[5]},
+        "tuning": tuned,
         "pass_ms": {k: round(v / n_eager, 4) for k, v in pass_ms.items()},
         "kernels": kern,
         "roofline": roofline,

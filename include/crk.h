@@ -96,6 +96,11 @@ typedef struct {
                            species (never narrower than max(r_c, 2 h_max)) */
     int32_t grid_mult;  /* persistent grid = grid_mult x CU count; 0 = one
                            workgroup per leaf (default 0)                    */
+    int32_t xcd_remap;  /* 1: with one workgroup per leaf, give each of the
+                           8 XCDs a contiguous range of leaves (default 0)   */
+    int32_t walk_mask;  /* passes whose sweep walks per-lane hit lists:
+                           bit 0 density, 1 coefficients, 2 hydro, 3 gravity
+                           (default 0)                                       */
 } crk_tuning;
 
 /* ------------------------------------------------------------------------ */
@@ -234,12 +239,13 @@ typedef struct {
 } crk_tree_info;
 int crk_tree_get_info(const crk_tree *tree, crk_tree_info *info);
 
-/* Exact numbers of in-range ordered pairs under each pass's own pair test
- * (a diagnostic for throughput accounting; synchronises):
- * totals[0]: gas pairs with r_ij < 2 h_i, i = j included (density and
- * coefficients); totals[1]: gas pairs i != j with r_ij < 2 max(h_i, h_j)
- * (hydro forces); totals[2]: pairs with 0 < r_ij < r_c (gravity). */
-int crk_count_pairs(crk_ctx *ctx, crk_tree *tree, int64_t totals[3]);
+/* Pair counts under each pass's own pair test (a diagnostic for throughput
+ * accounting; synchronises).  totals[0]: gas pairs with r_ij < 2 h_i, i = j
+ * included (density and coefficients); totals[1]: gas pairs i != j with
+ * r_ij < 2 max(h_i, h_j) (hydro forces); totals[2]: pairs with
+ * 0 < r_ij < r_c (gravity).  totals[3..5]: the (i, candidate) pairs the
+ * sweeps of those passes evaluate after culling against the leaf boxes. */
+int crk_count_pairs(crk_ctx *ctx, crk_tree *tree, int64_t totals[6]);
 
 /* Copies the tree-order permutation (caller index of each tree slot: gas
  * index, or n_gas + dm index) and the leaf table (start, count; host int64

@@ -7,8 +7,10 @@ there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from pathlib import Path
 
 import numpy as np
@@ -55,7 +57,8 @@ class crk_boxes(ctypes.Structure):
 
 class crk_tuning(ctypes.Structure):
     _fields_ = [("leaf_max", ctypes.c_int32), ("cm_factor", ctypes.c_double),
-                ("grid_mult", ctypes.c_int32)]
+                ("grid_mult", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("walk_mask", ctypes.c_int32)]
 
 
 class crk_tree_info(ctypes.Structure):
@@ -67,18 +70,29 @@ class crk_tree_info(ctypes.Structure):
 
 _lib = None
 _exiting = False
+_live_trees = weakref.WeakSet()
+_live_ctxs = weakref.WeakSet()
 
 
-def _mark_exit():
-    # native objects still alive at interpreter exit are left to the process
-    # teardown: their streams may already be gone
+def _release_all():
+    """Destroys every tree and context still alive at interpreter exit, while
+    the HIP runtime is still fully up (trees first, then contexts); native
+    teardown is skipped for anything finalised later."""
     global _exiting
+    for t in list(_live_trees):
+        try:
+            t.free()
+        except Exception:
+            pass
+    for c in list(_live_ctxs):
+        try:
+            c.close()
+        except Exception:
+            pass
     _exiting = True
 
 
-import atexit  # noqa: E402
-
-atexit.register(_mark_exit)
+atexit.register(_release_all)
 
 
 def load(path: Path | str | None = None):
@@ -170,6 +184,7 @@ class Context:
             ctypes.byref(h), CRK_FP32 if precision == "fp32" else CRK_FP64,
             ctypes.c_void_p(self.stream.cuda_stream), p))
         self.handle = h
+        _live_ctxs.add(self)
 
     def close(self):
         if getattr(self, "handle", None) and not _exiting:
@@ -182,9 +197,11 @@ class Context:
         except Exception:
             pass
 
-    def set_tuning(self, leaf_max=64, cm_factor=0.0, grid_mult=0):
+    def set_tuning(self, leaf_max=64, cm_factor=0.0, grid_mult=0, xcd_remap=0,
+                   walk_mask=0):
         check(self.lib.crk_set_tuning(self.handle, ctypes.byref(
-            crk_tuning(int(leaf_max), float(cm_factor), int(grid_mult)))))
+            crk_tuning(int(leaf_max), float(cm_factor), int(grid_mult),
+                       int(xcd_remap), int(walk_mask)))))
 
     def sync(self):
         req = ctypes.c_int64()
@@ -249,8 +266,9 @@ class Context:
             ag, ah, _ptr(dudt), xo, vo, _ptr(u)))
 
     def count_pairs(self, tree):
-        """In-range ordered pairs: (gather, hydro, gravity)."""
-        a = (ctypes.c_int64 * 3)()
+        """In-range ordered pairs (gather, hydro, gravity), then the swept
+        candidate pairs of the same three sweeps."""
+        a = (ctypes.c_int64 * 6)()
         check(self.lib.crk_count_pairs(self.handle, tree.handle, a))
         return tuple(int(v) for v in a)
 
@@ -282,6 +300,7 @@ class Tree:
     def __init__(self, ctx: Context):
         self.ctx = ctx
         self.handle = ctypes.c_void_p()
+        _live_trees.add(self)
 
     def info(self):
         i = crk_tree_info()

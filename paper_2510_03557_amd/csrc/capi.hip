@@ -163,6 +163,8 @@ int crk_ctx_create(crk_ctx **out, int precision, void *stream,
     c->tuning.leaf_max = 64;
     c->tuning.cm_factor = 0.0;
     c->tuning.grid_mult = 0;
+    c->tuning.xcd_remap = 0;
+    c->tuning.walk_mask = 0;
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount,
@@ -214,6 +216,10 @@ int crk_set_tuning(crk_ctx *ctx, const crk_tuning *t) {
         return set_error(CRK_EINVAL, "cm_factor must be 0 (auto) or in [1, 64]");
     if (t->grid_mult < 0 || t->grid_mult > 64)
         return set_error(CRK_EINVAL, "grid_mult must be in [0, 64]");
+    if (t->xcd_remap != 0 && t->xcd_remap != 1)
+        return set_error(CRK_EINVAL, "xcd_remap must be 0 or 1");
+    if (t->walk_mask < 0 || t->walk_mask > 31)
+        return set_error(CRK_EINVAL, "walk_mask must be in [0, 31]");
     if (ctx->capturing) return set_error(CRK_ESTATE, "tuning change during capture");
     ctx->tuning = *t;
     return CRK_OK;
@@ -405,7 +411,7 @@ int crk_integrate(crk_ctx *ctx, int64_t n, double dt, double *x64, double *v64,
     return integrate(ctx, n, dt, x64, v64, u64, a_grav, a_hydro, dudt, x, v, u);
 }
 
-int crk_count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[3]) {
+int crk_count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[6]) {
     CRK_TRY(check_tree_ready(ctx, t, true));
     if (!totals) return set_error(CRK_EINVAL, "null totals");
     if (ctx->capturing) return set_error(CRK_ESTATE, "count during capture");

@@ -153,6 +153,12 @@ struct crk_tree {
     crk::DevBuf g_cnt, h_cnt;          // int32 per leaf
     crk::DevBuf g_off, h_off;          // int64 per leaf + 1
     crk::DevBuf g_list, h_list;        // uint32 entries: leaf | shift << 27
+    // work queue: per-leaf cost (candidate pairs) and cost-descending order
+    crk::DevBuf g_cost, h_cost;        // int32 per leaf
+    crk::DevBuf ord_k[2], ord_v[2];    // radix-sort buffers
+    crk::DevBuf g_order, h_order;      // int32 leaf index per queue slot
+    crk::DevBuf q_counter;             // int32 queue heads (one per launch)
+    bool orders_built = false;
 
     // device: per-pass scratch (tree order)
     crk::DevBuf pf[32];                // pass fields, reused between passes
@@ -207,7 +213,7 @@ int pass_hydro(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
 int pass_gravity(crk_ctx *ctx, crk_tree *t, const void *m_gas,
                  const void *m_dm, void *ax_gas, void *ay_gas, void *az_gas,
                  void *ax_dm, void *ay_dm, void *az_dm);
-int count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[3]);
+int count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[6]);
 int integrate(crk_ctx *ctx, int64_t n, double dt, double *x64, double *v64,
               double *u64, const void *const a_grav[3],
               const void *const a_hydro[3], const void *dudt,

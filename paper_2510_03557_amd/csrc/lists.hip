@@ -29,6 +29,8 @@ __global__ __launch_bounds__(LB) void lists_kernel(
     const T *__restrict__ lhmax, const int32_t *__restrict__ bin_leaf,
     int64_t total_bins, const int *__restrict__ ncm,
     const int64_t *__restrict__ bin_base, const double *__restrict__ rc,
+    const int32_t *__restrict__ leaf_count, int32_t *__restrict__ g_cost,
+    int32_t *__restrict__ h_cost,
     int32_t *__restrict__ g_cnt, int32_t *__restrict__ h_cnt,
     const int64_t *__restrict__ g_off, const int64_t *__restrict__ h_off,
     uint32_t *__restrict__ g_list, uint32_t *__restrict__ h_list,
@@ -58,6 +60,7 @@ __global__ __launch_bounds__(LB) void lists_kernel(
     int64_t gpos = fill ? g_off[I] : 0;
     int64_t hpos = fill ? h_off[I] : 0;
     int32_t gc = 0, hc = 0;
+    int64_t gcost = 0, hcost = 0;  // candidate j particles (per lane)
     for (int ox = -1; ox <= 1; ++ox)
     for (int oy = -1; oy <= 1; ++oy)
     for (int oz = -1; oz <= 1; ++oz) {
@@ -91,6 +94,10 @@ __global__ __launch_bounds__(LB) void lists_kernel(
                         hok = d2 < Rh * Rh;
                     }
                 }
+                if (!fill) {
+                    if (gok) gcost += leaf_count[J];
+                    if (hok) hcost += leaf_count[J];
+                }
                 const uint64_t gm = __ballot(gok);
                 const uint64_t hm = __ballot(hok);
                 if (fill) {
@@ -112,10 +119,42 @@ __global__ __launch_bounds__(LB) void lists_kernel(
             }
         }
     }
-    if (!fill && lane == 0) {
-        g_cnt[I] = gc;
-        h_cnt[I] = hc;
+    if (!fill) {
+        // queue cost = i particles x candidate j particles
+        for (int off = 32; off > 0; off >>= 1) {
+            gcost += __shfl_xor(gcost, off);
+            hcost += __shfl_xor(hcost, off);
+        }
+        if (lane == 0) {
+            const int64_t ci = leaf_count[I];
+            g_cnt[I] = gc;
+            h_cnt[I] = hc;
+            g_cost[I] = (int32_t)min(ci * gcost, (int64_t)0x7FFFFFFF);
+            h_cost[I] = gasI ? (int32_t)min(ci * hcost, (int64_t)0x7FFFFFFF) : -1;
+        }
     }
+}
+
+// Queue keys: cost-descending, ties by leaf index (stable sort); slots
+// beyond the leaf count (and dm leaves for the hydro queue) sort last.
+__global__ void order_keys_kernel(const int32_t *__restrict__ cost,
+                                  const int32_t *__restrict__ nn_ptr,
+                                  int64_t cap, uint64_t *__restrict__ k,
+                                  int32_t *__restrict__ v) {
+    const int64_t nn = *nn_ptr;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = i < nn ? cost[i] : -1;
+        k[i] = c >= 0 ? (uint64_t)(0x7FFFFFFF - c) : 0xFFFFFFFFull;
+        v[i] = (int32_t)i;
+    }
+}
+
+__global__ void copy_order_kernel(const int32_t *__restrict__ a,
+                                  int32_t *__restrict__ b, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
 }
 
 template <typename T>
@@ -128,6 +167,8 @@ int lists_impl(crk_ctx *ctx, crk_tree *t) {
     int64_t *cnt64 = t->counters.as<int64_t>();
     int *err = dev_err_word(ctx);
     CRK_TRY(t->g_cnt.ensure((lcap + 1) * 4, cap));
+    CRK_TRY(t->g_cost.ensure((lcap + 1) * 4, cap));
+    CRK_TRY(t->h_cost.ensure((lcap + 1) * 4, cap));
     CRK_TRY(t->h_cnt.ensure((lcap + 1) * 4, cap));
     CRK_TRY(t->g_off.ensure((lcap + 1) * 8, cap));
     CRK_TRY(t->h_off.ensure((lcap + 1) * 8, cap));
@@ -142,7 +183,9 @@ int lists_impl(crk_ctx *ctx, crk_tree *t) {
                            t->leaf_hi.as<T>(), t->leaf_hmax.as<T>(),
                            t->bin_leaf.as<int32_t>(), t->total_bins,
                            t->d_ncm.as<int>(), t->d_bin_base.as<int64_t>(),
-                           t->d_rc.as<double>(), t->g_cnt.as<int32_t>(),
+                           t->d_rc.as<double>(), t->nd_count[cur].as<int32_t>(),
+                           t->g_cost.as<int32_t>(), t->h_cost.as<int32_t>(),
+                           t->g_cnt.as<int32_t>(),
                            t->h_cnt.as<int32_t>(), t->g_off.as<int64_t>(),
                            t->h_off.as<int64_t>(), t->g_list.as<uint32_t>(),
                            t->h_list.as<uint32_t>(), t->grav_cap, t->hydro_cap,
@@ -173,6 +216,36 @@ int lists_impl(crk_ctx *ctx, crk_tree *t) {
         }
     }
     CRK_TRY(launch(1));
+    // cost-ordered work queues for the persistent pass kernels
+    t->orders_built = false;
+    if (ctx->tuning.grid_mult > 0) {
+        const int64_t m = lcap + 1;
+        for (int i = 0; i < 2; ++i) {
+            CRK_TRY(t->ord_k[i].ensure(m * 8, cap));
+            CRK_TRY(t->ord_v[i].ensure(m * 4, cap));
+        }
+        CRK_TRY(t->g_order.ensure(m * 4, cap));
+        CRK_TRY(t->h_order.ensure(m * 4, cap));
+        CRK_TRY(t->q_counter.ensure(64, cap));
+        CRK_TRY(ctx->scratch.ensure(radix_tmp_bytes(m), cap));
+        uint64_t *K[2] = {t->ord_k[0].as<uint64_t>(), t->ord_k[1].as<uint64_t>()};
+        int32_t *V[2] = {t->ord_v[0].as<int32_t>(), t->ord_v[1].as<int32_t>()};
+        const unsigned g = (unsigned)std::min<int64_t>((m + 255) / 256, 65536);
+        for (int h = 0; h < 2; ++h) {
+            hipLaunchKernelGGL(order_keys_kernel, dim3(g), dim3(256), 0, s,
+                               h ? t->h_cost.as<int32_t>() : t->g_cost.as<int32_t>(),
+                               cnt + C_NN, m, K[0], V[0]);
+            CRK_HIP(hipGetLastError());
+            hipError_t he;
+            int r = radix_sort_u64_i32(K, V, m, 32, ctx->scratch.p, s, &he);
+            CRK_HIP(he);
+            hipLaunchKernelGGL(copy_order_kernel, dim3(g), dim3(256), 0, s, V[r],
+                               h ? t->h_order.as<int32_t>() : t->g_order.as<int32_t>(),
+                               m);
+            CRK_HIP(hipGetLastError());
+        }
+        t->orders_built = true;
+    }
     t->lists_built = true;
     return CRK_OK;
 }

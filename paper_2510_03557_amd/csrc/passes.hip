@@ -102,6 +102,8 @@ template <typename T> struct TreeView {
     const T *px, *py, *pz, *h;
     const T *lo, *hi, *hmax;  // leaf boxes (3 planes of lcap) and h_max
     int64_t lcap;
+    int xcd_remap;            // map blocks to contiguous leaf ranges per XCD
+    int walk_mask;            // passes (bit P::ID) that use the hit walk
     const double *rc, *eps;
     int64_t n_gas;
 };
@@ -124,20 +126,17 @@ __device__ inline void decode_shift(uint32_t code, int &sx, int &sy, int &sz) {
 //
 // Every j particle of a listed j-leaf is first tested against the i-leaf's
 // bounding box widened by the pair range; survivors are compacted (ballot +
-// prefix) into an LDS buffer of 2*BLOCK candidates that spans several
+// prefix) into an LDS buffer of CAPF*BLOCK candidates that spans several
 // j-leaves.  A full buffer is swept by every lane and its partial sums are
 // folded into the compensated totals.  Culled particles are out of range of
 // every i, so the sums do not change beyond rounding order.
 template <typename T, typename P, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
-                                                     const typename P::Args pa) {
-    constexpr int CAP = 2 * BLOCK;
+__device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
+                                             const typename P::Args &pa,
+                                             const int I, T *sj, int *sjid,
+                                             int *wcnt, uint32_t *smask) {
+    constexpr int CAP = P::CAPF * BLOCK;
     constexpr int NW = BLOCK / 64;
-    __shared__ __attribute__((aligned(16))) T sj[CAP * P::NJ];
-    __shared__ int sjid[CAP];
-    __shared__ int wcnt[NW];
-    const int I = (int)blockIdx.x;
-    if (I >= *tv.n_items) return;
     const int st = tv.leaf_start[I];
     // a leaf above BLOCK exists only after a capacity error (already
     // latched); clamping keeps every access inside the LDS buffer
@@ -168,9 +167,59 @@ __global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
     const int64_t e1 = min(tv.list_off[I + 1], tv.list_cap);
     const int nl = *tv.n_leaves;
     int nbuf = 0;
+    // Sweep of a full buffer.  Broadcast form: every lane evaluates every
+    // candidate (LDS broadcast reads); the pair function applies the exact
+    // range test and the wave skips the arithmetic when no lane is in range.
+    // Walk form (for passes in tv.walk_mask): every lane first tests all
+    // candidates against its own particle and stores a hit bitmask in LDS,
+    // then walks its own hits in candidate order with per-lane reads, so the
+    // pair arithmetic runs only for in-range pairs; the wave loops while any
+    // lane has hits left.  Buffers where hits are dense (at least a quarter
+    // of lane x candidate pairs) use the broadcast form.  Every lane meets
+    // its hits in candidate order either way, so the sums are the same.
+    constexpr int NWORDS = CAP / 32;
+    const int lanes = __popcll(__ballot(act));  // active lanes of this wave
+    const bool walk = (tv.walk_mask >> P::ID) & 1;
     auto sweep = [&](int n) {
         __syncthreads();
-        if (act) {
+        bool broadcast = true;
+        if (walk && n > 0) {
+            const int nw = (n + 31) / 32;
+            int hits = 0;
+            for (int w = 0; w < nw; ++w) {
+                uint32_t bits = 0;
+                for (int b = 0; b < 32; ++b) {
+                    const int k = w * 32 + b;
+                    if (k >= n) break;
+                    const bool hit =
+                        act && P::test(is, &sj[k * P::NJ], sjid[k] == i);
+                    bits |= (uint32_t)hit << b;
+                }
+                smask[w * BLOCK + t] = bits;
+                hits += __popc(bits);
+            }
+            int tot = hits;  // wave total (all lanes converged here)
+            for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+            broadcast = 4 * tot >= lanes * n;
+            if (!broadcast) {
+                int w = 0;
+                uint32_t mm = smask[t];
+                while (true) {
+                    while (mm == 0u && w + 1 < nw) {
+                        ++w;
+                        mm = smask[w * BLOCK + t];
+                    }
+                    const bool has = mm != 0u;
+                    if (!__any(has)) break;
+                    if (has) {
+                        const int k = w * 32 + __ffs(mm) - 1;
+                        mm &= mm - 1u;
+                        P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+                    }
+                }
+            }
+        }
+        if (broadcast && act) {
             for (int k = 0; k < n; ++k)
                 P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
         }
@@ -227,6 +276,57 @@ __global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
     if (act) P::finish(acc, is, pa, tv, i);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X, each
+// with its own L2.  Remapping block b (on XCD b % 8) to a contiguous range
+// of leaves per XCD keeps spatial neighbours -- which share j-leaves -- in
+// the same L2.  A bijection of [0, G) for any G.
+__device__ inline int xcd_block(int b, int G) {
+    constexpr int NX = 8;
+    const int q = G / NX, r = G % NX;
+    const int x = b % NX, k = b / NX;
+    return x * q + min(x, r) + k;
+}
+
+// One workgroup per leaf (leaf order remapped per XCD).
+template <typename T, typename P, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
+                                                     const typename P::Args pa) {
+    __shared__ __attribute__((aligned(16))) T sj[P::CAPF * BLOCK * P::NJ];
+    __shared__ int sjid[P::CAPF * BLOCK];
+    __shared__ int wcnt[BLOCK / 64];
+    __shared__ uint32_t smask[P::CAPF * BLOCK / 32 * BLOCK];
+    // the grid may exceed the device-side leaf count (graph capture sizes it
+    // by capacity): surplus blocks leave first, the remap covers [0, n)
+    const int n_items = *tv.n_items;
+    if ((int)blockIdx.x >= n_items) return;
+    const int I = tv.xcd_remap ? xcd_block(blockIdx.x, n_items) : (int)blockIdx.x;
+    process_leaf<T, P, BLOCK>(tv, pa, I, sj, sjid, wcnt, smask);
+}
+
+// Persistent grid: each workgroup pops queue slots from an atomic counter
+// (reset to 0 before the launch) until the queue is exhausted; the queue
+// lists the leaves by decreasing cost, so the longest items start first.
+// Every workgroup leaves the loop once the counter passes the item count.
+template <typename T, typename P, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void pair_kernel_queue(
+    const TreeView<T> tv, const typename P::Args pa,
+    const int32_t *__restrict__ order, int *__restrict__ head) {
+    __shared__ __attribute__((aligned(16))) T sj[P::CAPF * BLOCK * P::NJ];
+    __shared__ int sjid[P::CAPF * BLOCK];
+    __shared__ int wcnt[BLOCK / 64];
+    __shared__ uint32_t smask[P::CAPF * BLOCK / 32 * BLOCK];
+    __shared__ int slot;
+    const int n_items = *tv.n_items;
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) slot = atomicAdd(head, 1);
+        __syncthreads();
+        const int q = slot;
+        if (q >= n_items) break;
+        process_leaf<T, P, BLOCK>(tv, pa, order[q], sj, sjid, wcnt, smask);
+    }
+}
+
 // widened pair ranges (relative 1e-5 above the exact test, so that every
 // pair a float32 test accepts survives the culling)
 template <typename T> __device__ inline T widen(double r) {
@@ -243,6 +343,8 @@ template <typename T> struct DensityPass {
         T *V, *rho_t;     // caller order
     };
     static constexpr int NJ = 4;  // fx, fy, fz, m
+    static constexpr int CAPF = 4;  // candidate buffer = CAPF * BLOCK
+    static constexpr int ID = 0;    // bit in the walk mask
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
         return widen<T>(2.0 * (double)hI);
     }
@@ -272,6 +374,10 @@ template <typename T> struct DensityPass {
         d[1] = fy;
         d[2] = fz;
         d[3] = a.m[j];
+    }
+    __device__ static bool test(const I &is, const T *jd, bool) {
+        const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
+        return (dx * dx + dy * dy + dz * dz) * is.ih2 < T(4);
     }
     __device__ static void pair(Tile &tl, const I &is, const T *jd, bool) {
         const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
@@ -317,6 +423,8 @@ template <typename T> struct CoeffPass {
         double gamma;
     };
     static constexpr int NJ = 8;  // fx fy fz V m + pad
+    static constexpr int CAPF = 4;
+    static constexpr int ID = 1;
     static constexpr int NS = 33;
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
         return widen<T>(2.0 * (double)hI);
@@ -355,6 +463,12 @@ template <typename T> struct CoeffPass {
         d[5] = T(0);
         d[6] = T(0);
         d[7] = T(0);
+    }
+    __device__ static bool test(const I &is, const T *jd, bool) {
+        const T u0 = (is.ex - jd[0]) * is.ih;
+        const T u1 = (is.ey - jd[1]) * is.ih;
+        const T u2 = (is.ez - jd[2]) * is.ih;
+        return u0 * u0 + u1 * u1 + u2 * u2 < T(4);
     }
     __device__ static void pair(Tile &tl, const I &is, const T *jd, bool) {
         const T u0 = (is.ex - jd[0]) * is.ih;
@@ -519,7 +633,10 @@ template <typename T> struct HydroPass {
         const T *m;       // tree order
         T Cl, Cq, epsQ;
     };
-    static constexpr int NJ = 32;  // fx fy fz + HF fields + pad
+    static constexpr int NJ = 36;  // fx fy fz + HF fields + pad (stride
+                                   // 36 spreads per-lane reads over banks)
+    static constexpr int CAPF = 1;
+    static constexpr int ID = 2;
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T hJ) {
         return widen<T>(2.0 * (double)(hI > hJ ? hI : hJ));
     }
@@ -555,7 +672,6 @@ template <typename T> struct HydroPass {
         d[2] = fz;
 #pragma unroll
         for (int k = 0; k < HF; ++k) d[3 + k] = a.f[k * a.n_gas + j];
-        d[31] = T(0);
     }
     // gradient of the corrected kernel of particle with fields f at y
     __device__ static void grad_rk(const T *f, T y0, T y1, T y2, T r2, T out[3],
@@ -574,6 +690,11 @@ template <typename T> struct HydroPass {
             const T dby = f[14 + 3 * g] * y0 + f[15 + 3 * g] * y1 + f[16 + 3 * g] * y2;
             out[g] = by1 * fma(f[5 + g], w, c1 * y[g]) + w * (dby + f[11 + g]);
         }
+    }
+    __device__ static bool test(const I &is, const T *jd, bool self) {
+        const T x0 = is.ex - jd[0], x1 = is.ey - jd[1], x2 = is.ez - jd[2];
+        const T r2 = x0 * x0 + x1 * x1 + x2 * x2;
+        return !self && ((r2 * is.f[3] < T(4)) || (r2 * jd[6] < T(4)));
     }
     __device__ static void pair(Tile &tl, const I &is, const T *jd, bool self) {
         const T x0 = is.ex - jd[0], x1 = is.ey - jd[1], x2 = is.ez - jd[2];
@@ -633,6 +754,8 @@ template <typename T> struct GravityPass {
         int64_t n_gas;
     };
     static constexpr int NJ = 4;  // fx fy fz Gm
+    static constexpr int CAPF = 4;
+    static constexpr int ID = 3;
     __device__ static T range(const Args &, const TreeView<T> &tv, int box, T, T) {
         return widen<T>(tv.rc[box]);
     }
@@ -666,6 +789,11 @@ template <typename T> struct GravityPass {
         d[1] = fy;
         d[2] = fz;
         d[3] = a.m[j];
+    }
+    __device__ static bool test(const I &is, const T *jd, bool) {
+        const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        return (r2 > T(0)) && (r2 < is.rc2);
     }
     __device__ static void pair(Tile &tl, const I &is, const T *jd, bool) {
         const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
@@ -721,16 +849,21 @@ template <typename T> struct GravityPass {
 // mode 0: gas j with r < 2 h_i, j = i included (density, coefficients)
 // mode 1: gas j != i with r < 2 max(h_i, h_j)          (hydro forces)
 // mode 2: any j with 0 < r < r_c                      (gravity)
+// modes 3, 4, 5: every (i, candidate) pair the sweeps of modes 0, 1, 2
+// evaluate after culling (the work the pair kernels actually issue)
 template <typename T> struct CountPass {
     struct Args {
         int mode;
         int32_t *counts;  // tree order
     };
     static constexpr int NJ = 4;  // fx fy fz 1/h^2
+    static constexpr int CAPF = 4;
+    static constexpr int ID = 4;
     __device__ static T range(const Args &a, const TreeView<T> &tv, int box, T hI,
                               T hJ) {
-        if (a.mode == 2) return widen<T>(tv.rc[box]);
-        if (a.mode == 1) return widen<T>(2.0 * (double)(hI > hJ ? hI : hJ));
+        const int m = a.mode % 3;
+        if (m == 2) return widen<T>(tv.rc[box]);
+        if (m == 1) return widen<T>(2.0 * (double)(hI > hJ ? hI : hJ));
         return widen<T>(2.0 * (double)hI);
     }
     struct I {
@@ -755,7 +888,7 @@ template <typename T> struct CountPass {
         is.ey = ey;
         is.ez = ez;
         const T h = tv.h[i];
-        is.ih2 = a.mode == 2 ? T(0) : T(1) / (h * h);
+        is.ih2 = a.mode % 3 == 2 ? T(0) : T(1) / (h * h);
         const double rc = tv.rc[box];
         is.rc2 = (T)(rc * rc);
         is.mode = a.mode;
@@ -766,16 +899,17 @@ template <typename T> struct CountPass {
         d[1] = fy;
         d[2] = fz;
         const T h = tv.h[j];
-        d[3] = a.mode == 1 ? T(1) / (h * h) : T(0);
+        d[3] = a.mode % 3 == 1 ? T(1) / (h * h) : T(0);
     }
-    __device__ static void pair(Tile &tl, const I &is, const T *jd, bool self) {
+    __device__ static bool test(const I &is, const T *jd, bool self) {
         const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
         const T r2 = dx * dx + dy * dy + dz * dz;
-        bool in;
-        if (is.mode == 0) in = r2 * is.ih2 < T(4);
-        else if (is.mode == 1) in = !self && (r2 * is.ih2 < T(4) || r2 * jd[3] < T(4));
-        else in = r2 > T(0) && r2 < is.rc2;
-        tl.c += in ? 1 : 0;
+        if (is.mode == 0) return r2 * is.ih2 < T(4);
+        if (is.mode == 1) return !self && (r2 * is.ih2 < T(4) || r2 * jd[3] < T(4));
+        return r2 > T(0) && r2 < is.rc2;
+    }
+    __device__ static void pair(Tile &tl, const I &is, const T *jd, bool self) {
+        tl.c += (is.mode >= 3 || test(is, jd, self)) ? 1 : 0;
     }
     __device__ static void finish(const Acc &ac, const I &, const Args &a,
                                   const TreeView<T> &, int i) {
@@ -893,6 +1027,8 @@ TreeView<T> tree_view(crk_tree *t, bool hydro, const int32_t *n_items) {
     tv.hi = t->leaf_hi.as<T>();
     tv.hmax = t->leaf_hmax.as<T>();
     tv.lcap = t->leaf_cap;
+    tv.xcd_remap = t->owner->tuning.xcd_remap;
+    tv.walk_mask = t->owner->tuning.walk_mask;
     tv.rc = t->d_rc.as<double>();
     tv.eps = t->d_eps.as<double>();
     tv.n_gas = t->n_gas;
@@ -901,20 +1037,39 @@ TreeView<T> tree_view(crk_tree *t, bool hydro, const int32_t *n_items) {
 
 template <typename T, typename P>
 int launch_pair(crk_ctx *ctx, crk_tree *t, const TreeView<T> &tv,
-                const typename P::Args &pa, int64_t n_items_bound, int pass) {
+                const typename P::Args &pa, int64_t n_items_bound, int pass,
+                bool gas_queue) {
     const int L = t->leaf_max;
-    const unsigned grid = (unsigned)std::max<int64_t>(1, n_items_bound);
     hipEvent_t ev = nullptr;
+    const bool queue = ctx->tuning.grid_mult > 0 && t->orders_built;
+    int *head = nullptr;
+    const int32_t *order = nullptr;
+    unsigned grid = (unsigned)std::max<int64_t>(1, n_items_bound);
+    if (queue) {
+        // one queue head per launch slot so consecutive passes never share
+        head = t->q_counter.as<int>() + (pass >= 0 ? pass : 15);
+        order = gas_queue ? t->h_order.as<int32_t>() : t->g_order.as<int32_t>();
+        CRK_HIP(fill_i32(head, 0, 1, ctx->stream));
+        grid = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>(n_items_bound,
+                                 (int64_t)ctx->tuning.grid_mult * ctx->n_cu));
+    }
     if (pass >= 0) span_begin(ctx, pass, true, &ev);
-    if (L <= 64)
-        hipLaunchKernelGGL((pair_kernel<T, P, 64>), dim3(grid), dim3(64), 0,
+#define CRK_LAUNCH_PAIR(B)                                                      \
+    if (queue)                                                                  \
+        hipLaunchKernelGGL((pair_kernel_queue<T, P, B>), dim3(grid), dim3(B), 0, \
+                           ctx->stream, tv, pa, order, head);                   \
+    else                                                                        \
+        hipLaunchKernelGGL((pair_kernel<T, P, B>), dim3(grid), dim3(B), 0,      \
                            ctx->stream, tv, pa);
-    else if (L <= 128)
-        hipLaunchKernelGGL((pair_kernel<T, P, 128>), dim3(grid), dim3(128), 0,
-                           ctx->stream, tv, pa);
-    else
-        hipLaunchKernelGGL((pair_kernel<T, P, 256>), dim3(grid), dim3(256), 0,
-                           ctx->stream, tv, pa);
+    if (L <= 64) {
+        CRK_LAUNCH_PAIR(64)
+    } else if (L <= 128) {
+        CRK_LAUNCH_PAIR(128)
+    } else {
+        CRK_LAUNCH_PAIR(256)
+    }
+#undef CRK_LAUNCH_PAIR
     if (pass >= 0) span_end(ctx, pass, true, ev);
     CRK_HIP(hipGetLastError());
     return CRK_OK;
@@ -947,7 +1102,7 @@ int density_impl(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
     typename DensityPass<T>::Args pa{mt, static_cast<T *>(V),
                                      static_cast<T *>(rho_t)};
     return launch_pair<T, DensityPass<T>>(ctx, t, tree_view<T>(t, true, gas_leaf_count(t)),
-                                          pa, gas_bound(ctx, t), P_DENSITY);
+                                          pa, gas_bound(ctx, t), P_DENSITY, true);
 }
 
 template <typename T>
@@ -972,7 +1127,7 @@ int coeff_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *V,
                                    static_cast<T *>(rho), static_cast<T *>(P),
                                    static_cast<T *>(cs), ng, ctx->params.gamma};
     return launch_pair<T, CoeffPass<T>>(ctx, t, tree_view<T>(t, true, gas_leaf_count(t)),
-                                        pa, gas_bound(ctx, t), P_COEFF);
+                                        pa, gas_bound(ctx, t), P_COEFF, true);
 }
 
 template <typename T>
@@ -1002,7 +1157,7 @@ int hydro_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                                    (T)ctx->params.Cl, (T)ctx->params.Cq,
                                    (T)ctx->params.epsQ};
     return launch_pair<T, HydroPass<T>>(ctx, t, tree_view<T>(t, true, gas_leaf_count(t)),
-                                        pa, gas_bound(ctx, t), P_HYDRO);
+                                        pa, gas_bound(ctx, t), P_HYDRO, true);
 }
 
 template <typename T>
@@ -1023,33 +1178,32 @@ int gravity_impl(crk_ctx *ctx, crk_tree *t, const void *mg, const void *md,
                                      static_cast<T *>(ayd), static_cast<T *>(azd),
                                      t->n_gas};
     return launch_pair<T, GravityPass<T>>(ctx, t, tree_view<T>(t, false, all_leaf_count(t)),
-                                          pa, all_bound(ctx, t), P_GRAV);
+                                          pa, all_bound(ctx, t), P_GRAV, false);
 }
 
 template <typename T>
-int count_impl(crk_ctx *ctx, crk_tree *t, int64_t totals[3]) {
+int count_impl(crk_ctx *ctx, crk_tree *t, int64_t totals[6]) {
     const int64_t n = t->n;
     CRK_TRY(t->pf[9].ensure(std::max<int64_t>(n, 1) * 4, ctx->capturing));
     int32_t *cnt = t->pf[9].as<int32_t>();
     unsigned long long *tot =
         reinterpret_cast<unsigned long long *>(t->counters.as<int64_t>() + 16);
-    CRK_HIP(fill_i64(reinterpret_cast<int64_t *>(tot), 0, 3, ctx->stream));
-    for (int mode = 0; mode < 3; ++mode) {
-        const bool gas = mode < 2;
+    CRK_HIP(fill_i64(reinterpret_cast<int64_t *>(tot), 0, 6, ctx->stream));
+    for (int mode = 0; mode < 6; ++mode) {
+        const bool gas = mode % 3 < 2;
         CRK_HIP(fill_i32(cnt, 0, n, ctx->stream));
         typename CountPass<T>::Args pa{mode, cnt};
         CRK_TRY((launch_pair<T, CountPass<T>>(
-            ctx, t, tree_view<T>(t, mode == 1 || mode == 0, gas ? gas_leaf_count(t)
-                                                            : all_leaf_count(t)),
-            pa, gas ? gas_bound(ctx, t) : all_bound(ctx, t), -1)));
+            ctx, t, tree_view<T>(t, gas, gas ? gas_leaf_count(t) : all_leaf_count(t)),
+            pa, gas ? gas_bound(ctx, t) : all_bound(ctx, t), -1, gas)));
         hipLaunchKernelGGL(sum_counts_kernel, dim3(256), dim3(256), 0, ctx->stream,
                            cnt, gas ? t->n_gas : n, tot + mode);
         CRK_HIP(hipGetLastError());
     }
     int64_t *hb = ctx->err_host.as<int64_t>() + 16;
-    CRK_HIP(hipMemcpyAsync(hb, tot, 24, hipMemcpyDeviceToHost, ctx->stream));
+    CRK_HIP(hipMemcpyAsync(hb, tot, 48, hipMemcpyDeviceToHost, ctx->stream));
     CRK_HIP(hipStreamSynchronize(ctx->stream));
-    for (int k = 0; k < 3; ++k) totals[k] = hb[k];
+    for (int k = 0; k < 6; ++k) totals[k] = hb[k];
     return CRK_OK;
 }
 
@@ -1081,7 +1235,7 @@ int pass_hydro(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                              gradB, ax, ay, az, dudt);
 }
 
-int count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[3]) {
+int count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[6]) {
     if (ctx->precision == CRK_FP64) return count_impl<double>(ctx, t, totals);
     return count_impl<float>(ctx, t, totals);
 }

@@ -311,14 +311,17 @@ def test_capacity_overflow_in_graph_is_reported(step_cls):
     print("case graph capacity overflow", flush=True)
     wl = W.random_uniform(3000, 2000, 1101, n_ngb=48.0, h_spread=0.15)
     st = step_cls(wl, precision="fp32")
-    st.capture(integrate=False)
-    # clustering the particles after capture needs longer lists and deeper
-    # k-d trees than the captured capacities
-    g = wl.gas
-    st.set_inputs(gx=np.full(g.n, 1.5, np.float32) + np.float32(1e-4) *
-                  np.arange(g.n, dtype=np.float32) / g.n)
-    st.replay()
-    with pytest.raises(CrkError) as e:
-        st.sync()
-    assert e.value.status == CRK_ECAPACITY
-    st.close()
+    try:
+        st.capture(integrate=False)
+        # gathering all gas into one tiny region after capture needs deeper
+        # k-d trees and longer lists than the captured capacities
+        g = wl.gas
+        blob = (np.float32(1.5) + np.float32(1e-4) *
+                np.arange(g.n, dtype=np.float32) / g.n).astype(np.float32)
+        st.set_inputs(gx=blob, gy=blob[::-1].copy(), gz=blob)
+        st.replay()
+        with pytest.raises(CrkError) as e:
+            st.sync()
+        assert e.value.status == CRK_ECAPACITY
+    finally:
+        st.close()
