@@ -904,12 +904,13 @@ template <typename T> struct CountPass {
     __device__ static bool test(const I &is, const T *jd, bool self) {
         const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
         const T r2 = dx * dx + dy * dy + dz * dz;
+        if (is.mode >= 3) return true;  // swept pairs: every candidate
         if (is.mode == 0) return r2 * is.ih2 < T(4);
         if (is.mode == 1) return !self && (r2 * is.ih2 < T(4) || r2 * jd[3] < T(4));
         return r2 > T(0) && r2 < is.rc2;
     }
     __device__ static void pair(Tile &tl, const I &is, const T *jd, bool self) {
-        tl.c += (is.mode >= 3 || test(is, jd, self)) ? 1 : 0;
+        tl.c += test(is, jd, self) ? 1 : 0;
     }
     __device__ static void finish(const Acc &ac, const I &, const Args &a,
                                   const TreeView<T> &, int i) {
