@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--grid-mult", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--walk-mask", type=int, default=0)
+    ap.add_argument("--sub-sweep", type=int, default=0)
+    ap.add_argument("--tree-lds", type=int, default=1)
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--dt", type=float, default=1e-5)
@@ -129,7 +131,8 @@ def main():
     wl = workloads.make(args.workload)
     n = wl.n_total
     tuning = dict(leaf_max=args.leaf_max, grid_mult=args.grid_mult,
-                  xcd_remap=args.xcd_remap, walk_mask=args.walk_mask)
+                  xcd_remap=args.xcd_remap, walk_mask=args.walk_mask,
+                  sub_sweep=args.sub_sweep, tree_lds=args.tree_lds)
 
     # ---------------- float32 path: graph replay of the whole step ---------
     st = ShortRangeStep(wl, precision="fp32", tuning=tuning, dt=args.dt)
@@ -227,7 +230,9 @@ def main():
                    "leaf_max": tuning["leaf_max"],
                    "grid_mult": tuning["grid_mult"],
                    "xcd_remap": tuning.get("xcd_remap", 0),
-                   "walk_mask": tuning.get("walk_mask", 0), "launch": "hip_graph",
+                   "walk_mask": tuning.get("walk_mask", 0),
+                   "sub_sweep": tuning.get("sub_sweep", 0),
+                   "tree_lds": tuning.get("tree_lds", 1), "launch": "hip_graph",
                    "leaves": info["n_leaves"],
                    "list_entries": {"gravity": info["grav_entries"],
                                     "hydro": info["hydro_entries"]}},

@@ -99,8 +99,20 @@ typedef struct {
     int32_t xcd_remap;  /* 1: with one workgroup per leaf, give each of the
                            8 XCDs a contiguous range of leaves (default 0)   */
     int32_t walk_mask;  /* passes whose sweep walks per-lane hit lists:
-                           bit 0 density, 1 coefficients, 2 hydro, 3 gravity
-                           (default 0)                                       */
+                           bit 0 density, 1 coefficients, 2 hydro, 3 gravity;
+                           one workgroup per leaf of <= 64 only (default 0) */
+    int32_t sub_sweep;  /* sub-leaf sweeps (leaf_max <= 64, one workgroup per
+                           leaf): the tree splits every leaf into <= 4
+                           sub-leaves of <= 16, reordering the leaf's slots;
+                           1: each 16-lane group sweeps only the candidates
+                           near its sub-leaf; 2: one wavefront per sub-leaf,
+                           culled against the sub-leaf box, four lanes per
+                           particle; 0: whole-leaf sweep (default 0)        */
+    int32_t tree_lds;   /* 1: after one sort by bin, sort every bin along the
+                           three axes and run its k-d levels in LDS (bins of
+                           up to 4096 particles; larger bins fall back to
+                           the per-axis global sorts); 0: always the global
+                           sorts.  Both give the same tree (default 1)      */
 } crk_tuning;
 
 /* ------------------------------------------------------------------------ */

@@ -147,7 +147,17 @@ struct crk_tree {
     crk::DevBuf leaf_hmax;             // T
     crk::DevBuf bin_leaf;              // int32 [2*total_bins + 1]
     crk::DevBuf bin_cnt;               // int32 [2*total_bins + 1]
+    // sub-leaves: every leaf of <= 64 particles is split by up to two more
+    // k-d levels into <= 4 sub-leaves of <= 16 (slots 4*leaf + k)
+    bool has_sub = false;
+    crk::DevBuf sub_nsub;              // int32 per leaf
+    crk::DevBuf sub_start, sub_count;  // int32 per slot
+    crk::DevBuf sub_lo, sub_hi;        // T [3][4*leaf_cap]
+    crk::DevBuf sub_hmax;              // T per slot
     int cur_nodes = 0;                 // which node buffer holds the leaves
+    bool lds_tree = false;             // last eager build used the per-bin
+                                       // LDS build (captures follow it)
+    int32_t seg_size = 64;             // padded segment size of that build
 
     // device: interaction lists
     crk::DevBuf g_cnt, h_cnt;          // int32 per leaf
@@ -230,7 +240,7 @@ inline long long *dev_required(crk_ctx *ctx) {
 }
 
 // int32 counters of the tree build (tree->counters)
-enum { C_NN = 0, C_NN_NEXT = 1, C_ANY = 2 };
+enum { C_NN = 0, C_NN_NEXT = 1, C_ANY = 2, C_MAXC = 3 };
 // int64 counters of the list build (tree->counters, int64 view from 8)
 enum { C64_GTOT = 8, C64_HTOT = 9 };
 

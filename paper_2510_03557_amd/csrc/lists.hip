@@ -1,7 +1,8 @@
 // build_interaction_lists: leaf-leaf interaction lists (Sec. IV-B.1).
 //
-// One wavefront per i-leaf walks the 27 chaining-mesh bins around the
-// leaf's bin (own box, periodic images), and tests the bounding box of every
+// One wavefront per i-leaf takes the leaves of the 27 chaining-mesh bins
+// around the leaf's bin (own box, periodic images), both species, as one
+// flattened candidate sequence, and tests the bounding box of every
 // candidate leaf against its own in double precision.  Accepted leaves are
 // compacted with a ballot, so each list is in a fixed order (stencil order,
 // species, leaf index) independent of scheduling.  Two passes: count, then
@@ -25,7 +26,7 @@ template <typename T>
 __global__ __launch_bounds__(LB) void lists_kernel(
     int fill, const int32_t *__restrict__ nn_ptr, int64_t cap,
     const int32_t *__restrict__ leaf_key, const int32_t *__restrict__ leaf_box,
-    const T *__restrict__ lo, const T *__restrict__ hi,
+    const T *__restrict__ lo_, const T *__restrict__ hi_,
     const T *__restrict__ lhmax, const int32_t *__restrict__ bin_leaf,
     int64_t total_bins, const int *__restrict__ ncm,
     const int64_t *__restrict__ bin_base, const double *__restrict__ rc,
@@ -51,8 +52,8 @@ __global__ __launch_bounds__(LB) void lists_kernel(
     const int cz = (int)(lb % nc);
     double loI[3], hiI[3];
     for (int a = 0; a < 3; ++a) {
-        loI[a] = (double)lo[a * cap + I];
-        hiI[a] = (double)hi[a * cap + I];
+        loI[a] = (double)lo_[a * cap + I];
+        hiI[a] = (double)hi_[a * cap + I];
     }
     const double hmI = (double)lhmax[I];
     const double Rg = rc[b] * RANGE_WIDEN;
@@ -61,63 +62,90 @@ __global__ __launch_bounds__(LB) void lists_kernel(
     int64_t hpos = fill ? h_off[I] : 0;
     int32_t gc = 0, hc = 0;
     int64_t gcost = 0, hcost = 0;  // candidate j particles (per lane)
-    for (int ox = -1; ox <= 1; ++ox)
-    for (int oy = -1; oy <= 1; ++oy)
-    for (int oz = -1; oz <= 1; ++oz) {
+    // The 54 candidate ranges (27 stencil bins x 2 species, stencil order,
+    // species inner) are flattened: lane q2 < 54 computes range q2, a wave
+    // prefix sum gives their offsets, and every lane then takes candidates
+    // c = lane, lane + 64, ... in that flattened order.
+    int r0 = 0, rlen = 0;
+    uint32_t rcode = 0;
+    if (lane < 54) {
+        const int q = lane >> 1, sp = lane & 1;
+        const int ox = q / 9 - 1, oy = (q / 3) % 3 - 1, oz = q % 3 - 1;
         int nx = cx + ox, ny = cy + oy, nz = cz + oz;
         int sx = 0, sy = 0, sz = 0;
         if (nx < 0) { nx += nc; sx = -1; } else if (nx >= nc) { nx -= nc; sx = 1; }
         if (ny < 0) { ny += nc; sy = -1; } else if (ny >= nc) { ny -= nc; sy = 1; }
         if (nz < 0) { nz += nc; sz = -1; } else if (nz >= nc) { nz -= nc; sz = 1; }
         const int64_t ngbin = bin_base[b] + ((int64_t)nx * nc + ny) * nc + nz;
-        const uint32_t code = (uint32_t)((sx + 1) * 9 + (sy + 1) * 3 + (sz + 1));
-        const double S[3] = {(double)sx, (double)sy, (double)sz};
-        for (int sp = 0; sp < 2; ++sp) {
-            const int64_t k = sp * total_bins + ngbin;
-            const int r0 = bin_leaf[k], r1 = bin_leaf[k + 1];
-            for (int base = r0; base < r1; base += 64) {
-                const int J = base + lane;
-                const bool valid = J < r1;
-                bool gok = false, hok = false;
-                if (valid) {
-                    double d2 = 0.0;
-                    for (int a = 0; a < 3; ++a) {
-                        double l = (double)lo[a * cap + J] + S[a];
-                        double h = (double)hi[a * cap + J] + S[a];
-                        double g = fmax(0.0, fmax(l - hiI[a], loI[a] - h));
-                        d2 += g * g;
-                    }
-                    gok = d2 < Rg2;
-                    if (gasI && sp == 0) {
-                        double hm = fmax(hmI, (double)lhmax[J]);
-                        double Rh = 2.0 * hm * RANGE_WIDEN;
-                        hok = d2 < Rh * Rh;
-                    }
-                }
-                if (!fill) {
-                    if (gok) gcost += leaf_count[J];
-                    if (hok) hcost += leaf_count[J];
-                }
-                const uint64_t gm = __ballot(gok);
-                const uint64_t hm = __ballot(hok);
-                if (fill) {
-                    if (gok) {
-                        int64_t p = gpos + __popcll(gm & lt_mask);
-                        if (p < g_cap) g_list[p] = (uint32_t)J | (code << LIST_LEAF_BITS);
-                        else atomicOr(err, DEV_ERR_CAPACITY);
-                    }
-                    if (hok) {
-                        int64_t p = hpos + __popcll(hm & lt_mask);
-                        if (p < h_cap) h_list[p] = (uint32_t)J | (code << LIST_LEAF_BITS);
-                        else atomicOr(err, DEV_ERR_CAPACITY);
-                    }
-                }
-                gpos += __popcll(gm);
-                hpos += __popcll(hm);
-                gc += __popcll(gm);
-                hc += __popcll(hm);
+        const int64_t k = sp * total_bins + ngbin;
+        r0 = bin_leaf[k];
+        rlen = bin_leaf[k + 1] - r0;
+        rcode = (uint32_t)((sx + 1) * 9 + (sy + 1) * 3 + (sz + 1)) | ((uint32_t)sp << 8);
+    }
+    // inclusive scan of the range lengths across the wave
+    int incl = rlen;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+    }
+    const int total = __shfl(incl, 63);
+    const int excl = incl - rlen;
+    for (int base = 0; base < total; base += 64) {
+        const int c = base + lane;
+        const bool valid = c < total;
+        // range of candidate c: the last q2 with excl(q2) <= c (binary
+        // lifting over the lanes, same six steps on every lane; lanes 54-63
+        // hold excl = total, which no valid c reaches)
+        int q2 = 0;
+        for (int step = 32; step > 0; step >>= 1) {
+            const int em = __shfl(excl, q2 + step);
+            if (em <= c) q2 += step;
+        }
+        const int J = __shfl(r0, q2) + (c - __shfl(excl, q2));
+        const uint32_t rc_ = __shfl(rcode, q2);
+        const uint32_t code = rc_ & 0xFFu;
+        const int sp = (int)(rc_ >> 8);
+        const int sx = (int)(code / 9u) - 1, sy = (int)((code / 3u) % 3u) - 1,
+                  sz = (int)(code % 3u) - 1;
+        bool gok = false, hok = false;
+        if (valid) {
+            const double S[3] = {(double)sx, (double)sy, (double)sz};
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double l = (double)lo_[a * cap + J] + S[a];
+                double h = (double)hi_[a * cap + J] + S[a];
+                double g = fmax(0.0, fmax(l - hiI[a], loI[a] - h));
+                d2 += g * g;
+            }
+            gok = d2 < Rg2;
+            if (gasI && sp == 0) {
+                double hm = fmax(hmI, (double)lhmax[J]);
+                double Rh = 2.0 * hm * RANGE_WIDEN;
+                hok = d2 < Rh * Rh;
             }
         }
+        if (!fill) {
+            if (gok) gcost += leaf_count[J];
+            if (hok) hcost += leaf_count[J];
+        }
+        const uint64_t gm = __ballot(gok);
+        const uint64_t hm = __ballot(hok);
+        if (fill) {
+            if (gok) {
+                int64_t p = gpos + __popcll(gm & lt_mask);
+                if (p < g_cap) g_list[p] = (uint32_t)J | (code << LIST_LEAF_BITS);
+                else atomicOr(err, DEV_ERR_CAPACITY);
+            }
+            if (hok) {
+                int64_t p = hpos + __popcll(hm & lt_mask);
+                if (p < h_cap) h_list[p] = (uint32_t)J | (code << LIST_LEAF_BITS);
+                else atomicOr(err, DEV_ERR_CAPACITY);
+            }
+        }
+        gpos += __popcll(gm);
+        hpos += __popcll(hm);
+        gc += __popcll(gm);
+        hc += __popcll(hm);
     }
     if (!fill) {
         // queue cost = i particles x candidate j particles

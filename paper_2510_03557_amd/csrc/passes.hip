@@ -46,12 +46,19 @@ template <> struct Comp<float> {
         hi = s;
     }
     __device__ double value() const { return (double)hi + (double)lo; }
+    // adds the running sum of lane (this lane ^ m)
+    __device__ void add_lane(int m) {
+        const float oh = __shfl_xor(hi, m), ol = __shfl_xor(lo, m);
+        add(oh);
+        lo += ol;
+    }
 };
 template <> struct Comp<double> {
     double hi;
     __device__ void zero() { hi = 0.0; }
     __device__ void add(double t) { hi += t; }
     __device__ double value() const { return hi; }
+    __device__ void add_lane(int m) { hi += __shfl_xor(hi, m); }
 };
 
 template <typename T, int N> struct CompArr {
@@ -65,6 +72,14 @@ template <typename T, int N> struct CompArr {
         for (int k = 0; k < N; ++k) {
             c[k].add(t[k]);
             t[k] = T(0);
+        }
+    }
+    // sum over the 4 lanes of each quad (every lane of the quad converged)
+    __device__ void quad_reduce() {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            c[k].add_lane(1);
+            c[k].add_lane(2);
         }
     }
 };
@@ -104,14 +119,74 @@ template <typename T> struct TreeView {
     int64_t lcap;
     int xcd_remap;            // map blocks to contiguous leaf ranges per XCD
     int walk_mask;            // passes (bit P::ID) that use the hit walk
+    int groups;               // sub-leaf sweep: 1 lane groups, 2 split
+    const int32_t *nsub, *sst, *scnt;  // sub-leaves (slots 4*leaf + k)
+    const T *slo, *shi, *shm;          // their boxes (3 planes of 4*lcap), h_max
     const double *rc, *eps;
     int64_t n_gas;
 };
+
+// sweep forms of the pair kernels
+enum { SWEEP_BROADCAST = 0, SWEEP_WALK = 1, SWEEP_GROUPED = 2, SWEEP_SPLIT = 3 };
 
 __device__ inline void decode_shift(uint32_t code, int &sx, int &sy, int &sz) {
     sx = (int)(code / 9u) - 1;
     sy = (int)((code / 3u) % 3u) - 1;
     sz = (int)(code % 3u) - 1;
+}
+
+// Walks the list entries [e0, e1) of one leaf.  Each wavefront loads the
+// leaf data of 64 entries at once (one entry per lane) and prefetches the
+// positions of entry k + 1 while entry k is processed, so the dependent
+// global loads of the walk overlap.  visit(js, jc, code, hJ, x, y, z) gets
+// the j-leaf's first slot, size (clamped to CLAMP), periodic image code,
+// h_max, and the raw position of slot js + t for t < jc.  Entries that were
+// never written (after a capacity error) are skipped.  Every thread of the
+// workgroup calls visit for every entry.
+template <typename T, int CLAMP, typename F>
+__device__ __forceinline__ void walk_list(const TreeView<T> &tv, int64_t e0,
+                                          int64_t e1, int t, F &&visit) {
+    const int lane = t & 63;
+    const int nl = *tv.n_leaves;
+    for (int64_t eb = e0; eb < e1; eb += 64) {
+        const int nb = (int)min((int64_t)64, e1 - eb);
+        int bjs = 0, bjc = 0, bcode = 0;
+        T bh = T(0);
+        if (lane < nb) {
+            const uint32_t ent = tv.list[eb + lane];
+            const int J = (int)(ent & LIST_LEAF_MASK);
+            if (J < nl) {
+                bjs = tv.leaf_start[J];
+                bjc = min(tv.leaf_count[J], CLAMP);
+                bh = tv.hmax[J];
+                bcode = (int)(ent >> LIST_LEAF_BITS);
+            }
+        }
+        int js = __shfl(bjs, 0), jc = __shfl(bjc, 0);
+        T nx = T(0), ny = T(0), nz = T(0);
+        if (t < jc) {
+            nx = tv.px[js + t];
+            ny = tv.py[js + t];
+            nz = tv.pz[js + t];
+        }
+        for (int k = 0; k < nb; ++k) {
+            const int cjs = js, cjc = jc;
+            const T cx = nx, cy = ny, cz = nz;
+            const int code = __shfl(bcode, k);
+            const T hJ = __shfl(bh, k);
+            if (k + 1 < nb) {
+                js = __shfl(bjs, k + 1);
+                jc = __shfl(bjc, k + 1);
+                if (t < jc) {
+                    nx = tv.px[js + t];
+                    ny = tv.py[js + t];
+                    nz = tv.pz[js + t];
+                }
+            }
+            if (cjc == 0) continue;
+            visit(cjs, cjc, (uint32_t)code, hJ, cx, cy, cz);
+        }
+    }
 }
 
 // The common driver: P supplies the per-pass state and arithmetic.
@@ -130,11 +205,12 @@ __device__ inline void decode_shift(uint32_t code, int &sx, int &sy, int &sz) {
 // j-leaves.  A full buffer is swept by every lane and its partial sums are
 // folded into the compensated totals.  Culled particles are out of range of
 // every i, so the sums do not change beyond rounding order.
-template <typename T, typename P, int BLOCK>
+template <typename T, typename P, int BLOCK, int MODE>
 __device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
                                              const typename P::Args &pa,
                                              const int I, T *sj, int *sjid,
-                                             int *wcnt, uint32_t *smask) {
+                                             int *wcnt, uint32_t *smask,
+                                             short *glist) {
     constexpr int CAP = P::CAPF * BLOCK;
     constexpr int NW = BLOCK / 64;
     const int st = tv.leaf_start[I];
@@ -145,8 +221,14 @@ __device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
     const int lane = t & 63;
     const int wave = t >> 6;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const bool act = t < cnt;
-    const int i = st + (act ? t : 0);
+    // lane groups: with sub-leaves, lanes 16g..16g+15 hold sub-leaf g
+    const bool grouped = MODE == SWEEP_GROUPED;
+    const int ns = grouped ? tv.nsub[I] : 1;
+    const int g = grouped ? (t >> 4) : 0;
+    const int64_t slot = 4 * (int64_t)I + g;
+    const bool act = grouped ? (g < ns && (t & 15) < tv.scnt[g < ns ? slot : 4 * (int64_t)I])
+                             : (t < cnt);
+    const int i = act ? (grouped ? tv.sst[slot] + (t & 15) : st + t) : st;
     const T rx = tv.px[st], ry = tv.py[st], rz = tv.pz[st];
     const int box = tv.leaf_box[I];
     // i-leaf box relative to the reference particle (exact in float32)
@@ -165,21 +247,19 @@ __device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
     // past the allocation: clamp, and skip entries that were never written
     const int64_t e0 = min(tv.list_off[I], tv.list_cap);
     const int64_t e1 = min(tv.list_off[I + 1], tv.list_cap);
-    const int nl = *tv.n_leaves;
     int nbuf = 0;
     // Sweep of a full buffer.  Broadcast form: every lane evaluates every
     // candidate (LDS broadcast reads); the pair function applies the exact
     // range test and the wave skips the arithmetic when no lane is in range.
-    // Walk form (for passes in tv.walk_mask): every lane first tests all
+    // Walk form (MODE SWEEP_WALK): every lane first tests all
     // candidates against its own particle and stores a hit bitmask in LDS,
     // then walks its own hits in candidate order with per-lane reads, so the
     // pair arithmetic runs only for in-range pairs; the wave loops while any
     // lane has hits left.  Buffers where hits are dense (at least a quarter
     // of lane x candidate pairs) use the broadcast form.  Every lane meets
     // its hits in candidate order either way, so the sums are the same.
-    constexpr int NWORDS = CAP / 32;
     const int lanes = __popcll(__ballot(act));  // active lanes of this wave
-    const bool walk = (tv.walk_mask >> P::ID) & 1;
+    constexpr bool walk = MODE == SWEEP_WALK;
     auto sweep = [&](int n) {
         __syncthreads();
         bool broadcast = true;
@@ -219,34 +299,79 @@ __device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
                 }
             }
         }
-        if (broadcast && act) {
-            for (int k = 0; k < n; ++k)
+        if (MODE == SWEEP_GROUPED && broadcast && n > 0) {
+            // per sub-leaf candidate lists (ballot compaction, in order)
+            int len[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int gg = 0; gg < 4; ++gg) {
+                if (gg >= ns) break;
+                const int64_t sg = 4 * (int64_t)I + gg;
+                const T gl0 = tv.slo[sg] - rx, gl1 = tv.slo[4 * tv.lcap + sg] - ry,
+                        gl2 = tv.slo[8 * tv.lcap + sg] - rz;
+                const T gh0 = tv.shi[sg] - rx, gh1 = tv.shi[4 * tv.lcap + sg] - ry,
+                        gh2 = tv.shi[8 * tv.lcap + sg] - rz;
+                const T hg = tv.shm[sg];
+                int l = 0;
+                for (int base = 0; base < n; base += 64) {
+                    const int k = base + lane;
+                    bool hit = false;
+                    if (k < n) {
+                        const T *jd = &sj[k * P::NJ];
+                        const T R = P::sub_range(pa, tv, box, hg, jd);
+                        const T dx = fmax(fmax(gl0 - jd[0], jd[0] - gh0), T(0));
+                        const T dy = fmax(fmax(gl1 - jd[1], jd[1] - gh1), T(0));
+                        const T dz = fmax(fmax(gl2 - jd[2], jd[2] - gh2), T(0));
+                        hit = dx * dx + dy * dy + dz * dz < R * R;
+                    }
+                    const uint64_t mk = __ballot(hit);
+                    if (hit) glist[gg * CAP + l + __popcll(mk & lt_mask)] = (short)k;
+                    l += __popcll(mk);
+                }
+                len[gg] = l;
+            }
+            __syncthreads();
+            const int maxlen = max(max(len[0], len[1]), max(len[2], len[3]));
+            const int mylen = g == 0 ? len[0] : (g == 1 ? len[1] : (g == 2 ? len[2] : len[3]));
+            for (int it = 0; it < maxlen; ++it) {
+                if (act && it < mylen) {
+                    const int k = glist[g * CAP + it];
+                    P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+                }
+            }
+        } else if (broadcast) {
+            // every lane runs the loop (an inactive lane holds a valid
+            // particle and its sums are never written), so the loop is
+            // uniform; unrolled by 4 so that the LDS reads of several
+            // candidates are in flight together
+            int k = 0;
+            for (; k + 4 <= n; k += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    P::pair(tile, is, &sj[(k + u) * P::NJ], sjid[k + u] == i);
+            }
+            for (; k < n; ++k)
                 P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
         }
         acc.fold(tile);
         __syncthreads();
     };
-    for (int64_t e = e0; e < e1; ++e) {
-        const uint32_t ent = tv.list[e];
-        const int J = (int)(ent & LIST_LEAF_MASK);
-        if (J >= nl) continue;
+    walk_list<T, BLOCK>(tv, e0, e1, t, [&](int js, int jc, uint32_t code,
+                                            T hJ, T x, T y, T z) {
         int sx, sy, sz;
-        decode_shift(ent >> LIST_LEAF_BITS, sx, sy, sz);
-        const int js = tv.leaf_start[J];
-        const int jc = min(tv.leaf_count[J], BLOCK);
+        decode_shift(code, sx, sy, sz);
         if (nbuf + jc > CAP) {
             sweep(nbuf);
             nbuf = 0;
         }
-        const T R = P::range(pa, tv, box, hmI, tv.hmax[J]);
+        const T R = P::range(pa, tv, box, hmI, hJ);
         const T R2 = R * R;
         bool keep = false;
         T fx = T(0), fy = T(0), fz = T(0);
         const int j = js + t;
         if (t < jc) {
-            fx = (tv.px[j] - rx) + T(sx);
-            fy = (tv.py[j] - ry) + T(sy);
-            fz = (tv.pz[j] - rz) + T(sz);
+            fx = (x - rx) + T(sx);
+            fy = (y - ry) + T(sy);
+            fz = (z - rz) + T(sz);
             const T dx = fmax(fmax(blx - fx, fx - bhx), T(0));
             const T dy = fmax(fmax(bly - fy, fy - bhy), T(0));
             const T dz = fmax(fmax(blz - fz, fz - bhz), T(0));
@@ -271,7 +396,7 @@ __device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
             sjid[pos] = j;
         }
         nbuf += tot;
-    }
+    });
     sweep(nbuf);
     if (act) P::finish(acc, is, pa, tv, i);
 }
@@ -287,20 +412,129 @@ __device__ inline int xcd_block(int b, int G) {
     return x * q + min(x, r) + k;
 }
 
-// One workgroup per leaf (leaf order remapped per XCD).
-template <typename T, typename P, int BLOCK>
+// One workgroup per leaf (leaf order remapped per XCD).  MODE selects the
+// sweep form; the walk and group forms exist for BLOCK 64 only.
+template <typename T, typename P, int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
                                                      const typename P::Args pa) {
+    static_assert(MODE == SWEEP_BROADCAST || BLOCK == 64, "64-lane forms");
     __shared__ __attribute__((aligned(16))) T sj[P::CAPF * BLOCK * P::NJ];
     __shared__ int sjid[P::CAPF * BLOCK];
     __shared__ int wcnt[BLOCK / 64];
-    __shared__ uint32_t smask[P::CAPF * BLOCK / 32 * BLOCK];
+    __shared__ uint32_t smask[MODE == SWEEP_WALK ? P::CAPF * BLOCK / 32 * BLOCK : 1];
+    __shared__ short glist[MODE == SWEEP_GROUPED ? 4 * P::CAPF * BLOCK : 1];
     // the grid may exceed the device-side leaf count (graph capture sizes it
     // by capacity): surplus blocks leave first, the remap covers [0, n)
     const int n_items = *tv.n_items;
     if ((int)blockIdx.x >= n_items) return;
     const int I = tv.xcd_remap ? xcd_block(blockIdx.x, n_items) : (int)blockIdx.x;
-    process_leaf<T, P, BLOCK>(tv, pa, I, sj, sjid, wcnt, smask);
+    process_leaf<T, P, BLOCK, MODE>(tv, pa, I, sj, sjid, wcnt, smask, glist);
+}
+
+// Split form: one wavefront per sub-leaf (<= 16 particles), four lanes per
+// particle.  The wave walks the parent leaf's list, culls every j particle
+// against the sub-leaf's box (smaller than the leaf's, so fewer candidates
+// survive), and lane q of a particle's quad takes candidates q, q + 4, ...
+// of each buffer; the quad's compensated sums are combined at the end and
+// lane 0 of the quad writes the outputs.  Recentring uses the parent
+// leaf's first particle, as in the other forms.
+template <typename T, typename P>
+__device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
+                                                const typename P::Args &pa,
+                                                const int I, const int g,
+                                                T *sj, int *sjid) {
+    constexpr int CAP = P::CAPF * 64;
+    const int lane = threadIdx.x;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t slot = 4 * (int64_t)I + g;
+    const int sst = tv.sst[slot];
+    const int scnt = min(tv.scnt[slot], 16);
+    const int ii = lane >> 2, q = lane & 3;
+    const bool act = ii < scnt;
+    const int i = act ? sst + ii : sst;
+    const int st = tv.leaf_start[I];
+    const T rx = tv.px[st], ry = tv.py[st], rz = tv.pz[st];
+    const int box = tv.leaf_box[I];
+    const int64_t sl = 4 * tv.lcap;
+    const T blx = tv.slo[slot] - rx, bly = tv.slo[sl + slot] - ry,
+            blz = tv.slo[2 * sl + slot] - rz;
+    const T bhx = tv.shi[slot] - rx, bhy = tv.shi[sl + slot] - ry,
+            bhz = tv.shi[2 * sl + slot] - rz;
+    const T hmS = tv.shm[slot];
+    typename P::I is;
+    P::load_i(is, pa, tv, i, tv.px[i] - rx, tv.py[i] - ry, tv.pz[i] - rz, box);
+    typename P::Tile tile;
+    tile.zero();
+    typename P::Acc acc;
+    acc.zero();
+    const int64_t e0 = min(tv.list_off[I], tv.list_cap);
+    const int64_t e1 = min(tv.list_off[I + 1], tv.list_cap);
+    int nbuf = 0;
+    auto sweep = [&](int n) {
+        __syncthreads();
+        // every lane runs the loop (inactive lanes hold a valid particle
+        // whose sums are never written); blocks of 16 candidates unrolled
+        int k0 = 0;
+        for (; k0 + 16 <= n; k0 += 16) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + 4 * u + q;
+                P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+            }
+        }
+        for (int k = k0 + q; k < n; k += 4)
+            P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+        acc.fold(tile);
+        __syncthreads();
+    };
+    walk_list<T, 64>(tv, e0, e1, lane, [&](int js, int jc, uint32_t code,
+                                           T hJ, T x, T y, T z) {
+        int sx, sy, sz;
+        decode_shift(code, sx, sy, sz);
+        if (nbuf + jc > CAP) {
+            sweep(nbuf);
+            nbuf = 0;
+        }
+        const T R = P::range(pa, tv, box, hmS, hJ);
+        const T R2 = R * R;
+        bool keep = false;
+        T fx = T(0), fy = T(0), fz = T(0);
+        const int j = js + lane;
+        if (lane < jc) {
+            fx = (x - rx) + T(sx);
+            fy = (y - ry) + T(sy);
+            fz = (z - rz) + T(sz);
+            const T dx = fmax(fmax(blx - fx, fx - bhx), T(0));
+            const T dy = fmax(fmax(bly - fy, fy - bhy), T(0));
+            const T dz = fmax(fmax(blz - fz, fz - bhz), T(0));
+            keep = dx * dx + dy * dy + dz * dz < R2;
+        }
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int pos = nbuf + __popcll(m & lt_mask);
+            P::load_j(&sj[pos * P::NJ], pa, tv, j, fx, fy, fz);
+            sjid[pos] = j;
+        }
+        nbuf += __popcll(m);
+    });
+    sweep(nbuf);
+    acc.quad_reduce();
+    if (act && q == 0) P::finish(acc, is, pa, tv, i);
+}
+
+// One wavefront per sub-leaf: block b -> leaf b / 4, sub-leaf b % 4.
+template <typename T, typename P>
+__global__ __launch_bounds__(64) void pair_kernel_split(const TreeView<T> tv,
+                                                        const typename P::Args pa) {
+    __shared__ __attribute__((aligned(16))) T sj[P::CAPF * 64 * P::NJ];
+    __shared__ int sjid[P::CAPF * 64];
+    const int n_items = *tv.n_items;
+    if ((int)blockIdx.x >= 4 * n_items) return;
+    const int b = tv.xcd_remap ? xcd_block(blockIdx.x, 4 * n_items)
+                               : (int)blockIdx.x;
+    const int I = b >> 2, g = b & 3;
+    if (g >= tv.nsub[I]) return;
+    process_subleaf<T, P>(tv, pa, I, g, sj, sjid);
 }
 
 // Persistent grid: each workgroup pops queue slots from an atomic counter
@@ -314,7 +548,8 @@ __global__ __launch_bounds__(BLOCK) void pair_kernel_queue(
     __shared__ __attribute__((aligned(16))) T sj[P::CAPF * BLOCK * P::NJ];
     __shared__ int sjid[P::CAPF * BLOCK];
     __shared__ int wcnt[BLOCK / 64];
-    __shared__ uint32_t smask[P::CAPF * BLOCK / 32 * BLOCK];
+    __shared__ uint32_t smask[1];
+    __shared__ short glist[1];
     __shared__ int slot;
     const int n_items = *tv.n_items;
     while (true) {
@@ -323,7 +558,8 @@ __global__ __launch_bounds__(BLOCK) void pair_kernel_queue(
         __syncthreads();
         const int q = slot;
         if (q >= n_items) break;
-        process_leaf<T, P, BLOCK>(tv, pa, order[q], sj, sjid, wcnt, smask);
+        process_leaf<T, P, BLOCK, SWEEP_BROADCAST>(tv, pa, order[q], sj, sjid,
+                                                   wcnt, smask, glist);
     }
 }
 
@@ -348,6 +584,10 @@ template <typename T> struct DensityPass {
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
         return widen<T>(2.0 * (double)hI);
     }
+    __device__ static T sub_range(const Args &, const TreeView<T> &, int, T hg,
+                                  const T *) {
+        return widen<T>(2.0 * (double)hg);
+    }
     struct I {
         T ex, ey, ez, ih2, h;
     };
@@ -359,6 +599,7 @@ template <typename T> struct DensityPass {
         CompArr<T, 2> a;
         __device__ void zero() { a.zero(); }
         __device__ void fold(Tile &t) { a.fold(t.s); }
+        __device__ void quad_reduce() { a.quad_reduce(); }
     };
     __device__ static void load_i(I &is, const Args &, const TreeView<T> &tv,
                                   int i, T ex, T ey, T ez, int) {
@@ -379,18 +620,21 @@ template <typename T> struct DensityPass {
         const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
         return (dx * dx + dy * dy + dz * dz) * is.ih2 < T(4);
     }
+    // branch-free: out-of-range pairs add exact zeros, so the sums are
+    // bitwise those of the in-range pairs alone
     __device__ static void pair(Tile &tl, const I &is, const T *jd, bool) {
+        const T mj = jd[3];
         const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
         const T q2 = (dx * dx + dy * dy + dz * dz) * is.ih2;
-        if (q2 < T(4)) {
-            const T rq = rsq(q2);
-            const T q = q2 > T(0) ? q2 * rq : T(0);
-            const T t = T(2) - q;
-            const T w = q < T(1) ? fma(q * q, fma(T(0.75), q, T(-1.5)), T(1))
-                                 : T(0.25) * t * t * t;
-            tl.s[0] += w;
-            tl.s[1] = fma(jd[3], w, tl.s[1]);
-        }
+        const bool in = q2 < T(4);
+        const T rq = rsq(q2);
+        const T q = q2 > T(0) ? q2 * rq : T(0);
+        const T t = T(2) - q;
+        const T w = q < T(1) ? fma(q * q, fma(T(0.75), q, T(-1.5)), T(1))
+                             : T(0.25) * t * t * t;
+        const T wv = in ? w : T(0);
+        tl.s[0] += wv;
+        tl.s[1] = fma(mj, wv, tl.s[1]);
     }
     __device__ static void finish(const Acc &ac, const I &is, const Args &a,
                                   const TreeView<T> &tv, int i) {
@@ -429,6 +673,10 @@ template <typename T> struct CoeffPass {
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
         return widen<T>(2.0 * (double)hI);
     }
+    __device__ static T sub_range(const Args &, const TreeView<T> &, int, T hg,
+                                  const T *) {
+        return widen<T>(2.0 * (double)hg);
+    }
     struct I {
         T ex, ey, ez, ih;
         T h;
@@ -444,6 +692,7 @@ template <typename T> struct CoeffPass {
         CompArr<T, NS> a;
         __device__ void zero() { a.zero(); }
         __device__ void fold(Tile &t) { a.fold(t.s); }
+        __device__ void quad_reduce() { a.quad_reduce(); }
     };
     __device__ static void load_i(I &is, const Args &, const TreeView<T> &tv,
                                   int i, T ex, T ey, T ez, int) {
@@ -640,6 +889,11 @@ template <typename T> struct HydroPass {
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T hJ) {
         return widen<T>(2.0 * (double)(hI > hJ ? hI : hJ));
     }
+    __device__ static T sub_range(const Args &, const TreeView<T> &, int, T hg,
+                                  const T *jd) {
+        const T hj = jd[3 + 23];
+        return widen<T>(2.0 * (double)(hg > hj ? hg : hj));
+    }
     struct I {
         T ex, ey, ez;
         T Cl, Cq, epsQ;
@@ -653,6 +907,7 @@ template <typename T> struct HydroPass {
         CompArr<T, 4> a;
         __device__ void zero() { a.zero(); }
         __device__ void fold(Tile &t) { a.fold(t.s); }
+        __device__ void quad_reduce() { a.quad_reduce(); }
     };
     __device__ static void load_i(I &is, const Args &a, const TreeView<T> &,
                                   int i, T ex, T ey, T ez, int) {
@@ -759,6 +1014,10 @@ template <typename T> struct GravityPass {
     __device__ static T range(const Args &, const TreeView<T> &tv, int box, T, T) {
         return widen<T>(tv.rc[box]);
     }
+    __device__ static T sub_range(const Args &, const TreeView<T> &tv, int box, T,
+                                  const T *) {
+        return widen<T>(tv.rc[box]);
+    }
     struct I {
         T ex, ey, ez;
         T rc2, eps2, two_rc, cin;
@@ -771,6 +1030,7 @@ template <typename T> struct GravityPass {
         CompArr<T, 3> a;
         __device__ void zero() { a.zero(); }
         __device__ void fold(Tile &t) { a.fold(t.s); }
+        __device__ void quad_reduce() { a.quad_reduce(); }
     };
     __device__ static void load_i(I &is, const Args &, const TreeView<T> &tv,
                                   int, T ex, T ey, T ez, int box) {
@@ -795,6 +1055,9 @@ template <typename T> struct GravityPass {
         const T r2 = dx * dx + dy * dy + dz * dz;
         return (r2 > T(0)) && (r2 < is.rc2);
     }
+    // the mass is read under the range test, so the compiler skips the
+    // arithmetic when no lane of the wave is in range (frequent here: the
+    // candidates fill the leaf box widened by r_c)
     __device__ static void pair(Tile &tl, const I &is, const T *jd, bool) {
         const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
         const T r2 = dx * dx + dy * dy + dz * dz;
@@ -830,16 +1093,15 @@ template <typename T> struct GravityPass {
         const int c = tv.perm[i];
         const T x = (T)ac.a.c[0].value(), y = (T)ac.a.c[1].value(),
                 z = (T)ac.a.c[2].value();
-        if (c < a.n_gas) {
-            a.ax_g[c] = x;
-            a.ay_g[c] = y;
-            a.az_g[c] = z;
-        } else {
-            const int d = c - (int)a.n_gas;
-            a.ax_d[d] = x;
-            a.ay_d[d] = y;
-            a.az_d[d] = z;
-        }
+        // pointer selects (an if/else here puts the pointers in scratch)
+        const bool gas = c < a.n_gas;
+        const int k = gas ? c : c - (int)a.n_gas;
+        T *ox = gas ? a.ax_g : a.ax_d;
+        T *oy = gas ? a.ay_g : a.ay_d;
+        T *oz = gas ? a.az_g : a.az_d;
+        ox[k] = x;
+        oy[k] = y;
+        oz[k] = z;
     }
 };
 
@@ -866,6 +1128,17 @@ template <typename T> struct CountPass {
         if (m == 1) return widen<T>(2.0 * (double)(hI > hJ ? hI : hJ));
         return widen<T>(2.0 * (double)hI);
     }
+    // the sub-leaf ranges of the pass each mode mirrors
+    __device__ static T sub_range(const Args &a, const TreeView<T> &tv, int box,
+                                  T hg, const T *jd) {
+        const int m = a.mode % 3;
+        if (m == 2) return widen<T>(tv.rc[box]);
+        if (m == 1) {
+            const double hj = 1.0 / sqrt((double)jd[3]);
+            return widen<T>(2.0 * fmax((double)hg, hj));
+        }
+        return widen<T>(2.0 * (double)hg);
+    }
     struct I {
         T ex, ey, ez, ih2, rc2;
         int mode;
@@ -880,6 +1153,10 @@ template <typename T> struct CountPass {
         __device__ void fold(Tile &t) {
             c += t.c;
             t.c = 0;
+        }
+        __device__ void quad_reduce() {
+            c += __shfl_xor(c, 1);
+            c += __shfl_xor(c, 2);
         }
     };
     __device__ static void load_i(I &is, const Args &a, const TreeView<T> &tv,
@@ -1030,6 +1307,13 @@ TreeView<T> tree_view(crk_tree *t, bool hydro, const int32_t *n_items) {
     tv.lcap = t->leaf_cap;
     tv.xcd_remap = t->owner->tuning.xcd_remap;
     tv.walk_mask = t->owner->tuning.walk_mask;
+    tv.groups = t->has_sub ? t->owner->tuning.sub_sweep : 0;
+    tv.nsub = t->sub_nsub.as<int32_t>();
+    tv.sst = t->sub_start.as<int32_t>();
+    tv.scnt = t->sub_count.as<int32_t>();
+    tv.slo = t->sub_lo.as<T>();
+    tv.shi = t->sub_hi.as<T>();
+    tv.shm = t->sub_hmax.as<T>();
     tv.rc = t->d_rc.as<double>();
     tv.eps = t->d_eps.as<double>();
     tv.n_gas = t->n_gas;
@@ -1061,9 +1345,24 @@ int launch_pair(crk_ctx *ctx, crk_tree *t, const TreeView<T> &tv,
         hipLaunchKernelGGL((pair_kernel_queue<T, P, B>), dim3(grid), dim3(B), 0, \
                            ctx->stream, tv, pa, order, head);                   \
     else                                                                        \
-        hipLaunchKernelGGL((pair_kernel<T, P, B>), dim3(grid), dim3(B), 0,      \
+        hipLaunchKernelGGL((pair_kernel<T, P, B, SWEEP_BROADCAST>), dim3(grid), \
+                           dim3(B), 0, ctx->stream, tv, pa);
+    // the walk and group forms: one workgroup per leaf of <= 64 only
+    const int mode = (queue || L > 64) ? SWEEP_BROADCAST
+                     : ((ctx->tuning.walk_mask >> P::ID) & 1) ? SWEEP_WALK
+                     : tv.groups == 1 ? SWEEP_GROUPED
+                     : tv.groups == 2 ? SWEEP_SPLIT : SWEEP_BROADCAST;
+    if (mode == SWEEP_SPLIT) {
+        const unsigned g4 = (unsigned)std::max<int64_t>(1, 4 * n_items_bound);
+        hipLaunchKernelGGL((pair_kernel_split<T, P>), dim3(g4), dim3(64), 0,
                            ctx->stream, tv, pa);
-    if (L <= 64) {
+    } else if (mode == SWEEP_WALK) {
+        hipLaunchKernelGGL((pair_kernel<T, P, 64, SWEEP_WALK>), dim3(grid),
+                           dim3(64), 0, ctx->stream, tv, pa);
+    } else if (mode == SWEEP_GROUPED) {
+        hipLaunchKernelGGL((pair_kernel<T, P, 64, SWEEP_GROUPED>), dim3(grid),
+                           dim3(64), 0, ctx->stream, tv, pa);
+    } else if (L <= 64) {
         CRK_LAUNCH_PAIR(64)
     } else if (L <= 128) {
         CRK_LAUNCH_PAIR(128)

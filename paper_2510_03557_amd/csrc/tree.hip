@@ -110,7 +110,7 @@ __global__ void keys_kernel(const T *__restrict__ gx, const T *__restrict__ gy,
             ph[c] = h;
         }
         T v = axis == 0 ? x : (axis == 1 ? y : z);
-        kout[c] = (bk << 23) | coord_bits(v);
+        kout[c] = axis < 3 ? ((bk << 23) | coord_bits(v)) : bk;
         vout[c] = (int32_t)c;
     }
 }
@@ -121,12 +121,12 @@ __global__ void copy_i32_kernel(const int32_t *__restrict__ a,
 }
 
 __global__ void seg_flags_kernel(const uint64_t *__restrict__ k, int64_t n,
-                                 int32_t *__restrict__ flags,
+                                 int shift, int32_t *__restrict__ flags,
                                  int32_t *__restrict__ binkey) {
     GRID_STRIDE(p, n) {
-        uint32_t bk = (uint32_t)(k[p] >> 23);
+        uint32_t bk = (uint32_t)(k[p] >> shift);
         binkey[p] = (int32_t)bk;
-        flags[p] = (p == 0 || (uint32_t)(k[p - 1] >> 23) != bk) ? 1 : 0;
+        flags[p] = (p == 0 || (uint32_t)(k[p - 1] >> shift) != bk) ? 1 : 0;
     }
 }
 
@@ -339,35 +339,587 @@ __global__ void gather_tree_kernel(const int32_t *__restrict__ S0,
     }
 }
 
+// wave-wide reductions (all 64 lanes converged)
+template <typename T> __device__ inline T wave_min(T v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        T o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+template <typename T> __device__ inline T wave_max(T v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        T o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// ascending bitonic sort of one value per lane across the wavefront: lane r
+// ends with the r-th smallest (all 64 lanes converged)
+__device__ inline uint32_t wave_sort_u32(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+    for (int k = 2; k <= 64; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t o = __shfl_xor(v, j);
+            const bool up = (lane & k) == 0;
+            const bool lower = (lane & j) == 0;
+            v = (lower == up) ? min(v, o) : max(v, o);
+        }
+    }
+    return v;
+}
+
+// Leaf boxes (exact min / max of the members), h_max, box id and the count
+// of leaves per (species, bin).  One wavefront per leaf.
 template <typename T>
-__global__ void leaves_kernel(
+__global__ __launch_bounds__(256) void leaves_kernel(
     const int32_t *__restrict__ nd_start, const int32_t *__restrict__ nd_count,
     const int32_t *__restrict__ nd_key, const int32_t *__restrict__ nn_ptr,
-    int64_t cap, const int32_t *__restrict__ S0, const int32_t *__restrict__ S1,
-    const int32_t *__restrict__ S2, const T *__restrict__ px,
-    const T *__restrict__ py, const T *__restrict__ pz,
-    const T *__restrict__ th, int64_t total_bins, int nb,
-    const int64_t *__restrict__ bin_base, int32_t *__restrict__ leaf_box,
-    T *__restrict__ lo, T *__restrict__ hi, T *__restrict__ lhmax,
-    int32_t *__restrict__ bin_cnt) {
+    int64_t cap, const T *__restrict__ tx, const T *__restrict__ ty,
+    const T *__restrict__ tz, const T *__restrict__ th, int64_t total_bins,
+    int nb, const int64_t *__restrict__ bin_base,
+    int32_t *__restrict__ leaf_box, T *__restrict__ lo, T *__restrict__ hi,
+    T *__restrict__ lhmax, int32_t *__restrict__ bin_cnt) {
     const int64_t nn = *nn_ptr;
-    GRID_STRIDE(k, cap) {
-        if (k >= nn) break;
-        int st = nd_start[k], cnt = nd_count[k], key = nd_key[k];
-        int e = st + cnt - 1;
-        int64_t gbin = key >= total_bins ? key - total_bins : key;
+    const int lane = threadIdx.x & 63;
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= nn) return;  // the whole wavefront leaves together
+    const int st = nd_start[k], cnt = nd_count[k], key = nd_key[k];
+    const T BIG = T(4), SMALL = T(0);
+    T lx = BIG, ly = BIG, lz = BIG, hx = SMALL, hy = SMALL, hz = SMALL;
+    T hm = SMALL;
+    for (int p = st + lane; p < st + cnt; p += 64) {
+        const T x = tx[p], y = ty[p], z = tz[p], h = th[p];
+        lx = x < lx ? x : lx;
+        hx = x > hx ? x : hx;
+        ly = y < ly ? y : ly;
+        hy = y > hy ? y : hy;
+        lz = z < lz ? z : lz;
+        hz = z > hz ? z : hz;
+        hm = h > hm ? h : hm;
+    }
+    lx = wave_min(lx);
+    ly = wave_min(ly);
+    lz = wave_min(lz);
+    hx = wave_max(hx);
+    hy = wave_max(hy);
+    hz = wave_max(hz);
+    hm = wave_max(hm);
+    if (lane == 0) {
+        const int64_t gbin = key >= total_bins ? key - total_bins : key;
         leaf_box[k] = find_box(bin_base, nb, gbin);
-        lo[k] = px[S0[st]];
-        hi[k] = px[S0[e]];
-        lo[cap + k] = py[S1[st]];
-        hi[cap + k] = py[S1[e]];
-        lo[2 * cap + k] = pz[S2[st]];
-        hi[2 * cap + k] = pz[S2[e]];
-        T hm = T(0);
-        for (int p = st; p <= e; ++p) hm = th[p] > hm ? th[p] : hm;
+        lo[k] = lx;
+        hi[k] = hx;
+        lo[cap + k] = ly;
+        hi[cap + k] = hy;
+        lo[2 * cap + k] = lz;
+        hi[2 * cap + k] = hz;
         lhmax[k] = hm;
         atomicAdd(&bin_cnt[key], 1);
     }
+}
+
+// Splits every leaf of <= 64 particles by up to two more k-d levels (widest
+// extent of the node, left side taking ceil(k/2) of the k sub-leaves of
+// <= 16 it needs, ties by position in the leaf) and reorders the leaf's
+// slots sub-leaf by sub-leaf (keeping the previous relative order inside
+// each).  Writes per leaf the number of sub-leaves and per slot 4*leaf + k
+// the sub-leaf's start, count, bounding box and h_max.  One wavefront per
+// leaf, one particle per lane.
+template <typename T>
+__global__ __launch_bounds__(64) void subleaf_kernel(
+    const int32_t *__restrict__ nn_ptr, const int32_t *__restrict__ leaf_start,
+    const int32_t *__restrict__ leaf_count, int64_t cap, T *__restrict__ px,
+    T *__restrict__ py, T *__restrict__ pz, T *__restrict__ ph,
+    int32_t *__restrict__ perm, int32_t *__restrict__ nsub,
+    int32_t *__restrict__ sst, int32_t *__restrict__ scnt,
+    T *__restrict__ slo, T *__restrict__ shi, T *__restrict__ shm) {
+    const int I = (int)blockIdx.x;
+    if (I >= *nn_ptr) return;
+    const int t = threadIdx.x;
+    const int st = leaf_start[I];
+    const int c = min(leaf_count[I], 64);
+    const bool act = t < c;
+    const int p = st + (act ? t : 0);
+    const T x = px[p], y = py[p], z = pz[p], h = ph[p];
+    const int pm = perm[p];
+    const T BIG = T(4), SMALL = T(0);
+    int node = 0;
+    for (int lev = 0; lev < 2; ++lev) {
+        int side = 0;
+        const int nodes = 1 << lev;
+        for (int n = 0; n < nodes; ++n) {
+            const bool in = act && node == n;
+            const int cn = __popcll(__ballot(in));
+            if (cn <= 16) continue;
+            const T ex = wave_max(in ? x : SMALL) - wave_min(in ? x : BIG);
+            const T ey = wave_max(in ? y : SMALL) - wave_min(in ? y : BIG);
+            const T ez = wave_max(in ? z : SMALL) - wave_min(in ? z : BIG);
+            int a = 0;
+            T best = ex;
+            if (ey > best) {
+                a = 1;
+                best = ey;
+            }
+            if (ez > best) a = 2;
+            // order key: coordinate bits along the axis, then the slot
+            const T key = a == 0 ? x : (a == 1 ? y : z);
+            const uint32_t k32 =
+                in ? ((coord_bits(key) << 6) | (uint32_t)t) : 0xFFFFFFFFu;
+            const uint32_t sorted = wave_sort_u32(k32);
+            const int nl = (cn + 15) / 16;
+            const int nleft = (nl + 1) / 2;
+            const int left = (cn * nleft + nl / 2) / nl;
+            // the right part starts at the left-th smallest key of the node
+            const uint32_t thr = __shfl(sorted, left);
+            if (in) side = k32 >= thr ? 1 : 0;
+        }
+        node = 2 * node + side;
+    }
+    // final order: sub-leaf by sub-leaf, previous order inside each
+    int cnt4[4];
+    uint64_t msk[4];
+    for (int m = 0; m < 4; ++m) {
+        msk[m] = __ballot(act && node == m);
+        cnt4[m] = __popcll(msk[m]);
+    }
+    const uint64_t lt = (t == 0) ? 0ull : (~0ull >> (64 - t));
+    const uint64_t mine = node == 0 ? msk[0]
+                        : (node == 1 ? msk[1] : (node == 2 ? msk[2] : msk[3]));
+    const int within = __popcll(mine & lt);
+    int off = 0;
+    for (int m = 0; m < node; ++m) off += cnt4[m];
+    // every lane holds its particle in registers: safe to overwrite
+    __syncthreads();
+    if (act) {
+        const int q = st + off + within;
+        px[q] = x;
+        py[q] = y;
+        pz[q] = z;
+        ph[q] = h;
+        perm[q] = pm;
+    }
+    // boxes of the sub-leaves: stage the new leaf order in LDS, then lanes
+    // 16k..16k+15 hold non-empty sub-leaf k and reduce within their group
+    __shared__ T sx[64], sy[64], sz[64], sh[64];
+    if (act) {
+        sx[off + within] = x;
+        sy[off + within] = y;
+        sz[off + within] = z;
+        sh[off + within] = h;
+    }
+    int kst[4] = {0, 0, 0, 0}, kcn[4] = {0, 0, 0, 0};
+    int nk = 0, o = 0;
+    for (int m = 0; m < 4; ++m) {
+        if (cnt4[m] == 0) continue;
+        kst[nk] = o;
+        kcn[nk] = cnt4[m];
+        o += cnt4[m];
+        ++nk;
+    }
+    __syncthreads();
+    const int g = t >> 4, u = t & 15;
+    const int gst = g == 0 ? kst[0] : (g == 1 ? kst[1] : (g == 2 ? kst[2] : kst[3]));
+    const int gcn = g == 0 ? kcn[0] : (g == 1 ? kcn[1] : (g == 2 ? kcn[2] : kcn[3]));
+    const bool v = g < nk && u < gcn;
+    T lx = v ? sx[gst + u] : BIG, hx = v ? sx[gst + u] : SMALL;
+    T ly = v ? sy[gst + u] : BIG, hy = v ? sy[gst + u] : SMALL;
+    T lz = v ? sz[gst + u] : BIG, hz = v ? sz[gst + u] : SMALL;
+    T hm = v ? sh[gst + u] : SMALL;
+    for (int off2 = 8; off2 > 0; off2 >>= 1) {
+        T w;
+        w = __shfl_xor(lx, off2); lx = w < lx ? w : lx;
+        w = __shfl_xor(hx, off2); hx = w > hx ? w : hx;
+        w = __shfl_xor(ly, off2); ly = w < ly ? w : ly;
+        w = __shfl_xor(hy, off2); hy = w > hy ? w : hy;
+        w = __shfl_xor(lz, off2); lz = w < lz ? w : lz;
+        w = __shfl_xor(hz, off2); hz = w > hz ? w : hz;
+        w = __shfl_xor(hm, off2); hm = w > hm ? w : hm;
+    }
+    if (u == 0 && g < nk) {
+        const int64_t sl = 4 * (int64_t)I + g;
+        sst[sl] = st + gst;
+        scnt[sl] = gcn;
+        slo[sl] = lx;
+        shi[sl] = hx;
+        slo[4 * cap + sl] = ly;
+        shi[4 * cap + sl] = hy;
+        slo[8 * cap + sl] = lz;
+        shi[8 * cap + sl] = hz;
+        shm[sl] = hm;
+    }
+    if (t == 0) nsub[I] = nk;
+}
+
+// ---------------------------------------------------------------------------
+// Per-bin build in LDS.  After one stable sort by (species, bin) key alone,
+// every segment holds its particles in caller order; one workgroup per
+// segment then (a) sorts the segment along each axis by (coordinate key,
+// position in the segment) -- the same order the per-axis global sorts give,
+// since position in the segment is caller order -- and (b) runs every k-d
+// level of that segment on the three sorted arrays in LDS with the same
+// split rule and the same stable partitions as the global levels.  The
+// leaves come out identical, in the same order, at the leaf offsets given by
+// a prefix sum of ceil(count / leaf_max) per segment (the exact leaf count of
+// the balanced split).
+
+constexpr int SEG_TB = 256;      // threads per segment workgroup
+constexpr int SEG_MAX = 4096;    // largest segment sorted in LDS
+constexpr int SEG_RANK = 512;    // up to here: rank sort (else bitonic)
+
+// Bytes of the sort-key region.  Rank sort (SEG <= 512): u32 keys
+// (coordinate bits << 9 | position) of all three axes, which stay valid
+// through the k-d levels, then the level scratch; bitonic sort: u64 keys of
+// one axis at a time, aliased by the level scratch afterwards.
+__device__ __host__ inline size_t seg_key_bytes(int SEG) {
+    return (size_t)(SEG <= SEG_RANK ? 12 + 8 : 8) * SEG;
+}
+
+// leaves the balanced split makes of a node of c particles
+__device__ __host__ inline int seg_leaves(int c, int L) {
+    return c <= 0 ? 0 : (c + L - 1) / L;
+}
+
+__global__ void seg_leafcount_kernel(const int32_t *__restrict__ nd_count,
+                                     const int32_t *__restrict__ nn_ptr,
+                                     int64_t cap, int L,
+                                     int32_t *__restrict__ nl,
+                                     int32_t *__restrict__ maxc) {
+    const int64_t nn = *nn_ptr;
+    GRID_STRIDE(k, cap) {
+        if (k >= nn) {
+            nl[k] = 0;
+            continue;
+        }
+        const int c = nd_count[k];
+        nl[k] = seg_leaves(c, L);
+        atomicMax(maxc, c);
+    }
+}
+
+// exclusive prefix of v over the workgroup (SEG_TB threads); *total gets the
+// sum.  wsum: SEG_TB / 64 ints of LDS.  All threads must call it.
+__device__ inline int block_excl_scan(int v, int *wsum, int *total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int q = 0; q < SEG_TB / 64; ++q) {
+        const int s = wsum[q];
+        base += q < w ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - v;
+}
+
+template <typename T>
+__device__ inline T seg_coord(const T *px, const T *py, const T *pz, int a,
+                              int32_t c) {
+    return a == 0 ? px[c] : (a == 1 ? py[c] : pz[c]);
+}
+
+// One workgroup per segment; SEG (a power of two >= 64, <= SEG_MAX) is the
+// padded segment size the dynamic LDS is laid out for:
+//   SEG <= SEG_RANK: keys u32[3][SEG], then the level scratch
+//   larger SEG:      keys u64[SEG] (one axis at a time), aliased by the
+//                    level scratch
+//   level scratch:   spare u16[SEG], en u16[SEG], pre u16[SEG], flag u8[SEG]
+//   S0, S1, S2 u16[SEG] (axis-sorted positions in the segment)
+//   node arrays: start, count (two generations), left, axis, child
+// A segment larger than SEG raises the capacity error and is cut into
+// consecutive chunks of leaf_max (bounds-safe, not a k-d split).
+template <typename T>
+__global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
+    const int32_t *__restrict__ nn_ptr, const int32_t *__restrict__ seg_start,
+    const int32_t *__restrict__ seg_count, const int32_t *__restrict__ seg_key,
+    const int32_t *__restrict__ leaf_off, const int32_t *__restrict__ V,
+    const T *__restrict__ px, const T *__restrict__ py,
+    const T *__restrict__ pz, int L, int SEG, int64_t lcap,
+    int32_t *__restrict__ S0g, int32_t *__restrict__ lf_start,
+    int32_t *__restrict__ lf_count, int32_t *__restrict__ lf_key,
+    int *__restrict__ err) {
+    extern __shared__ __align__(16) unsigned char seg_lds[];
+    const int sg = (int)blockIdx.x;
+    if (sg >= *nn_ptr) return;
+    const int t = threadIdx.x;
+    const int s0 = seg_start[sg], cnt = seg_count[sg], key = seg_key[sg];
+    const int loff = leaf_off[sg];
+    const int nlv = seg_leaves(cnt, L);
+    if ((int64_t)loff + nlv > lcap || cnt > SEG) {
+        // a leaf count beyond the capacity is reported by the count kernel
+        // and cannot happen (the capacity bounds the sum of ceil(c / L));
+        // a segment beyond SEG is cut in chunks: every slot stays valid
+        if (t == 0) atomicOr(err, DEV_ERR_CAPACITY);
+        for (int p = t; p < cnt; p += SEG_TB) S0g[s0 + p] = V[s0 + p];
+        if ((int64_t)loff + nlv > lcap) return;
+        for (int k = t; k < nlv; k += SEG_TB) {
+            lf_start[loff + k] = s0 + k * L;
+            lf_count[loff + k] = min(L, cnt - k * L);
+            lf_key[loff + k] = key;
+        }
+        return;
+    }
+    const int MAXN = SEG / 16 + 2;
+    const bool rank = SEG <= SEG_RANK;
+    uint64_t *keys = reinterpret_cast<uint64_t *>(seg_lds);
+    uint32_t *CK = reinterpret_cast<uint32_t *>(seg_lds);  // rank: [3][SEG]
+    uint16_t *spare = reinterpret_cast<uint16_t *>(
+        seg_lds + (rank ? (size_t)12 * SEG : 0));
+    uint16_t *en = spare + SEG;
+    uint16_t *pre = en + SEG;
+    uint8_t *flag = reinterpret_cast<uint8_t *>(pre + SEG);
+    uint16_t *Sa[3];
+    Sa[0] = reinterpret_cast<uint16_t *>(seg_lds + seg_key_bytes(SEG));
+    Sa[1] = Sa[0] + SEG;
+    Sa[2] = Sa[1] + SEG;
+    int32_t *nst[2], *ncnt[2];
+    nst[0] = reinterpret_cast<int32_t *>(Sa[2] + SEG);
+    nst[1] = nst[0] + MAXN;
+    ncnt[0] = nst[1] + MAXN;
+    ncnt[1] = ncnt[0] + MAXN;
+    int32_t *nleft = ncnt[1] + MAXN;
+    int32_t *naxis = nleft + MAXN;
+    int32_t *nchild = naxis + MAXN;
+    __shared__ int wsum[SEG_TB / 64];
+    __shared__ int s_nn;
+
+    // (a) three sorts by (coordinate key, position)
+    if (rank) {
+        // rank sort: the rank of an element is the number of smaller keys
+        // (keys are distinct: coordinate bits, then the position in the
+        // segment); each thread ranks positions t and t + 256 along all
+        // three axes in one sweep of broadcast LDS reads
+        uint32_t *K0 = CK, *K1 = CK + SEG, *K2 = CK + 2 * SEG;
+        for (int p = t; p < cnt; p += SEG_TB) {
+            const int32_t c = V[s0 + p];
+            K0[p] = (coord_bits(px[c]) << 9) | (uint32_t)p;
+            K1[p] = (coord_bits(py[c]) << 9) | (uint32_t)p;
+            K2[p] = (coord_bits(pz[c]) << 9) | (uint32_t)p;
+        }
+        __syncthreads();
+        const int p0 = t, p1 = t + SEG_TB;
+        const uint32_t NONE = 0xFFFFFFFFu;
+        const uint32_t a0 = p0 < cnt ? K0[p0] : NONE, b0 = p0 < cnt ? K1[p0] : NONE,
+                       c0 = p0 < cnt ? K2[p0] : NONE;
+        const uint32_t a1 = p1 < cnt ? K0[p1] : NONE, b1 = p1 < cnt ? K1[p1] : NONE,
+                       c1 = p1 < cnt ? K2[p1] : NONE;
+        int ra0 = 0, rb0 = 0, rc0 = 0, ra1 = 0, rb1 = 0, rc1 = 0;
+        for (int q = 0; q < cnt; ++q) {
+            const uint32_t ka = K0[q], kb = K1[q], kc = K2[q];
+            ra0 += ka < a0 ? 1 : 0;
+            rb0 += kb < b0 ? 1 : 0;
+            rc0 += kc < c0 ? 1 : 0;
+            ra1 += ka < a1 ? 1 : 0;
+            rb1 += kb < b1 ? 1 : 0;
+            rc1 += kc < c1 ? 1 : 0;
+        }
+        if (p0 < cnt) {
+            Sa[0][ra0] = (uint16_t)p0;
+            Sa[1][rb0] = (uint16_t)p0;
+            Sa[2][rc0] = (uint16_t)p0;
+        }
+        if (p1 < cnt) {
+            Sa[0][ra1] = (uint16_t)p1;
+            Sa[1][rb1] = (uint16_t)p1;
+            Sa[2][rc1] = (uint16_t)p1;
+        }
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            for (int p = t; p < SEG; p += SEG_TB) {
+                uint64_t kk = ~0ull;
+                if (p < cnt)
+                    kk = ((uint64_t)coord_bits(seg_coord(px, py, pz, a, V[s0 + p]))
+                          << 16) | (uint64_t)p;
+                keys[p] = kk;
+            }
+            __syncthreads();
+            for (int k = 2; k <= SEG; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int i = t; i < SEG; i += SEG_TB) {
+                        const int ixj = i ^ j;
+                        if (ixj > i) {
+                            const uint64_t x = keys[i], y = keys[ixj];
+                            const bool up = (i & k) == 0;
+                            if ((x > y) == up) {
+                                keys[i] = y;
+                                keys[ixj] = x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int p = t; p < cnt; p += SEG_TB)
+                Sa[a][p] = (uint16_t)(keys[p] & 0xFFFFu);
+            __syncthreads();
+        }
+    }
+
+    // (b) k-d levels
+    int cur = 0;
+    int nn = 1;
+    if (t == 0) {
+        nst[0][0] = 0;
+        ncnt[0][0] = cnt;
+    }
+    for (int p = t; p < cnt; p += SEG_TB) en[p] = 0;
+    __syncthreads();
+    // positions per thread in the scans: a contiguous run of PER
+    const int PER = SEG / SEG_TB > 0 ? SEG / SEG_TB : 1;
+    for (;;) {
+        int any = 0;
+        for (int k = t; k < nn; k += SEG_TB) {
+            const int st = nst[cur][k], c = ncnt[cur][k];
+            int lf = 0, ax = 0;
+            if (c > L) {
+                const int e = st + c - 1;
+                if (sizeof(T) == 4 && rank) {
+                    // float coordinates in [1, 2) share one exponent: the
+                    // difference of their bits orders the extents exactly
+                    const int ex = (int)(CK[Sa[0][e]] >> 9) - (int)(CK[Sa[0][st]] >> 9);
+                    const int ey = (int)(CK[SEG + Sa[1][e]] >> 9) -
+                                   (int)(CK[SEG + Sa[1][st]] >> 9);
+                    const int ez = (int)(CK[2 * SEG + Sa[2][e]] >> 9) -
+                                   (int)(CK[2 * SEG + Sa[2][st]] >> 9);
+                    int best = ex;
+                    if (ey > best) {
+                        ax = 1;
+                        best = ey;
+                    }
+                    if (ez > best) ax = 2;
+                } else {
+                    const T ex = px[V[s0 + Sa[0][e]]] - px[V[s0 + Sa[0][st]]];
+                    const T ey = py[V[s0 + Sa[1][e]]] - py[V[s0 + Sa[1][st]]];
+                    const T ez = pz[V[s0 + Sa[2][e]]] - pz[V[s0 + Sa[2][st]]];
+                    T best = ex;
+                    if (ey > best) {
+                        ax = 1;
+                        best = ey;
+                    }
+                    if (ez > best) ax = 2;
+                }
+                const int nl = (c + L - 1) / L;
+                const int nlft = (nl + 1) / 2;
+                lf = (int)(((long long)c * nlft + nl / 2) / nl);
+                any = 1;
+            }
+            nleft[k] = lf;
+            naxis[k] = ax;
+        }
+        if (!__syncthreads_or(any)) break;
+        if (t == 0) {
+            int acc = 0;
+            for (int k = 0; k < nn; ++k) {
+                nchild[k] = acc;
+                acc += nleft[k] ? 2 : 1;
+            }
+            s_nn = acc;
+        }
+        // left-side flag per position in the segment (indexed by position
+        // in the unsorted segment, which every sorted array refers to)
+        for (int p = t; p < cnt; p += SEG_TB) {
+            const int k = en[p];
+            const int lf = nleft[k];
+            if (lf) {
+                const int ax = naxis[k];
+                const uint16_t *Sx = ax == 0 ? Sa[0] : (ax == 1 ? Sa[1] : Sa[2]);
+                flag[Sx[p]] = (p - nst[cur][k] < lf) ? 1 : 0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            // stable partition of every splitting node of Sa[b]
+            const int p0 = t * PER;
+            int fl[16];
+            int sum = 0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                if (u >= PER) break;
+                const int p = p0 + u;
+                int f = 1;
+                if (p < cnt) {
+                    const int k = en[p];
+                    if (nleft[k]) f = flag[Sa[b][p]];
+                } else {
+                    f = 0;
+                }
+                fl[u] = f;
+                sum += f;
+            }
+            int tot;
+            int run = block_excl_scan(sum, wsum, &tot);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                if (u >= PER) break;
+                const int p = p0 + u;
+                if (p < cnt) pre[p] = (uint16_t)run;
+                run += fl[u];
+            }
+            __syncthreads();
+            for (int p = t; p < cnt; p += SEG_TB) {
+                const int k = en[p];
+                const int st = nst[cur][k];
+                const int lf = nleft[k];
+                const int lc = lf ? lf : ncnt[cur][k];
+                const int f = lf ? flag[Sa[b][p]] : 1;
+                const int rl = (int)pre[p] - (int)pre[st];
+                const int np = f ? st + rl : st + lc + (p - st - rl);
+                spare[np] = Sa[b][p];
+            }
+            __syncthreads();
+            uint16_t *tmp = Sa[b];
+            Sa[b] = spare;
+            spare = tmp;
+        }
+        // children and the position -> node map of the next level
+        const int nxt = cur ^ 1;
+        for (int k = t; k < nn; k += SEG_TB) {
+            const int cb = nchild[k], st = nst[cur][k], c = ncnt[cur][k];
+            const int lf = nleft[k];
+            if (lf) {
+                nst[nxt][cb] = st;
+                ncnt[nxt][cb] = lf;
+                nst[nxt][cb + 1] = st + lf;
+                ncnt[nxt][cb + 1] = c - lf;
+            } else {
+                nst[nxt][cb] = st;
+                ncnt[nxt][cb] = c;
+            }
+        }
+        for (int p = t; p < cnt; p += SEG_TB) {
+            const int k = en[p];
+            const int lf = nleft[k];
+            en[p] = (uint16_t)(nchild[k] +
+                               ((lf && p - nst[cur][k] >= lf) ? 1 : 0));
+        }
+        __syncthreads();
+        nn = s_nn;
+        cur = nxt;
+    }
+
+    // (c) leaves and the tree order of the segment
+    for (int p = t; p < cnt; p += SEG_TB) S0g[s0 + p] = V[s0 + Sa[0][p]];
+    for (int k = t; k < nn; k += SEG_TB) {
+        lf_start[loff + k] = s0 + nst[cur][k];
+        lf_count[loff + k] = ncnt[cur][k];
+        lf_key[loff + k] = key;
+    }
+}
+
+size_t seg_lds_bytes(int SEG) {
+    const int MAXN = SEG / 16 + 2;
+    return seg_key_bytes(SEG) + (size_t)SEG * 6 + (size_t)MAXN * 7 * 4;
 }
 
 int ensure_all(crk_tree *t, int64_t n, int64_t leaf_cap, size_t elem,
@@ -438,111 +990,192 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
     int32_t *flags = t->f_pos.as<int32_t>();
     int32_t *sf = t->f_scan.as<int32_t>();
     const int key_bits = 23 + t->bin_bits;
-
-    // 1. one stable sort per axis by (bin key, coordinate), caller index as
-    //    the tie-break (input order)
-    for (int a = 0; a < 3; ++a) {
+    const int L = t->leaf_max;
+    // segments: one per non-empty (species, bin)
+    const int64_t seg_cap = std::min<int64_t>(n, 2 * t->total_bins);
+    int cur = 0;
+    bool use_lds = cap ? t->lds_tree : ctx->tuning.tree_lds != 0;
+    if (use_lds) {
+        // 1. one stable sort by (species, bin): caller order inside a bin
         hipLaunchKernelGGL((keys_kernel<T>), dim3(grid_for(n)), dim3(TB), 0, s,
                            gx, gy, gz, gh, dx, dy, dz, t->n_gas, n, t->n_boxes,
                            t->d_gas_off.as<int64_t>(), t->d_dm_off.as<int64_t>(),
                            t->d_ncm.as<int>(), t->d_bin_base.as<int64_t>(),
-                           t->d_hmax.as<double>(), t->total_bins, a,
-                           a == 0 ? 1 : 0, px, py, pz, ph, K[0], Vv[0], err);
+                           t->d_hmax.as<double>(), t->total_bins, 3, 1, px, py,
+                           pz, ph, K[0], Vv[0], err);
         CRK_HIP(hipGetLastError());
         hipError_t he;
-        int r = radix_sort_u64_i32(K, Vv, n, key_bits, ctx->scratch.p, s, &he);
+        const int r = radix_sort_u64_i32(K, Vv, n, t->bin_bits, ctx->scratch.p,
+                                         s, &he);
         CRK_HIP(he);
-        hipLaunchKernelGGL(copy_i32_kernel, dim3(grid_for(n)), dim3(TB), 0, s,
-                           Vv[r], S[a], n);
+        hipLaunchKernelGGL(seg_flags_kernel, dim3(grid_for(n)), dim3(TB), 0, s,
+                           K[r], n, 0, flags, t->binkey.as<int32_t>());
         CRK_HIP(hipGetLastError());
-        if (a == 0) {
-            // 2. segments of equal (species, bin) are the initial k-d nodes
-            hipLaunchKernelGGL(seg_flags_kernel, dim3(grid_for(n)), dim3(TB), 0,
-                               s, K[r], n, flags, t->binkey.as<int32_t>());
-            CRK_HIP(hipGetLastError());
-        }
-    }
-    CRK_HIP(exclusive_scan_i32(flags, sf, n, cnt + C_NN, ctx->scratch.p, s));
-    int cur = 0;
-    int32_t *en = t->elem_node.as<int32_t>();
-    int32_t *en2 = t->elem_node2.as<int32_t>();
-    hipLaunchKernelGGL(seg_nodes_kernel, dim3(grid_for(n)), dim3(TB), 0, s,
-                       flags, sf, t->binkey.as<int32_t>(), n,
-                       t->nd_start[cur].as<int32_t>(),
-                       t->nd_key[cur].as<int32_t>(), en);
-    CRK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(node_counts_kernel, dim3(grid_for(lcap)), dim3(TB), 0, s,
-                       t->nd_start[cur].as<int32_t>(), cnt + C_NN, lcap, n,
-                       t->nd_count[cur].as<int32_t>());
-    CRK_HIP(hipGetLastError());
-
-    // 3. k-d levels
-    const int max_levels = cap ? t->kd_levels + 2 : 64;
-    int levels_run = 0;
-    for (int lev = 0; lev < max_levels; ++lev) {
-        const int last = (cap && lev == max_levels - 1) ? 1 : 0;
-        int32_t *ns = t->nd_start[cur].as<int32_t>();
-        int32_t *nc = t->nd_count[cur].as<int32_t>();
-        int32_t *nk = t->nd_key[cur].as<int32_t>();
-        CRK_HIP(fill_i32(cnt + C_ANY, 0, 1, s));
-        hipLaunchKernelGGL((kd_plan_kernel<T>), dim3(grid_for(lcap)), dim3(TB), 0,
-                           s, ns, nc, cnt + C_NN, lcap, t->leaf_max, last, S[0],
-                           S[1], S[2], px, py, pz, t->nd_split.as<int32_t>(),
-                           t->nd_left.as<int32_t>(), t->nd_axis.as<int32_t>(),
-                           t->nd_nchild.as<int32_t>(), cnt + C_ANY, err);
+        CRK_HIP(exclusive_scan_i32(flags, sf, n, cnt + C_NN, ctx->scratch.p, s));
+        hipLaunchKernelGGL(seg_nodes_kernel, dim3(grid_for(n)), dim3(TB), 0, s,
+                           flags, sf, t->binkey.as<int32_t>(), n,
+                           t->nd_start[0].as<int32_t>(),
+                           t->nd_key[0].as<int32_t>(),
+                           t->elem_node.as<int32_t>());
         CRK_HIP(hipGetLastError());
-        if (last) break;
+        hipLaunchKernelGGL(node_counts_kernel, dim3(grid_for(seg_cap)), dim3(TB),
+                           0, s, t->nd_start[0].as<int32_t>(), cnt + C_NN,
+                           seg_cap, n, t->nd_count[0].as<int32_t>());
+        CRK_HIP(hipGetLastError());
+        // 2. leaves per segment and their offsets; the largest segment
+        CRK_HIP(fill_i32(cnt + C_MAXC, 0, 1, s));
+        hipLaunchKernelGGL(seg_leafcount_kernel, dim3(grid_for(seg_cap)),
+                           dim3(TB), 0, s, t->nd_count[0].as<int32_t>(),
+                           cnt + C_NN, seg_cap, L,
+                           t->nd_nchild.as<int32_t>(), cnt + C_MAXC);
+        CRK_HIP(hipGetLastError());
+        CRK_HIP(exclusive_scan_i32(t->nd_nchild.as<int32_t>(),
+                                   t->nd_child.as<int32_t>(), seg_cap,
+                                   cnt + C_NN_NEXT, ctx->scratch.p, s));
         if (!cap) {
             int32_t *hb = ctx->err_host.as<int32_t>() + 8;
-            CRK_HIP(hipMemcpyAsync(hb, cnt + C_ANY, 4, hipMemcpyDeviceToHost, s));
+            CRK_HIP(hipMemcpyAsync(hb, cnt + C_MAXC, 4, hipMemcpyDeviceToHost, s));
             CRK_HIP(hipStreamSynchronize(s));
-            if (*hb == 0) break;
+            const int maxc = hb[0];
+            if (maxc > SEG_MAX) {
+                use_lds = false;
+            } else {
+                // room for growth of the largest bin before a captured
+                // replay reports capacity
+                int seg = 64;
+                while (seg < maxc + maxc / 4 + 16 && seg < SEG_MAX) seg <<= 1;
+                t->seg_size = seg;
+                int lev = 0;
+                while ((1 << lev) < seg_leaves(maxc, L)) ++lev;
+                t->kd_levels = lev;
+            }
+            t->lds_tree = use_lds;
         }
-        ++levels_run;
-        CRK_HIP(exclusive_scan_i32(t->nd_nchild.as<int32_t>(),
-                                   t->nd_child.as<int32_t>(), lcap,
-                                   cnt + C_NN_NEXT, ctx->scratch.p, s));
-        hipLaunchKernelGGL(kd_flag_kernel, dim3(grid_for(n)), dim3(TB), 0, s, en,
-                           ns, t->nd_split.as<int32_t>(),
-                           t->nd_left.as<int32_t>(), t->nd_axis.as<int32_t>(),
-                           S[0], S[1], S[2], n, cnt + C_NN_NEXT, lcap,
-                           t->flag_c.as<int32_t>());
-        CRK_HIP(hipGetLastError());
-        for (int a = 0; a < 3; ++a) {
-            hipLaunchKernelGGL(kd_part_flags_kernel, dim3(grid_for(n)), dim3(TB),
-                               0, s, en, t->nd_split.as<int32_t>(), S[a],
-                               t->flag_c.as<int32_t>(), n, cnt + C_NN_NEXT,
-                               lcap, flags);
+        if (use_lds) {
+            // 3. sorts and k-d levels of every segment in LDS
+            const int SEG = t->seg_size;
+            hipLaunchKernelGGL((seg_build_kernel<T>),
+                               dim3((unsigned)std::max<int64_t>(1, seg_cap)),
+                               dim3(SEG_TB), seg_lds_bytes(SEG), s, cnt + C_NN,
+                               t->nd_start[0].as<int32_t>(),
+                               t->nd_count[0].as<int32_t>(),
+                               t->nd_key[0].as<int32_t>(),
+                               t->nd_child.as<int32_t>(), Vv[r], px, py, pz, L,
+                               SEG, lcap, S[0], t->nd_start[1].as<int32_t>(),
+                               t->nd_count[1].as<int32_t>(),
+                               t->nd_key[1].as<int32_t>(), err);
             CRK_HIP(hipGetLastError());
-            CRK_HIP(exclusive_scan_i32(flags, sf, n, nullptr, ctx->scratch.p, s));
-            hipLaunchKernelGGL(kd_part_scatter_kernel, dim3(grid_for(n)),
-                               dim3(TB), 0, s, en, ns, nc,
-                               t->nd_split.as<int32_t>(),
-                               t->nd_left.as<int32_t>(), flags, sf, S[a], n,
-                               cnt + C_NN_NEXT, lcap, Sn[a]);
+            hipLaunchKernelGGL(next_count_kernel, dim3(1), dim3(1), 0, s,
+                               cnt + C_NN_NEXT, lcap, cnt + C_NN, err);
             CRK_HIP(hipGetLastError());
+            cur = 1;
         }
-        hipLaunchKernelGGL(kd_children_kernel, dim3(grid_for(lcap)), dim3(TB), 0,
-                           s, ns, nc, nk, t->nd_split.as<int32_t>(),
-                           t->nd_left.as<int32_t>(), t->nd_child.as<int32_t>(),
-                           cnt + C_NN, cnt + C_NN_NEXT, lcap,
-                           t->nd_start[cur ^ 1].as<int32_t>(),
-                           t->nd_count[cur ^ 1].as<int32_t>(),
-                           t->nd_key[cur ^ 1].as<int32_t>());
-        CRK_HIP(hipGetLastError());
-        hipLaunchKernelGGL(kd_elem_node_kernel, dim3(grid_for(n)), dim3(TB), 0, s,
-                           en, ns, t->nd_split.as<int32_t>(),
-                           t->nd_left.as<int32_t>(), t->nd_child.as<int32_t>(),
-                           n, cnt + C_NN_NEXT, lcap, en2);
-        CRK_HIP(hipGetLastError());
-        hipLaunchKernelGGL(next_count_kernel, dim3(1), dim3(1), 0, s,
-                           cnt + C_NN_NEXT, lcap, cnt + C_NN, err);
-        CRK_HIP(hipGetLastError());
-        for (int a = 0; a < 3; ++a) std::swap(S[a], Sn[a]);
-        std::swap(en, en2);
-        cur ^= 1;
     }
-    if (!cap) t->kd_levels = levels_run;
+    if (!use_lds) {
+        // 1. one stable sort per axis by (bin key, coordinate), caller index as
+        //    the tie-break (input order)
+        for (int a = 0; a < 3; ++a) {
+            hipLaunchKernelGGL((keys_kernel<T>), dim3(grid_for(n)), dim3(TB), 0, s,
+                               gx, gy, gz, gh, dx, dy, dz, t->n_gas, n, t->n_boxes,
+                               t->d_gas_off.as<int64_t>(), t->d_dm_off.as<int64_t>(),
+                               t->d_ncm.as<int>(), t->d_bin_base.as<int64_t>(),
+                               t->d_hmax.as<double>(), t->total_bins, a,
+                               a == 0 ? 1 : 0, px, py, pz, ph, K[0], Vv[0], err);
+            CRK_HIP(hipGetLastError());
+            hipError_t he;
+            int r = radix_sort_u64_i32(K, Vv, n, key_bits, ctx->scratch.p, s, &he);
+            CRK_HIP(he);
+            hipLaunchKernelGGL(copy_i32_kernel, dim3(grid_for(n)), dim3(TB), 0, s,
+                               Vv[r], S[a], n);
+            CRK_HIP(hipGetLastError());
+            if (a == 0) {
+                // 2. segments of equal (species, bin) are the initial k-d nodes
+                hipLaunchKernelGGL(seg_flags_kernel, dim3(grid_for(n)), dim3(TB), 0,
+                                   s, K[r], n, 23, flags, t->binkey.as<int32_t>());
+                CRK_HIP(hipGetLastError());
+            }
+        }
+        CRK_HIP(exclusive_scan_i32(flags, sf, n, cnt + C_NN, ctx->scratch.p, s));
+        int32_t *en = t->elem_node.as<int32_t>();
+        int32_t *en2 = t->elem_node2.as<int32_t>();
+        hipLaunchKernelGGL(seg_nodes_kernel, dim3(grid_for(n)), dim3(TB), 0, s,
+                           flags, sf, t->binkey.as<int32_t>(), n,
+                           t->nd_start[cur].as<int32_t>(),
+                           t->nd_key[cur].as<int32_t>(), en);
+        CRK_HIP(hipGetLastError());
+        hipLaunchKernelGGL(node_counts_kernel, dim3(grid_for(lcap)), dim3(TB), 0, s,
+                           t->nd_start[cur].as<int32_t>(), cnt + C_NN, lcap, n,
+                           t->nd_count[cur].as<int32_t>());
+        CRK_HIP(hipGetLastError());
+
+        // 3. k-d levels
+        const int max_levels = cap ? t->kd_levels + 2 : 64;
+        int levels_run = 0;
+        for (int lev = 0; lev < max_levels; ++lev) {
+            const int last = (cap && lev == max_levels - 1) ? 1 : 0;
+            int32_t *ns = t->nd_start[cur].as<int32_t>();
+            int32_t *nc = t->nd_count[cur].as<int32_t>();
+            int32_t *nk = t->nd_key[cur].as<int32_t>();
+            CRK_HIP(fill_i32(cnt + C_ANY, 0, 1, s));
+            hipLaunchKernelGGL((kd_plan_kernel<T>), dim3(grid_for(lcap)), dim3(TB), 0,
+                               s, ns, nc, cnt + C_NN, lcap, t->leaf_max, last, S[0],
+                               S[1], S[2], px, py, pz, t->nd_split.as<int32_t>(),
+                               t->nd_left.as<int32_t>(), t->nd_axis.as<int32_t>(),
+                               t->nd_nchild.as<int32_t>(), cnt + C_ANY, err);
+            CRK_HIP(hipGetLastError());
+            if (last) break;
+            if (!cap) {
+                int32_t *hb = ctx->err_host.as<int32_t>() + 8;
+                CRK_HIP(hipMemcpyAsync(hb, cnt + C_ANY, 4, hipMemcpyDeviceToHost, s));
+                CRK_HIP(hipStreamSynchronize(s));
+                if (*hb == 0) break;
+            }
+            ++levels_run;
+            CRK_HIP(exclusive_scan_i32(t->nd_nchild.as<int32_t>(),
+                                       t->nd_child.as<int32_t>(), lcap,
+                                       cnt + C_NN_NEXT, ctx->scratch.p, s));
+            hipLaunchKernelGGL(kd_flag_kernel, dim3(grid_for(n)), dim3(TB), 0, s, en,
+                               ns, t->nd_split.as<int32_t>(),
+                               t->nd_left.as<int32_t>(), t->nd_axis.as<int32_t>(),
+                               S[0], S[1], S[2], n, cnt + C_NN_NEXT, lcap,
+                               t->flag_c.as<int32_t>());
+            CRK_HIP(hipGetLastError());
+            for (int a = 0; a < 3; ++a) {
+                hipLaunchKernelGGL(kd_part_flags_kernel, dim3(grid_for(n)), dim3(TB),
+                                   0, s, en, t->nd_split.as<int32_t>(), S[a],
+                                   t->flag_c.as<int32_t>(), n, cnt + C_NN_NEXT,
+                                   lcap, flags);
+                CRK_HIP(hipGetLastError());
+                CRK_HIP(exclusive_scan_i32(flags, sf, n, nullptr, ctx->scratch.p, s));
+                hipLaunchKernelGGL(kd_part_scatter_kernel, dim3(grid_for(n)),
+                                   dim3(TB), 0, s, en, ns, nc,
+                                   t->nd_split.as<int32_t>(),
+                                   t->nd_left.as<int32_t>(), flags, sf, S[a], n,
+                                   cnt + C_NN_NEXT, lcap, Sn[a]);
+                CRK_HIP(hipGetLastError());
+            }
+            hipLaunchKernelGGL(kd_children_kernel, dim3(grid_for(lcap)), dim3(TB), 0,
+                               s, ns, nc, nk, t->nd_split.as<int32_t>(),
+                               t->nd_left.as<int32_t>(), t->nd_child.as<int32_t>(),
+                               cnt + C_NN, cnt + C_NN_NEXT, lcap,
+                               t->nd_start[cur ^ 1].as<int32_t>(),
+                               t->nd_count[cur ^ 1].as<int32_t>(),
+                               t->nd_key[cur ^ 1].as<int32_t>());
+            CRK_HIP(hipGetLastError());
+            hipLaunchKernelGGL(kd_elem_node_kernel, dim3(grid_for(n)), dim3(TB), 0, s,
+                               en, ns, t->nd_split.as<int32_t>(),
+                               t->nd_left.as<int32_t>(), t->nd_child.as<int32_t>(),
+                               n, cnt + C_NN_NEXT, lcap, en2);
+            CRK_HIP(hipGetLastError());
+            hipLaunchKernelGGL(next_count_kernel, dim3(1), dim3(1), 0, s,
+                               cnt + C_NN_NEXT, lcap, cnt + C_NN, err);
+            CRK_HIP(hipGetLastError());
+            for (int a = 0; a < 3; ++a) std::swap(S[a], Sn[a]);
+            std::swap(en, en2);
+            cur ^= 1;
+        }
+        if (!cap) t->kd_levels = levels_run;
+    }
     // remember which buffers hold the final state
     t->cur_nodes = cur;
     for (int a = 0; a < 3; ++a) t->S_final[a] = S[a];
@@ -555,19 +1188,44 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
                        t->hsm.as<T>());
     CRK_HIP(hipGetLastError());
     CRK_HIP(fill_i32(t->bin_cnt.as<int32_t>(), 0, nbin2 + 1, s));
-    hipLaunchKernelGGL((leaves_kernel<T>), dim3(grid_for(lcap)), dim3(TB), 0, s,
+    hipLaunchKernelGGL((leaves_kernel<T>),
+                       dim3((unsigned)std::max<int64_t>(1, (lcap + 3) / 4)),
+                       dim3(256), 0, s,
                        t->nd_start[cur].as<int32_t>(),
                        t->nd_count[cur].as<int32_t>(),
-                       t->nd_key[cur].as<int32_t>(), cnt + C_NN, lcap, S[0], S[1],
-                       S[2], px, py, pz, t->hsm.as<T>(), t->total_bins,
-                       t->n_boxes, t->d_bin_base.as<int64_t>(),
-                       t->leaf_box.as<int32_t>(), t->leaf_lo.as<T>(),
-                       t->leaf_hi.as<T>(), t->leaf_hmax.as<T>(),
-                       t->bin_cnt.as<int32_t>());
+                       t->nd_key[cur].as<int32_t>(), cnt + C_NN, lcap,
+                       t->pos[0].as<T>(), t->pos[1].as<T>(), t->pos[2].as<T>(),
+                       t->hsm.as<T>(), t->total_bins, t->n_boxes,
+                       t->d_bin_base.as<int64_t>(), t->leaf_box.as<int32_t>(),
+                       t->leaf_lo.as<T>(), t->leaf_hi.as<T>(),
+                       t->leaf_hmax.as<T>(), t->bin_cnt.as<int32_t>());
     CRK_HIP(hipGetLastError());
     CRK_HIP(exclusive_scan_i32(t->bin_cnt.as<int32_t>(),
                                t->bin_leaf.as<int32_t>(), nbin2 + 1, nullptr,
                                ctx->scratch.p, s));
+    // 5. sub-leaves (leaves of <= 64 particles, for the sub-leaf sweeps)
+    t->has_sub = t->leaf_max <= 64 && ctx->tuning.sub_sweep != 0;
+    if (t->has_sub) {
+        const int64_t sl = 4 * (lcap + 1);
+        CRK_TRY(t->sub_nsub.ensure((lcap + 1) * 4, cap));
+        CRK_TRY(t->sub_start.ensure(sl * 4, cap));
+        CRK_TRY(t->sub_count.ensure(sl * 4, cap));
+        CRK_TRY(t->sub_lo.ensure(3 * sl * sizeof(T), cap));
+        CRK_TRY(t->sub_hi.ensure(3 * sl * sizeof(T), cap));
+        CRK_TRY(t->sub_hmax.ensure(sl * sizeof(T), cap));
+        const int64_t grid = cap ? lcap : std::max<int64_t>(1, 0);
+        (void)grid;
+        hipLaunchKernelGGL((subleaf_kernel<T>), dim3((unsigned)std::max<int64_t>(1, lcap)),
+                           dim3(64), 0, s, cnt + C_NN,
+                           t->nd_start[cur].as<int32_t>(),
+                           t->nd_count[cur].as<int32_t>(), lcap,
+                           t->pos[0].as<T>(), t->pos[1].as<T>(), t->pos[2].as<T>(),
+                           t->hsm.as<T>(), t->perm.as<int32_t>(),
+                           t->sub_nsub.as<int32_t>(), t->sub_start.as<int32_t>(),
+                           t->sub_count.as<int32_t>(), t->sub_lo.as<T>(),
+                           t->sub_hi.as<T>(), t->sub_hmax.as<T>());
+        CRK_HIP(hipGetLastError());
+    }
     if (!cap) {
         // sizes for the host: leaves, gas leaves
         int32_t *hb = ctx->err_host.as<int32_t>() + 8;

@@ -325,3 +325,69 @@ def test_capacity_overflow_in_graph_is_reported(step_cls):
         assert e.value.status == CRK_ECAPACITY
     finally:
         st.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_sub_leaf_sweeps_match_whole_leaf_sweep(orc, step_cls, precision):
+    """Sub-leaf sweeps (lane groups; one wavefront per sub-leaf with four
+    lanes per particle) only drop candidates that are out of range of every
+    particle of the sub-leaf.  The sub-leaf split reorders the slots inside
+    each leaf and the split form sums each particle's candidates in four
+    interleaved streams, so sums agree with the whole-leaf sweep up to
+    rounding order, and all agree with the oracle."""
+    print(f"case sub-leaf sweeps vs whole-leaf sweep {precision}", flush=True)
+    wl = W.random_uniform(6000, 5000, 1301, n_ngb=48.0, clustered=True)
+    outs = []
+    for ss in (0, 1, 2):
+        st, o = run(step_cls, wl, precision,
+                    tuning=dict(leaf_max=64, sub_sweep=ss))
+        outs.append(o)
+        st.close()
+    tol_same = 2e-6 if precision == "fp32" else 1e-12
+    compare(outs[1], outs[0], tol_same)
+    compare(outs[2], outs[0], tol_same)
+    ref = orc.step(wl)
+    compare(outs[2], ref, FP32_TOL if precision == "fp32" else FP64_TOL)
+
+
+@pytest.mark.parametrize("tuning", [dict(grid_mult=16), dict(xcd_remap=1),
+                                    dict(walk_mask=15),
+                                    dict(grid_mult=8, leaf_max=128)])
+def test_launch_shapes_are_bitwise_identical(step_cls, tuning):
+    """The persistent cost-ordered queue, the XCD remap and the per-lane hit
+    walk change only which workgroup or lane order runs a leaf: each lane
+    still meets its candidates in list order, so the sums are bitwise the
+    same as one workgroup per leaf with the broadcast sweep."""
+    print(f"case launch shape {tuning}", flush=True)
+    wl = W.random_uniform(6000, 5000, 1501, n_ngb=48.0, clustered=True)
+    L = tuning.get("leaf_max", 64)
+    st, ref = run(step_cls, wl, "fp32", tuning=dict(leaf_max=L))
+    st.close()
+    st, got = run(step_cls, wl, "fp32", tuning=dict(leaf_max=L, **{
+        k: v for k, v in tuning.items() if k != "leaf_max"}))
+    st.close()
+    for k in KEYS:
+        assert np.array_equal(ref[k], got[k]), k
+
+
+@pytest.mark.parametrize("precision,L,cm", [("fp32", 64, 0.0), ("fp64", 32, 0.0),
+                                            ("fp32", 64, 64.0)])
+def test_lds_tree_matches_global_sorts(step_cls, precision, L, cm):
+    """The per-bin LDS build gives the same tree as the per-axis global
+    sorts (same leaves, same slot order), hence bitwise the same outputs.
+    cm_factor 64 makes one bin per species per box, larger than the LDS
+    segment bound, which takes the global path under either setting."""
+    print(f"case lds tree vs global sorts {precision} L={L} cm={cm}",
+          flush=True)
+    wl = W.random_uniform(6000, 5000, 1401, n_ngb=48.0, clustered=True)
+    trees, outs = [], []
+    for lds in (0, 1):
+        st, o = run(step_cls, wl, precision,
+                    tuning=dict(leaf_max=L, cm_factor=cm, tree_lds=lds))
+        trees.append(st.tree.leaves())
+        outs.append(o)
+        st.close()
+    for a, b in zip(trees[0], trees[1]):
+        assert np.array_equal(a, b)
+    for k in KEYS:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
