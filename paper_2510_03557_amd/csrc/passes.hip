@@ -137,15 +137,18 @@ __device__ inline void decode_shift(uint32_t code, int &sx, int &sy, int &sz) {
 
 // Walks the list entries [e0, e1) of one leaf.  Each wavefront loads the
 // leaf data of 64 entries at once (one entry per lane) and prefetches the
-// positions of entry k + 1 while entry k is processed, so the dependent
-// global loads of the walk overlap.  visit(js, jc, code, hJ, x, y, z) gets
-// the j-leaf's first slot, size (clamped to CLAMP), periodic image code,
-// h_max, and the raw position of slot js + t for t < jc.  Entries that were
-// never written (after a capacity error) are skipped.  Every thread of the
+// position and the P::NP prefetched fields of slot js + t of entry k + 1
+// while entry k is processed, so the dependent global loads of the walk
+// overlap.  visit(js, jc, code, hJ, x, y, z, f) gets the j-leaf's first
+// slot, size (clamped to CLAMP), periodic image code, h_max, and the raw
+// position and fields of slot js + t for t < jc.  Entries that were never
+// written (after a capacity error) are skipped.  Every thread of the
 // workgroup calls visit for every entry.
-template <typename T, int CLAMP, typename F>
-__device__ __forceinline__ void walk_list(const TreeView<T> &tv, int64_t e0,
-                                          int64_t e1, int t, F &&visit) {
+template <typename T, typename P, int CLAMP, typename F>
+__device__ __forceinline__ void walk_list(const TreeView<T> &tv,
+                                          const typename P::Args &pa,
+                                          int64_t e0, int64_t e1, int t,
+                                          F &&visit) {
     const int lane = t & 63;
     const int nl = *tv.n_leaves;
     for (int64_t eb = e0; eb < e1; eb += 64) {
@@ -164,14 +167,21 @@ __device__ __forceinline__ void walk_list(const TreeView<T> &tv, int64_t e0,
         }
         int js = __shfl(bjs, 0), jc = __shfl(bjc, 0);
         T nx = T(0), ny = T(0), nz = T(0);
+        T nf[P::NP];
+#pragma unroll
+        for (int u = 0; u < P::NP; ++u) nf[u] = T(0);
         if (t < jc) {
             nx = tv.px[js + t];
             ny = tv.py[js + t];
             nz = tv.pz[js + t];
+            P::fetch_j(nf, pa, tv, js + t);
         }
         for (int k = 0; k < nb; ++k) {
             const int cjs = js, cjc = jc;
             const T cx = nx, cy = ny, cz = nz;
+            T cf[P::NP];
+#pragma unroll
+            for (int u = 0; u < P::NP; ++u) cf[u] = nf[u];
             const int code = __shfl(bcode, k);
             const T hJ = __shfl(bh, k);
             if (k + 1 < nb) {
@@ -181,10 +191,11 @@ __device__ __forceinline__ void walk_list(const TreeView<T> &tv, int64_t e0,
                     nx = tv.px[js + t];
                     ny = tv.py[js + t];
                     nz = tv.pz[js + t];
+                    P::fetch_j(nf, pa, tv, js + t);
                 }
             }
             if (cjc == 0) continue;
-            visit(cjs, cjc, (uint32_t)code, hJ, cx, cy, cz);
+            visit(cjs, cjc, (uint32_t)code, hJ, cx, cy, cz, cf);
         }
     }
 }
@@ -193,7 +204,8 @@ __device__ __forceinline__ void walk_list(const TreeView<T> &tv, int64_t e0,
 //   P::NJ        number of T fields staged per j particle
 //   P::I         per-lane i-state
 //   P::load_i(I&, args, tv, i, ex, ey, ez, box)
-//   P::load_j(T* dst, args, tv, j, fx, fy, fz)
+//   P::NP, P::fetch_j(T f[NP], args, tv, j)  fields loaded with the position
+//   P::store_j(T* dst, f, args, tv, j, fx, fy, fz)  stage a culling survivor
 //   P::range(args, tv, box, hmax_I, hmax_J)  interaction range of a leaf pair
 //   P::Tile / P::Acc  per-sweep sums and compensated totals
 //   P::pair(Tile&, const I&, const T* jd, bool self)
@@ -355,8 +367,9 @@ __device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
         acc.fold(tile);
         __syncthreads();
     };
-    walk_list<T, BLOCK>(tv, e0, e1, t, [&](int js, int jc, uint32_t code,
-                                            T hJ, T x, T y, T z) {
+    walk_list<T, P, BLOCK>(tv, pa, e0, e1, t, [&](int js, int jc, uint32_t code,
+                                                  T hJ, T x, T y, T z,
+                                                  const T *f) {
         int sx, sy, sz;
         decode_shift(code, sx, sy, sz);
         if (nbuf + jc > CAP) {
@@ -392,7 +405,7 @@ __device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
         }
         if (keep) {
             const int pos = nbuf + off;
-            P::load_j(&sj[pos * P::NJ], pa, tv, j, fx, fy, fz);
+            P::store_j(&sj[pos * P::NJ], f, pa, tv, j, fx, fy, fz);
             sjid[pos] = j;
         }
         nbuf += tot;
@@ -487,8 +500,9 @@ __device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
         acc.fold(tile);
         __syncthreads();
     };
-    walk_list<T, 64>(tv, e0, e1, lane, [&](int js, int jc, uint32_t code,
-                                           T hJ, T x, T y, T z) {
+    walk_list<T, P, 64>(tv, pa, e0, e1, lane, [&](int js, int jc, uint32_t code,
+                                                  T hJ, T x, T y, T z,
+                                                  const T *f) {
         int sx, sy, sz;
         decode_shift(code, sx, sy, sz);
         if (nbuf + jc > CAP) {
@@ -512,7 +526,7 @@ __device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
         const uint64_t m = __ballot(keep);
         if (keep) {
             const int pos = nbuf + __popcll(m & lt_mask);
-            P::load_j(&sj[pos * P::NJ], pa, tv, j, fx, fy, fz);
+            P::store_j(&sj[pos * P::NJ], f, pa, tv, j, fx, fy, fz);
             sjid[pos] = j;
         }
         nbuf += __popcll(m);
@@ -609,12 +623,17 @@ template <typename T> struct DensityPass {
         is.h = tv.h[i];
         is.ih2 = T(1) / (is.h * is.h);
     }
-    __device__ static void load_j(T *d, const Args &a, const TreeView<T> &,
-                                  int j, T fx, T fy, T fz) {
+    static constexpr int NP = 1;  // prefetched with the position: m
+    __device__ static void fetch_j(T *f, const Args &a, const TreeView<T> &,
+                                   int j) {
+        f[0] = a.m[j];
+    }
+    __device__ static void store_j(T *d, const T *f, const Args &,
+                                   const TreeView<T> &, int, T fx, T fy, T fz) {
         d[0] = fx;
         d[1] = fy;
         d[2] = fz;
-        d[3] = a.m[j];
+        d[3] = f[0];
     }
     __device__ static bool test(const I &is, const T *jd, bool) {
         const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
@@ -702,13 +721,19 @@ template <typename T> struct CoeffPass {
         is.h = tv.h[i];
         is.ih = T(1) / is.h;
     }
-    __device__ static void load_j(T *d, const Args &a, const TreeView<T> &,
-                                  int j, T fx, T fy, T fz) {
+    static constexpr int NP = 2;  // prefetched with the position: V, m
+    __device__ static void fetch_j(T *f, const Args &a, const TreeView<T> &,
+                                   int j) {
+        f[0] = a.V[j];
+        f[1] = a.m[j];
+    }
+    __device__ static void store_j(T *d, const T *f, const Args &,
+                                   const TreeView<T> &, int, T fx, T fy, T fz) {
         d[0] = fx;
         d[1] = fy;
         d[2] = fz;
-        d[3] = a.V[j];
-        d[4] = a.m[j];
+        d[3] = f[0];
+        d[4] = f[1];
         d[5] = T(0);
         d[6] = T(0);
         d[7] = T(0);
@@ -920,8 +945,13 @@ template <typename T> struct HydroPass {
 #pragma unroll
         for (int k = 0; k < HF; ++k) is.f[k] = a.f[k * a.n_gas + i];
     }
-    __device__ static void load_j(T *d, const Args &a, const TreeView<T> &,
-                                  int j, T fx, T fy, T fz) {
+    // the fields are many: loaded for the culling survivors only
+    static constexpr int NP = 1;
+    __device__ static void fetch_j(T *, const Args &, const TreeView<T> &,
+                                   int) {}
+    __device__ static void store_j(T *d, const T *, const Args &a,
+                                   const TreeView<T> &, int j, T fx, T fy,
+                                   T fz) {
         d[0] = fx;
         d[1] = fy;
         d[2] = fz;
@@ -1043,12 +1073,17 @@ template <typename T> struct GravityPass {
         is.two_rc = (T)(2.0 / rc);
         is.cin = (T)(2.0 / (35.0 * rc * rc * rc));
     }
-    __device__ static void load_j(T *d, const Args &a, const TreeView<T> &,
-                                  int j, T fx, T fy, T fz) {
+    static constexpr int NP = 1;  // prefetched with the position: G m
+    __device__ static void fetch_j(T *f, const Args &a, const TreeView<T> &,
+                                   int j) {
+        f[0] = a.m[j];
+    }
+    __device__ static void store_j(T *d, const T *f, const Args &,
+                                   const TreeView<T> &, int, T fx, T fy, T fz) {
         d[0] = fx;
         d[1] = fy;
         d[2] = fz;
-        d[3] = a.m[j];
+        d[3] = f[0];
     }
     __device__ static bool test(const I &is, const T *jd, bool) {
         const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
@@ -1170,12 +1205,17 @@ template <typename T> struct CountPass {
         is.rc2 = (T)(rc * rc);
         is.mode = a.mode;
     }
-    __device__ static void load_j(T *d, const Args &a, const TreeView<T> &tv,
-                                  int j, T fx, T fy, T fz) {
+    static constexpr int NP = 1;  // prefetched with the position: h
+    __device__ static void fetch_j(T *f, const Args &, const TreeView<T> &tv,
+                                   int j) {
+        f[0] = tv.h[j];
+    }
+    __device__ static void store_j(T *d, const T *f, const Args &a,
+                                   const TreeView<T> &, int, T fx, T fy, T fz) {
         d[0] = fx;
         d[1] = fy;
         d[2] = fz;
-        const T h = tv.h[j];
+        const T h = f[0];
         d[3] = a.mode % 3 == 1 ? T(1) / (h * h) : T(0);
     }
     __device__ static bool test(const I &is, const T *jd, bool self) {

@@ -1,9 +1,11 @@
 """GPU parity at the full sizes of the large configurations, in the launch
-shape the benchmark uses (persistent cost-ordered queue), checked on sampled
-particles: the oracle computes each sampled particle's outputs from its full
-neighbourhood closure (coefficients of its force neighbours, volumes of
-theirs), so the comparison is exact in definition.  Same bound as the small
-cases: relative RMS <= 1e-5 per output over the sample."""
+shape the benchmark uses (one workgroup per leaf of <= 64, HIP-graph-free
+single step), checked on sampled particles: the oracle computes each
+sampled particle's outputs from its full neighbourhood closure (coefficients
+of its force neighbours, volumes of theirs), so the comparison is exact in
+definition.  Same bound as the small cases: relative RMS <= 1e-5 per output
+over the sample.  The 13.5 M-particle batch also runs the sub-leaf split
+sweep."""
 import numpy as np
 import pytest
 
@@ -34,23 +36,26 @@ def pick_gas(wl, rng, n_random, n_dense):
     return g
 
 
-@pytest.mark.parametrize("name,n_gas_rand,n_dense,n_dm", [
-    ("uneven_boxes512", 60, 0, 200),
-    ("plummer64M", 24, 8, 200),
-    ("zeldovich448", 32, 0, 200),
+@pytest.mark.parametrize("name,n_gas_rand,n_dense,n_dm,sub", [
+    ("uneven_boxes512", 60, 0, 200, 0),
+    ("uneven_boxes512", 40, 0, 100, 2),
+    ("plummer64M", 24, 8, 200, 0),
+    ("zeldovich448", 32, 0, 200, 0),
 ])
-def test_large_config_sampled(orc, name, n_gas_rand, n_dense, n_dm):
+def test_large_config_sampled(orc, name, n_gas_rand, n_dense, n_dm, sub):
     from paper_2510_03557_amd.step import ShortRangeStep
-    print(f"case {name}: generating", flush=True)
+    print(f"case {name} sub_sweep={sub}: generating", flush=True)
     wl = W.make(name)
     print(f"case {name}: {wl.n_total} particles in {wl.n_boxes} boxes, GPU "
           "step", flush=True)
     st = ShortRangeStep(wl, precision="fp32",
-                        tuning=dict(leaf_max=64, grid_mult=4))
+                        tuning=dict(leaf_max=64, sub_sweep=sub))
     st.run()
     got = st.outputs()
     pairs = st.ctx.count_pairs(st.tree)
-    print(f"case {name}: pairs gather/hydro/gravity {pairs}", flush=True)
+    info = st.tree.info()
+    print(f"case {name}: pairs {pairs}, leaves {info['n_leaves']}, "
+          f"k-d levels {info['kd_levels']}", flush=True)
     st.close()
     del st
     rng = np.random.default_rng(11)
