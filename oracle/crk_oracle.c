@@ -6,9 +6,9 @@
  * baseline leg of the benchmark do.  It shares no code with the GPU path.
  *
  * Plain, slow and obviously correct: one target particle at a time, its
- * neighbours found either by brute force over all particles or by a
- * periodic linked-cell list, every sum accumulated in double precision in a
- * fixed order.  Inputs are the float32 values the GPU path consumes,
+ * neighbours found either by brute force over all particles or with a
+ * periodic k-d tree, every sum accumulated in double precision in
+ * ascending neighbour index.  Inputs are the float32 values the GPU path consumes,
  * widened to double.
  *
  * What each function computes (the paper names the method, CRKSPH, and the
@@ -32,7 +32,7 @@
  *     beyond r_c.
  * Parity-pinned by the tests under tests/ (normalisation, reproducing
  * conditions, lattice symmetry, conservation, closed forms, quadrature,
- * brute force versus cells).  The viscosity form and constants are a
+ * brute force versus the tree).  The viscosity form and constants are a
  * reading: parity unpinned beyond conservation and Galilean invariance.
  */
 #include <math.h>
@@ -121,74 +121,169 @@ double orc_grav_g(double r, double r_c, double eps)
 /* neighbour search                                                           */
 /* ------------------------------------------------------------------------ */
 
-/* A periodic linked-cell list over n points of the unit box with cells of
- * width >= w.  With fewer than three cells per side the search falls back
- * to brute force over all points. */
+/* A k-d tree over n points of the periodic unit box (coordinates in [1, 2)):
+ * nodes split at the median of their widest extent down to leaves of at
+ * most KD_LEAF points, each node with its bounding box and, when smoothing
+ * lengths are given, the largest h of its points.  brute = 1 skips the tree
+ * and tests every point.  Any search structure gives the same neighbours:
+ * every list is sorted by index, so the sums run in ascending neighbour
+ * index whatever the structure (and equal the brute-force sums exactly). */
+#define KD_LEAF 32
 typedef struct {
     int64_t n;
-    int nc;            /* cells per side, 0 = brute force */
-    int64_t *head;     /* nc^3 + 1 offsets */
-    int64_t *items;    /* n point indices, grouped by cell, ascending */
-} cells_t;
+    int brute;
+    int64_t *idx;          /* point indices, grouped by node */
+    int64_t nn;            /* nodes in use */
+    int64_t *start, *count;
+    int64_t *left;         /* first child (the second is left + 1), -1: leaf */
+    double *lo, *hi;       /* 3 per node */
+    double *hmax;          /* per node, NULL without smoothing lengths */
+} search_t;
 
-static int cell_of(double x, int nc)
+static double coord(const double *x, const double *y, const double *z, int a,
+                    int64_t i)
 {
-    int c = (int)floor((x - 1.0) * nc);
-    if (c < 0) c = 0;
-    if (c >= nc) c = nc - 1;
-    return c;
+    return a == 0 ? x[i] : (a == 1 ? y[i] : z[i]);
 }
 
-static int cells_build(cells_t *cl, int64_t n, const double *x,
-                       const double *y, const double *z, double w, int brute)
+/* Reorders idx[0..n) so that idx[k] holds the point of rank k along axis a
+ * (ties in any order), smaller keys before it and larger after it:
+ * quickselect with a three-way partition around a median-of-three pivot. */
+static void select_kth(int64_t *idx, int64_t n, int64_t k, const double *x,
+                       const double *y, const double *z, int a)
 {
-    cl->n = n;
-    cl->head = NULL;
-    cl->items = NULL;
-    int nc = (w > 0.0) ? (int)floor(1.0 / w) : 0;
-    if (nc > 512) nc = 512;
-    if (brute || nc < 3) {
-        cl->nc = 0;
+    int64_t lo = 0, hi = n;  /* the rank-k element lies in [lo, hi) */
+    while (hi - lo > 1) {
+        double p0 = coord(x, y, z, a, idx[lo]);
+        double p1 = coord(x, y, z, a, idx[lo + (hi - lo) / 2]);
+        double p2 = coord(x, y, z, a, idx[hi - 1]);
+        double piv = p0 < p1 ? (p1 < p2 ? p1 : (p0 < p2 ? p2 : p0))
+                             : (p0 < p2 ? p0 : (p1 < p2 ? p2 : p1));
+        /* [lo, lt) < piv, [lt, i) == piv, (gt, hi) > piv */
+        int64_t lt = lo, i = lo, gt = hi - 1;
+        while (i <= gt) {
+            double v = coord(x, y, z, a, idx[i]);
+            if (v < piv) {
+                int64_t t = idx[lt]; idx[lt] = idx[i]; idx[i] = t;
+                ++lt; ++i;
+            } else if (v > piv) {
+                int64_t t = idx[gt]; idx[gt] = idx[i]; idx[i] = t;
+                --gt;
+            } else {
+                ++i;
+            }
+        }
+        if (k < lt) hi = lt;
+        else if (k > gt) lo = gt + 1;
+        else return;
+    }
+}
+
+/* Fills node nd (bounding box, h_max) and splits it at the median of its
+ * widest extent; large subtrees are built as parallel tasks (the node
+ * numbering then depends on scheduling, the neighbour lists do not). */
+static void build_node(search_t *s, int64_t nd, const double *x,
+                       const double *y, const double *z, const double *h)
+{
+    int64_t st = s->start[nd], c = s->count[nd];
+    int64_t *I = s->idx + st;
+    double lo[3] = {4.0, 4.0, 4.0}, hi[3] = {-4.0, -4.0, -4.0}, hm = 0.0;
+    for (int64_t q = 0; q < c; ++q) {
+        int64_t i = I[q];
+        double p[3] = {x[i], y[i], z[i]};
+        for (int a = 0; a < 3; ++a) {
+            if (p[a] < lo[a]) lo[a] = p[a];
+            if (p[a] > hi[a]) hi[a] = p[a];
+        }
+        if (h && h[i] > hm) hm = h[i];
+    }
+    for (int a = 0; a < 3; ++a) {
+        s->lo[3 * nd + a] = lo[a];
+        s->hi[3 * nd + a] = hi[a];
+    }
+    if (h) s->hmax[nd] = hm;
+    s->left[nd] = -1;
+    if (c <= KD_LEAF) return;
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+        if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
+    int64_t half = c / 2;
+    select_kth(I, c, half, x, y, z, ax);
+    int64_t l;
+#pragma omp atomic capture
+    { l = s->nn; s->nn += 2; }
+    s->start[l] = st;
+    s->count[l] = half;
+    s->start[l + 1] = st + half;
+    s->count[l + 1] = c - half;
+    s->left[nd] = l;
+    if (c > 200000) {
+#pragma omp task
+        build_node(s, l, x, y, z, h);
+#pragma omp task
+        build_node(s, l + 1, x, y, z, h);
+#pragma omp taskwait
+    } else {
+        build_node(s, l, x, y, z, h);
+        build_node(s, l + 1, x, y, z, h);
+    }
+}
+
+static int search_build(search_t *s, int64_t n, const double *x,
+                        const double *y, const double *z, const double *h,
+                        int brute)
+{
+    memset(s, 0, sizeof(*s));
+    s->n = n;
+    s->brute = brute;
+    if (brute || n == 0) {
+        s->brute = 1;
         return 0;
     }
-    cl->nc = nc;
-    int64_t ncell = (int64_t)nc * nc * nc;
-    cl->head = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
-    cl->items = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
-    int64_t *cid = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
-    if (!cl->head || !cl->items || !cid) {
-        free(cl->head); free(cl->items); free(cid);
+    int64_t cap = 2 * (n / (KD_LEAF / 2) + 2);
+    s->idx = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    s->start = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    s->count = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    s->left = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    s->lo = (double *)malloc((size_t)cap * 3 * sizeof(double));
+    s->hi = (double *)malloc((size_t)cap * 3 * sizeof(double));
+    if (h) s->hmax = (double *)malloc((size_t)cap * sizeof(double));
+    if (!s->idx || !s->start || !s->count || !s->left || !s->lo || !s->hi ||
+        (h && !s->hmax))
         return -1;
-    }
-    for (int64_t i = 0; i < n; ++i) {
-        int64_t c = ((int64_t)cell_of(x[i], nc) * nc + cell_of(y[i], nc)) * nc
-                    + cell_of(z[i], nc);
-        cid[i] = c;
-        cl->head[c + 1]++;
-    }
-    for (int64_t c = 0; c < ncell; ++c) cl->head[c + 1] += cl->head[c];
-    int64_t *fill = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
-    if (!fill) { free(cl->head); free(cl->items); free(cid); return -1; }
-    memcpy(fill, cl->head, (size_t)ncell * sizeof(int64_t));
-    for (int64_t i = 0; i < n; ++i) cl->items[fill[cid[i]]++] = i;
-    free(fill);
-    free(cid);
+    for (int64_t i = 0; i < n; ++i) s->idx[i] = i;
+    s->nn = 1;
+    s->start[0] = 0;
+    s->count[0] = n;
+#pragma omp parallel
+#pragma omp single
+    build_node(s, 0, x, y, z, h);
     return 0;
 }
 
-static void cells_free(cells_t *cl)
+static void search_free(search_t *s)
 {
-    free(cl->head);
-    free(cl->items);
+    free(s->idx);
+    free(s->start);
+    free(s->count);
+    free(s->left);
+    free(s->lo);
+    free(s->hi);
+    free(s->hmax);
 }
 
-/* Neighbour candidates of one target: indices j, in a fixed order (cell by
- * cell, ascending index within a cell), whose minimum-image separation
- * x_i - x_j satisfies r^2 < R2. */
+/* Neighbours of one target: indices j, sorted ascending, whose
+ * minimum-image separation x_i - x_j has r^2 < R^2 (hi <= 0), or
+ * r < 2 max(hi, h_j) (hi > 0, smoothing lengths h given). */
+typedef struct {
+    int64_t j;
+    double dx, dy, dz, r2;
+} nbr_rec;
 typedef struct {
     int64_t n, cap;
-    int64_t *j;
-    double *d; /* dx, dy, dz, r2 per entry */
+    nbr_rec *r;
+    int64_t *stack;
+    int64_t scap;
 } nbr_t;
 
 static void nbr_push(nbr_t *nb, int64_t j, double dx, double dy, double dz,
@@ -196,65 +291,94 @@ static void nbr_push(nbr_t *nb, int64_t j, double dx, double dy, double dz,
 {
     if (nb->n == nb->cap) {
         nb->cap = nb->cap ? 2 * nb->cap : 256;
-        nb->j = (int64_t *)realloc(nb->j, (size_t)nb->cap * sizeof(int64_t));
-        nb->d = (double *)realloc(nb->d, (size_t)nb->cap * 4 * sizeof(double));
-        if (!nb->j || !nb->d) abort();
+        nb->r = (nbr_rec *)realloc(nb->r, (size_t)nb->cap * sizeof(nbr_rec));
+        if (!nb->r) abort();
     }
-    nb->j[nb->n] = j;
-    nb->d[4 * nb->n + 0] = dx;
-    nb->d[4 * nb->n + 1] = dy;
-    nb->d[4 * nb->n + 2] = dz;
-    nb->d[4 * nb->n + 3] = r2;
-    nb->n++;
+    nbr_rec *e = &nb->r[nb->n++];
+    e->j = j;
+    e->dx = dx;
+    e->dy = dy;
+    e->dz = dz;
+    e->r2 = r2;
 }
 
 static void nbr_free(nbr_t *nb)
 {
-    free(nb->j);
-    free(nb->d);
+    free(nb->r);
+    free(nb->stack);
+}
+
+static int nbr_cmp(const void *a, const void *b)
+{
+    int64_t ja = ((const nbr_rec *)a)->j, jb = ((const nbr_rec *)b)->j;
+    return (ja > jb) - (ja < jb);
 }
 
 static void test_point(nbr_t *nb, int64_t j, const double *X, const double *Y,
-                       const double *Z, double px, double py, double pz,
-                       double R2)
+                       const double *Z, const double *H, double px, double py,
+                       double pz, double R, double hi)
 {
     double dx = min_image(px - X[j]);
     double dy = min_image(py - Y[j]);
     double dz = min_image(pz - Z[j]);
     double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < R2) nbr_push(nb, j, dx, dy, dz, r2);
+    double lim = hi > 0.0 ? 2.0 * (hi > H[j] ? hi : H[j]) : R;
+    if (r2 < lim * lim) nbr_push(nb, j, dx, dy, dz, r2);
 }
 
-static void find_neighbours(const cells_t *cl, const double *X,
-                            const double *Y, const double *Z, double px,
-                            double py, double pz, double R2, nbr_t *nb)
+/* distance from p to the interval [lo, hi] over the periodic images of p */
+static double box_gap(double p, double lo, double hi)
+{
+    double best = 1.0;
+    for (int s = -1; s <= 1; ++s) {
+        double q = p + (double)s;
+        double d = q < lo ? lo - q : (q > hi ? q - hi : 0.0);
+        if (d < best) best = d;
+    }
+    return best;
+}
+
+static void find_neighbours(const search_t *s, const double *X,
+                            const double *Y, const double *Z, const double *H,
+                            double px, double py, double pz, double R,
+                            double hi, nbr_t *nb)
 {
     nb->n = 0;
-    if (cl->nc == 0) {
-        for (int64_t j = 0; j < cl->n; ++j)
-            test_point(nb, j, X, Y, Z, px, py, pz, R2);
+    if (s->brute) {
+        for (int64_t j = 0; j < s->n; ++j)
+            test_point(nb, j, X, Y, Z, H, px, py, pz, R, hi);
         return;
     }
-    int nc = cl->nc;
-    int cx = cell_of(px, nc), cy = cell_of(py, nc), cz = cell_of(pz, nc);
-    for (int ox = -1; ox <= 1; ++ox)
-        for (int oy = -1; oy <= 1; ++oy)
-            for (int oz = -1; oz <= 1; ++oz) {
-                int ax = (cx + ox + nc) % nc;
-                int ay = (cy + oy + nc) % nc;
-                int az = (cz + oz + nc) % nc;
-                int64_t c = ((int64_t)ax * nc + ay) * nc + az;
-                for (int64_t k = cl->head[c]; k < cl->head[c + 1]; ++k)
-                    test_point(nb, cl->items[k], X, Y, Z, px, py, pz, R2);
+    if (nb->scap < 256) {
+        nb->scap = 256;
+        nb->stack = (int64_t *)realloc(nb->stack, 256 * sizeof(int64_t));
+        if (!nb->stack) abort();
+    }
+    int64_t sp = 0;
+    nb->stack[sp++] = 0;
+    while (sp > 0) {
+        int64_t nd = nb->stack[--sp];
+        double gx = box_gap(px, s->lo[3 * nd], s->hi[3 * nd]);
+        double gy = box_gap(py, s->lo[3 * nd + 1], s->hi[3 * nd + 1]);
+        double gz = box_gap(pz, s->lo[3 * nd + 2], s->hi[3 * nd + 2]);
+        double rad = hi > 0.0 ? 2.0 * (hi > s->hmax[nd] ? hi : s->hmax[nd]) : R;
+        if (gx * gx + gy * gy + gz * gz >= rad * rad) continue;
+        if (s->left[nd] < 0) {
+            const int64_t *I = s->idx + s->start[nd];
+            for (int64_t q = 0; q < s->count[nd]; ++q)
+                test_point(nb, I[q], X, Y, Z, H, px, py, pz, R, hi);
+        } else {
+            if (sp + 2 > nb->scap) {
+                nb->scap *= 2;
+                nb->stack = (int64_t *)realloc(nb->stack,
+                                               (size_t)nb->scap * sizeof(int64_t));
+                if (!nb->stack) abort();
             }
-}
-
-static double max_of(int64_t n, const double *a)
-{
-    double m = 0.0;
-    for (int64_t i = 0; i < n; ++i)
-        if (a[i] > m) m = a[i];
-    return m;
+            nb->stack[sp++] = s->left[nd] + 1;
+            nb->stack[sp++] = s->left[nd];
+        }
+    }
+    qsort(nb->r, (size_t)nb->n, sizeof(nbr_rec), nbr_cmp);
 }
 
 static int64_t target_index(const int64_t *targets, int64_t k)
@@ -276,22 +400,21 @@ int orc_neighbours(int64_t n, const double *x, const double *y,
                    const int64_t *targets, int brute, int64_t *counts,
                    const int64_t *offsets, int64_t *idx)
 {
-    double hmax = max_of(n, h);
-    cells_t cl;
-    if (cells_build(&cl, n, x, y, z, 2.0 * hmax, brute)) return -1;
+    search_t cl;
+    if (search_build(&cl, n, x, y, z, h, brute)) return -1;
 #pragma omp parallel
     {
-    nbr_t nb = {0, 0, NULL, NULL};
+    nbr_t nb = {0, 0, NULL, NULL, 0};
 #pragma omp for schedule(dynamic, 16)
     for (int64_t k = 0; k < nt; ++k) {
         int64_t i = target_index(targets, k);
         double hi = h[i];
-        double R = mode ? 2.0 * hmax : 2.0 * hi;
         int64_t c = 0;
-        find_neighbours(&cl, x, y, z, x[i], y[i], z[i], R * R, &nb);
+        find_neighbours(&cl, x, y, z, h, x[i], y[i], z[i], 2.0 * hi,
+                        mode ? hi : 0.0, &nb);
         for (int64_t q = 0; q < nb.n; ++q) {
-            int64_t j = nb.j[q];
-            double r2 = nb.d[4 * q + 3];
+            int64_t j = nb.r[q].j;
+            double r2 = nb.r[q].r2;
             double lim = mode ? 2.0 * (hi > h[j] ? hi : h[j]) : 2.0 * hi;
             if (r2 < lim * lim) {
                 if (idx) idx[offsets[k] + c] = j;
@@ -302,7 +425,7 @@ int orc_neighbours(int64_t n, const double *x, const double *y,
     }
     nbr_free(&nb);
     }
-    cells_free(&cl);
+    search_free(&cl);
     return 0;
 }
 
@@ -315,22 +438,20 @@ int orc_density(int64_t n, const double *x, const double *y, const double *z,
                 const int64_t *targets, int brute, double *V,
                 double *rho_tilde)
 {
-    double hmax = max_of(n, h);
-    cells_t cl;
-    if (cells_build(&cl, n, x, y, z, 2.0 * hmax, brute)) return -1;
+    search_t cl;
+    if (search_build(&cl, n, x, y, z, h, brute)) return -1;
 #pragma omp parallel
     {
-    nbr_t nb = {0, 0, NULL, NULL};
+    nbr_t nb = {0, 0, NULL, NULL, 0};
 #pragma omp for schedule(dynamic, 16)
     for (int64_t k = 0; k < nt; ++k) {
         int64_t i = target_index(targets, k);
         double hi = h[i];
         double sw = 0.0, smw = 0.0;
-        double R = 2.0 * hi;
-        find_neighbours(&cl, x, y, z, x[i], y[i], z[i], R * R, &nb);
+        find_neighbours(&cl, x, y, z, h, x[i], y[i], z[i], 2.0 * hi, 0.0, &nb);
         for (int64_t q = 0; q < nb.n; ++q) {
-            int64_t j = nb.j[q];
-            double r2 = nb.d[4 * q + 3];
+            int64_t j = nb.r[q].j;
+            double r2 = nb.r[q].r2;
             double W, dW;
             orc_kernel(sqrt(r2), hi, &W, &dW);
             sw += W;
@@ -341,7 +462,7 @@ int orc_density(int64_t n, const double *x, const double *y, const double *z,
     }
     nbr_free(&nb);
     }
-    cells_free(&cl);
+    search_free(&cl);
     return 0;
 }
 
@@ -421,12 +542,11 @@ int orc_coefficients(int64_t n, const double *x, const double *y,
                      double *B, double *gradA, double *gradB, double *rho,
                      double *P, double *cs, int *degenerate)
 {
-    double hmax = max_of(n, h);
-    cells_t cl;
-    if (cells_build(&cl, n, x, y, z, 2.0 * hmax, brute)) return -1;
+    search_t cl;
+    if (search_build(&cl, n, x, y, z, h, brute)) return -1;
 #pragma omp parallel
     {
-    nbr_t nb = {0, 0, NULL, NULL};
+    nbr_t nb = {0, 0, NULL, NULL, 0};
 #pragma omp for schedule(dynamic, 16)
     for (int64_t k = 0; k < nt; ++k) {
         int64_t i = target_index(targets, k);
@@ -435,12 +555,11 @@ int orc_coefficients(int64_t n, const double *x, const double *y,
         double sxdw[3][3] = {{0}};        /* sum V x^a d_g W   [g][a]    */
         double sxxdw[3][3][3] = {{{0}}};  /* sum V x^a x^b d_g W [g][a][b] */
         double M1[3] = {0, 0, 0}, rt = 0.0;
-        double R = 2.0 * hi;
-        find_neighbours(&cl, x, y, z, x[i], y[i], z[i], R * R, &nb);
+        find_neighbours(&cl, x, y, z, h, x[i], y[i], z[i], 2.0 * hi, 0.0, &nb);
         for (int64_t q = 0; q < nb.n; ++q) {
-            int64_t j = nb.j[q];
-            double dx = nb.d[4 * q], dy = nb.d[4 * q + 1];
-            double dz = nb.d[4 * q + 2], r2 = nb.d[4 * q + 3];
+            int64_t j = nb.r[q].j;
+            double dx = nb.r[q].dx, dy = nb.r[q].dy;
+            double dz = nb.r[q].dz, r2 = nb.r[q].r2;
             double r = sqrt(r2);
             double W, dW;
             orc_kernel(r, hi, &W, &dW);
@@ -487,7 +606,7 @@ int orc_coefficients(int64_t n, const double *x, const double *y,
     }
     nbr_free(&nb);
     }
-    cells_free(&cl);
+    search_free(&cl);
     return 0;
 }
 
@@ -522,23 +641,21 @@ int orc_hydro(int64_t n, const double *x, const double *y, const double *z,
               int64_t nt, const int64_t *targets, int brute, double *ax,
               double *ay, double *az, double *dudt)
 {
-    double hmax = max_of(n, h);
-    cells_t cl;
-    if (cells_build(&cl, n, x, y, z, 2.0 * hmax, brute)) return -1;
+    search_t cl;
+    if (search_build(&cl, n, x, y, z, h, brute)) return -1;
 #pragma omp parallel
     {
-    nbr_t nb = {0, 0, NULL, NULL};
+    nbr_t nb = {0, 0, NULL, NULL, 0};
 #pragma omp for schedule(dynamic, 16)
     for (int64_t k = 0; k < nt; ++k) {
         int64_t i = target_index(targets, k);
         double hi = h[i];
         double f[3] = {0, 0, 0}, work = 0.0;
-        double R = 2.0 * hmax;
-        find_neighbours(&cl, x, y, z, x[i], y[i], z[i], R * R, &nb);
+        find_neighbours(&cl, x, y, z, h, x[i], y[i], z[i], 0.0, hi, &nb);
         for (int64_t q = 0; q < nb.n; ++q) {
-            int64_t j = nb.j[q];
-            double dx = nb.d[4 * q], dy = nb.d[4 * q + 1];
-            double dz = nb.d[4 * q + 2], r2 = nb.d[4 * q + 3];
+            int64_t j = nb.r[q].j;
+            double dx = nb.r[q].dx, dy = nb.r[q].dy;
+            double dz = nb.r[q].dz, r2 = nb.r[q].r2;
             double lim = 2.0 * (hi > h[j] ? hi : h[j]);
             if (j != i && r2 < lim * lim) {
                 double xij[3] = {dx, dy, dz};
@@ -570,7 +687,7 @@ int orc_hydro(int64_t n, const double *x, const double *y, const double *z,
     }
     nbr_free(&nb);
     }
-    cells_free(&cl);
+    search_free(&cl);
     return 0;
 }
 
@@ -585,20 +702,20 @@ int orc_gravity(int64_t n, const double *x, const double *y, const double *z,
                 const int64_t *targets, int brute, double *ax, double *ay,
                 double *az)
 {
-    cells_t cl;
-    if (cells_build(&cl, n, x, y, z, r_c, brute)) return -1;
+    search_t cl;
+    if (search_build(&cl, n, x, y, z, NULL, brute)) return -1;
 #pragma omp parallel
     {
-    nbr_t nb = {0, 0, NULL, NULL};
+    nbr_t nb = {0, 0, NULL, NULL, 0};
 #pragma omp for schedule(dynamic, 16)
     for (int64_t k = 0; k < nt; ++k) {
         int64_t i = target_index(targets, k);
         double a[3] = {0, 0, 0};
-        find_neighbours(&cl, x, y, z, x[i], y[i], z[i], r_c * r_c, &nb);
+        find_neighbours(&cl, x, y, z, NULL, x[i], y[i], z[i], r_c, 0.0, &nb);
         for (int64_t q = 0; q < nb.n; ++q) {
-            int64_t j = nb.j[q];
-            double dx = nb.d[4 * q], dy = nb.d[4 * q + 1];
-            double dz = nb.d[4 * q + 2], r2 = nb.d[4 * q + 3];
+            int64_t j = nb.r[q].j;
+            double dx = nb.r[q].dx, dy = nb.r[q].dy;
+            double dz = nb.r[q].dz, r2 = nb.r[q].r2;
             if (j != i && r2 > 0.0) {
                 double r = sqrt(r2);
                 double s = -G * m[j] * orc_grav_g(r, r_c, eps) / r;
@@ -613,7 +730,7 @@ int orc_gravity(int64_t n, const double *x, const double *y, const double *z,
     }
     nbr_free(&nb);
     }
-    cells_free(&cl);
+    search_free(&cl);
     return 0;
 }
 

@@ -153,7 +153,7 @@ def zeldovich_displacement(ng: int, spectral_index: float, rms_cells: float,
     del k2
     psi = []
     for kk in (kx[:, None, None], kx[None, :, None], kz[None, None, :]):
-        psi.append(np.fft.irfftn(1j * kk * wk, s=(ng, ng, ng)))
+        psi.append(np.fft.irfftn(1j * kk * wk, s=(ng, ng, ng), axes=(0, 1, 2)))
     del wk
     rms = np.sqrt(np.mean(psi[0] ** 2 + psi[1] ** 2 + psi[2] ** 2))
     scale = rms_cells / ng / rms

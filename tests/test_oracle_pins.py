@@ -378,14 +378,18 @@ def test_galilean_translation_permutation(orc):
         assert np.abs(perm[k] - moved[k][p]).max() <= 1e-9 * np.abs(moved[k]).max()
 
 
-def test_brute_force_equals_linked_cells(orc):
-    w = wl_mod.random_uniform(30000, 20000, 41, n_ngb=40.0, h_spread=0.1)
+@pytest.mark.parametrize("clustered", [False, True])
+def test_brute_force_equals_tree_search(orc, clustered):
+    """The k-d tree finds exactly the brute-force neighbours and the sums
+    run in ascending neighbour index either way, so the outputs are equal
+    to the last bit."""
+    w = wl_mod.random_uniform(30000, 20000, 41, n_ngb=40.0, h_spread=0.1,
+                              clustered=clustered)
     a = orc.step(w, brute=False)
     b = orc.step(w, brute=True)
     for k in ("V", "rho_tilde", "A", "B", "gradA", "gradB", "rho", "a_hydro",
               "dudt", "a_grav_gas", "a_grav_dm"):
-        ref = np.abs(b[k]).max()
-        assert np.abs(a[k] - b[k]).max() < 1e-10 * ref, k
+        assert np.array_equal(a[k], b[k]), k
 
 
 def test_sampled_step_matches_full_step(orc):
