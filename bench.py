@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--grid-mult", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--walk-mask", type=int, default=0)
-    ap.add_argument("--sub-sweep", type=int, default=0)
+    ap.add_argument("--sub-sweep", type=int, default=2)
     ap.add_argument("--tree-lds", type=int, default=1)
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3)
@@ -103,9 +103,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the short-range step of one "
-              "box set runs on a single MI355X here; multi-GPU runs are not "
-              "part of this build (see DESIGN.md for how it would shard).",
+        print("bench.py measures one GPU only: the short-range step runs on "
+              "a single MI355X; spreading boxes or subdomains over several "
+              "GPUs is described as a design, not implemented.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -231,7 +231,7 @@ def main():
                    "grid_mult": tuning["grid_mult"],
                    "xcd_remap": tuning.get("xcd_remap", 0),
                    "walk_mask": tuning.get("walk_mask", 0),
-                   "sub_sweep": tuning.get("sub_sweep", 0),
+                   "sub_sweep": tuning.get("sub_sweep", 2),
                    "tree_lds": tuning.get("tree_lds", 1), "launch": "hip_graph",
                    "leaves": info["n_leaves"],
                    "list_entries": {"gravity": info["grav_entries"],

@@ -107,7 +107,7 @@ typedef struct {
                            1: each 16-lane group sweeps only the candidates
                            near its sub-leaf; 2: one wavefront per sub-leaf,
                            culled against the sub-leaf box, four lanes per
-                           particle; 0: whole-leaf sweep (default 0)        */
+                           particle (default); 0: whole-leaf sweep          */
     int32_t tree_lds;   /* 1: after one sort by bin, sort every bin along the
                            three axes and run its k-d levels in LDS (bins of
                            up to 4096 particles; larger bins fall back to

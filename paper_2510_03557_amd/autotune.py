@@ -1,7 +1,7 @@
 """Launch-shape tuner of the short-range step.
 
-Times the whole captured step for a small grid of (leaf_max, grid_mult)
-choices on the workload itself and keeps the fastest.  Every choice gives
+Times the whole captured step for a small grid of (leaf_max, sweep form,
+launch shape) choices on the workload itself and keeps the fastest.  Every choice gives
 the same results up to floating-point rounding order (tested), so the tuner
 can only change speed.  Results are cached per (workload signature, GPU
 architecture) in ~/.cache/crk_mi355x/tuning.json.
@@ -13,10 +13,11 @@ import json
 import os
 import time
 
-CANDIDATES = ([dict(leaf_max=L, grid_mult=0, xcd_remap=x) for L in (32, 64, 128)
-               for x in (0, 1)]
-              + [dict(leaf_max=L, grid_mult=g, xcd_remap=1) for L in (32, 64, 128)
-                 for g in (16, 32)])
+CANDIDATES = ([dict(leaf_max=L, sub_sweep=s) for L in (32, 48, 64)
+               for s in (0, 2)]
+              + [dict(leaf_max=64, sub_sweep=2, xcd_remap=1),
+                 dict(leaf_max=128, sub_sweep=0),
+                 dict(leaf_max=64, sub_sweep=0, grid_mult=16)])
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "crk_mi355x",
                      "tuning.json")
 
@@ -57,7 +58,8 @@ def _store_cache(d: dict):
 
 
 def _name(c) -> str:
-    return f"L{c['leaf_max']}_g{c['grid_mult']}_x{c.get('xcd_remap', 1)}"
+    return (f"L{c['leaf_max']}_g{c.get('grid_mult', 0)}_x{c.get('xcd_remap', 0)}"
+            f"_s{c.get('sub_sweep', 2)}")
 
 
 def tune(step, candidates=None, reps: int = 5, use_cache: bool = True,

@@ -165,7 +165,7 @@ int crk_ctx_create(crk_ctx **out, int precision, void *stream,
     c->tuning.grid_mult = 0;
     c->tuning.xcd_remap = 0;
     c->tuning.walk_mask = 0;
-    c->tuning.sub_sweep = 0;
+    c->tuning.sub_sweep = 2;
     c->tuning.tree_lds = 1;
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess)

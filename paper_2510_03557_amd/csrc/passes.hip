@@ -142,13 +142,14 @@ __device__ inline void decode_shift(uint32_t code, int &sx, int &sy, int &sz) {
 // overlap.  visit(js, jc, code, hJ, x, y, z, f) gets the j-leaf's first
 // slot, size (clamped to CLAMP), periodic image code, h_max, and the raw
 // position and fields of slot js + t for t < jc.  Entries that were never
-// written (after a capacity error) are skipped.  Every thread of the
-// workgroup calls visit for every entry.
-template <typename T, typename P, int CLAMP, typename F>
+// written (after a capacity error), and entries for which keep(J, code, hJ)
+// is false, are skipped.  Every thread of the workgroup calls visit for
+// every entry kept.
+template <typename T, typename P, int CLAMP, typename K, typename F>
 __device__ __forceinline__ void walk_list(const TreeView<T> &tv,
                                           const typename P::Args &pa,
                                           int64_t e0, int64_t e1, int t,
-                                          F &&visit) {
+                                          K &&keep, F &&visit) {
     const int lane = t & 63;
     const int nl = *tv.n_leaves;
     for (int64_t eb = e0; eb < e1; eb += 64) {
@@ -159,10 +160,12 @@ __device__ __forceinline__ void walk_list(const TreeView<T> &tv,
             const uint32_t ent = tv.list[eb + lane];
             const int J = (int)(ent & LIST_LEAF_MASK);
             if (J < nl) {
-                bjs = tv.leaf_start[J];
-                bjc = min(tv.leaf_count[J], CLAMP);
                 bh = tv.hmax[J];
                 bcode = (int)(ent >> LIST_LEAF_BITS);
+                if (keep(J, (uint32_t)bcode, bh)) {
+                    bjs = tv.leaf_start[J];
+                    bjc = min(tv.leaf_count[J], CLAMP);
+                }
             }
         }
         int js = __shfl(bjs, 0), jc = __shfl(bjc, 0);
@@ -367,9 +370,11 @@ __device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
         acc.fold(tile);
         __syncthreads();
     };
-    walk_list<T, P, BLOCK>(tv, pa, e0, e1, t, [&](int js, int jc, uint32_t code,
-                                                  T hJ, T x, T y, T z,
-                                                  const T *f) {
+    // the leaf's list holds exactly the j-leaves in range of its box
+    auto keep_all = [](int, uint32_t, T) { return true; };
+    walk_list<T, P, BLOCK>(tv, pa, e0, e1, t, keep_all,
+                           [&](int js, int jc, uint32_t code, T hJ, T x, T y,
+                               T z, const T *f) {
         int sx, sy, sz;
         decode_shift(code, sx, sy, sz);
         if (nbuf + jc > CAP) {
@@ -500,9 +505,28 @@ __device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
         acc.fold(tile);
         __syncthreads();
     };
-    walk_list<T, P, 64>(tv, pa, e0, e1, lane, [&](int js, int jc, uint32_t code,
-                                                  T hJ, T x, T y, T z,
-                                                  const T *f) {
+    // j-leaves of the parent's list out of range of this sub-leaf's box are
+    // skipped before their particles are loaded.  The box gap is computed in
+    // T from coordinates in [1, 2) shifted by at most one box (a few ulp of
+    // error at most), against the pair range widened by 1e-4 relative plus
+    // 1e-6 absolute, so nothing in range is dropped.
+    const T slx = tv.slo[slot], sly = tv.slo[sl + slot], slz = tv.slo[2 * sl + slot];
+    const T shx = tv.shi[slot], shy = tv.shi[sl + slot], shz = tv.shi[2 * sl + slot];
+    auto keep_near = [&](int J, uint32_t code, T hJ) {
+        int sx, sy, sz;
+        decode_shift(code, sx, sy, sz);
+        const int64_t lc = tv.lcap;
+        const T gx = fmax(T(0), fmax((tv.lo[J] + T(sx)) - shx, slx - (tv.hi[J] + T(sx))));
+        const T gy = fmax(T(0), fmax((tv.lo[lc + J] + T(sy)) - shy,
+                                     sly - (tv.hi[lc + J] + T(sy))));
+        const T gz = fmax(T(0), fmax((tv.lo[2 * lc + J] + T(sz)) - shz,
+                                     slz - (tv.hi[2 * lc + J] + T(sz))));
+        const T R = P::range(pa, tv, box, hmS, hJ) * T(1.0001) + T(1e-6);
+        return gx * gx + gy * gy + gz * gz < R * R;
+    };
+    walk_list<T, P, 64>(tv, pa, e0, e1, lane, keep_near,
+                        [&](int js, int jc, uint32_t code, T hJ, T x, T y, T z,
+                            const T *f) {
         int sx, sy, sz;
         decode_shift(code, sx, sy, sz);
         if (nbuf + jc > CAP) {

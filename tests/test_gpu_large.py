@@ -1,11 +1,11 @@
 """GPU parity at the full sizes of the large configurations, in the launch
-shape the benchmark uses (one workgroup per leaf of <= 64, HIP-graph-free
-single step), checked on sampled particles: the oracle computes each
-sampled particle's outputs from its full neighbourhood closure (coefficients
-of its force neighbours, volumes of theirs), so the comparison is exact in
-definition.  Same bound as the small cases: relative RMS <= 1e-5 per output
-over the sample.  The 13.5 M-particle batch also runs the sub-leaf split
-sweep."""
+shape the benchmark uses (leaves of <= 64, one wavefront per sub-leaf with
+four lanes per particle), checked on sampled particles: the oracle computes
+each sampled particle's outputs from its full neighbourhood closure
+(coefficients of its force neighbours, volumes of theirs), so the
+comparison is exact in definition.  Same bound as the small cases: relative
+RMS <= 1e-5 per output over the sample.  The 13.5 M-particle batch also
+runs the whole-leaf broadcast sweep."""
 import numpy as np
 import pytest
 
@@ -39,8 +39,8 @@ def pick_gas(wl, rng, n_random, n_dense):
 @pytest.mark.parametrize("name,n_gas_rand,n_dense,n_dm,sub", [
     ("uneven_boxes512", 60, 0, 200, 0),
     ("uneven_boxes512", 40, 0, 100, 2),
-    ("plummer64M", 24, 8, 200, 0),
-    ("zeldovich448", 32, 0, 200, 0),
+    ("plummer64M", 24, 8, 200, 2),
+    ("zeldovich448", 32, 0, 200, 2),
 ])
 def test_large_config_sampled(orc, name, n_gas_rand, n_dense, n_dm, sub):
     from paper_2510_03557_amd.step import ShortRangeStep

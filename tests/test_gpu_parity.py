@@ -361,9 +361,9 @@ def test_launch_shapes_are_bitwise_identical(step_cls, tuning):
     print(f"case launch shape {tuning}", flush=True)
     wl = W.random_uniform(6000, 5000, 1501, n_ngb=48.0, clustered=True)
     L = tuning.get("leaf_max", 64)
-    st, ref = run(step_cls, wl, "fp32", tuning=dict(leaf_max=L))
+    st, ref = run(step_cls, wl, "fp32", tuning=dict(leaf_max=L, sub_sweep=0))
     st.close()
-    st, got = run(step_cls, wl, "fp32", tuning=dict(leaf_max=L, **{
+    st, got = run(step_cls, wl, "fp32", tuning=dict(leaf_max=L, sub_sweep=0, **{
         k: v for k, v in tuning.items() if k != "leaf_max"}))
     st.close()
     for k in KEYS:
@@ -391,3 +391,18 @@ def test_lds_tree_matches_global_sorts(step_cls, precision, L, cm):
         assert np.array_equal(a, b)
     for k in KEYS:
         assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+def test_autotune_keeps_results(orc, step_cls):
+    """The tuner only picks among launch shapes; after it the step still
+    matches the oracle."""
+    from paper_2510_03557_amd import autotune
+    print("case autotune", flush=True)
+    wl = W.random_uniform(3000, 2500, 1601, n_ngb=48.0, h_spread=0.15)
+    st = step_cls(wl, precision="fp32")
+    cands = [dict(leaf_max=32, sub_sweep=0), dict(leaf_max=64, sub_sweep=2)]
+    res = autotune.tune(st, candidates=cands, reps=2, use_cache=False)
+    assert res["tuning"] in cands and len(res["ms"]) == 2
+    st.run()
+    compare(st.outputs(), orc.step(wl), FP32_TOL)
+    st.close()
