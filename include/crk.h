@@ -151,9 +151,11 @@ int crk_sync(crk_ctx *ctx, int64_t *required);
  * leaves are kept.
  * gx, gy, gz, gh: gas positions and smoothing lengths (n_gas values);
  * dx, dy, dz: dark-matter positions (n_dm values); n_gas = gas_off[n_boxes],
- * n_dm = dm_off[n_boxes].  The positions and h are copied into the tree (in
- * tree order); later calls use the copies.  *tree is created on first use
- * and reused (grown as needed) when non-NULL. */
+ * n_dm = dm_off[n_boxes]; boxes may be empty, but n_gas + n_dm = 0 is
+ * rejected with CRK_EINVAL (there is nothing to build).  The positions and
+ * h are copied into the tree (in tree order); later calls use the copies.
+ * *tree is created on first use and reused (grown as needed) when
+ * non-NULL. */
 int build_tree(crk_ctx *ctx, const crk_boxes *boxes, const void *gx,
                const void *gy, const void *gz, const void *gh,
                const void *dx, const void *dy, const void *dz,

@@ -470,6 +470,14 @@ int orc_density(int64_t n, const double *x, const double *y, const double *z,
 /* reproducing-kernel correction coefficients                                 */
 /* ------------------------------------------------------------------------ */
 
+/* m2 counts as singular when det(m2) <= DEGENERATE (tr(m2)/3)^3, i.e. its
+ * eigenvalues multiply to less than 1e-5 of the cube of their mean: such a
+ * neighbourhood (a single particle, a pair, three points, a sheet) cannot fix
+ * the linear correction, and the bound lies far above the rounding noise
+ * of float32 moment sums (about 1e-7 relative), so that float32 and float64
+ * evaluations take the same branch. */
+#define DEGENERATE 1e-5
+
 /* Solve the reproducing conditions at one particle from its moments.
  * m2 is symmetric; inverted through its adjugate.  Returns 1 when m2 is
  * singular (then B = grad B = 0, A = 1/m0, grad A = -grad m0 / m0^2). */
@@ -485,7 +493,7 @@ static int solve_coefficients(double m0, const double m1[3],
     double c02 = m2[1][0] * m2[2][1] - m2[1][1] * m2[2][0];
     double det = m2[0][0] * c00 + m2[0][1] * c01 + m2[0][2] * c02;
     double tr = m2[0][0] + m2[1][1] + m2[2][2];
-    if (!(fabs(det) > 1e-12 * tr * tr * tr / 27.0) || !(tr > 0.0)) {
+    if (!(fabs(det) > DEGENERATE * tr * tr * tr / 27.0) || !(tr > 0.0)) {
         *A = 1.0 / m0;
         for (int g = 0; g < 3; ++g) {
             B[g] = 0.0;

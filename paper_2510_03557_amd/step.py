@@ -74,6 +74,8 @@ class ShortRangeStep:
     def run(self, integrate: bool = False, passes=("density", "coefficients",
                                                     "hydro", "gravity")):
         c, t, wl = self.ctx, self.tree, self.wl
+        if wl.n_total == 0:
+            return  # the library rejects an empty tree; outputs stay empty
         c.build_tree(t, wl.gas_off, wl.dm_off, wl.r_c, wl.eps, self.h_max,
                      self.gx, self.gy, self.gz, self.gh, self.dx, self.dy,
                      self.dz)
