@@ -155,6 +155,12 @@ def main():
     pass_ms, kern_ms, launches = st.ctx.pass_times()
     st.ctx.timing(False)
     st.sync()
+    # the same float32 step launched eagerly (no graph): separates the gain
+    # of graph replay from that of the precision
+    sec_eager = time_steps(lambda: st.run(integrate=True),
+                           lambda: st.ctx.stream.synchronize(),
+                           max(args.steps // 2, 3), 1)
+    st.sync()
     log("[bench] fp32 path: graph capture and timed replays")
     st.capture(integrate=True)
     sec = time_steps(st.replay, lambda: (torch.cuda.synchronize(),
@@ -236,6 +242,8 @@ def main():
                    "leaves": info["n_leaves"],
                    "list_entries": {"gravity": info["grav_entries"],
                                     "hydro": info["hydro_entries"]}},
+        "fp32_eager": {"value": n / sec_eager, "ms_per_step": sec_eager * 1e3,
+                       "launch": "eager"},
         "fp64_plain": fp64,
         "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "pairs": {"gather": pairs[0], "hydro": pairs[1], "gravity": pairs[2]},
