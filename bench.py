@@ -87,7 +87,7 @@ def main():
     # MI355X (--tune re-runs the search)
     ap.add_argument("--leaf-max", type=int, default=64)
     ap.add_argument("--grid-mult", type=int, default=0)
-    ap.add_argument("--xcd-remap", type=int, default=0)
+    ap.add_argument("--xcd-remap", type=int, default=1)
     ap.add_argument("--walk-mask", type=int, default=0)
     ap.add_argument("--sub-sweep", type=int, default=2)
     ap.add_argument("--tree-lds", type=int, default=1)
@@ -235,7 +235,7 @@ def main():
                    "n_particles": n, "boxes": wl.n_boxes,
                    "leaf_max": tuning["leaf_max"],
                    "grid_mult": tuning["grid_mult"],
-                   "xcd_remap": tuning.get("xcd_remap", 0),
+                   "xcd_remap": tuning.get("xcd_remap", 1),
                    "walk_mask": tuning.get("walk_mask", 0),
                    "sub_sweep": tuning.get("sub_sweep", 2),
                    "tree_lds": tuning.get("tree_lds", 1), "launch": "hip_graph",

@@ -96,8 +96,9 @@ typedef struct {
                            species (never narrower than max(r_c, 2 h_max)) */
     int32_t grid_mult;  /* persistent grid = grid_mult x CU count; 0 = one
                            workgroup per leaf (default 0)                    */
-    int32_t xcd_remap;  /* 1: with one workgroup per leaf, give each of the
-                           8 XCDs a contiguous range of leaves (default 0)   */
+    int32_t xcd_remap;  /* 1: with one workgroup per leaf or sub-leaf, give
+                           each of the 8 XCDs a contiguous range of them
+                           (default 1)                                       */
     int32_t walk_mask;  /* passes whose sweep walks per-lane hit lists:
                            bit 0 density, 1 coefficients, 2 hydro, 3 gravity;
                            one workgroup per leaf of <= 64 only (default 0) */

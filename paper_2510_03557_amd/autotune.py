@@ -15,7 +15,7 @@ import time
 
 CANDIDATES = ([dict(leaf_max=L, sub_sweep=s) for L in (32, 48, 64)
                for s in (0, 2)]
-              + [dict(leaf_max=64, sub_sweep=2, xcd_remap=1),
+              + [dict(leaf_max=64, sub_sweep=2, xcd_remap=0),
                  dict(leaf_max=128, sub_sweep=0),
                  dict(leaf_max=64, sub_sweep=0, grid_mult=16)])
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "crk_mi355x",

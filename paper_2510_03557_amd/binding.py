@@ -198,7 +198,7 @@ class Context:
         except Exception:
             pass
 
-    def set_tuning(self, leaf_max=64, cm_factor=0.0, grid_mult=0, xcd_remap=0,
+    def set_tuning(self, leaf_max=64, cm_factor=0.0, grid_mult=0, xcd_remap=1,
                    walk_mask=0, sub_sweep=2, tree_lds=1):
         check(self.lib.crk_set_tuning(self.handle, ctypes.byref(
             crk_tuning(int(leaf_max), float(cm_factor), int(grid_mult),

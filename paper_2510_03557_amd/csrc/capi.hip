@@ -163,7 +163,7 @@ int crk_ctx_create(crk_ctx **out, int precision, void *stream,
     c->tuning.leaf_max = 64;
     c->tuning.cm_factor = 0.0;
     c->tuning.grid_mult = 0;
-    c->tuning.xcd_remap = 0;
+    c->tuning.xcd_remap = 1;
     c->tuning.walk_mask = 0;
     c->tuning.sub_sweep = 2;
     c->tuning.tree_lds = 1;

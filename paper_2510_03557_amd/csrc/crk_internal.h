@@ -108,6 +108,10 @@ struct crk_tree {
     int64_t leaf_cap = 0;       // upper bound of the leaf count
     int64_t n_leaves = 0;       // last eager value (host)
     int64_t n_gas_leaves = 0;   // last eager value (host)
+    // launch bounds of leaf-indexed kernels: the eager counts, or under
+    // capture the graph bounds (eager count + 25 % + 1024, at most leaf_cap)
+    int64_t nb_launch = 0, ngb_launch = 0;
+    int64_t graph_nb = 0, graph_ngb = 0;
     int32_t kd_levels = 0;      // levels run by the last eager build
     int64_t grav_cap = 0, hydro_cap = 0;        // list capacities (entries)
     int64_t grav_entries = 0, hydro_entries = 0;  // last eager values

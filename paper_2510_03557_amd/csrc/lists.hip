@@ -201,9 +201,11 @@ int lists_impl(crk_ctx *ctx, crk_tree *t) {
     CRK_TRY(t->g_off.ensure((lcap + 1) * 8, cap));
     CRK_TRY(t->h_off.ensure((lcap + 1) * 8, cap));
     CRK_TRY(ctx->scratch.ensure(scan_tmp_bytes(lcap + 1), cap));
-    CRK_HIP(fill_i32(t->g_cnt.as<int32_t>(), 0, lcap + 1, s));
-    CRK_HIP(fill_i32(t->h_cnt.as<int32_t>(), 0, lcap + 1, s));
-    const unsigned grid = (unsigned)std::max<int64_t>(1, (lcap + 3) / 4);
+    // leaves in [0, nbl) at most: the tree build's launch bound
+    const int64_t nbl = std::max<int64_t>(1, t->nb_launch);
+    CRK_HIP(fill_i32(t->g_cnt.as<int32_t>(), 0, nbl + 1, s));
+    CRK_HIP(fill_i32(t->h_cnt.as<int32_t>(), 0, nbl + 1, s));
+    const unsigned grid = (unsigned)((nbl + 3) / 4);
     auto launch = [&](int fill) -> int {
         hipLaunchKernelGGL((lists_kernel<T>), dim3(grid), dim3(LB), 0, s, fill,
                            cnt + C_NN, lcap, t->nd_key[cur].as<int32_t>(),
@@ -223,9 +225,9 @@ int lists_impl(crk_ctx *ctx, crk_tree *t) {
     };
     CRK_TRY(launch(0));
     CRK_HIP(exclusive_scan_i32_to_i64(t->g_cnt.as<int32_t>(), t->g_off.as<int64_t>(),
-                                      lcap + 1, cnt64 + C64_GTOT, ctx->scratch.p, s));
+                                      nbl + 1, cnt64 + C64_GTOT, ctx->scratch.p, s));
     CRK_HIP(exclusive_scan_i32_to_i64(t->h_cnt.as<int32_t>(), t->h_off.as<int64_t>(),
-                                      lcap + 1, cnt64 + C64_HTOT, ctx->scratch.p, s));
+                                      nbl + 1, cnt64 + C64_HTOT, ctx->scratch.p, s));
     if (!cap) {
         int64_t *hb = ctx->err_host.as<int64_t>() + 8;
         CRK_HIP(hipMemcpyAsync(hb, cnt64 + C64_GTOT, 16, hipMemcpyDeviceToHost, s));
@@ -247,15 +249,18 @@ int lists_impl(crk_ctx *ctx, crk_tree *t) {
     // cost-ordered work queues for the persistent pass kernels
     t->orders_built = false;
     if (ctx->tuning.grid_mult > 0) {
-        const int64_t m = lcap + 1;
+        // buffers sized by the capacity (no growth under capture), work
+        // over the launch bound
+        const int64_t mc = lcap + 1;
+        const int64_t m = nbl + 1;
         for (int i = 0; i < 2; ++i) {
-            CRK_TRY(t->ord_k[i].ensure(m * 8, cap));
-            CRK_TRY(t->ord_v[i].ensure(m * 4, cap));
+            CRK_TRY(t->ord_k[i].ensure(mc * 8, cap));
+            CRK_TRY(t->ord_v[i].ensure(mc * 4, cap));
         }
-        CRK_TRY(t->g_order.ensure(m * 4, cap));
-        CRK_TRY(t->h_order.ensure(m * 4, cap));
+        CRK_TRY(t->g_order.ensure(mc * 4, cap));
+        CRK_TRY(t->h_order.ensure(mc * 4, cap));
         CRK_TRY(t->q_counter.ensure(64, cap));
-        CRK_TRY(ctx->scratch.ensure(radix_tmp_bytes(m), cap));
+        CRK_TRY(ctx->scratch.ensure(radix_tmp_bytes(mc), cap));
         uint64_t *K[2] = {t->ord_k[0].as<uint64_t>(), t->ord_k[1].as<uint64_t>()};
         int32_t *V[2] = {t->ord_v[0].as<int32_t>(), t->ord_v[1].as<int32_t>()};
         const unsigned g = (unsigned)std::min<int64_t>((m + 255) / 256, 65536);

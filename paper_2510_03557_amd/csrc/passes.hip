@@ -1461,12 +1461,10 @@ inline const int32_t *gas_leaf_count(crk_tree *t) {
 inline const int32_t *all_leaf_count(crk_tree *t) {
     return t->counters.as<int32_t>() + C_NN;
 }
-inline int64_t gas_bound(crk_ctx *ctx, crk_tree *t) {
-    return ctx->capturing ? t->leaf_cap : t->n_gas_leaves;
-}
-inline int64_t all_bound(crk_ctx *ctx, crk_tree *t) {
-    return ctx->capturing ? t->leaf_cap : t->n_leaves;
-}
+// launch bounds set by the tree build: the exact counts when built eagerly,
+// the graph bounds (checked on the device) when built under capture
+inline int64_t gas_bound(crk_ctx *, crk_tree *t) { return t->ngb_launch; }
+inline int64_t all_bound(crk_ctx *, crk_tree *t) { return t->nb_launch; }
 
 template <typename T>
 int density_impl(crk_ctx *ctx, crk_tree *t, const void *m, void *V,

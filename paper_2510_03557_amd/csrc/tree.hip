@@ -320,6 +320,21 @@ __global__ void next_count_kernel(const int32_t *__restrict__ nn_next,
     else *nn = *nn_next;
 }
 
+// a leaf count above the launch bound fixed at capture: error, and clamp
+// (the clamped leaves are all written, so later kernels stay in bounds)
+__global__ void bound_clamp_kernel(int32_t *__restrict__ nn, int64_t bound,
+                                   int *__restrict__ err) {
+    if (*nn > bound) {
+        atomicOr(err, DEV_ERR_CAPACITY);
+        *nn = (int32_t)bound;
+    }
+}
+
+__global__ void bound_check_kernel(const int32_t *__restrict__ nn,
+                                   int64_t bound, int *__restrict__ err) {
+    if (*nn > bound) atomicOr(err, DEV_ERR_CAPACITY);
+}
+
 template <typename T>
 __global__ void gather_tree_kernel(const int32_t *__restrict__ S0,
                                    const T *__restrict__ px,
@@ -1180,7 +1195,26 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
     t->cur_nodes = cur;
     for (int a = 0; a < 3; ++a) t->S_final[a] = S[a];
 
-    // 4. tree order, leaves, bin -> leaf table
+    // 4. launch bound of the leaf-indexed kernels: the exact leaf count
+    //    (eager; read back here), or under capture the bound set by the last
+    //    eager build -- a larger device count raises the capacity error and
+    //    is clamped, so every later kernel stays inside written leaves
+    if (!cap) {
+        int32_t *hb = ctx->err_host.as<int32_t>() + 8;
+        CRK_HIP(hipMemcpyAsync(hb, cnt + C_NN, 4, hipMemcpyDeviceToHost, s));
+        CRK_HIP(hipStreamSynchronize(s));
+        t->n_leaves = hb[0];
+        t->graph_nb = std::min<int64_t>(lcap, t->n_leaves + t->n_leaves / 4 + 1024);
+        t->nb_launch = t->n_leaves;
+    } else {
+        t->nb_launch = t->graph_nb;
+        hipLaunchKernelGGL(bound_clamp_kernel, dim3(1), dim3(1), 0, s,
+                           cnt + C_NN, t->graph_nb, err);
+        CRK_HIP(hipGetLastError());
+    }
+    const int64_t nbl = std::max<int64_t>(1, t->nb_launch);
+
+    // 5. tree order, leaves, bin -> leaf table
     const int64_t nbin2 = 2 * t->total_bins;
     hipLaunchKernelGGL((gather_tree_kernel<T>), dim3(grid_for(n)), dim3(TB), 0, s,
                        S[0], px, py, pz, ph, n, t->perm.as<int32_t>(),
@@ -1189,8 +1223,7 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
     CRK_HIP(hipGetLastError());
     CRK_HIP(fill_i32(t->bin_cnt.as<int32_t>(), 0, nbin2 + 1, s));
     hipLaunchKernelGGL((leaves_kernel<T>),
-                       dim3((unsigned)std::max<int64_t>(1, (lcap + 3) / 4)),
-                       dim3(256), 0, s,
+                       dim3((unsigned)((nbl + 3) / 4)), dim3(256), 0, s,
                        t->nd_start[cur].as<int32_t>(),
                        t->nd_count[cur].as<int32_t>(),
                        t->nd_key[cur].as<int32_t>(), cnt + C_NN, lcap,
@@ -1203,7 +1236,7 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
     CRK_HIP(exclusive_scan_i32(t->bin_cnt.as<int32_t>(),
                                t->bin_leaf.as<int32_t>(), nbin2 + 1, nullptr,
                                ctx->scratch.p, s));
-    // 5. sub-leaves (leaves of <= 64 particles, for the sub-leaf sweeps)
+    // 6. sub-leaves (leaves of <= 64 particles, for the sub-leaf sweeps)
     t->has_sub = t->leaf_max <= 64 && ctx->tuning.sub_sweep != 0;
     if (t->has_sub) {
         const int64_t sl = 4 * (lcap + 1);
@@ -1213,9 +1246,7 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
         CRK_TRY(t->sub_lo.ensure(3 * sl * sizeof(T), cap));
         CRK_TRY(t->sub_hi.ensure(3 * sl * sizeof(T), cap));
         CRK_TRY(t->sub_hmax.ensure(sl * sizeof(T), cap));
-        const int64_t grid = cap ? lcap : std::max<int64_t>(1, 0);
-        (void)grid;
-        hipLaunchKernelGGL((subleaf_kernel<T>), dim3((unsigned)std::max<int64_t>(1, lcap)),
+        hipLaunchKernelGGL((subleaf_kernel<T>), dim3((unsigned)nbl),
                            dim3(64), 0, s, cnt + C_NN,
                            t->nd_start[cur].as<int32_t>(),
                            t->nd_count[cur].as<int32_t>(), lcap,
@@ -1226,15 +1257,21 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
                            t->sub_hi.as<T>(), t->sub_hmax.as<T>());
         CRK_HIP(hipGetLastError());
     }
+    int32_t *gas_nl = t->bin_leaf.as<int32_t>() + t->total_bins;
     if (!cap) {
-        // sizes for the host: leaves, gas leaves
+        // gas leaves for the host
         int32_t *hb = ctx->err_host.as<int32_t>() + 8;
-        CRK_HIP(hipMemcpyAsync(hb, cnt + C_NN, 4, hipMemcpyDeviceToHost, s));
-        CRK_HIP(hipMemcpyAsync(hb + 1, t->bin_leaf.as<int32_t>() + t->total_bins,
-                               4, hipMemcpyDeviceToHost, s));
+        CRK_HIP(hipMemcpyAsync(hb + 1, gas_nl, 4, hipMemcpyDeviceToHost, s));
         CRK_HIP(hipStreamSynchronize(s));
-        t->n_leaves = hb[0];
         t->n_gas_leaves = hb[1];
+        t->graph_ngb = std::min<int64_t>(
+            lcap, t->n_gas_leaves + t->n_gas_leaves / 4 + 1024);
+        t->ngb_launch = t->n_gas_leaves;
+    } else {
+        t->ngb_launch = t->graph_ngb;
+        hipLaunchKernelGGL(bound_check_kernel, dim3(1), dim3(1), 0, s, gas_nl,
+                           t->graph_ngb, err);
+        CRK_HIP(hipGetLastError());
     }
     return CRK_OK;
 }

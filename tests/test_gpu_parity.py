@@ -361,10 +361,10 @@ def test_launch_shapes_are_bitwise_identical(step_cls, tuning):
     print(f"case launch shape {tuning}", flush=True)
     wl = W.random_uniform(6000, 5000, 1501, n_ngb=48.0, clustered=True)
     L = tuning.get("leaf_max", 64)
-    st, ref = run(step_cls, wl, "fp32", tuning=dict(leaf_max=L, sub_sweep=0))
+    base = dict(leaf_max=L, sub_sweep=0, xcd_remap=0)
+    st, ref = run(step_cls, wl, "fp32", tuning=base)
     st.close()
-    st, got = run(step_cls, wl, "fp32", tuning=dict(leaf_max=L, sub_sweep=0, **{
-        k: v for k, v in tuning.items() if k != "leaf_max"}))
+    st, got = run(step_cls, wl, "fp32", tuning=dict(base, **tuning))
     st.close()
     for k in KEYS:
         assert np.array_equal(ref[k], got[k]), k
