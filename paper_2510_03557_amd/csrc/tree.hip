@@ -395,7 +395,10 @@ __global__ __launch_bounds__(256) void leaves_kernel(
     const T *__restrict__ tz, const T *__restrict__ th, int64_t total_bins,
     int nb, const int64_t *__restrict__ bin_base,
     int32_t *__restrict__ leaf_box, T *__restrict__ lo, T *__restrict__ hi,
-    T *__restrict__ lhmax, int32_t *__restrict__ bin_cnt) {
+    T *__restrict__ lhmax, int32_t *__restrict__ bin_cnt, int sub,
+    const int32_t *__restrict__ sub_n, const int32_t *__restrict__ sub_st,
+    const int32_t *__restrict__ sub_c, T *__restrict__ slo,
+    T *__restrict__ shi, T *__restrict__ shm) {
     const int64_t nn = *nn_ptr;
     const int lane = threadIdx.x & 63;
     const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -432,6 +435,36 @@ __global__ __launch_bounds__(256) void leaves_kernel(
         hi[2 * cap + k] = hz;
         lhmax[k] = hm;
         atomicAdd(&bin_cnt[key], 1);
+    }
+    if (sub) {
+        // sub-leaf g (<= 16 slots) on lanes 16g..16g+15, reduced per group
+        const int g = lane >> 4, u = lane & 15;
+        const int64_t sl = 4 * k + g;
+        const bool v = g < sub_n[k] && u < sub_c[sl];
+        const int q = v ? sub_st[sl] + u : st;
+        const T x = tx[q], y = ty[q], z = tz[q], h = th[q];
+        T ax = v ? x : BIG, bx = v ? x : SMALL, ay = v ? y : BIG,
+          by = v ? y : SMALL, az = v ? z : BIG, bz = v ? z : SMALL,
+          bh = v ? h : SMALL;
+        for (int off = 8; off > 0; off >>= 1) {
+            T w;
+            w = __shfl_xor(ax, off); ax = w < ax ? w : ax;
+            w = __shfl_xor(bx, off); bx = w > bx ? w : bx;
+            w = __shfl_xor(ay, off); ay = w < ay ? w : ay;
+            w = __shfl_xor(by, off); by = w > by ? w : by;
+            w = __shfl_xor(az, off); az = w < az ? w : az;
+            w = __shfl_xor(bz, off); bz = w > bz ? w : bz;
+            w = __shfl_xor(bh, off); bh = w > bh ? w : bh;
+        }
+        if (u == 0 && g < sub_n[k]) {
+            slo[sl] = ax;
+            shi[sl] = bx;
+            slo[4 * cap + sl] = ay;
+            shi[4 * cap + sl] = by;
+            slo[8 * cap + sl] = az;
+            shi[8 * cap + sl] = bz;
+            shm[sl] = bh;
+        }
     }
 }
 
@@ -580,15 +613,16 @@ __global__ __launch_bounds__(64) void subleaf_kernel(
 // the balanced split).
 
 constexpr int SEG_TB = 256;      // threads per segment workgroup
-constexpr int SEG_MAX = 4096;    // largest segment sorted in LDS
+constexpr int SEG_MAX = 2048;    // largest segment sorted in LDS
 constexpr int SEG_RANK = 512;    // up to here: rank sort (else bitonic)
 
-// Bytes of the sort-key region.  Rank sort (SEG <= 512): u32 keys
-// (coordinate bits << 9 | position) of all three axes, which stay valid
-// through the k-d levels, then the level scratch; bitonic sort: u64 keys of
-// one axis at a time, aliased by the level scratch afterwards.
+// Bytes before the sorted position arrays.  Rank sort (SEG <= 512): u32
+// keys (coordinate bits << 9 | position) of all three axes, which stay
+// valid through the k-d levels, then the level scratch (9 B per slot);
+// bitonic sort: u64 keys of one axis at a time, aliased by the level
+// scratch afterwards.
 __device__ __host__ inline size_t seg_key_bytes(int SEG) {
-    return (size_t)(SEG <= SEG_RANK ? 12 + 8 : 8) * SEG;
+    return (size_t)(SEG <= SEG_RANK ? 12 + 9 : 9) * SEG;
 }
 
 // leaves the balanced split makes of a node of c particles
@@ -646,21 +680,25 @@ __device__ inline T seg_coord(const T *px, const T *py, const T *pz, int a,
 //   SEG <= SEG_RANK: keys u32[3][SEG], then the level scratch
 //   larger SEG:      keys u64[SEG] (one axis at a time), aliased by the
 //                    level scratch
-//   level scratch:   spare u16[SEG], en u16[SEG], pre u16[SEG], flag u8[SEG]
+//   level scratch:   spare u16[3][SEG], en u16[SEG], flag u8[SEG]
 //   S0, S1, S2 u16[SEG] (axis-sorted positions in the segment)
-//   node arrays: start, count (two generations), left, axis, child
+//   node arrays (MAXN = SEG/8 + 2 each): start, count (two generations),
+//   left, axis, child, three partition bases, saved leaf start and count
+// With sub = 1 (leaf_max <= 64), every leaf is then split by further levels
+// at 16 into <= 4 sub-leaves (same rule), written per leaf slot 4*leaf + k.
 // A segment larger than SEG raises the capacity error and is cut into
-// consecutive chunks of leaf_max (bounds-safe, not a k-d split).
+// consecutive chunks of leaf_max (and 16) (bounds-safe, not a k-d split).
 template <typename T>
 __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
     const int32_t *__restrict__ nn_ptr, const int32_t *__restrict__ seg_start,
     const int32_t *__restrict__ seg_count, const int32_t *__restrict__ seg_key,
     const int32_t *__restrict__ leaf_off, const int32_t *__restrict__ V,
     const T *__restrict__ px, const T *__restrict__ py,
-    const T *__restrict__ pz, int L, int SEG, int64_t lcap,
+    const T *__restrict__ pz, int L, int SEG, int64_t lcap, int sub,
     int32_t *__restrict__ S0g, int32_t *__restrict__ lf_start,
     int32_t *__restrict__ lf_count, int32_t *__restrict__ lf_key,
-    int *__restrict__ err) {
+    int32_t *__restrict__ sub_n, int32_t *__restrict__ sub_st,
+    int32_t *__restrict__ sub_c, int *__restrict__ err) {
     extern __shared__ __align__(16) unsigned char seg_lds[];
     const int sg = (int)blockIdx.x;
     if (sg >= *nn_ptr) return;
@@ -676,21 +714,30 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
         for (int p = t; p < cnt; p += SEG_TB) S0g[s0 + p] = V[s0 + p];
         if ((int64_t)loff + nlv > lcap) return;
         for (int k = t; k < nlv; k += SEG_TB) {
+            const int c = min(L, cnt - k * L);
             lf_start[loff + k] = s0 + k * L;
-            lf_count[loff + k] = min(L, cnt - k * L);
+            lf_count[loff + k] = c;
             lf_key[loff + k] = key;
+            if (sub) {
+                const int ns = min(4, (c + 15) / 16);
+                sub_n[loff + k] = ns;
+                for (int g = 0; g < ns; ++g) {
+                    sub_st[4 * (int64_t)(loff + k) + g] = s0 + k * L + 16 * g;
+                    sub_c[4 * (int64_t)(loff + k) + g] = min(16, c - 16 * g);
+                }
+            }
         }
         return;
     }
-    const int MAXN = SEG / 16 + 2;
+    const int MAXN = SEG / 8 + 2;
     const bool rank = SEG <= SEG_RANK;
     uint64_t *keys = reinterpret_cast<uint64_t *>(seg_lds);
     uint32_t *CK = reinterpret_cast<uint32_t *>(seg_lds);  // rank: [3][SEG]
-    uint16_t *spare = reinterpret_cast<uint16_t *>(
+    uint16_t *spare0 = reinterpret_cast<uint16_t *>(
         seg_lds + (rank ? (size_t)12 * SEG : 0));
-    uint16_t *en = spare + SEG;
-    uint16_t *pre = en + SEG;
-    uint8_t *flag = reinterpret_cast<uint8_t *>(pre + SEG);
+    uint16_t *spare[3] = {spare0, spare0 + SEG, spare0 + 2 * SEG};
+    uint16_t *en = spare0 + 3 * SEG;
+    uint8_t *flag = reinterpret_cast<uint8_t *>(en + SEG);
     uint16_t *Sa[3];
     Sa[0] = reinterpret_cast<uint16_t *>(seg_lds + seg_key_bytes(SEG));
     Sa[1] = Sa[0] + SEG;
@@ -703,7 +750,11 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
     int32_t *nleft = ncnt[1] + MAXN;
     int32_t *naxis = nleft + MAXN;
     int32_t *nchild = naxis + MAXN;
+    int32_t *nbase = nchild + MAXN;  // [3][MAXN]
+    int32_t *lst = nbase + 3 * MAXN;
+    int32_t *lct = lst + MAXN;
     __shared__ int wsum[SEG_TB / 64];
+    __shared__ long long wsum64[SEG_TB / 64];
     __shared__ int s_nn;
 
     // (a) three sorts by (coordinate key, position)
@@ -780,7 +831,7 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
         }
     }
 
-    // (b) k-d levels
+    // (b) k-d levels: first at L, then (sub) at 16 inside the leaves
     int cur = 0;
     int nn = 1;
     if (t == 0) {
@@ -789,14 +840,15 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
     }
     for (int p = t; p < cnt; p += SEG_TB) en[p] = 0;
     __syncthreads();
-    // positions per thread in the scans: a contiguous run of PER
+    // positions per thread in the partition: a contiguous run of PER
     const int PER = SEG / SEG_TB > 0 ? SEG / SEG_TB : 1;
-    for (;;) {
+    const int p0 = t * PER;
+    auto level = [&](const int Lc) -> bool {
         int any = 0;
         for (int k = t; k < nn; k += SEG_TB) {
             const int st = nst[cur][k], c = ncnt[cur][k];
             int lf = 0, ax = 0;
-            if (c > L) {
+            if (c > Lc) {
                 const int e = st + c - 1;
                 if (sizeof(T) == 4 && rank) {
                     // float coordinates in [1, 2) share one exponent: the
@@ -823,7 +875,7 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
                     }
                     if (ez > best) ax = 2;
                 }
-                const int nl = (c + L - 1) / L;
+                const int nl = (c + Lc - 1) / Lc;
                 const int nlft = (nl + 1) / 2;
                 lf = (int)(((long long)c * nlft + nl / 2) / nl);
                 any = 1;
@@ -831,7 +883,7 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
             nleft[k] = lf;
             naxis[k] = ax;
         }
-        if (!__syncthreads_or(any)) break;
+        if (!__syncthreads_or(any)) return false;
         if (t == 0) {
             int acc = 0;
             for (int k = 0; k < nn; ++k) {
@@ -852,50 +904,86 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
             }
         }
         __syncthreads();
+        // stable partition of every splitting node of all three arrays at
+        // once: one prefix sum of the three left-flags packed in 21-bit
+        // fields (counts <= SEG_MAX), node bases from the node starts
+        int fb[16];
+        long long sum = 0;
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            // stable partition of every splitting node of Sa[b]
-            const int p0 = t * PER;
-            int fl[16];
-            int sum = 0;
+        for (int u = 0; u < 16; ++u) {
+            if (u >= PER) break;
+            const int p = p0 + u;
+            int f = 0;
+            if (p < cnt) {
+                const int k = en[p];
+                if (nleft[k])
+                    f = flag[Sa[0][p]] | (flag[Sa[1][p]] << 1) | (flag[Sa[2][p]] << 2);
+                else
+                    f = 7;
+            }
+            fb[u] = f;
+            sum += (long long)(f & 1) | ((long long)((f >> 1) & 1) << 21) |
+                   ((long long)(f >> 2) << 42);
+        }
+        long long run;
+        {
+            const int lane = t & 63, w = t >> 6;
+            long long incl = sum;
+            for (int off = 1; off < 64; off <<= 1) {
+                const long long o = __shfl_up(incl, off);
+                if (lane >= off) incl += o;
+            }
+            if (lane == 63) wsum64[w] = incl;
+            __syncthreads();
+            long long base = 0;
+            for (int q = 0; q < SEG_TB / 64; ++q) base += q < w ? wsum64[q] : 0;
+            run = base + incl - sum;
+        }
+        {
+            long long r = run;
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 if (u >= PER) break;
                 const int p = p0 + u;
-                int f = 1;
                 if (p < cnt) {
                     const int k = en[p];
-                    if (nleft[k]) f = flag[Sa[b][p]];
-                } else {
-                    f = 0;
+                    if (nst[cur][k] == p) {
+                        nbase[k] = (int)(r & 0x1FFFFF);
+                        nbase[MAXN + k] = (int)((r >> 21) & 0x1FFFFF);
+                        nbase[2 * MAXN + k] = (int)(r >> 42);
+                    }
                 }
-                fl[u] = f;
-                sum += f;
+                const int f = fb[u];
+                r += (long long)(f & 1) | ((long long)((f >> 1) & 1) << 21) |
+                     ((long long)(f >> 2) << 42);
             }
-            int tot;
-            int run = block_excl_scan(sum, wsum, &tot);
+        }
+        __syncthreads();
+        {
+            long long r = run;
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 if (u >= PER) break;
                 const int p = p0 + u;
-                if (p < cnt) pre[p] = (uint16_t)run;
-                run += fl[u];
+                if (p < cnt) {
+                    const int k = en[p];
+                    const int st = nst[cur][k];
+                    const int lf = nleft[k];
+                    const int lc = lf ? lf : ncnt[cur][k];
+                    const int f = fb[u];
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const int rb = (int)((r >> (21 * b)) & 0x1FFFFF);
+                        const int rl = rb - nbase[b * MAXN + k];
+                        const int np = ((f >> b) & 1) ? st + rl
+                                                      : st + lc + (p - st - rl);
+                        spare[b][np] = Sa[b][p];
+                    }
+                }
+                const int f = fb[u];
+                r += (long long)(f & 1) | ((long long)((f >> 1) & 1) << 21) |
+                     ((long long)(f >> 2) << 42);
             }
-            __syncthreads();
-            for (int p = t; p < cnt; p += SEG_TB) {
-                const int k = en[p];
-                const int st = nst[cur][k];
-                const int lf = nleft[k];
-                const int lc = lf ? lf : ncnt[cur][k];
-                const int f = lf ? flag[Sa[b][p]] : 1;
-                const int rl = (int)pre[p] - (int)pre[st];
-                const int np = f ? st + rl : st + lc + (p - st - rl);
-                spare[np] = Sa[b][p];
-            }
-            __syncthreads();
-            uint16_t *tmp = Sa[b];
-            Sa[b] = spare;
-            spare = tmp;
         }
         // children and the position -> node map of the next level
         const int nxt = cur ^ 1;
@@ -912,29 +1000,72 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
                 ncnt[nxt][cb] = c;
             }
         }
-        for (int p = t; p < cnt; p += SEG_TB) {
-            const int k = en[p];
-            const int lf = nleft[k];
-            en[p] = (uint16_t)(nchild[k] +
-                               ((lf && p - nst[cur][k] >= lf) ? 1 : 0));
+        // (the positions this thread scattered from: no other thread reads
+        // their en in this level)
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (u >= PER) break;
+            const int p = p0 + u;
+            if (p < cnt) {
+                const int k = en[p];
+                const int lf = nleft[k];
+                en[p] = (uint16_t)(nchild[k] +
+                                   ((lf && p - nst[cur][k] >= lf) ? 1 : 0));
+            }
         }
         __syncthreads();
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            uint16_t *tmp = Sa[b];
+            Sa[b] = spare[b];
+            spare[b] = tmp;
+        }
         nn = s_nn;
         cur = nxt;
+        return true;
+    };
+    while (level(L)) {
     }
-
-    // (c) leaves and the tree order of the segment
-    for (int p = t; p < cnt; p += SEG_TB) S0g[s0 + p] = V[s0 + Sa[0][p]];
+    // the leaves
+    const int nleaves = nn;
     for (int k = t; k < nn; k += SEG_TB) {
+        lst[k] = nst[cur][k];
+        lct[k] = ncnt[cur][k];
         lf_start[loff + k] = s0 + nst[cur][k];
         lf_count[loff + k] = ncnt[cur][k];
         lf_key[loff + k] = key;
     }
+    if (sub) {
+        __syncthreads();
+        while (level(16)) {
+        }
+        // final node m lies in leaf k: its slot is 4 (loff + k) + (m - first
+        // node of leaf k); nodes and leaves are both in position order
+        for (int k = t; k < nleaves; k += SEG_TB) {
+            int lo = 0, hi = nn;  // first node with start >= lst[k]
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (nst[cur][mid] < lst[k]) lo = mid + 1;
+                else hi = mid;
+            }
+            int m = lo, g = 0;
+            while (m < nn && nst[cur][m] < lst[k] + lct[k] && g < 4) {
+                sub_st[4 * (int64_t)(loff + k) + g] = s0 + nst[cur][m];
+                sub_c[4 * (int64_t)(loff + k) + g] = ncnt[cur][m];
+                ++m;
+                ++g;
+            }
+            sub_n[loff + k] = g;
+        }
+    }
+
+    // (c) the tree order of the segment
+    for (int p = t; p < cnt; p += SEG_TB) S0g[s0 + p] = V[s0 + Sa[0][p]];
 }
 
 size_t seg_lds_bytes(int SEG) {
-    const int MAXN = SEG / 16 + 2;
-    return seg_key_bytes(SEG) + (size_t)SEG * 6 + (size_t)MAXN * 7 * 4;
+    const int MAXN = SEG / 8 + 2;
+    return seg_key_bytes(SEG) + (size_t)SEG * 6 + (size_t)MAXN * 12 * 4;
 }
 
 int ensure_all(crk_tree *t, int64_t n, int64_t leaf_cap, size_t elem,
@@ -1006,6 +1137,18 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
     int32_t *sf = t->f_scan.as<int32_t>();
     const int key_bits = 23 + t->bin_bits;
     const int L = t->leaf_max;
+    // sub-leaves (leaves of <= 64 particles, for the sub-leaf sweeps)
+    t->has_sub = L <= 64 && ctx->tuning.sub_sweep != 0;
+    bool sub_done = false;  // split by the per-bin build
+    if (t->has_sub) {
+        const int64_t sl = 4 * (lcap + 1);
+        CRK_TRY(t->sub_nsub.ensure((lcap + 1) * 4, cap));
+        CRK_TRY(t->sub_start.ensure(sl * 4, cap));
+        CRK_TRY(t->sub_count.ensure(sl * 4, cap));
+        CRK_TRY(t->sub_lo.ensure(3 * sl * sizeof(T), cap));
+        CRK_TRY(t->sub_hi.ensure(3 * sl * sizeof(T), cap));
+        CRK_TRY(t->sub_hmax.ensure(sl * sizeof(T), cap));
+    }
     // segments: one per non-empty (species, bin)
     const int64_t seg_cap = std::min<int64_t>(n, 2 * t->total_bins);
     int cur = 0;
@@ -1076,10 +1219,15 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
                                t->nd_count[0].as<int32_t>(),
                                t->nd_key[0].as<int32_t>(),
                                t->nd_child.as<int32_t>(), Vv[r], px, py, pz, L,
-                               SEG, lcap, S[0], t->nd_start[1].as<int32_t>(),
+                               SEG, lcap, t->has_sub ? 1 : 0, S[0],
+                               t->nd_start[1].as<int32_t>(),
                                t->nd_count[1].as<int32_t>(),
-                               t->nd_key[1].as<int32_t>(), err);
+                               t->nd_key[1].as<int32_t>(),
+                               t->sub_nsub.as<int32_t>(),
+                               t->sub_start.as<int32_t>(),
+                               t->sub_count.as<int32_t>(), err);
             CRK_HIP(hipGetLastError());
+            sub_done = t->has_sub;
             hipLaunchKernelGGL(next_count_kernel, dim3(1), dim3(1), 0, s,
                                cnt + C_NN_NEXT, lcap, cnt + C_NN, err);
             CRK_HIP(hipGetLastError());
@@ -1231,21 +1379,17 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
                        t->hsm.as<T>(), t->total_bins, t->n_boxes,
                        t->d_bin_base.as<int64_t>(), t->leaf_box.as<int32_t>(),
                        t->leaf_lo.as<T>(), t->leaf_hi.as<T>(),
-                       t->leaf_hmax.as<T>(), t->bin_cnt.as<int32_t>());
+                       t->leaf_hmax.as<T>(), t->bin_cnt.as<int32_t>(),
+                       sub_done ? 1 : 0, t->sub_nsub.as<int32_t>(),
+                       t->sub_start.as<int32_t>(), t->sub_count.as<int32_t>(),
+                       t->sub_lo.as<T>(), t->sub_hi.as<T>(),
+                       t->sub_hmax.as<T>());
     CRK_HIP(hipGetLastError());
     CRK_HIP(exclusive_scan_i32(t->bin_cnt.as<int32_t>(),
                                t->bin_leaf.as<int32_t>(), nbin2 + 1, nullptr,
                                ctx->scratch.p, s));
-    // 6. sub-leaves (leaves of <= 64 particles, for the sub-leaf sweeps)
-    t->has_sub = t->leaf_max <= 64 && ctx->tuning.sub_sweep != 0;
-    if (t->has_sub) {
-        const int64_t sl = 4 * (lcap + 1);
-        CRK_TRY(t->sub_nsub.ensure((lcap + 1) * 4, cap));
-        CRK_TRY(t->sub_start.ensure(sl * 4, cap));
-        CRK_TRY(t->sub_count.ensure(sl * 4, cap));
-        CRK_TRY(t->sub_lo.ensure(3 * sl * sizeof(T), cap));
-        CRK_TRY(t->sub_hi.ensure(3 * sl * sizeof(T), cap));
-        CRK_TRY(t->sub_hmax.ensure(sl * sizeof(T), cap));
+    // 6. sub-leaves of the general path: one wavefront per leaf
+    if (t->has_sub && !sub_done) {
         hipLaunchKernelGGL((subleaf_kernel<T>), dim3((unsigned)nbl),
                            dim3(64), 0, s, cnt + C_NN,
                            t->nd_start[cur].as<int32_t>(),

@@ -383,7 +383,8 @@ def test_lds_tree_matches_global_sorts(step_cls, precision, L, cm):
     trees, outs = [], []
     for lds in (0, 1):
         st, o = run(step_cls, wl, precision,
-                    tuning=dict(leaf_max=L, cm_factor=cm, tree_lds=lds))
+                    tuning=dict(leaf_max=L, cm_factor=cm, tree_lds=lds,
+                                sub_sweep=0))
         trees.append(st.tree.leaves())
         outs.append(o)
         st.close()
@@ -391,6 +392,20 @@ def test_lds_tree_matches_global_sorts(step_cls, precision, L, cm):
         assert np.array_equal(a, b)
     for k in KEYS:
         assert np.array_equal(outs[0][k], outs[1][k]), k
+    # with sub-leaves the two paths split the leaves independently (the
+    # per-bin build continues its levels at 16, the general path splits
+    # each leaf in a wavefront): same leaves, sums equal up to rounding
+    subs = []
+    for lds in (0, 1):
+        st, o = run(step_cls, wl, precision,
+                    tuning=dict(leaf_max=L, cm_factor=cm, tree_lds=lds,
+                                sub_sweep=2))
+        _, start, count = st.tree.leaves()
+        assert np.array_equal(start, trees[0][1])
+        assert np.array_equal(count, trees[0][2])
+        subs.append(o)
+        st.close()
+    compare(subs[1], subs[0], 2e-6 if precision == "fp32" else 1e-12)
 
 
 def test_autotune_keeps_results(orc, step_cls):
