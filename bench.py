@@ -35,10 +35,26 @@ FLOP_PER_PAIR = {"density": 20, "coefficients": 89, "hydro": 178,
                  "gravity": 38}
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector, published (packed)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
-KERNEL_NAMES = {"density": "pair_kernel<float, DensityPass<float>>",
-                "coefficients": "pair_kernel<float, CoeffPass<float>>",
-                "hydro": "pair_kernel<float, HydroPass<float>>",
-                "gravity": "pair_kernel<float, GravityPass<float>>"}
+PASS_TYPES = {"density": "DensityPass", "coefficients": "CoeffPass",
+              "hydro": "HydroPass", "gravity": "GravityPass"}
+
+
+def kernel_name(p: str, tuning: dict) -> str:
+    """The float32 kernel a pass launches under a tuning (as rocprofv3 names
+    it, namespaces dropped)."""
+    t = PASS_TYPES[p]
+    L = tuning.get("leaf_max", 64)
+    if tuning.get("grid_mult", 0) > 0:
+        b = 64 if L <= 64 else (128 if L <= 128 else 256)
+        return f"pair_kernel_queue<float, {t}<float>, {b}>"
+    if L <= 64 and (tuning.get("walk_mask", 0) >> list(PASS_TYPES).index(p)) & 1:
+        return f"pair_kernel<float, {t}<float>, 64, 1>"
+    if L <= 64 and tuning.get("sub_sweep", 2) == 2:
+        return f"pair_kernel_split<float, {t}<float> >"
+    if L <= 64 and tuning.get("sub_sweep", 2) == 1:
+        return f"pair_kernel<float, {t}<float>, 64, 2>"
+    b = 64 if L <= 64 else (128 if L <= 128 else 256)
+    return f"pair_kernel<float, {t}<float>, {b}, 0>"
 
 
 def log(*a):
@@ -53,15 +69,16 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(pass_name: str):
+def measured_traffic(pass_name: str, kname: str, workload: str):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; otherwise None."""
-    path = os.path.join(ROOT, "profiles", f"{pass_name}_pmc_zeldovich128.json")
+    was taken on the same workload, kernel and kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{pass_name}_pmc_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != source_hash():
+    if (d.get("source_hash") != source_hash() or d.get("kernel_name") != kname
+            or d.get("workload") != workload):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -196,11 +213,11 @@ def main():
                        "tflops": flop / (avg * 1e-3) / 1e12}
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
     ach = kern[dom]["tflops"]
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(dom, kernel_name(dom, tuning), args.workload)
     roofline = {"bound": "alu", "achieved": round(ach, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic, "kernel": KERNEL_NAMES[dom],
+                "traffic": traffic, "kernel": kernel_name(dom, tuning),
                 "avg_launch_ms": round(kern[dom]["avg_ms"], 4),
                 "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
                 "frac_unpacked": round(ach / PEAK_FP32_UNPACKED_TFLOPS, 4)}
