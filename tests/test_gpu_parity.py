@@ -147,10 +147,19 @@ def test_lattice32_fp64_and_fp32(orc, step_cls):
 
 
 def test_zeldovich128_fp32_full(orc, step_cls):
-    print("case zeldovich128 (4,194,304 particles) fp32, leaf 128", flush=True)
+    """The benchmark box in full, in the benchmark's launch shape (default
+    tuning, graph replay of the whole step) and with leaves of 128 (the
+    whole-leaf broadcast sweep), against one oracle step."""
+    print("case zeldovich128 (4,194,304 particles) fp32, bench shape + leaf 128",
+          flush=True)
     wl = W.make("zeldovich128")
-    st, got = run(step_cls, wl, "fp32", tuning=dict(leaf_max=128))
     ref = orc.step(wl)
+    st = step_cls(wl, precision="fp32")
+    st.capture(integrate=False)
+    st.replay()
+    compare(st.outputs(), ref, FP32_TOL)
+    st.close()
+    st, got = run(step_cls, wl, "fp32", tuning=dict(leaf_max=128))
     compare(got, ref, FP32_TOL)
     st.close()
 
