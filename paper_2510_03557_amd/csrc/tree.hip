@@ -759,43 +759,90 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
 
     // (a) three sorts by (coordinate key, position)
     if (rank) {
-        // rank sort: the rank of an element is the number of smaller keys
-        // (keys are distinct: coordinate bits, then the position in the
-        // segment); each thread ranks positions t and t + 256 along all
-        // three axes in one sweep of broadcast LDS reads
-        uint32_t *K0 = CK, *K1 = CK + SEG, *K2 = CK + 2 * SEG;
+        // bucketed rank sort: keys are distinct (coordinate bits, then the
+        // position in the segment); per axis the positions are grouped into
+        // 64 buckets of equal coordinate width (counting sort in LDS), and
+        // the rank of an element is its bucket's start plus the number of
+        // smaller keys inside its bucket
+        uint32_t *K[3] = {CK, CK + SEG, CK + 2 * SEG};
+        __shared__ int hist[3][64], bst[3][64], bcur[3][64];
+        __shared__ uint32_t wmn[SEG_TB / 64][3], wmx[SEG_TB / 64][3];
+        uint32_t lmn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+        uint32_t lmx[3] = {0u, 0u, 0u};
         for (int p = t; p < cnt; p += SEG_TB) {
             const int32_t c = V[s0 + p];
-            K0[p] = (coord_bits(px[c]) << 9) | (uint32_t)p;
-            K1[p] = (coord_bits(py[c]) << 9) | (uint32_t)p;
-            K2[p] = (coord_bits(pz[c]) << 9) | (uint32_t)p;
+            const uint32_t kx = coord_bits(px[c]), ky = coord_bits(py[c]),
+                           kz = coord_bits(pz[c]);
+            K[0][p] = (kx << 9) | (uint32_t)p;
+            K[1][p] = (ky << 9) | (uint32_t)p;
+            K[2][p] = (kz << 9) | (uint32_t)p;
+            lmn[0] = min(lmn[0], kx);
+            lmx[0] = max(lmx[0], kx);
+            lmn[1] = min(lmn[1], ky);
+            lmx[1] = max(lmx[1], ky);
+            lmn[2] = min(lmn[2], kz);
+            lmx[2] = max(lmx[2], kz);
+        }
+        if (t < 3 * 64) (&hist[0][0])[t] = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            for (int off = 32; off > 0; off >>= 1) {
+                lmn[a] = min(lmn[a], (uint32_t)__shfl_xor((int)lmn[a], off));
+                lmx[a] = max(lmx[a], (uint32_t)__shfl_xor((int)lmx[a], off));
+            }
+            if ((t & 63) == 0) {
+                wmn[t >> 6][a] = lmn[a];
+                wmx[t >> 6][a] = lmx[a];
+            }
         }
         __syncthreads();
-        const int p0 = t, p1 = t + SEG_TB;
-        const uint32_t NONE = 0xFFFFFFFFu;
-        const uint32_t a0 = p0 < cnt ? K0[p0] : NONE, b0 = p0 < cnt ? K1[p0] : NONE,
-                       c0 = p0 < cnt ? K2[p0] : NONE;
-        const uint32_t a1 = p1 < cnt ? K0[p1] : NONE, b1 = p1 < cnt ? K1[p1] : NONE,
-                       c1 = p1 < cnt ? K2[p1] : NONE;
-        int ra0 = 0, rb0 = 0, rc0 = 0, ra1 = 0, rb1 = 0, rc1 = 0;
-        for (int q = 0; q < cnt; ++q) {
-            const uint32_t ka = K0[q], kb = K1[q], kc = K2[q];
-            ra0 += ka < a0 ? 1 : 0;
-            rb0 += kb < b0 ? 1 : 0;
-            rc0 += kc < c0 ? 1 : 0;
-            ra1 += ka < a1 ? 1 : 0;
-            rb1 += kb < b1 ? 1 : 0;
-            rc1 += kc < c1 ? 1 : 0;
+        uint32_t mn[3], wd[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            uint32_t m0 = 0xFFFFFFFFu, m1 = 0u;
+            for (int w = 0; w < SEG_TB / 64; ++w) {
+                m0 = min(m0, wmn[w][a]);
+                m1 = max(m1, wmx[w][a]);
+            }
+            mn[a] = m0;
+            wd[a] = m1 >= m0 ? m1 - m0 + 1 : 1;
         }
-        if (p0 < cnt) {
-            Sa[0][ra0] = (uint16_t)p0;
-            Sa[1][rb0] = (uint16_t)p0;
-            Sa[2][rc0] = (uint16_t)p0;
+        auto bucket = [&](int a, uint32_t k) {
+            return (int)((uint64_t)((k >> 9) - mn[a]) * 64u / wd[a]);
+        };
+        for (int p = t; p < cnt; p += SEG_TB) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) atomicAdd(&hist[a][bucket(a, K[a][p])], 1);
         }
-        if (p1 < cnt) {
-            Sa[0][ra1] = (uint16_t)p1;
-            Sa[1][rb1] = (uint16_t)p1;
-            Sa[2][rc1] = (uint16_t)p1;
+        __syncthreads();
+        if (t < 3) {
+            int acc = 0;
+            for (int q = 0; q < 64; ++q) {
+                bst[t][q] = acc;
+                bcur[t][q] = acc;
+                acc += hist[t][q];
+            }
+        }
+        __syncthreads();
+        // bucket members (any order inside a bucket) in the level scratch
+        for (int p = t; p < cnt; p += SEG_TB) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int bk = bucket(a, K[a][p]);
+                spare[a][atomicAdd(&bcur[a][bk], 1)] = (uint16_t)p;
+            }
+        }
+        __syncthreads();
+        for (int p = t; p < cnt; p += SEG_TB) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const uint32_t kp = K[a][p];
+                const int bk = bucket(a, kp);
+                const int b0 = bst[a][bk], b1 = b0 + hist[a][bk];
+                int r = b0;
+                for (int q = b0; q < b1; ++q) r += K[a][spare[a][q]] < kp ? 1 : 0;
+                Sa[a][r] = (uint16_t)p;
+            }
         }
         __syncthreads();
     } else {
