@@ -2,12 +2,15 @@
 // correction coefficients, hydro forces, and short-range gravity.  Each is a
 // per-particle sum phi_i = sum_j phi_ij over the leaf-leaf lists (Eq. (1)).
 //
-// Kernel shape (MI355X, wave64): one workgroup of BLOCK >= leaf_max threads
-// owns one i-leaf, one i-particle per lane.  For each j-leaf of the i-leaf's
-// list the workgroup stages the j-leaf's fields in LDS (one particle per
-// lane, coalesced global reads) and every lane sweeps the tile, reading each
-// j by LDS broadcast; per-particle sums stay in registers and each output is
-// written once (no atomics), which keeps results independent of scheduling.
+// Kernel shapes (MI355X, wave64).  Default (split): one wavefront owns one
+// sub-leaf of <= 16 i-particles with four lanes per particle; it walks the
+// parent leaf's list, stages the j particles that survive a cull against
+// the sub-leaf box in LDS (coalesced global reads, ballot compaction), and
+// lane q of each quad sweeps candidates q, q + 4, ...  Whole-leaf forms:
+// one workgroup of BLOCK >= leaf_max threads owns one i-leaf, one particle
+// per lane, every lane sweeping every candidate by LDS broadcast.  Either
+// way per-particle sums stay in registers and each output is written once
+// (no atomics), which keeps results independent of scheduling.
 //
 // Precision.  Positions are float32 in [1, 2): they are recentred on the
 // i-leaf's first particle, e_i = x_i - x_ref and f_j = (x_j - x_ref) + S
@@ -227,12 +230,12 @@ __device__ __forceinline__ void walk_list(const TreeView<T> &tv,
 //   P::pair(Tile&, const I&, const T* jd, bool self)
 //   P::finish(const Acc&, const I&, args, tv, i)
 //
-// Every j particle of a listed j-leaf is first tested against the i-leaf's
+// Every j particle of a listed j-leaf is first tested against the i-set's
 // bounding box widened by the pair range; survivors are compacted (ballot +
 // prefix) into an LDS buffer of CAPF*BLOCK candidates that spans several
-// j-leaves.  A full buffer is swept by every lane and its partial sums are
-// folded into the compensated totals.  Culled particles are out of range of
-// every i, so the sums do not change beyond rounding order.
+// j-leaves.  A full buffer is swept and its partial sums are folded into
+// the compensated totals.  Culled particles are out of range of every i,
+// so the sums do not change beyond rounding order.
 template <typename T, typename P, int BLOCK, int MODE>
 __device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
                                              const typename P::Args &pa,
