@@ -1028,8 +1028,10 @@ template <typename T> struct HydroPass {
         const T r2 = x0 * x0 + x1 * x1 + x2 * x2;
         const T *fj = jd + 3;
         const T *fi = is.f;
-        const bool near = (r2 * fi[3] < T(4)) || (r2 * fj[3] < T(4));
-        if (near && !self) {
+        // both range tests evaluated (no short circuit: no branch around the
+        // LDS read of the j-side 1/h^2)
+        const bool near = (r2 * fi[3] < T(4)) | (r2 * fj[3] < T(4));
+        if (near & !self) {
             T gi[3], gj[3];
             bool oi, oj;
             grad_rk(fi, x0, x1, x2, r2, gi, oi);
