@@ -490,10 +490,6 @@ __device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
     const T rx = tv.px[st], ry = tv.py[st], rz = tv.pz[st];
     const int box = tv.leaf_box[I];
     const int64_t sl = 4 * tv.lcap;
-    const T blx = tv.slo[slot] - rx, bly = tv.slo[sl + slot] - ry,
-            blz = tv.slo[2 * sl + slot] - rz;
-    const T bhx = tv.shi[slot] - rx, bhy = tv.shi[sl + slot] - ry,
-            bhz = tv.shi[2 * sl + slot] - rz;
     const T hmS = tv.shm[slot];
     typename P::I is;
     P::load_i(is, pa, tv, i, tv.px[i] - rx, tv.py[i] - ry, tv.pz[i] - rz, box);
@@ -549,22 +545,27 @@ __device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
             sweep(nbuf);
             nbuf = 0;
         }
-        const T R = P::range(pa, tv, box, hmS, hJ);
+        // cull in raw coordinates against the sub-leaf box moved to this
+        // image (its shifted bounds round by at most a few 1e-7: the range
+        // gets an absolute 1e-6 on top of its relative widening)
+        const T R = P::range(pa, tv, box, hmS, hJ) + T(1e-6);
         const T R2 = R * R;
+        const T clx = slx - T(sx), chx = shx - T(sx);
+        const T cly = sly - T(sy), chy = shy - T(sy);
+        const T clz = slz - T(sz), chz = shz - T(sz);
         bool keep = false;
-        T fx = T(0), fy = T(0), fz = T(0);
         const int j = js + lane;
         if (lane < jc) {
-            fx = (x - rx) + T(sx);
-            fy = (y - ry) + T(sy);
-            fz = (z - rz) + T(sz);
-            const T dx = fmax(fmax(blx - fx, fx - bhx), T(0));
-            const T dy = fmax(fmax(bly - fy, fy - bhy), T(0));
-            const T dz = fmax(fmax(blz - fz, fz - bhz), T(0));
+            const T dx = fmax(fmax(clx - x, x - chx), T(0));
+            const T dy = fmax(fmax(cly - y, y - chy), T(0));
+            const T dz = fmax(fmax(clz - z, z - chz), T(0));
             keep = dx * dx + dy * dy + dz * dz < R2;
         }
         const uint64_t m = __ballot(keep);
         if (keep) {
+            // recentred (exact for every pair in range)
+            const T fx = (x - rx) + T(sx), fy = (y - ry) + T(sy),
+                    fz = (z - rz) + T(sz);
             const int pos = nbuf + __popcll(m & lt_mask);
             P::store_j(&sj[pos * P::NJ], f, pa, tv, j, fx, fy, fz);
             sjid[pos] = j;
