@@ -30,7 +30,7 @@ int DevBuf::ensure(size_t n, bool capturing) {
                          "a buffer would have to grow during graph capture; "
                          "run the step once eagerly at this size first");
     if (p) {
-        hipFree(p);
+        (void)hipFree(p);
         p = nullptr;
         bytes = 0;
     }
@@ -46,14 +46,14 @@ int DevBuf::ensure(size_t n, bool capturing) {
 }
 
 void DevBuf::release() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
 }
 
 int HostBuf::ensure(size_t n) {
     if (n <= bytes && p) return CRK_OK;
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
     p = nullptr;
     bytes = 0;
     size_t want = std::max<size_t>((n + 255) & ~size_t(255), 256);
@@ -67,7 +67,7 @@ int HostBuf::ensure(size_t n) {
 }
 
 void HostBuf::release() {
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
     p = nullptr;
     bytes = 0;
 }
@@ -79,7 +79,7 @@ void span_begin(crk_ctx *ctx, int pass, bool kernel, hipEvent_t *ev) {
         *ev = nullptr;
         return;
     }
-    hipEventRecord(*ev, ctx->stream);
+    (void)hipEventRecord(*ev, ctx->stream);
     (void)pass;
     (void)kernel;
 }
@@ -88,10 +88,10 @@ void span_end(crk_ctx *ctx, int pass, bool kernel, hipEvent_t ev) {
     if (!ev) return;
     hipEvent_t b;
     if (hipEventCreate(&b) != hipSuccess) {
-        hipEventDestroy(ev);
+        (void)hipEventDestroy(ev);
         return;
     }
-    hipEventRecord(b, ctx->stream);
+    (void)hipEventRecord(b, ctx->stream);
     ctx->spans.push_back(TimedSpan{pass, kernel, ev, b});
 }
 
@@ -194,14 +194,14 @@ int crk_ctx_create(crk_ctx **out, int precision, void *stream,
 
 int crk_ctx_destroy(crk_ctx *ctx) {
     if (!ctx) return CRK_OK;
-    if (ctx->stream) hipStreamSynchronize(ctx->stream);
-    else hipDeviceSynchronize();
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
     for (auto &s : ctx->spans) {
-        hipEventDestroy(s.a);
-        hipEventDestroy(s.b);
+        (void)hipEventDestroy(s.a);
+        (void)hipEventDestroy(s.b);
     }
-    if (ctx->graph_exec) hipGraphExecDestroy(ctx->graph_exec);
-    if (ctx->graph) hipGraphDestroy(ctx->graph);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     ctx->err.release();
     ctx->err_host.release();
     ctx->scratch.release();
@@ -478,8 +478,8 @@ int crk_graph_end(crk_ctx *ctx) {
     ctx->capturing = false;
     hipGraph_t g = nullptr;
     CRK_HIP(hipStreamEndCapture(ctx->stream, &g));
-    if (ctx->graph_exec) hipGraphExecDestroy(ctx->graph_exec);
-    if (ctx->graph) hipGraphDestroy(ctx->graph);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     ctx->graph = g;
     ctx->graph_exec = nullptr;
     CRK_HIP(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
@@ -497,8 +497,8 @@ int crk_tree_free(crk_tree *t) {
     if (!t) return CRK_OK;
     crk_ctx *c = t->owner;
     if (c) {
-        if (c->stream) hipStreamSynchronize(c->stream);
-        else hipDeviceSynchronize();
+        if (c->stream) (void)hipStreamSynchronize(c->stream);
+        else (void)hipDeviceSynchronize();
     }
     DevBuf *bufs[] = {&t->d_gas_off, &t->d_dm_off, &t->d_ncm, &t->d_bin_base,
                       &t->d_rc, &t->d_eps, &t->d_hmax, &t->binkey, &t->flag_c,
@@ -546,15 +546,15 @@ int crk_pass_times(crk_ctx *ctx, double pass_ms[7], double kernel_ms[7],
     }
     for (auto &s : ctx->spans) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, s.a, s.b);
+        (void)hipEventElapsedTime(&ms, s.a, s.b);
         if (s.kernel) {
             if (kernel_ms) kernel_ms[s.pass] += ms;
             if (launches) launches[s.pass] += 1;
         } else if (pass_ms) {
             pass_ms[s.pass] += ms;
         }
-        hipEventDestroy(s.a);
-        hipEventDestroy(s.b);
+        (void)hipEventDestroy(s.a);
+        (void)hipEventDestroy(s.b);
     }
     ctx->spans.clear();
     return CRK_OK;

@@ -647,28 +647,6 @@ __global__ void seg_leafcount_kernel(const int32_t *__restrict__ nd_count,
     }
 }
 
-// exclusive prefix of v over the workgroup (SEG_TB threads); *total gets the
-// sum.  wsum: SEG_TB / 64 ints of LDS.  All threads must call it.
-__device__ inline int block_excl_scan(int v, int *wsum, int *total) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int incl = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(incl, off);
-        if (lane >= off) incl += o;
-    }
-    if (lane == 63) wsum[w] = incl;
-    __syncthreads();
-    int base = 0, tot = 0;
-    for (int q = 0; q < SEG_TB / 64; ++q) {
-        const int s = wsum[q];
-        base += q < w ? s : 0;
-        tot += s;
-    }
-    __syncthreads();
-    *total = tot;
-    return base + incl - v;
-}
-
 template <typename T>
 __device__ inline T seg_coord(const T *px, const T *py, const T *pz, int a,
                               int32_t c) {
@@ -753,7 +731,6 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
     int32_t *nbase = nchild + MAXN;  // [3][MAXN]
     int32_t *lst = nbase + 3 * MAXN;
     int32_t *lct = lst + MAXN;
-    __shared__ int wsum[SEG_TB / 64];
     __shared__ long long wsum64[SEG_TB / 64];
     __shared__ int s_nn;
 
