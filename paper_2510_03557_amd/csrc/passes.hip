@@ -465,58 +465,28 @@ __global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
     process_leaf<T, P, BLOCK, MODE>(tv, pa, I, sj, sjid, wcnt, smask, glist);
 }
 
-// Split form: one wavefront per sub-leaf (<= 16 particles), four lanes per
-// particle.  The wave walks the parent leaf's list, culls every j particle
-// against the sub-leaf's box (smaller than the leaf's, so fewer candidates
-// survive), and lane q of a particle's quad takes candidates q, q + 4, ...
-// of each buffer; the quad's compensated sums are combined at the end and
-// lane 0 of the quad writes the outputs.  Recentring uses the parent
-// leaf's first particle, as in the other forms.
-template <typename T, typename P>
-__device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
-                                                const typename P::Args &pa,
-                                                const int I, const int g,
-                                                T *sj, int *sjid) {
+// Split forms: one wavefront per sub-leaf (<= 16 particles).  The wave
+// walks the parent leaf's list, skips j-leaves out of range of the
+// sub-leaf's box, culls every j particle against that box (smaller than the
+// leaf's, so fewer candidates survive) and stages the survivors, recentred
+// on the parent leaf's first particle as in the other forms, in an LDS
+// buffer of P::CAPF * 64 candidates; sweep(n) consumes a full buffer.
+template <typename T, typename P, typename Sweep>
+__device__ __forceinline__ void stage_subleaf(const TreeView<T> &tv,
+                                              const typename P::Args &pa,
+                                              const int I, const int64_t slot,
+                                              T *sj, int *sjid, Sweep &&sweep) {
     constexpr int CAP = P::CAPF * 64;
     const int lane = threadIdx.x;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t slot = 4 * (int64_t)I + g;
-    const int sst = tv.sst[slot];
-    const int scnt = min(tv.scnt[slot], 16);
-    const int ii = lane >> 2, q = lane & 3;
-    const bool act = ii < scnt;
-    const int i = act ? sst + ii : sst;
     const int st = tv.leaf_start[I];
     const T rx = tv.px[st], ry = tv.py[st], rz = tv.pz[st];
     const int box = tv.leaf_box[I];
     const int64_t sl = 4 * tv.lcap;
     const T hmS = tv.shm[slot];
-    typename P::I is;
-    P::load_i(is, pa, tv, i, tv.px[i] - rx, tv.py[i] - ry, tv.pz[i] - rz, box);
-    typename P::Tile tile;
-    tile.zero();
-    typename P::Acc acc;
-    acc.zero();
     const int64_t e0 = min(tv.list_off[I], tv.list_cap);
     const int64_t e1 = min(tv.list_off[I + 1], tv.list_cap);
     int nbuf = 0;
-    auto sweep = [&](int n) {
-        __syncthreads();
-        // every lane runs the loop (inactive lanes hold a valid particle
-        // whose sums are never written); blocks of 16 candidates unrolled
-        int k0 = 0;
-        for (; k0 + 16 <= n; k0 += 16) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = k0 + 4 * u + q;
-                P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
-            }
-        }
-        for (int k = k0 + q; k < n; k += 4)
-            P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
-        acc.fold(tile);
-        __syncthreads();
-    };
     // j-leaves of the parent's list out of range of this sub-leaf's box are
     // skipped before their particles are loaded.  The box gap is computed in
     // T from coordinates in [1, 2) shifted by at most one box (a few ulp of
@@ -573,6 +543,86 @@ __device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
         nbuf += __popcll(m);
     });
     sweep(nbuf);
+}
+
+// Quad form: four lanes per particle.  Lane q of a particle's quad takes
+// candidates q, q + 4, ... of each buffer; the quad's compensated sums are
+// combined at the end and lane 0 of the quad writes the outputs.
+template <typename T, typename P>
+__device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
+                                                const typename P::Args &pa,
+                                                const int I, const int g,
+                                                T *sj, int *sjid) {
+    const int lane = threadIdx.x;
+    const int64_t slot = 4 * (int64_t)I + g;
+    const int sst = tv.sst[slot];
+    const int scnt = min(tv.scnt[slot], 16);
+    const int ii = lane >> 2, q = lane & 3;
+    const bool act = ii < scnt;
+    const int i = act ? sst + ii : sst;
+    const int st = tv.leaf_start[I];
+    const T rx = tv.px[st], ry = tv.py[st], rz = tv.pz[st];
+    const int box = tv.leaf_box[I];
+    typename P::I is;
+    P::load_i(is, pa, tv, i, tv.px[i] - rx, tv.py[i] - ry, tv.pz[i] - rz, box);
+    typename P::Tile tile;
+    tile.zero();
+    typename P::Acc acc;
+    acc.zero();
+    auto sweep = [&](int n) {
+        __syncthreads();
+        // every lane runs the loop (inactive lanes hold a valid particle
+        // whose sums are never written)
+        if constexpr (P::MASKED) {
+            // two phases: the range test of every candidate of the lane
+            // (k = 4 t + q) sets bit t of a mask, then the lane evaluates
+            // its in-range candidates in ascending t.  The pair body runs
+            // on in-range pairs only, and each lane adds its pairs in the
+            // same order as a plain sweep that skips the out-of-range ones.
+            using M = uint64_t;
+            constexpr int MB = 64;
+            const int nt = (n + 3) >> 2;  // candidate slots per lane (CAP % 4 == 0)
+            for (int t0 = 0; t0 < nt; t0 += MB) {
+                const int tn = min(nt - t0, MB);
+                M m = 0;
+                int t = 0;
+                for (; t + 4 <= tn; t += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int k = 4 * (t0 + t + u) + q;
+                        const bool c = P::test(is, &sj[k * P::NJ], sjid[k] == i);
+                        m |= M((k < n) & c) << (t + u);
+                    }
+                }
+                for (; t < tn; ++t) {
+                    const int k = 4 * (t0 + t) + q;
+                    const bool c = P::test(is, &sj[k * P::NJ], sjid[k] == i);
+                    m |= M((k < n) & c) << t;
+                }
+                while (m) {
+                    const int b = __builtin_ctzll(m);
+                    m &= m - 1;
+                    const int k = 4 * (t0 + b) + q;
+                    P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+                }
+            }
+        } else {
+            // blocks of 16 candidates unrolled
+            int k0 = 0;
+            for (; k0 + 16 <= n; k0 += 16) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = k0 + 4 * u + q;
+                    P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+                }
+            }
+            for (int k = k0 + q; k < n; k += 4)
+                P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+        }
+        acc.fold(tile);
+        __syncthreads();
+    };
+    stage_subleaf<T, P>(tv, pa, I, slot, sj, sjid, sweep);
     acc.quad_reduce();
     if (act && q == 0) P::finish(acc, is, pa, tv, i);
 }
@@ -636,6 +686,8 @@ template <typename T> struct DensityPass {
     static constexpr int NJ = 4;  // fx, fy, fz, m
     static constexpr int CAPF = 4;  // candidate buffer = CAPF * BLOCK
     static constexpr int ID = 0;    // bit in the walk mask
+    // split sweep: one phase (the pair body is about as cheap as its test)
+    static constexpr bool MASKED = false;
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
         return widen<T>(2.0 * (double)hI);
     }
@@ -729,6 +781,7 @@ template <typename T> struct CoeffPass {
     static constexpr int NJ = 8;  // fx fy fz V m + pad
     static constexpr int CAPF = 4;
     static constexpr int ID = 1;
+    static constexpr bool MASKED = true;  // split sweep: test, then pairs
     static constexpr int NS = 33;
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
         return widen<T>(2.0 * (double)hI);
@@ -954,6 +1007,10 @@ template <typename T> struct HydroPass {
                                    // 36 spreads per-lane reads over banks)
     static constexpr int CAPF = 1;
     static constexpr int ID = 2;
+    // split sweep: one phase.  The in-range candidates of one buffer are
+    // clustered in space, so the per-lane counts of a two-phase sweep are
+    // uneven and its longest lane costs more than the plain sweep.
+    static constexpr bool MASKED = false;
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T hJ) {
         return widen<T>(2.0 * (double)(hI > hJ ? hI : hJ));
     }
@@ -1022,7 +1079,7 @@ template <typename T> struct HydroPass {
     __device__ static bool test(const I &is, const T *jd, bool self) {
         const T x0 = is.ex - jd[0], x1 = is.ey - jd[1], x2 = is.ez - jd[2];
         const T r2 = x0 * x0 + x1 * x1 + x2 * x2;
-        return !self && ((r2 * is.f[3] < T(4)) || (r2 * jd[6] < T(4)));
+        return !self & ((r2 * is.f[3] < T(4)) | (r2 * jd[6] < T(4)));
     }
     __device__ static void pair(Tile &tl, const I &is, const T *jd, bool self) {
         const T x0 = is.ex - jd[0], x1 = is.ey - jd[1], x2 = is.ez - jd[2];
@@ -1086,6 +1143,7 @@ template <typename T> struct GravityPass {
     static constexpr int NJ = 4;  // fx fy fz Gm
     static constexpr int CAPF = 4;
     static constexpr int ID = 3;
+    static constexpr bool MASKED = false;  // (as for the hydro forces)
     __device__ static T range(const Args &, const TreeView<T> &tv, int box, T, T) {
         return widen<T>(tv.rc[box]);
     }
@@ -1201,6 +1259,7 @@ template <typename T> struct CountPass {
     static constexpr int NJ = 4;  // fx fy fz 1/h^2
     static constexpr int CAPF = 4;
     static constexpr int ID = 4;
+    static constexpr bool MASKED = false;
     __device__ static T range(const Args &a, const TreeView<T> &tv, int box, T hI,
                               T hJ) {
         const int m = a.mode % 3;
