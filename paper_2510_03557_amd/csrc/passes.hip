@@ -1003,8 +1003,10 @@ template <typename T> struct HydroPass {
         const T *m;       // tree order
         T Cl, Cq, epsQ;
     };
-    static constexpr int NJ = 36;  // fx fy fz + HF fields + pad (stride
-                                   // 36 spreads per-lane reads over banks)
+    // candidate record: fx fy fz, one pad, the HF fields from float FO on
+    // (16-byte aligned, so they load as 128-bit LDS reads), pad to 36
+    static constexpr int FO = 4;
+    static constexpr int NJ = 36;
     static constexpr int CAPF = 1;
     static constexpr int ID = 2;
     // split sweep: one phase.  The in-range candidates of one buffer are
@@ -1016,7 +1018,7 @@ template <typename T> struct HydroPass {
     }
     __device__ static T sub_range(const Args &, const TreeView<T> &, int, T hg,
                                   const T *jd) {
-        const T hj = jd[3 + 23];
+        const T hj = jd[FO + 23];
         return widen<T>(2.0 * (double)(hg > hj ? hg : hj));
     }
     struct I {
@@ -1055,8 +1057,9 @@ template <typename T> struct HydroPass {
         d[0] = fx;
         d[1] = fy;
         d[2] = fz;
+        d[3] = T(0);
 #pragma unroll
-        for (int k = 0; k < HF; ++k) d[3 + k] = a.f[k * a.n_gas + j];
+        for (int k = 0; k < HF; ++k) d[FO + k] = a.f[k * a.n_gas + j];
     }
     // gradient of the corrected kernel of particle with fields f at y
     __device__ static void grad_rk(const T *f, T y0, T y1, T y2, T r2, T out[3],
@@ -1079,12 +1082,12 @@ template <typename T> struct HydroPass {
     __device__ static bool test(const I &is, const T *jd, bool self) {
         const T x0 = is.ex - jd[0], x1 = is.ey - jd[1], x2 = is.ez - jd[2];
         const T r2 = x0 * x0 + x1 * x1 + x2 * x2;
-        return !self & ((r2 * is.f[3] < T(4)) | (r2 * jd[6] < T(4)));
+        return !self & ((r2 * is.f[3] < T(4)) | (r2 * jd[FO + 3] < T(4)));
     }
     __device__ static void pair(Tile &tl, const I &is, const T *jd, bool self) {
         const T x0 = is.ex - jd[0], x1 = is.ey - jd[1], x2 = is.ez - jd[2];
         const T r2 = x0 * x0 + x1 * x1 + x2 * x2;
-        const T *fj = jd + 3;
+        const T *fj = jd + FO;
         const T *fi = is.f;
         // both range tests evaluated (no short circuit: no branch around the
         // LDS read of the j-side 1/h^2)
