@@ -324,3 +324,149 @@ def step_sampled(wl, gas_targets, dm_targets, params=PARAMS):
         res["a_grav_gas"][:, sel] = (ax[:k], ay[:k], az[:k])
         res["a_grav_dm"][:, dsel] = (ax[k:], ay[k:], az[k:])
     return res
+
+
+# ----------------------------------------------------------------------------
+# hierarchical time steps on a fixed tree (adaptive integration, Sec. IV-A;
+# active leaves, Sec. IV-B.1).  The paper describes the scheme but prints no
+# formulas; the readings below are stated where they are used.
+# ----------------------------------------------------------------------------
+
+# Time-step constants (readings): Courant factor for gas, accuracy parameter
+# of the acceleration criterion dt = sqrt(2 eta eps / |a|).
+STEP_PARAMS = dict(c_cfl=0.25, eta=0.025)
+
+
+def timestep_bins(dt, max_level, eps, ax, ay, az, h=None, cs=None,
+                  c_cfl=STEP_PARAMS["c_cfl"], eta=STEP_PARAMS["eta"]):
+    """Bin level b in [0, max_level] of every particle: the smallest b whose
+    step tau_b = dt / 2^b satisfies tau_b^4 |a|^2 <= (2 eta eps)^2 (the
+    acceleration criterion squared twice) and, for gas (h and cs given),
+    tau_b cs <= c_cfl h (Courant); max_level when none does.  Every
+    quantity is a double product or sum rounded once, in this order, so
+    that another implementation taking the same steps takes the same
+    integer decision."""
+    ax, ay, az = (np.asarray(a, np.float64) for a in (ax, ay, az))
+    a2 = (ax * ax + ay * ay) + az * az
+    rhs_a = (2.0 * eta * eps) ** 2
+    n = ax.shape[0]
+    bins = np.full(n, max_level, np.int32)
+    done = np.zeros(n, bool)
+    if h is not None:
+        rhs_c = c_cfl * np.asarray(h, np.float64)
+        cs = np.asarray(cs, np.float64)
+    for b in range(max_level + 1):
+        tau = dt * 2.0 ** (-b)
+        t2 = tau * tau
+        ok = (t2 * t2) * a2 <= rhs_a
+        if h is not None:
+            ok &= tau * cs <= rhs_c
+        new = ok & ~done
+        bins[new] = b
+        done |= ok
+    return bins
+
+
+def _wrap(x):
+    x = x - np.floor(x - 1.0)
+    return np.where(x >= 2.0, x - 1.0, x)
+
+
+def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
+                  counts=None):
+    """One interval dt of hierarchical block steps (kick-drift-kick) with
+    2^max_level substeps of dt / 2^max_level.  A particle of bin b takes
+    steps tau_b = dt / 2^b, starting at substeps s with s % 2^(L-b) == 0
+    (L = max_level) and ending after substeps s with (s + 1) % 2^(L-b) == 0.
+
+    Readings: all particles are evaluated at the start; at each substep the
+    particles starting a step get the opening half-kick v += a tau_b / 2,
+    u += du/dt tau_b / 2 with their latest a and du/dt; every particle
+    drifts x += v dt / 2^L; then the four passes run for the particles
+    ending a step (density, coefficients, hydro forces and gravity at those
+    particles only, over all neighbours at their current positions, with
+    the latest values of inactive neighbours, their half-kicked v and u
+    included) and they get the closing half-kick with the new a and du/dt.
+    Smoothing lengths and masses stay fixed; positions are wrapped into
+    [1, 2) at the end.  Returns the final x, v, u (float64, (3, n) / n per
+    species) and the state of the last evaluation.  counts, if a dict,
+    receives the number of evaluations of every particle."""
+    g, d = wl.gas, wl.dm
+    ng, nd = g.n, d.n
+    L = int(max_level)
+    bg = np.asarray(bins_gas, np.int64)
+    bd = np.asarray(bins_dm, np.int64)
+    xg = np.array([g.x, g.y, g.z], np.float64)
+    vg = np.array([g.vx, g.vy, g.vz], np.float64)
+    xd = np.array([d.x, d.y, d.z], np.float64)
+    vd = np.array([d.vx, d.vy, d.vz], np.float64)
+    u = np.asarray(g.u, np.float64).copy() if ng else np.zeros(0)
+    st = {k: np.zeros(ng) for k in ("V", "rho_tilde", "A", "rho", "P", "cs",
+                                     "dudt")}
+    st.update(B=np.zeros((ng, 3)), gradA=np.zeros((ng, 3)),
+              gradB=np.zeros((ng, 3, 3)), a_hydro=np.zeros((3, ng)),
+              a_grav_gas=np.zeros((3, ng)), a_grav_dm=np.zeros((3, nd)))
+    ev_g = np.zeros(ng, np.int64)
+    ev_d = np.zeros(nd, np.int64)
+
+    def evaluate(act_g, act_d):
+        ev_g[act_g] += 1
+        ev_d[act_d] += 1
+        for b, gs, ds in _box_slices(wl):
+            n = gs.stop - gs.start
+            X = _wrap(xg[:, gs])
+            Tg = np.nonzero(act_g[gs])[0]
+            if Tg.size:
+                hh, mm = g.h[gs], g.m[gs]
+                V, rt = density(X[0], X[1], X[2], hh, mm, targets=Tg)
+                st["V"][gs.start + Tg] = V
+                st["rho_tilde"][gs.start + Tg] = rt
+                c = coefficients(X[0], X[1], X[2], hh, mm, st["V"][gs],
+                                 u[gs], params["gamma"], targets=Tg)
+                for k in ("A", "B", "gradA", "gradB", "rho", "P", "cs"):
+                    st[k][gs.start + Tg] = c[k]
+                ax, ay, az, du = hydro(
+                    X[0], X[1], X[2], vg[0, gs], vg[1, gs], vg[2, gs], hh, mm,
+                    st["V"][gs], st["rho"][gs], st["P"][gs], st["cs"][gs],
+                    st["A"][gs], st["B"][gs], st["gradA"][gs],
+                    st["gradB"][gs], params["Cl"], params["Cq"],
+                    params["epsQ"], targets=Tg)
+                st["a_hydro"][:, gs.start + Tg] = (ax, ay, az)
+                st["dudt"][gs.start + Tg] = du
+            Td = np.nonzero(act_d[ds])[0]
+            if Tg.size or Td.size:
+                XD = _wrap(xd[:, ds])
+                XA = np.concatenate([X, XD], axis=1)
+                M = np.concatenate([g.m[gs], d.m[ds]])
+                ax, ay, az = gravity(XA[0], XA[1], XA[2], M, float(wl.r_c[b]),
+                                     float(wl.eps[b]), params["G"],
+                                     targets=np.concatenate([Tg, Td + n]))
+                k = Tg.size
+                st["a_grav_gas"][:, gs.start + Tg] = (ax[:k], ay[:k], az[:k])
+                st["a_grav_dm"][:, ds.start + Td] = (ax[k:], ay[k:], az[k:])
+
+    def kick(act_g, act_d):
+        tg = dt * 2.0 ** (-bg[act_g].astype(np.float64)) * 0.5
+        td = dt * 2.0 ** (-bd[act_d].astype(np.float64)) * 0.5
+        vg[:, act_g] += (st["a_grav_gas"][:, act_g] + st["a_hydro"][:, act_g]) * tg
+        u[act_g] += st["dudt"][act_g] * tg
+        vd[:, act_d] += st["a_grav_dm"][:, act_d] * td
+
+    evaluate(np.ones(ng, bool), np.ones(nd, bool))
+    delta = dt * 2.0 ** (-L)
+    for s in range(2 ** L):
+        start_g = (s % (2 ** (L - bg))) == 0
+        start_d = (s % (2 ** (L - bd))) == 0
+        kick(start_g, start_d)
+        xg += vg * delta
+        xd += vd * delta
+        end_g = ((s + 1) % (2 ** (L - bg))) == 0
+        end_d = ((s + 1) % (2 ** (L - bd))) == 0
+        evaluate(end_g, end_d)
+        kick(end_g, end_d)
+    if counts is not None:
+        counts["gas"] = ev_g
+        counts["dm"] = ev_d
+    out = dict(xg=_wrap(xg), vg=vg, u=u, xd=_wrap(xd), vd=vd)
+    out.update(st)
+    return out
