@@ -49,7 +49,9 @@ typedef enum {
     CRK_EINVAL = -1,    /* bad argument (host side) or bad input value      */
     CRK_ECAPACITY = -2, /* a capacity fixed at graph capture was exceeded    */
     CRK_EDEVICE = -3,   /* HIP runtime error                                 */
-    CRK_ESTATE = -4     /* call out of order (e.g. lists before tree)        */
+    CRK_ESTATE = -4,    /* call out of order (e.g. lists before tree)        */
+    CRK_ESTALE = -5     /* the tree no longer covers the particles' motion:
+                           rebuild it (crk_tree_refit)                       */
 } crk_status;
 
 typedef enum {
@@ -239,6 +241,77 @@ int crk_integrate(crk_ctx *ctx, int64_t n, double dt, double *x64,
                   double *v64, double *u64, const void *const a_grav[3],
                   const void *const a_hydro[3], const void *dudt,
                   void *const x[3], void *const v[3], void *u);
+
+/* ------------------------------------------------------------------------ */
+/* hierarchical time steps on a tree kept for an interval                    */
+/* ------------------------------------------------------------------------ */
+/* The adaptive integration of Sec. IV-A groups particles into timestep bins
+ * and subcycles them inside a long step; Sec. IV-B.1 keeps the tree for the
+ * whole interval, lets the leaf bounding boxes grow, and updates only active
+ * leaves at a substep.  The interval dt is cut into 2^max_level substeps;
+ * a particle of bin b steps by tau_b = dt / 2^b, starting at substeps s with
+ * s % 2^(max_level-b) == 0 and ending after substeps s with
+ * (s + 1) % 2^(max_level-b) == 0.  One substep of a block kick-drift-kick
+ * cycle: crk_kick (phase 0), crk_drift (no wrap), crk_tree_refit,
+ * build_interaction_lists, crk_tree_set_active (substep s), the four passes
+ * (they then run over the active leaves and write only active particles;
+ * inactive ones keep their outputs), crk_kick (phase 1); after the last
+ * substep every particle is synchronised and crk_drift with delta 0 and
+ * wrap 1 wraps the positions.  All arrays are device memory in caller
+ * order unless stated. */
+
+/* Timestep bin of n particles: the smallest b in [0, max_level] whose
+ * tau_b = dt / 2^b satisfies tau_b^4 |a|^2 <= (2 eta eps)^2 (the criterion
+ * tau <= sqrt(2 eta eps / |a|) with softening eps) and, when h and cs are
+ * given (gas), the Courant condition tau_b cs <= c_cfl h; max_level when
+ * none does.  |a|^2 = ((ax^2 + ay^2) + az^2) with a = a_grav + a_hydro
+ * (a_hydro may be NULL), evaluated in double with every operation rounded
+ * once in that order, so the integer result is reproducible.  a_grav,
+ * a_hydro: 3 planes, h, cs: n values (context precision, or NULL for dark
+ * matter); bins: n int32 (out).  dt > 0, 0 <= max_level <= 30. */
+int crk_timestep_bins(crk_ctx *ctx, int64_t n, double dt, int32_t max_level,
+                      double eps, double c_cfl, double eta,
+                      const void *const a_grav[3], const void *const a_hydro[3],
+                      const void *h, const void *cs, int32_t *bins);
+
+/* Selects the particles ending a step after substep `substep` of a cycle
+ * with 2^max_level substeps (bins_gas: n_gas, bins_dm: n_dm int32 levels,
+ * clamped to [0, max_level]); the leaves holding any of them become the work
+ * items of the pair passes, which then write outputs for those particles
+ * only.  substep < 0 selects everything (the state after build_tree).
+ * Synchronises (reads the active leaf counts back). */
+int crk_tree_set_active(crk_ctx *ctx, crk_tree *tree, const int32_t *bins_gas,
+                        const int32_t *bins_dm, int32_t max_level,
+                        int64_t substep);
+
+/* Copies the particles' current positions (caller order, context
+ * precision; not wrapped inside an interval) into the tree and grows every
+ * leaf and sub-leaf bounding box to contain them; boxes never shrink and the
+ * smoothing lengths stay those of build_tree.  Returns CRK_ESTALE when a
+ * leaf box reaches so far out of its chaining-mesh bin (by d) that the
+ * 27-bin stencil could miss a pair (2 d + range > bin width): the tree must
+ * then be rebuilt.  Synchronises. */
+int crk_tree_refit(crk_ctx *ctx, crk_tree *tree, const void *gx,
+                   const void *gy, const void *gz, const void *dx,
+                   const void *dy, const void *dz);
+
+/* Block kick at substep s: the particles starting (phase 0) or ending
+ * (phase 1) a step at s get v += (a_grav + a_hydro) tau_b / 2 and
+ * u += dudt tau_b / 2 in double, then the context-precision copies v and u
+ * are refreshed.  v64: 3 planes of doubles (in/out); u64: doubles or NULL;
+ * a_grav: 3 planes, a_hydro: 3 planes or NULL, dudt (with u64); v: 3
+ * pointers to the copies, u: copy or NULL. */
+int crk_kick(crk_ctx *ctx, int64_t n, double dt, int32_t max_level,
+             int64_t substep, int32_t phase, const int32_t *bins, double *v64,
+             double *u64, const void *const a_grav[3],
+             const void *const a_hydro[3], const void *dudt, void *const v[3],
+             void *u);
+
+/* Drift of every particle, x += v delta in double (x64, v64: 3 planes),
+ * wrapped into [1, 2) when wrap != 0, then the context-precision copies x
+ * (3 pointers) are refreshed. */
+int crk_drift(crk_ctx *ctx, int64_t n, double delta, int32_t wrap,
+              double *x64, const double *v64, void *const x[3]);
 
 /* ------------------------------------------------------------------------ */
 /* tree queries, graph capture, release                                      */

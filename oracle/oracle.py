@@ -348,7 +348,8 @@ def timestep_bins(dt, max_level, eps, ax, ay, az, h=None, cs=None,
     integer decision."""
     ax, ay, az = (np.asarray(a, np.float64) for a in (ax, ay, az))
     a2 = (ax * ax + ay * ay) + az * az
-    rhs_a = (2.0 * eta * eps) ** 2
+    r = 2.0 * eta * eps
+    rhs_a = r * r
     n = ax.shape[0]
     bins = np.full(n, max_level, np.int32)
     done = np.zeros(n, bool)
@@ -373,7 +374,7 @@ def _wrap(x):
 
 
 def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
-                  counts=None):
+                  counts=None, forces_at="float64"):
     """One interval dt of hierarchical block steps (kick-drift-kick) with
     2^max_level substeps of dt / 2^max_level.  A particle of bin b takes
     steps tau_b = dt / 2^b, starting at substeps s with s % 2^(L-b) == 0
@@ -388,9 +389,17 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
     the latest values of inactive neighbours, their half-kicked v and u
     included) and they get the closing half-kick with the new a and du/dt.
     Smoothing lengths and masses stay fixed; positions are wrapped into
-    [1, 2) at the end.  Returns the final x, v, u (float64, (3, n) / n per
+    [1, 2) at the end.  forces_at="float32" evaluates the passes at the
+    float32 roundings of the double positions (not wrapped inside the
+    interval), velocities and energies: the mixed-precision split of
+    Sec. IV-A, where the short-range solver works on float32 copies of a
+    double state.  Returns the final x, v, u (float64, (3, n) / n per
     species) and the state of the last evaluation.  counts, if a dict,
     receives the number of evaluations of every particle."""
+    f32 = forces_at == "float32"
+
+    def q(a):
+        return a.astype(np.float32).astype(np.float64) if f32 else a
     g, d = wl.gas, wl.dm
     ng, nd = g.n, d.n
     L = int(max_level)
@@ -414,7 +423,7 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
         ev_d[act_d] += 1
         for b, gs, ds in _box_slices(wl):
             n = gs.stop - gs.start
-            X = _wrap(xg[:, gs])
+            X = _wrap(q(xg[:, gs]))
             Tg = np.nonzero(act_g[gs])[0]
             if Tg.size:
                 hh, mm = g.h[gs], g.m[gs]
@@ -422,11 +431,12 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
                 st["V"][gs.start + Tg] = V
                 st["rho_tilde"][gs.start + Tg] = rt
                 c = coefficients(X[0], X[1], X[2], hh, mm, st["V"][gs],
-                                 u[gs], params["gamma"], targets=Tg)
+                                 q(u[gs]), params["gamma"], targets=Tg)
                 for k in ("A", "B", "gradA", "gradB", "rho", "P", "cs"):
                     st[k][gs.start + Tg] = c[k]
+                V3 = q(vg[:, gs])
                 ax, ay, az, du = hydro(
-                    X[0], X[1], X[2], vg[0, gs], vg[1, gs], vg[2, gs], hh, mm,
+                    X[0], X[1], X[2], V3[0], V3[1], V3[2], hh, mm,
                     st["V"][gs], st["rho"][gs], st["P"][gs], st["cs"][gs],
                     st["A"][gs], st["B"][gs], st["gradA"][gs],
                     st["gradB"][gs], params["Cl"], params["Cq"],
@@ -435,7 +445,7 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
                 st["dudt"][gs.start + Tg] = du
             Td = np.nonzero(act_d[ds])[0]
             if Tg.size or Td.size:
-                XD = _wrap(xd[:, ds])
+                XD = _wrap(q(xd[:, ds]))
                 XA = np.concatenate([X, XD], axis=1)
                 M = np.concatenate([g.m[gs], d.m[ds]])
                 ax, ay, az = gravity(XA[0], XA[1], XA[2], M, float(wl.r_c[b]),

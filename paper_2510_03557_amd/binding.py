@@ -19,6 +19,7 @@ _HERE = Path(__file__).resolve().parent
 LIB_PATH = Path(os.environ.get("CRK_LIB", _HERE / "libcrk.so"))
 
 CRK_OK, CRK_EINVAL, CRK_ECAPACITY, CRK_EDEVICE, CRK_ESTATE = 0, -1, -2, -3, -4
+CRK_ESTALE = -5
 CRK_FP64, CRK_FP32 = 0, 1
 PASS_NAMES = ("tree", "lists", "density", "coefficients", "hydro", "gravity",
               "integrate")
@@ -30,7 +31,8 @@ EXPORTS = (
     "shortrange_gravity", "crk_integrate", "crk_tree_get_info",
     "crk_tree_get_leaves", "crk_count_pairs", "crk_graph_begin", "crk_graph_end",
     "crk_graph_launch", "crk_tree_free", "crk_timing_enable",
-    "crk_pass_times",
+    "crk_pass_times", "crk_timestep_bins", "crk_tree_set_active",
+    "crk_tree_refit", "crk_kick", "crk_drift",
 )
 
 
@@ -137,6 +139,15 @@ def load(path: Path | str | None = None):
     lib.crk_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64)]
+    P = ctypes.POINTER(vp)
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.crk_timestep_bins.argtypes = [vp, i64, f64, i32, f64, f64, f64, P, P,
+                                      vp, vp, vp]
+    lib.crk_tree_set_active.argtypes = [vp, vp, vp, vp, i32, i64]
+    lib.crk_tree_refit.argtypes = [vp, vp] + [vp] * 6
+    lib.crk_kick.argtypes = [vp, i64, f64, i32, i64, i32, vp, vp, vp, P, P, vp,
+                             P, vp]
+    lib.crk_drift.argtypes = [vp, i64, f64, i32, vp, vp, P]
     for name in EXPORTS:
         getattr(lib, name).restype = (ctypes.c_char_p if name == "crk_last_error"
                                       else ctypes.c_int)
@@ -266,6 +277,42 @@ class Context:
         check(self.lib.crk_integrate(
             self.handle, int(n), float(dt), _ptr(x64), _ptr(v64), _ptr(u64),
             ag, ah, _ptr(dudt), xo, vo, _ptr(u)))
+
+    # hierarchical time steps ------------------------------------------------
+    @staticmethod
+    def _p3(ts):
+        if ts is None:
+            return None
+        return (ctypes.c_void_p * 3)(*[t.data_ptr() for t in ts])
+
+    def timestep_bins(self, n, dt, max_level, eps, c_cfl, eta, a_grav,
+                      a_hydro, h, cs, bins):
+        check(self.lib.crk_timestep_bins(
+            self.handle, int(n), float(dt), int(max_level), float(eps),
+            float(c_cfl), float(eta), self._p3(a_grav), self._p3(a_hydro),
+            _ptr(h), _ptr(cs), _ptr(bins)))
+
+    def tree_set_active(self, tree, bins_gas, bins_dm, max_level, substep):
+        check(self.lib.crk_tree_set_active(
+            self.handle, tree.handle, _ptr(bins_gas), _ptr(bins_dm),
+            int(max_level), int(substep)))
+
+    def tree_refit(self, tree, gx, gy, gz, dx, dy, dz):
+        check(self.lib.crk_tree_refit(self.handle, tree.handle, _ptr(gx),
+                                      _ptr(gy), _ptr(gz), _ptr(dx), _ptr(dy),
+                                      _ptr(dz)))
+
+    def kick(self, n, dt, max_level, substep, phase, bins, v64, u64, a_grav,
+             a_hydro, dudt, v, u):
+        check(self.lib.crk_kick(
+            self.handle, int(n), float(dt), int(max_level), int(substep),
+            int(phase), _ptr(bins), _ptr(v64), _ptr(u64), self._p3(a_grav),
+            self._p3(a_hydro), _ptr(dudt), self._p3(v), _ptr(u)))
+
+    def drift(self, n, delta, wrap, x64, v64, x):
+        check(self.lib.crk_drift(self.handle, int(n), float(delta),
+                                 int(bool(wrap)), _ptr(x64), _ptr(v64),
+                                 self._p3(x)))
 
     def count_pairs(self, tree):
         """In-range ordered pairs (gather, hydro, gravity), then the swept

@@ -310,6 +310,7 @@ int build_tree(crk_ctx *ctx, const crk_boxes *boxes, const void *gx,
         return set_error(CRK_ESTATE, "tree belongs to another context");
     }
     PassSpan sp(ctx, P_TREE);
+    t->act_on = false;  // a new tree starts with every leaf active
     return tree_build(ctx, t, boxes, gx, gy, gz, gh, dx, dy, dz);
 }
 
@@ -415,6 +416,115 @@ int crk_integrate(crk_ctx *ctx, int64_t n, double dt, double *x64, double *v64,
     }
     PassSpan sp(ctx, P_INTEG);
     return integrate(ctx, n, dt, x64, v64, u64, a_grav, a_hydro, dudt, x, v, u);
+}
+
+int crk_timestep_bins(crk_ctx *ctx, int64_t n, double dt, int32_t max_level,
+                      double eps, double c_cfl, double eta,
+                      const void *const a_grav[3], const void *const a_hydro[3],
+                      const void *h, const void *cs, int32_t *bins) {
+    CRK_TRY(check_ctx(ctx));
+    if (n < 0) return set_error(CRK_EINVAL, "n must be >= 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(CRK_EINVAL, "dt must be > 0");
+    if (max_level < 0 || max_level > 30)
+        return set_error(CRK_EINVAL, "max_level must be in [0, 30]");
+    if (!(eps > 0.0) || !(eta > 0.0) || !std::isfinite(eps) || !std::isfinite(eta))
+        return set_error(CRK_EINVAL, "eps and eta must be > 0");
+    if ((h == nullptr) != (cs == nullptr))
+        return set_error(CRK_EINVAL, "h and cs: both or neither");
+    if (h && !(c_cfl > 0.0)) return set_error(CRK_EINVAL, "c_cfl must be > 0");
+    if (n == 0) return CRK_OK;
+    if (!a_grav) return set_error(CRK_EINVAL, "null a_grav");
+    const size_t el = ctx->elem();
+    for (int a = 0; a < 3; ++a) {
+        CRK_TRY(check_ptr(a_grav[a], el, "a_grav", true));
+        if (a_hydro) CRK_TRY(check_ptr(a_hydro[a], el, "a_hydro", true));
+    }
+    CRK_TRY(check_ptr(h, el, "h", false));
+    CRK_TRY(check_ptr(cs, el, "cs", false));
+    CRK_TRY(check_ptr(bins, 4, "bins", true));
+    return timestep_bins(ctx, n, dt, max_level, eps, c_cfl, eta, a_grav, a_hydro,
+                         h, cs, bins);
+}
+
+int crk_tree_set_active(crk_ctx *ctx, crk_tree *t, const int32_t *bins_gas,
+                        const int32_t *bins_dm, int32_t max_level,
+                        int64_t substep) {
+    CRK_TRY(check_tree_ready(ctx, t, false));
+    if (ctx->capturing) return set_error(CRK_ESTATE, "set_active during capture");
+    if (substep >= 0) {
+        if (max_level < 0 || max_level > 30)
+            return set_error(CRK_EINVAL, "max_level must be in [0, 30]");
+        if (substep >= ((int64_t)1 << max_level))
+            return set_error(CRK_EINVAL, "substep must be < 2^max_level");
+        CRK_TRY(check_ptr(bins_gas, 4, "bins_gas", t->n_gas > 0));
+        CRK_TRY(check_ptr(bins_dm, 4, "bins_dm", t->n_dm > 0));
+    }
+    return tree_set_active(ctx, t, bins_gas, bins_dm, max_level, substep);
+}
+
+int crk_tree_refit(crk_ctx *ctx, crk_tree *t, const void *gx, const void *gy,
+                   const void *gz, const void *dx, const void *dy,
+                   const void *dz) {
+    CRK_TRY(check_tree_ready(ctx, t, false));
+    if (ctx->capturing) return set_error(CRK_ESTATE, "refit during capture");
+    const size_t el = ctx->elem();
+    const bool g = t->n_gas > 0, d = t->n_dm > 0;
+    CRK_TRY(check_ptr(gx, el, "gx", g));
+    CRK_TRY(check_ptr(gy, el, "gy", g));
+    CRK_TRY(check_ptr(gz, el, "gz", g));
+    CRK_TRY(check_ptr(dx, el, "dx", d));
+    CRK_TRY(check_ptr(dy, el, "dy", d));
+    CRK_TRY(check_ptr(dz, el, "dz", d));
+    PassSpan sp(ctx, P_TREE);
+    return tree_refit(ctx, t, gx, gy, gz, dx, dy, dz);
+}
+
+int crk_kick(crk_ctx *ctx, int64_t n, double dt, int32_t max_level,
+             int64_t substep, int32_t phase, const int32_t *bins, double *v64,
+             double *u64, const void *const a_grav[3],
+             const void *const a_hydro[3], const void *dudt, void *const v[3],
+             void *u) {
+    CRK_TRY(check_ctx(ctx));
+    if (n < 0) return set_error(CRK_EINVAL, "n must be >= 0");
+    if (!std::isfinite(dt)) return set_error(CRK_EINVAL, "dt must be finite");
+    if (max_level < 0 || max_level > 30)
+        return set_error(CRK_EINVAL, "max_level must be in [0, 30]");
+    if (substep < 0 || substep >= ((int64_t)1 << max_level))
+        return set_error(CRK_EINVAL, "substep must be in [0, 2^max_level)");
+    if (phase != 0 && phase != 1) return set_error(CRK_EINVAL, "phase must be 0 or 1");
+    if (n == 0) return CRK_OK;
+    if (!a_grav || !v) return set_error(CRK_EINVAL, "null pointer array");
+    const size_t el = ctx->elem();
+    CRK_TRY(check_ptr(bins, 4, "bins", true));
+    CRK_TRY(check_ptr(v64, 8, "v64", true));
+    CRK_TRY(check_ptr(u64, 8, "u64", false));
+    for (int a = 0; a < 3; ++a) {
+        CRK_TRY(check_ptr(a_grav[a], el, "a_grav", true));
+        CRK_TRY(check_ptr(v[a], el, "v", true));
+        if (a_hydro) CRK_TRY(check_ptr(a_hydro[a], el, "a_hydro", true));
+    }
+    if (u64) {
+        CRK_TRY(check_ptr(dudt, el, "dudt", true));
+        CRK_TRY(check_ptr(u, el, "u", true));
+    }
+    PassSpan sp(ctx, P_INTEG);
+    return block_kick(ctx, n, dt, max_level, substep, phase, bins, v64, u64,
+                      a_grav, a_hydro, dudt, v, u);
+}
+
+int crk_drift(crk_ctx *ctx, int64_t n, double delta, int32_t wrap, double *x64,
+              const double *v64, void *const x[3]) {
+    CRK_TRY(check_ctx(ctx));
+    if (n < 0) return set_error(CRK_EINVAL, "n must be >= 0");
+    if (!std::isfinite(delta)) return set_error(CRK_EINVAL, "delta must be finite");
+    if (n == 0) return CRK_OK;
+    if (!x) return set_error(CRK_EINVAL, "null pointer array");
+    const size_t el = ctx->elem();
+    CRK_TRY(check_ptr(x64, 8, "x64", true));
+    CRK_TRY(check_ptr(v64, 8, "v64", true));
+    for (int a = 0; a < 3; ++a) CRK_TRY(check_ptr(x[a], el, "x", true));
+    PassSpan sp(ctx, P_INTEG);
+    return drift(ctx, n, delta, wrap ? 1 : 0, x64, v64, x);
 }
 
 int crk_count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[6]) {

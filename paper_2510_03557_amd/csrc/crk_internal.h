@@ -176,6 +176,17 @@ struct crk_tree {
 
     // device: per-pass scratch (tree order)
     crk::DevBuf pf[32];                // pass fields, reused between passes
+
+    // active subset of a hierarchical time step (crk_tree_set_active):
+    // per-slot flags, active leaves in leaf order (gas leaves first), device
+    // counts {all, gas} and their host copies
+    bool act_on = false;
+    crk::DevBuf act_flags;             // uint8 per slot
+    crk::DevBuf act_leaf;              // int32 per leaf (flag, then scan)
+    crk::DevBuf act_items;             // int32 per active leaf
+    crk::DevBuf act_count;             // int32 [2]
+    int64_t act_nall = 0, act_ngas = 0;
+    crk::DevBuf overhang;              // float per box (refit)
 };
 
 namespace crk {
@@ -232,6 +243,23 @@ int integrate(crk_ctx *ctx, int64_t n, double dt, double *x64, double *v64,
               double *u64, const void *const a_grav[3],
               const void *const a_hydro[3], const void *dudt,
               void *const x[3], void *const v[3], void *u);
+// hierarchical time steps (substep.hip)
+int timestep_bins(crk_ctx *ctx, int64_t n, double dt, int max_level,
+                  double eps, double c_cfl, double eta,
+                  const void *const a_grav[3], const void *const a_hydro[3],
+                  const void *h, const void *cs, int32_t *bins);
+int tree_set_active(crk_ctx *ctx, crk_tree *t, const int32_t *bins_gas,
+                    const int32_t *bins_dm, int max_level, int64_t substep);
+int tree_refit(crk_ctx *ctx, crk_tree *t, const void *gx, const void *gy,
+               const void *gz, const void *dx, const void *dy,
+               const void *dz);
+int block_kick(crk_ctx *ctx, int64_t n, double dt, int max_level,
+               int64_t substep, int phase, const int32_t *bins, double *v64,
+               double *u64, const void *const a_grav[3],
+               const void *const a_hydro[3], const void *dudt,
+               void *const v[3], void *u);
+int drift(crk_ctx *ctx, int64_t n, double delta, int wrap, double *x64,
+          const double *v64, void *const x[3]);
 
 // timing helpers (capi.cpp): bracket a span on the context stream
 void span_begin(crk_ctx *ctx, int pass, bool kernel, hipEvent_t *ev);

@@ -127,7 +127,19 @@ template <typename T> struct TreeView {
     const T *slo, *shi, *shm;          // their boxes (3 planes of 4*lcap), h_max
     const double *rc, *eps;
     int64_t n_gas;
+    // active subset (hierarchical time steps): work item k is leaf items[k]
+    // and only slots with act[i] != 0 write outputs; both NULL: all leaves
+    const int32_t *items;
+    const uint8_t *act;
 };
+
+// leaf of work item k, and whether slot i writes its outputs
+template <typename T> __device__ inline int item_leaf(const TreeView<T> &tv, int k) {
+    return tv.items ? tv.items[k] : k;
+}
+template <typename T> __device__ inline bool slot_active(const TreeView<T> &tv, int i) {
+    return !tv.act || tv.act[i] != 0;
+}
 
 // a wave-uniform value moved to a scalar register
 __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -432,7 +444,7 @@ __device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
         nbuf += tot;
     });
     sweep(nbuf);
-    if (act) P::finish(acc, is, pa, tv, i);
+    if (act && slot_active(tv, i)) P::finish(acc, is, pa, tv, i);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of an MI355X, each
@@ -461,7 +473,8 @@ __global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
     // by capacity): surplus blocks leave first, the remap covers [0, n)
     const int n_items = *tv.n_items;
     if ((int)blockIdx.x >= n_items) return;
-    const int I = tv.xcd_remap ? xcd_block(blockIdx.x, n_items) : (int)blockIdx.x;
+    const int I = item_leaf(tv, tv.xcd_remap ? xcd_block(blockIdx.x, n_items)
+                                             : (int)blockIdx.x);
     process_leaf<T, P, BLOCK, MODE>(tv, pa, I, sj, sjid, wcnt, smask, glist);
 }
 
@@ -624,7 +637,7 @@ __device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
     };
     stage_subleaf<T, P>(tv, pa, I, slot, sj, sjid, sweep);
     acc.quad_reduce();
-    if (act && q == 0) P::finish(acc, is, pa, tv, i);
+    if (act && q == 0 && slot_active(tv, i)) P::finish(acc, is, pa, tv, i);
 }
 
 // One wavefront per sub-leaf: block b -> leaf b / 4, sub-leaf b % 4.
@@ -637,7 +650,7 @@ __global__ __launch_bounds__(64) void pair_kernel_split(const TreeView<T> tv,
     if ((int)blockIdx.x >= 4 * n_items) return;
     const int b = tv.xcd_remap ? xcd_block(blockIdx.x, 4 * n_items)
                                : (int)blockIdx.x;
-    const int I = b >> 2, g = b & 3;
+    const int I = item_leaf(tv, b >> 2), g = b & 3;
     if (g >= tv.nsub[I]) return;
     process_subleaf<T, P>(tv, pa, I, g, sj, sjid);
 }
@@ -1464,6 +1477,8 @@ TreeView<T> tree_view(crk_tree *t, bool hydro, const int32_t *n_items) {
     tv.rc = t->d_rc.as<double>();
     tv.eps = t->d_eps.as<double>();
     tv.n_gas = t->n_gas;
+    tv.items = t->act_on ? t->act_items.as<int32_t>() : nullptr;
+    tv.act = t->act_on ? t->act_flags.as<uint8_t>() : nullptr;
     return tv;
 }
 
@@ -1473,7 +1488,7 @@ int launch_pair(crk_ctx *ctx, crk_tree *t, const TreeView<T> &tv,
                 bool gas_queue) {
     const int L = t->leaf_max;
     hipEvent_t ev = nullptr;
-    const bool queue = ctx->tuning.grid_mult > 0 && t->orders_built;
+    const bool queue = ctx->tuning.grid_mult > 0 && t->orders_built && !t->act_on;
     int *head = nullptr;
     const int32_t *order = nullptr;
     unsigned grid = (unsigned)std::max<int64_t>(1, n_items_bound);
@@ -1522,17 +1537,26 @@ int launch_pair(crk_ctx *ctx, crk_tree *t, const TreeView<T> &tv,
     return CRK_OK;
 }
 
-// number of gas leaves lives in bin_leaf[total_bins]; all leaves in C_NN
+// number of gas leaves lives in bin_leaf[total_bins]; all leaves in C_NN;
+// with an active subset, the active leaves (gas first) and active gas
+// leaves counted by crk_tree_set_active
 inline const int32_t *gas_leaf_count(crk_tree *t) {
+    if (t->act_on) return t->act_count.as<int32_t>() + 1;
     return t->bin_leaf.as<int32_t>() + t->total_bins;
 }
 inline const int32_t *all_leaf_count(crk_tree *t) {
+    if (t->act_on) return t->act_count.as<int32_t>();
     return t->counters.as<int32_t>() + C_NN;
 }
 // launch bounds set by the tree build: the exact counts when built eagerly,
-// the graph bounds (checked on the device) when built under capture
-inline int64_t gas_bound(crk_ctx *, crk_tree *t) { return t->ngb_launch; }
-inline int64_t all_bound(crk_ctx *, crk_tree *t) { return t->nb_launch; }
+// the graph bounds (checked on the device) when built under capture; the
+// active counts (read back by crk_tree_set_active) with an active subset
+inline int64_t gas_bound(crk_ctx *, crk_tree *t) {
+    return t->act_on ? t->act_ngas : t->ngb_launch;
+}
+inline int64_t all_bound(crk_ctx *, crk_tree *t) {
+    return t->act_on ? t->act_nall : t->nb_launch;
+}
 
 template <typename T>
 int density_impl(crk_ctx *ctx, crk_tree *t, const void *m, void *V,

@@ -1,0 +1,458 @@
+// Hierarchical time steps on a tree kept for a whole interval: timestep
+// bins, the active subset of a substep, the refit of the leaf boxes to
+// drifted positions, and the block kick / drift of the double-precision
+// state.  The paper's adaptive integration groups particles into timestep
+// bins (Sec. IV-A); only active leaves are updated at a substep, and leaf
+// bounding boxes grow instead of the tree being rebuilt (Sec. IV-B.1).
+// Elementwise or per-leaf work, HBM/latency-bound.
+#include <algorithm>
+#include <cmath>
+
+#include "crk_internal.h"
+
+namespace crk {
+
+namespace {
+
+inline unsigned grid_n(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    return (unsigned)std::max<int64_t>(1, g);
+}
+
+#define GRID_LOOP(i, n)                                                     \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
+         i += (int64_t)gridDim.x * blockDim.x)
+
+// Bin of every particle: the smallest b in [0, L] whose step
+// tau = dt / 2^b satisfies tau^4 |a|^2 <= rhs_a (rhs_a = (2 eta eps)^2,
+// the acceleration criterion tau <= sqrt(2 eta eps / |a|) squared twice)
+// and, for gas, tau cs <= c_cfl h; L when none does.  Every product and
+// sum is rounded once, in a fixed order (no contraction), so the integer
+// decision is reproducible by any implementation of the same steps.
+template <typename T>
+__global__ void bins_kernel(int64_t n, double dt, int L, double rhs_a,
+                            double c_cfl, const T *__restrict__ g0,
+                            const T *__restrict__ g1, const T *__restrict__ g2,
+                            const T *__restrict__ h0, const T *__restrict__ h1,
+                            const T *__restrict__ h2, const T *__restrict__ hs,
+                            const T *__restrict__ cs, int32_t *__restrict__ bins) {
+#pragma clang fp contract(off)
+    GRID_LOOP(i, n) {
+        double ax = (double)g0[i], ay = (double)g1[i], az = (double)g2[i];
+        if (h0) {
+            ax = ax + (double)h0[i];
+            ay = ay + (double)h1[i];
+            az = az + (double)h2[i];
+        }
+        const double xx = ax * ax, yy = ay * ay, zz = az * az;
+        const double a2 = (xx + yy) + zz;
+        const double rc = hs ? c_cfl * (double)hs[i] : 0.0;
+        const double c = hs ? (double)cs[i] : 0.0;
+        int b = L;
+        for (int k = 0; k <= L; ++k) {
+            const double tau = ldexp(dt, -k);  // exact
+            const double t2 = tau * tau;
+            const double t4 = t2 * t2;
+            bool ok = t4 * a2 <= rhs_a;
+            if (hs) ok = ok && (tau * c <= rc);
+            if (ok) {
+                b = k;
+                break;
+            }
+        }
+        bins[i] = b;
+    }
+}
+
+// level of slot p's particle (caller bins, clamped to [0, L])
+__device__ inline int slot_bin(const int32_t *perm, int64_t n_gas,
+                               const int32_t *bg, const int32_t *bd, int L,
+                               int64_t p) {
+    const int64_t c = perm[p];
+    const int b = c < n_gas ? bg[c] : bd[c - n_gas];
+    return b < 0 ? 0 : (b > L ? L : b);
+}
+
+// s < 0: every slot; else the slots ending a step after substep s
+__global__ void act_flags_kernel(int64_t n, int64_t n_gas,
+                                 const int32_t *__restrict__ perm,
+                                 const int32_t *__restrict__ bg,
+                                 const int32_t *__restrict__ bd, int L, int64_t s,
+                                 uint8_t *__restrict__ act) {
+    GRID_LOOP(p, n) {
+        bool a = true;
+        if (s >= 0) {
+            const int64_t per = (int64_t)1 << (L - slot_bin(perm, n_gas, bg, bd, L, p));
+            a = ((s + 1) % per) == 0;
+        }
+        act[p] = a ? 1 : 0;
+    }
+}
+
+// per leaf: 1 when any of its slots is active
+__global__ void act_leaf_kernel(const int32_t *__restrict__ nn_ptr, int64_t cap,
+                                const int32_t *__restrict__ lst,
+                                const int32_t *__restrict__ lct,
+                                const uint8_t *__restrict__ act,
+                                int32_t *__restrict__ flag) {
+    const int64_t nn = *nn_ptr;
+    GRID_LOOP(I, cap) {
+        int f = 0;
+        if (I < nn) {
+            const int st = lst[I], c = lct[I];
+            for (int k = 0; k < c && !f; ++k) f = act[st + k];
+        }
+        flag[I] = f;
+    }
+}
+
+__global__ void act_items_kernel(const int32_t *__restrict__ nn_ptr, int64_t cap,
+                                 const int32_t *__restrict__ flag,
+                                 const int32_t *__restrict__ pos,
+                                 int32_t *__restrict__ items) {
+    const int64_t nn = *nn_ptr;
+    GRID_LOOP(I, cap) {
+        if (I < nn && flag[I]) items[pos[I]] = (int32_t)I;
+    }
+}
+
+// counts {all active leaves, active gas leaves}: gas leaves come first in
+// leaf order, so the active gas leaves are the items before position
+// pos[number of gas leaves]
+__global__ void act_count_kernel(const int32_t *__restrict__ nn_ptr,
+                                 const int32_t *__restrict__ ngl_ptr,
+                                 const int32_t *__restrict__ pos,
+                                 const int32_t *__restrict__ total,
+                                 int32_t *__restrict__ out) {
+    const int nn = *nn_ptr, ngl = *ngl_ptr;
+    out[0] = *total;
+    out[1] = ngl < nn ? pos[ngl] : *total;
+}
+
+// new positions into tree order
+template <typename T>
+__global__ void refit_pos_kernel(int64_t n, int64_t n_gas,
+                                 const int32_t *__restrict__ perm,
+                                 const T *__restrict__ gx, const T *__restrict__ gy,
+                                 const T *__restrict__ gz, const T *__restrict__ dx,
+                                 const T *__restrict__ dy, const T *__restrict__ dz,
+                                 T *__restrict__ p0, T *__restrict__ p1,
+                                 T *__restrict__ p2) {
+    GRID_LOOP(p, n) {
+        const int64_t c = perm[p];
+        if (c < n_gas) {
+            p0[p] = gx[c];
+            p1[p] = gy[c];
+            p2[p] = gz[c];
+        } else {
+            p0[p] = dx[c - n_gas];
+            p1[p] = dy[c - n_gas];
+            p2[p] = dz[c - n_gas];
+        }
+    }
+}
+
+// grows the box of slots [st, st + c) (three planes of stride ld, entry k)
+template <typename T>
+__device__ inline void grow_box(const T *p0, const T *p1, const T *p2, int st,
+                                int c, T *lo, T *hi, int64_t ld, int64_t k) {
+    T l0 = lo[k], l1 = lo[ld + k], l2 = lo[2 * ld + k];
+    T u0 = hi[k], u1 = hi[ld + k], u2 = hi[2 * ld + k];
+    for (int q = st; q < st + c; ++q) {
+        l0 = fmin(l0, p0[q]);
+        u0 = fmax(u0, p0[q]);
+        l1 = fmin(l1, p1[q]);
+        u1 = fmax(u1, p1[q]);
+        l2 = fmin(l2, p2[q]);
+        u2 = fmax(u2, p2[q]);
+    }
+    lo[k] = l0;
+    lo[ld + k] = l1;
+    lo[2 * ld + k] = l2;
+    hi[k] = u0;
+    hi[ld + k] = u1;
+    hi[2 * ld + k] = u2;
+}
+
+// One thread per leaf: grow the leaf box and its sub-leaf boxes to the
+// current positions (boxes never shrink), and record per box the largest
+// distance by which a leaf box reaches out of its chaining-mesh bin.
+template <typename T>
+__global__ void refit_box_kernel(
+    const int32_t *__restrict__ nn_ptr, int64_t lcap,
+    const int32_t *__restrict__ lst, const int32_t *__restrict__ lct,
+    const int32_t *__restrict__ lkey, const int32_t *__restrict__ lbox,
+    const T *__restrict__ p0, const T *__restrict__ p1, const T *__restrict__ p2,
+    T *__restrict__ lo, T *__restrict__ hi, int has_sub,
+    const int32_t *__restrict__ nsub, const int32_t *__restrict__ sst,
+    const int32_t *__restrict__ scnt, T *__restrict__ slo, T *__restrict__ shi,
+    int64_t total_bins, const int *__restrict__ ncm,
+    const int64_t *__restrict__ bin_base, float *__restrict__ overhang) {
+    const int64_t nn = *nn_ptr;
+    GRID_LOOP(I, nn) {
+        grow_box(p0, p1, p2, lst[I], lct[I], lo, hi, lcap, I);
+        if (has_sub) {
+            const int ns = nsub[I];
+            for (int g = 0; g < ns; ++g) {
+                const int64_t sl = 4 * I + g;
+                grow_box(p0, p1, p2, sst[sl], scnt[sl], slo, shi, 4 * lcap, sl);
+            }
+        }
+        const int key = lkey[I];
+        const int64_t gbin = key < total_bins ? key : key - total_bins;
+        const int b = lbox[I];
+        const int nc = ncm[b];
+        const int64_t lb = gbin - bin_base[b];
+        const int64_t cc[3] = {lb / ((int64_t)nc * nc), (lb / nc) % nc, lb % nc};
+        double ov = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double cl = 1.0 + (double)cc[a] / nc;
+            const double ch = 1.0 + (double)(cc[a] + 1) / nc;
+            ov = fmax(ov, fmax(cl - (double)lo[a * lcap + I],
+                               (double)hi[a * lcap + I] - ch));
+        }
+        // non-negative floats order like their bit patterns
+        atomicMax(reinterpret_cast<int *>(overhang) + b,
+                  __float_as_int((float)(ov * (1.0 + 1e-6))));
+    }
+}
+
+// Block kick: the particles starting (phase 0: s % 2^(L-b) == 0) or ending
+// (phase 1: (s + 1) % 2^(L-b) == 0) a step of tau_b = dt / 2^b at substep
+// s get v += (a_grav + a_hydro) tau_b / 2 and u += du/dt tau_b / 2; the
+// context-precision copies follow.
+template <typename T>
+__global__ void kick_kernel(int64_t n, double dt, int L, int64_t s, int phase,
+                            const int32_t *__restrict__ bins,
+                            double *__restrict__ v64, double *__restrict__ u64,
+                            const T *__restrict__ g0, const T *__restrict__ g1,
+                            const T *__restrict__ g2, const T *__restrict__ h0,
+                            const T *__restrict__ h1, const T *__restrict__ h2,
+                            const T *__restrict__ dudt, T *__restrict__ v0,
+                            T *__restrict__ v1, T *__restrict__ v2,
+                            T *__restrict__ u) {
+    const T *g[3] = {g0, g1, g2};
+    const T *h[3] = {h0, h1, h2};
+    T *vo[3] = {v0, v1, v2};
+    GRID_LOOP(i, n) {
+        int b = bins[i];
+        b = b < 0 ? 0 : (b > L ? L : b);
+        const int64_t per = (int64_t)1 << (L - b);
+        const bool sel = phase == 0 ? (s % per) == 0 : ((s + 1) % per) == 0;
+        if (!sel) continue;
+        const double half = ldexp(dt, -b) * 0.5;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double acc = (double)g[a][i];
+            if (h0) acc += (double)h[a][i];
+            const double v = v64[a * n + i] + acc * half;
+            v64[a * n + i] = v;
+            vo[a][i] = (T)v;
+        }
+        if (u64) {
+            const double uu = u64[i] + (double)dudt[i] * half;
+            u64[i] = uu;
+            u[i] = (T)uu;
+        }
+    }
+}
+
+// Drift of every particle, x += v delta; wrapped into [1, 2) only when
+// wrap is set (inside an interval the tree keeps unwrapped positions).
+template <typename T>
+__global__ void drift_kernel(int64_t n, double delta, int wrap,
+                             double *__restrict__ x64, const double *__restrict__ v64,
+                             T *__restrict__ x0, T *__restrict__ x1,
+                             T *__restrict__ x2) {
+    T *xo[3] = {x0, x1, x2};
+    GRID_LOOP(i, n) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double x = x64[a * n + i] + v64[a * n + i] * delta;
+            if (wrap) {
+                x = x - floor(x - 1.0);
+                if (x >= 2.0) x -= 1.0;
+            }
+            x64[a * n + i] = x;
+            T xs = (T)x;
+            if (wrap && xs >= T(2)) xs = T(1);  // rounding up to 2 wraps to 1
+            xo[a][i] = xs;
+        }
+    }
+}
+
+template <typename T> const T *cp(const void *p) { return static_cast<const T *>(p); }
+template <typename T> T *mp(void *p) { return static_cast<T *>(p); }
+
+template <typename T>
+int bins_impl(crk_ctx *ctx, int64_t n, double dt, int L, double eps,
+              double c_cfl, double eta, const void *const ag[3],
+              const void *const ah[3], const void *h, const void *cs,
+              int32_t *bins) {
+    double r = 2.0 * eta * eps;
+    r = r * r;
+    hipLaunchKernelGGL((bins_kernel<T>), dim3(grid_n(n)), dim3(256), 0,
+                       ctx->stream, n, dt, L, r, c_cfl, cp<T>(ag[0]),
+                       cp<T>(ag[1]), cp<T>(ag[2]), ah ? cp<T>(ah[0]) : nullptr,
+                       ah ? cp<T>(ah[1]) : nullptr, ah ? cp<T>(ah[2]) : nullptr,
+                       cp<T>(h), cp<T>(cs), bins);
+    CRK_HIP(hipGetLastError());
+    return CRK_OK;
+}
+
+template <typename T>
+int refit_impl(crk_ctx *ctx, crk_tree *t, const void *gx, const void *gy,
+               const void *gz, const void *dx, const void *dy, const void *dz) {
+    hipStream_t s = ctx->stream;
+    const int64_t n = t->n;
+    hipLaunchKernelGGL((refit_pos_kernel<T>), dim3(grid_n(n)), dim3(256), 0, s,
+                       n, t->n_gas, t->perm.as<int32_t>(), cp<T>(gx), cp<T>(gy),
+                       cp<T>(gz), cp<T>(dx), cp<T>(dy), cp<T>(dz),
+                       t->pos[0].as<T>(), t->pos[1].as<T>(), t->pos[2].as<T>());
+    CRK_HIP(hipGetLastError());
+    const int nb = t->n_boxes;
+    CRK_TRY(t->overhang.ensure((size_t)nb * 4, false));
+    CRK_HIP(fill_i32(t->overhang.as<int32_t>(), 0, nb, s));
+    const int cur = t->cur_nodes;
+    hipLaunchKernelGGL((refit_box_kernel<T>), dim3(grid_n(t->n_leaves)), dim3(256),
+                       0, s, t->counters.as<int32_t>() + C_NN, t->leaf_cap,
+                       t->nd_start[cur].as<int32_t>(), t->nd_count[cur].as<int32_t>(),
+                       t->nd_key[cur].as<int32_t>(), t->leaf_box.as<int32_t>(),
+                       t->pos[0].as<T>(), t->pos[1].as<T>(), t->pos[2].as<T>(),
+                       t->leaf_lo.as<T>(), t->leaf_hi.as<T>(), t->has_sub ? 1 : 0,
+                       t->sub_nsub.as<int32_t>(), t->sub_start.as<int32_t>(),
+                       t->sub_count.as<int32_t>(), t->sub_lo.as<T>(),
+                       t->sub_hi.as<T>(), t->total_bins, t->d_ncm.as<int>(),
+                       t->d_bin_base.as<int64_t>(), t->overhang.as<float>());
+    CRK_HIP(hipGetLastError());
+    // every pair the lists miss has a particle that left its bin: with the
+    // largest excursion d of a box out of its bin, pairs stay inside the
+    // 27-bin stencil while 2 d + range <= bin width
+    std::vector<float> ov(nb);
+    CRK_HIP(hipMemcpyAsync(ov.data(), t->overhang.p, (size_t)nb * 4,
+                           hipMemcpyDeviceToHost, s));
+    CRK_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < nb; ++b) {
+        const double w = 1.0 / t->h_ncm[b];
+        const double R = std::max(t->cur_rc[b], 2.0 * t->cur_hmax[b]) * (1.0 + 1e-5);
+        if (2.0 * (double)ov[b] + R > w)
+            return set_error(CRK_ESTALE,
+                             "tree_refit: particles moved too far out of their "
+                             "chaining-mesh bins for the interaction stencil; "
+                             "rebuild the tree");
+    }
+    return CRK_OK;
+}
+
+template <typename T>
+int kick_impl(crk_ctx *ctx, int64_t n, double dt, int L, int64_t s, int phase,
+              const int32_t *bins, double *v64, double *u64,
+              const void *const ag[3], const void *const ah[3], const void *dudt,
+              void *const v[3], void *u) {
+    hipLaunchKernelGGL((kick_kernel<T>), dim3(grid_n(n)), dim3(256), 0,
+                       ctx->stream, n, dt, L, s, phase, bins, v64, u64,
+                       cp<T>(ag[0]), cp<T>(ag[1]), cp<T>(ag[2]),
+                       ah ? cp<T>(ah[0]) : nullptr, ah ? cp<T>(ah[1]) : nullptr,
+                       ah ? cp<T>(ah[2]) : nullptr, cp<T>(dudt), mp<T>(v[0]),
+                       mp<T>(v[1]), mp<T>(v[2]), mp<T>(u));
+    CRK_HIP(hipGetLastError());
+    return CRK_OK;
+}
+
+template <typename T>
+int drift_impl(crk_ctx *ctx, int64_t n, double delta, int wrap, double *x64,
+               const double *v64, void *const x[3]) {
+    hipLaunchKernelGGL((drift_kernel<T>), dim3(grid_n(n)), dim3(256), 0,
+                       ctx->stream, n, delta, wrap, x64, v64, mp<T>(x[0]),
+                       mp<T>(x[1]), mp<T>(x[2]));
+    CRK_HIP(hipGetLastError());
+    return CRK_OK;
+}
+
+}  // namespace
+
+int timestep_bins(crk_ctx *ctx, int64_t n, double dt, int max_level, double eps,
+                  double c_cfl, double eta, const void *const a_grav[3],
+                  const void *const a_hydro[3], const void *h, const void *cs,
+                  int32_t *bins) {
+    if (n == 0) return CRK_OK;
+    if (ctx->precision == CRK_FP64)
+        return bins_impl<double>(ctx, n, dt, max_level, eps, c_cfl, eta, a_grav,
+                                 a_hydro, h, cs, bins);
+    return bins_impl<float>(ctx, n, dt, max_level, eps, c_cfl, eta, a_grav,
+                            a_hydro, h, cs, bins);
+}
+
+int tree_set_active(crk_ctx *ctx, crk_tree *t, const int32_t *bins_gas,
+                    const int32_t *bins_dm, int max_level, int64_t substep) {
+    hipStream_t s = ctx->stream;
+    if (substep < 0) {
+        t->act_on = false;
+        return CRK_OK;
+    }
+    const int64_t n = t->n, lcap = t->leaf_cap;
+    CRK_TRY(t->act_flags.ensure((size_t)std::max<int64_t>(n, 1), false));
+    CRK_TRY(t->act_leaf.ensure((size_t)(lcap + 1) * 2 * 4, false));
+    CRK_TRY(t->act_items.ensure((size_t)(lcap + 1) * 4, false));
+    CRK_TRY(t->act_count.ensure(4 * 4, false));
+    CRK_TRY(ctx->scratch.ensure(scan_tmp_bytes(lcap + 1), false));
+    hipLaunchKernelGGL(act_flags_kernel, dim3(grid_n(n)), dim3(256), 0, s, n,
+                       t->n_gas, t->perm.as<int32_t>(), bins_gas, bins_dm,
+                       max_level, substep, t->act_flags.as<uint8_t>());
+    CRK_HIP(hipGetLastError());
+    const int cur = t->cur_nodes;
+    int32_t *flag = t->act_leaf.as<int32_t>();
+    int32_t *pos = flag + (lcap + 1);
+    int32_t *cnt = t->act_count.as<int32_t>();
+    hipLaunchKernelGGL(act_leaf_kernel, dim3(grid_n(lcap)), dim3(256), 0, s,
+                       t->counters.as<int32_t>() + C_NN, lcap,
+                       t->nd_start[cur].as<int32_t>(), t->nd_count[cur].as<int32_t>(),
+                       t->act_flags.as<uint8_t>(), flag);
+    CRK_HIP(hipGetLastError());
+    CRK_HIP(exclusive_scan_i32(flag, pos, lcap, cnt + 2, ctx->scratch.p, s));
+    hipLaunchKernelGGL(act_items_kernel, dim3(grid_n(lcap)), dim3(256), 0, s,
+                       t->counters.as<int32_t>() + C_NN, lcap, flag, pos,
+                       t->act_items.as<int32_t>());
+    CRK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(act_count_kernel, dim3(1), dim3(1), 0, s,
+                       t->counters.as<int32_t>() + C_NN,
+                       t->bin_leaf.as<int32_t>() + t->total_bins, pos, cnt + 2, cnt);
+    CRK_HIP(hipGetLastError());
+    int32_t hc[2];
+    CRK_HIP(hipMemcpyAsync(hc, cnt, 8, hipMemcpyDeviceToHost, s));
+    CRK_HIP(hipStreamSynchronize(s));
+    t->act_nall = hc[0];
+    t->act_ngas = hc[1];
+    t->act_on = true;
+    return CRK_OK;
+}
+
+int tree_refit(crk_ctx *ctx, crk_tree *t, const void *gx, const void *gy,
+               const void *gz, const void *dx, const void *dy, const void *dz) {
+    if (ctx->precision == CRK_FP64)
+        return refit_impl<double>(ctx, t, gx, gy, gz, dx, dy, dz);
+    return refit_impl<float>(ctx, t, gx, gy, gz, dx, dy, dz);
+}
+
+int block_kick(crk_ctx *ctx, int64_t n, double dt, int max_level, int64_t substep,
+               int phase, const int32_t *bins, double *v64, double *u64,
+               const void *const a_grav[3], const void *const a_hydro[3],
+               const void *dudt, void *const v[3], void *u) {
+    if (n == 0) return CRK_OK;
+    if (ctx->precision == CRK_FP64)
+        return kick_impl<double>(ctx, n, dt, max_level, substep, phase, bins, v64,
+                                 u64, a_grav, a_hydro, dudt, v, u);
+    return kick_impl<float>(ctx, n, dt, max_level, substep, phase, bins, v64, u64,
+                            a_grav, a_hydro, dudt, v, u);
+}
+
+int drift(crk_ctx *ctx, int64_t n, double delta, int wrap, double *x64,
+          const double *v64, void *const x[3]) {
+    if (n == 0) return CRK_OK;
+    if (ctx->precision == CRK_FP64)
+        return drift_impl<double>(ctx, n, delta, wrap, x64, v64, x);
+    return drift_impl<float>(ctx, n, delta, wrap, x64, v64, x);
+}
+
+}  // namespace crk

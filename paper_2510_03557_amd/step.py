@@ -109,6 +109,117 @@ class ShortRangeStep:
                         (self.dx, self.dy, self.dz),
                         (self.dvx, self.dvy, self.dvz), None)
 
+    # --------------------------------------------------------------------
+    def _passes(self):
+        c, t = self.ctx, self.tree
+        c.build_interaction_lists(t)
+        if self.ng:
+            c.density(t, self.gm, self.V, self.rho_t)
+            c.coefficients(t, self.gm, self.V, self.gu, self.A, self.B,
+                           self.gA, self.gB, self.rho, self.P, self.cs)
+            c.hydro_forces(t, self.gm, self.gvx, self.gvy, self.gvz, self.V,
+                           self.rho, self.P, self.cs, self.A, self.B, self.gA,
+                           self.gB, self.ahx, self.ahy, self.ahz, self.dudt)
+        c.shortrange_gravity(t, self.gm, self.dm, self.agx, self.agy,
+                             self.agz, self.adx, self.ady, self.adz)
+
+    def _kick(self, dt, L, s, phase):
+        c = self.ctx
+        if self.ng:
+            c.kick(self.ng, dt, L, s, phase, self.bins_g, self.gv64,
+                   self.gu64, (self.agx, self.agy, self.agz),
+                   (self.ahx, self.ahy, self.ahz), self.dudt,
+                   (self.gvx, self.gvy, self.gvz), self.gu)
+        if self.nd:
+            c.kick(self.nd, dt, L, s, phase, self.bins_d, self.dv64, None,
+                   (self.adx, self.ady, self.adz), None, None,
+                   (self.dvx, self.dvy, self.dvz), None)
+
+    def _drift(self, delta, wrap):
+        c = self.ctx
+        if self.ng:
+            c.drift(self.ng, delta, wrap, self.gx64, self.gv64,
+                    (self.gx, self.gy, self.gz))
+        if self.nd:
+            c.drift(self.nd, delta, wrap, self.dx64, self.dv64,
+                    (self.dx, self.dy, self.dz))
+
+    def set_bins(self, bins_gas, bins_dm):
+        """Timestep bins (numpy int, caller order) for substep_cycle."""
+        torch = self.torch
+        with torch.cuda.stream(self.ctx.stream):
+            self.bins_g = torch.from_numpy(np.ascontiguousarray(
+                bins_gas, np.int32).reshape(-1)).to("cuda") if self.ng else None
+            self.bins_d = torch.from_numpy(np.ascontiguousarray(
+                bins_dm, np.int32).reshape(-1)).to("cuda") if self.nd else None
+        self.ctx.stream.synchronize()
+
+    def timestep_bins(self, dt, max_level, c_cfl=0.25, eta=0.025):
+        """Bins from the current accelerations (crk_timestep_bins), per
+        box with that box's softening; kept for substep_cycle and returned
+        as numpy arrays (gas, dm)."""
+        torch, c, wl = self.torch, self.ctx, self.wl
+        with torch.cuda.stream(c.stream):
+            bg = torch.zeros(max(self.ng, 1), dtype=torch.int32, device="cuda")
+            bd = torch.zeros(max(self.nd, 1), dtype=torch.int32, device="cuda")
+        for b in range(wl.n_boxes):
+            g0, g1 = int(wl.gas_off[b]), int(wl.gas_off[b + 1])
+            d0, d1 = int(wl.dm_off[b]), int(wl.dm_off[b + 1])
+            eps = float(wl.eps[b])
+            if g1 > g0:
+                sl = slice(g0, g1)
+                c.timestep_bins(g1 - g0, dt, max_level, eps, c_cfl, eta,
+                                (self.agx[sl], self.agy[sl], self.agz[sl]),
+                                (self.ahx[sl], self.ahy[sl], self.ahz[sl]),
+                                self.gh[sl], self.cs[sl], bg[sl])
+            if d1 > d0:
+                sl = slice(d0, d1)
+                c.timestep_bins(d1 - d0, dt, max_level, eps, c_cfl, eta,
+                                (self.adx[sl], self.ady[sl], self.adz[sl]),
+                                None, None, None, bd[sl])
+        self.bins_g = bg if self.ng else None
+        self.bins_d = bd if self.nd else None
+        c.stream.synchronize()
+        return (bg[:self.ng].cpu().numpy(), bd[:self.nd].cpu().numpy())
+
+    def substep_cycle(self, dt, max_level):
+        """One interval dt of hierarchical block steps with 2^max_level
+        substeps on one tree (built here at the start): every particle is
+        evaluated first; each substep kicks the particles starting a step,
+        drifts all, refits the leaf boxes, rebuilds the lists, evaluates the
+        particles ending a step (active leaves only) and kicks them; the
+        positions are wrapped at the end.  Bins come from set_bins or
+        timestep_bins."""
+        c, t, wl = self.ctx, self.tree, self.wl
+        L = int(max_level)
+        c.build_tree(t, wl.gas_off, wl.dm_off, wl.r_c, wl.eps, self.h_max,
+                     self.gx, self.gy, self.gz, self.gh, self.dx, self.dy,
+                     self.dz)
+        self._passes()
+        delta = dt / 2 ** L
+        for s in range(2 ** L):
+            self._kick(dt, L, s, 0)
+            self._drift(delta, False)
+            c.tree_refit(t, self.gx, self.gy, self.gz, self.dx, self.dy,
+                         self.dz)
+            c.tree_set_active(t, self.bins_g, self.bins_d, L, s)
+            self._passes()
+            self._kick(dt, L, s, 1)
+        c.tree_set_active(t, None, None, 0, -1)
+        self._drift(0.0, True)
+
+    def state(self) -> dict:
+        """The double-precision state (numpy, (3, n) / n)."""
+        self.ctx.sync()
+        ng, nd = self.ng, self.nd
+
+        def h3(t, n):
+            return t[:3 * n].cpu().numpy().reshape(3, n) if n else np.zeros((3, 0))
+
+        return dict(xg=h3(self.gx64, ng), vg=h3(self.gv64, ng),
+                    u=self.gu64[:ng].cpu().numpy() if ng else np.zeros(0),
+                    xd=h3(self.dx64, nd), vd=h3(self.dv64, nd))
+
     def capture(self, integrate: bool = True):
         """Runs the step once eagerly (sizes), then captures it in a graph."""
         self.run(integrate=integrate)

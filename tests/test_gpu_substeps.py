@@ -1,0 +1,282 @@
+"""GPU parity of the hierarchical time steps (timestep bins, active leaves on
+a refitted tree, block kick-drift-kick cycle) against the FP64 oracle,
+through the C ABI.
+
+Bins are integers decided in double on both sides from the same inputs:
+bit-exact.  The cycle's changes of velocity, position and energy and the
+last evaluation's outputs: relative RMS <= 1e-5 (float32 path) and 1e-9
+(float64 path, rounding order only, accumulated over the substeps).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from paper_2510_03557_amd import workloads as W  # noqa: E402
+
+FP32_TOL = 1e-5
+FP64_TOL = 1e-9
+KEYS = ("V", "rho_tilde", "A", "B", "gradA", "gradB", "rho", "P", "cs",
+        "a_hydro", "dudt", "a_grav_gas", "a_grav_dm")
+
+
+def rel_rms(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    den = np.sqrt(np.sum(b * b))
+    num = np.sqrt(np.sum((a - b) ** 2))
+    return num / den if den > 0 else num
+
+
+@pytest.fixture()
+def step_cls():
+    """The step class; every step made in a test is closed at its end,
+    also when the test fails."""
+    from paper_2510_03557_amd.step import ShortRangeStep
+    assert torch.cuda.is_available()
+    made = []
+
+    def make(*args, **kw):
+        st = ShortRangeStep(*args, **kw)
+        made.append(st)
+        return st
+
+    yield make
+    for st in made:
+        st.close()
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# bins
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_timestep_bins_match_oracle(orc, precision):
+    from paper_2510_03557_amd.binding import Context
+    print(f"case timestep bins {precision}", flush=True)
+    rng = np.random.default_rng(7)
+    n = 200_000
+    dt, L, eps, c_cfl, eta = 0.01, 8, 1e-4, 0.25, 0.025
+    npT = np.float32 if precision == "fp32" else np.float64
+    # accelerations over five decades, some exactly zero
+    mag = 10.0 ** rng.uniform(-1, 4, n)
+    mag[::97] = 0.0
+    ag = (rng.standard_normal((3, n)) * mag).astype(npT)
+    ah = (0.3 * rng.standard_normal((3, n)) * mag).astype(npT)
+    h = (0.01 * np.exp(0.5 * rng.standard_normal(n))).astype(npT)
+    cs = (10.0 ** rng.uniform(-1, 2.5, n)).astype(npT)
+    ctx = Context(precision)
+    try:
+        _bins_case(orc, ctx, n, dt, L, eps, c_cfl, eta, ag, ah, h, cs)
+    finally:
+        ctx.close()
+        torch.cuda.synchronize()
+
+
+def _bins_case(orc, ctx, n, dt, L, eps, c_cfl, eta, ag, ah, h, cs):
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda()
+           for a in (*ag, *ah, h, cs)]
+    bins = torch.zeros(n, dtype=torch.int32, device="cuda")
+    ctx.timestep_bins(n, dt, L, eps, c_cfl, eta, dev[0:3], dev[3:6], dev[6],
+                      dev[7], bins)
+    ctx.stream.synchronize()
+    a64 = ag.astype(np.float64) + ah.astype(np.float64)
+    ref = orc.timestep_bins(dt, L, eps, a64[0], a64[1], a64[2],
+                            h=h.astype(np.float64), cs=cs.astype(np.float64),
+                            c_cfl=c_cfl, eta=eta)
+    got = bins.cpu().numpy()
+    print("gas bin counts", np.bincount(ref, minlength=L + 1), flush=True)
+    assert np.array_equal(got, ref)
+    assert len(np.unique(ref)) >= 6
+    # dark matter: acceleration only
+    ctx.timestep_bins(n, dt, L, eps, c_cfl, eta, dev[0:3], None, None, None,
+                      bins)
+    ctx.stream.synchronize()
+    ref = orc.timestep_bins(dt, L, eps, *ag.astype(np.float64), eta=eta)
+    assert np.array_equal(bins.cpu().numpy(), ref)
+
+
+# ---------------------------------------------------------------------------
+# one pass over active leaves writes exactly the active particles
+# ---------------------------------------------------------------------------
+
+def test_active_passes_write_active_particles_only(step_cls):
+    """After crk_tree_set_active, each pass writes, for the active particles,
+    bitwise the values of the full pass (their leaves are swept the same
+    way) and leaves every other output untouched."""
+    print("case active passes random_uniform(6000, 5000)", flush=True)
+    wl = W.random_uniform(6000, 5000, 401, n_ngb=48.0, h_spread=0.15)
+    st = step_cls(wl, "fp32")
+    st.run()
+    full = st.outputs()
+    rng = np.random.default_rng(5)
+    L = 3
+    bg = rng.integers(0, L + 1, st.ng)
+    bd = rng.integers(0, L + 1, st.nd)
+    st.set_bins(bg, bd)
+    c, t = st.ctx, st.tree
+    s = 2  # ends a step: (s + 1) % 2^(L - b) == 0 -> bins 3 and 2
+    act_g = ((s + 1) % (2 ** (L - bg))) == 0
+    act_d = ((s + 1) % (2 ** (L - bd))) == 0
+    assert 0 < act_g.sum() < st.ng and 0 < act_d.sum() < st.nd
+    c.tree_set_active(t, st.bins_g, st.bins_d, L, s)
+    sentinel = -7.25
+    groups = {
+        "density": (("V", "rho_t"), ("V", "rho_tilde")),
+        "coefficients": (("A", "B", "gA", "gB", "rho", "P", "cs"),
+                         ("A", "B", "gradA", "gradB", "rho", "P", "cs")),
+        "hydro": (("ahx", "ahy", "ahz", "dudt"), ("a_hydro", "dudt")),
+        "gravity": (("agx", "agy", "agz", "adx", "ady", "adz"),
+                    ("a_grav_gas", "a_grav_dm")),
+    }
+    saved = {k: getattr(st, k).clone()
+             for names, _ in groups.values() for k in names}
+    for name, (attrs, keys) in groups.items():
+        with torch.cuda.stream(c.stream):
+            for k in attrs:
+                getattr(st, k).fill_(sentinel)
+        if name == "density":
+            c.density(t, st.gm, st.V, st.rho_t)
+        elif name == "coefficients":
+            c.coefficients(t, st.gm, st.V, st.gu, st.A, st.B, st.gA, st.gB,
+                           st.rho, st.P, st.cs)
+        elif name == "hydro":
+            c.hydro_forces(t, st.gm, st.gvx, st.gvy, st.gvz, st.V, st.rho,
+                           st.P, st.cs, st.A, st.B, st.gA, st.gB, st.ahx,
+                           st.ahy, st.ahz, st.dudt)
+        else:
+            c.shortrange_gravity(t, st.gm, st.dm, st.agx, st.agy, st.agz,
+                                 st.adx, st.ady, st.adz)
+        got = st.outputs()
+        for k in keys:
+            g, f = got[k], full[k]
+            act = act_d if k == "a_grav_dm" else act_g
+            ga = g[..., act] if k.startswith("a_") else g[act]
+            fa = f[..., act] if k.startswith("a_") else f[act]
+            gi = g[..., ~act] if k.startswith("a_") else g[~act]
+            assert np.array_equal(ga, fa), (name, k)
+            assert np.all(gi == sentinel), (name, k)
+        # restore the full values before the next pass reads them
+        with torch.cuda.stream(c.stream):
+            for k in attrs:
+                getattr(st, k).copy_(saved[k])
+    c.tree_set_active(t, None, None, 0, -1)
+    st.close()
+
+
+# ---------------------------------------------------------------------------
+# whole cycles
+# ---------------------------------------------------------------------------
+
+def _cycle_errors(wl, got, ref):
+    g, d = wl.gas, wl.dm
+    x0g = np.array([g.x, g.y, g.z], np.float64)
+    v0g = np.array([g.vx, g.vy, g.vz], np.float64)
+    x0d = np.array([d.x, d.y, d.z], np.float64)
+    v0d = np.array([d.vx, d.vy, d.vz], np.float64)
+
+    def disp(x, x0):
+        e = x - x0
+        return e - np.round(e)
+
+    errs = dict(
+        dx_gas=rel_rms(disp(got["xg"], x0g), disp(ref["xg"], x0g)),
+        dv_gas=rel_rms(got["vg"] - v0g, ref["vg"] - v0g),
+        du=rel_rms(got["u"] - np.asarray(g.u, np.float64),
+                   ref["u"] - np.asarray(g.u, np.float64)),
+        dx_dm=rel_rms(disp(got["xd"], x0d), disp(ref["xd"], x0d)),
+        dv_dm=rel_rms(got["vd"] - v0d, ref["vd"] - v0d))
+    return errs
+
+
+# The clustered set is asserted on the float64 path only: there a random
+# one-ulp change of the float32 positions alone moves B, grad B and a_hydro
+# by ~3e-5 (relative RMS; ill-conditioned moment matrices between the
+# blobs), so float32 trajectories that differ by an ulp cannot agree to
+# 1e-5; the float64 path checks the same cycle logic to rounding.
+@pytest.mark.parametrize("precision,clustered,L,seed", [
+    ("fp32", False, 3, 501), ("fp64", True, 2, 502), ("fp64", False, 2, 503)])
+def test_substep_cycle_matches_oracle(orc, step_cls, precision, clustered, L,
+                                      seed):
+    print(f"case cycle {precision} clustered={clustered} L={L}", flush=True)
+    wl = W.random_uniform(12000, 10000, seed, n_ngb=48.0, h_spread=0.15,
+                          clustered=clustered)
+    rng = np.random.default_rng(seed)
+    bg = rng.integers(0, L + 1, wl.gas.n)
+    bd = rng.integers(0, L + 1, wl.dm.n)
+    dt = 0.02
+    st = step_cls(wl, precision)
+    st.set_bins(bg, bd)
+    st.substep_cycle(dt, L)
+    got = st.state()
+    outs = st.outputs()
+    ref = orc.substep_cycle(wl, bg, bd, dt, L, forces_at=(
+        "float32" if precision == "fp32" else "float64"))
+    tol = FP32_TOL if precision == "fp32" else FP64_TOL
+    errs = _cycle_errors(wl, got, ref)
+    errs.update({k: rel_rms(outs[k], ref[k]) for k in KEYS})
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, bad
+    # positions wrapped back into [1, 2)
+    assert np.all((got["xg"] >= 1) & (got["xg"] < 2))
+    st.close()
+
+
+def test_cycle_bins_from_accelerations(orc, step_cls):
+    """Bins from crk_timestep_bins on the step's own accelerations (gas:
+    Courant and acceleration; dm: acceleration), then a cycle: the bins
+    equal the oracle's decision on the same float32 inputs and the cycle
+    matches the oracle run with those bins."""
+    print("case cycle with computed bins", flush=True)
+    wl = W.random_uniform(10000, 9000, 601, n_ngb=48.0, h_spread=0.15,
+                          clustered=True)
+    st = step_cls(wl, "fp32")
+    st.run()
+    out = st.outputs()
+    dt, L = 0.01, 4
+    eps = float(wl.eps[0])
+    bg, bd = st.timestep_bins(dt, L, c_cfl=0.25, eta=0.025)
+    a = (out["a_grav_gas"].astype(np.float32).astype(np.float64)
+         + out["a_hydro"].astype(np.float32).astype(np.float64))
+    ref_g = orc.timestep_bins(dt, L, eps, *a, h=wl.gas.h.astype(np.float64),
+                              cs=out["cs"], c_cfl=0.25, eta=0.025)
+    ref_d = orc.timestep_bins(dt, L, eps, *out["a_grav_dm"], eta=0.025)
+    print("bins gas", np.bincount(bg, minlength=L + 1),
+          "dm", np.bincount(bd, minlength=L + 1), flush=True)
+    assert np.array_equal(bg, ref_g) and np.array_equal(bd, ref_d)
+    assert len(np.unique(bg)) >= 3
+    st.close()
+    st = step_cls(wl, "fp32")
+    st.set_bins(bg, bd)
+    st.substep_cycle(dt, L)
+    got = st.state()
+    ref = orc.substep_cycle(wl, bg, bd, dt, L, forces_at="float32")
+    errs = _cycle_errors(wl, got, ref)
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert all(v <= FP32_TOL for v in errs.values()), errs
+    st.close()
+
+
+def test_refit_reports_stale_tree(step_cls):
+    """Positions moved far out of their bins: crk_tree_refit returns
+    CRK_ESTALE (the stencil could miss pairs) instead of a wrong result."""
+    from paper_2510_03557_amd.binding import CrkError, CRK_ESTALE
+    print("case stale refit", flush=True)
+    wl = W.random_uniform(20000, 20000, 701, n_ngb=48.0)
+    st = step_cls(wl, "fp32")
+    st.run()
+    c, t = st.ctx, st.tree
+    # a small move is accepted
+    with torch.cuda.stream(c.stream):
+        st.gx.add_(1e-4)
+    c.tree_refit(t, st.gx, st.gy, st.gz, st.dx, st.dy, st.dz)
+    with torch.cuda.stream(c.stream):
+        st.gx.add_(0.2)
+    with pytest.raises(CrkError) as e:
+        c.tree_refit(t, st.gx, st.gy, st.gz, st.dx, st.dy, st.dz)
+    assert e.value.status == CRK_ESTALE
+    st.close()
