@@ -94,6 +94,75 @@ def time_steps(fn, sync, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
+    """Hierarchical time steps on the same workload.  Per particle, the step
+    its criteria allow, tau_i = min(c_cfl h / cs (gas), sqrt(2 eta eps /
+    |a|)), from the step's own accelerations; the interval dt is about four
+    median steps (at most the time in which the fastest particle crosses
+    r_c / 4), cut into 2^L substeps with L the smallest level count
+    (at most max_levels) whose deepest step resolves the smallest tau_i;
+    bins from crk_timestep_bins.  Then timed block kick-drift-kick cycles
+    (tree built once per cycle, refitted every substep, passes over the
+    active leaves only)."""
+    import numpy as np
+    import torch
+    from paper_2510_03557_amd.step import ShortRangeStep
+    c_cfl, eta = 0.25, 0.025
+    st = ShortRangeStep(wl, precision="fp32", tuning=tuning)
+    st.run()
+    out = st.outputs()
+    eps = float(wl.eps[0])
+    ag = np.linalg.norm(out["a_grav_gas"] + out["a_hydro"], axis=0)
+    ad = np.linalg.norm(out["a_grav_dm"], axis=0)
+    tau_g = np.minimum(c_cfl * np.asarray(wl.gas.h, np.float64)
+                       / np.maximum(out["cs"], 1e-30),
+                       np.sqrt(2 * eta * eps / np.maximum(ag, 1e-30)))
+    tau_d = np.sqrt(2 * eta * eps / np.maximum(ad, 1e-30))
+    tau = np.concatenate([tau_g, tau_d])
+    tmed, tmin = float(np.median(tau)), float(np.min(tau))
+    # the tree serves the whole interval: the fastest particle moves at most
+    # r_c / 4 (well inside the chaining-mesh margin, so no rebuild is due)
+    vmax = max(float(np.max(np.sqrt(wl.gas.vx.astype(np.float64) ** 2
+                                    + wl.gas.vy.astype(np.float64) ** 2
+                                    + wl.gas.vz.astype(np.float64) ** 2))),
+               float(np.max(np.sqrt(wl.dm.vx.astype(np.float64) ** 2
+                                    + wl.dm.vy.astype(np.float64) ** 2
+                                    + wl.dm.vz.astype(np.float64) ** 2))))
+    dt = min(4.0 * tmed, 0.25 * float(wl.r_c[0]) / max(vmax, 1e-30))
+    levels = int(min(max(np.ceil(np.log2(dt / tmin)), 1), max_levels))
+    bg, bd = st.timestep_bins(dt, levels, c_cfl=c_cfl, eta=eta)
+    steps = int(np.sum(2 ** bg.astype(np.int64)) + np.sum(2 ** bd.astype(np.int64)))
+    n = wl.n_total
+    log(f"[bench] substep cycle: {levels} levels, dt {dt:.3g} (median tau "
+        f"{tmed:.3g}, min {tmin:.3g}), bins gas "
+        f"{np.bincount(bg, minlength=levels + 1).tolist()} dm "
+        f"{np.bincount(bd, minlength=levels + 1).tolist()}")
+    st.substep_cycle(dt, levels)  # warm-up (sizes)
+    st.sync()
+    st.ctx.timing(True)
+    sec = time_steps(lambda: st.substep_cycle(dt, levels),
+                     lambda: (torch.cuda.synchronize(),
+                              st.ctx.stream.synchronize()), cycles, 0)
+    pass_ms, _, _ = st.ctx.pass_times()
+    st.ctx.timing(False)
+    st.sync()
+    st.close()
+    flat = (2 ** levels) * ms_per_step if ms_per_step else None
+    return {"levels": levels, "substeps": 2 ** levels, "dt": dt,
+            "tau_median": tmed, "tau_min": tmin, "v_max": vmax,
+            "bins_gas": np.bincount(bg, minlength=levels + 1).tolist(),
+            "bins_dm": np.bincount(bd, minlength=levels + 1).tolist(),
+            "cycles": cycles, "ms_per_cycle": sec * 1e3,
+            "particle_steps": steps,
+            "particle_steps_per_s": steps / sec,
+            "evaluations_per_s": (n + steps) / sec,
+            "pass_ms_per_cycle": {k: round(v / cycles, 3)
+                                  for k, v in pass_ms.items()},
+            "flat_deepest_ms": flat,
+            "speedup_vs_flat": (flat / (sec * 1e3)) if flat else None,
+            "launch": "eager"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +182,13 @@ def main():
     ap.add_argument("--dt", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--substep-levels", type=int, default=8,
+                    help="most levels of the hierarchical time-step cycle "
+                         "timed after the step (0: none)")
+    ap.add_argument("--cycles", type=int, default=3)
+    ap.add_argument("--cycle-only", action="store_true",
+                    help="time only the hierarchical time-step cycle and "
+                         "print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times "
                          "(reference kernel for scaling HBM byte counters)")
@@ -150,6 +226,11 @@ def main():
     tuning = dict(leaf_max=args.leaf_max, grid_mult=args.grid_mult,
                   xcd_remap=args.xcd_remap, walk_mask=args.walk_mask,
                   sub_sweep=args.sub_sweep, tree_lds=args.tree_lds)
+
+    if args.cycle_only:
+        print(json.dumps(measure_cycle(wl, tuning, max(args.substep_levels, 1),
+                                       args.cycles, None, log)), flush=True)
+        return
 
     # ---------------- float32 path: graph replay of the whole step ---------
     st = ShortRangeStep(wl, precision="fp32", tuning=tuning, dt=args.dt)
@@ -222,6 +303,13 @@ def main():
                 "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
                 "frac_unpacked": round(ach / PEAK_FP32_UNPACKED_TFLOPS, 4)}
 
+    # ---------------- hierarchical time steps ---------------------------------
+    cycle = None
+    if args.substep_levels > 0:
+        st.close()
+        cycle = measure_cycle(wl, tuning, args.substep_levels, args.cycles,
+                              sec * 1e3, log)
+
     # ---------------- CPU baseline: the FP64 oracle ---------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -271,6 +359,7 @@ def main():
         "kernels": kern,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "substep_cycle": cycle,
         "context": "paper: 46.6e9 particles/s on 9,000 Frontier nodes for the"
                    " whole solver per PM step (not like-for-like)",
     }

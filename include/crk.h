@@ -253,12 +253,12 @@ int crk_integrate(crk_ctx *ctx, int64_t n, double dt, double *x64,
  * s % 2^(max_level-b) == 0 and ending after substeps s with
  * (s + 1) % 2^(max_level-b) == 0.  One substep of a block kick-drift-kick
  * cycle: crk_kick (phase 0), crk_drift (no wrap), crk_tree_refit,
- * build_interaction_lists, crk_tree_set_active (substep s), the four passes
- * (they then run over the active leaves and write only active particles;
- * inactive ones keep their outputs), crk_kick (phase 1); after the last
- * substep every particle is synchronised and crk_drift with delta 0 and
- * wrap 1 wraps the positions.  All arrays are device memory in caller
- * order unless stated. */
+ * crk_tree_set_active (substep s), build_interaction_lists (lists of the
+ * active leaves only), the four passes (they then run over the active
+ * leaves and write only active particles; inactive ones keep their
+ * outputs), crk_kick (phase 1); after the last substep every particle is
+ * synchronised and crk_drift with delta 0 and wrap 1 wraps the positions.
+ * All arrays are device memory in caller order unless stated. */
 
 /* Timestep bin of n particles: the smallest b in [0, max_level] whose
  * tau_b = dt / 2^b satisfies tau_b^4 |a|^2 <= (2 eta eps)^2 (the criterion
@@ -279,6 +279,8 @@ int crk_timestep_bins(crk_ctx *ctx, int64_t n, double dt, int32_t max_level,
  * clamped to [0, max_level]); the leaves holding any of them become the work
  * items of the pair passes, which then write outputs for those particles
  * only.  substep < 0 selects everything (the state after build_tree).
+ * The lists must be rebuilt after every call (build_interaction_lists then
+ * lists the active leaves only; the passes report CRK_ESTATE until then).
  * Synchronises (reads the active leaf counts back). */
 int crk_tree_set_active(crk_ctx *ctx, crk_tree *tree, const int32_t *bins_gas,
                         const int32_t *bins_dm, int32_t max_level,

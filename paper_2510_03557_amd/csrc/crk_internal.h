@@ -186,7 +186,7 @@ struct crk_tree {
     crk::DevBuf act_items;             // int32 per active leaf
     crk::DevBuf act_count;             // int32 [2]
     int64_t act_nall = 0, act_ngas = 0;
-    crk::DevBuf overhang;              // float per box (refit)
+    crk::DevBuf overhang;              // int flag: a leaf left the stencil (refit)
 };
 
 namespace crk {

@@ -35,11 +35,15 @@ __global__ __launch_bounds__(LB) void lists_kernel(
     int32_t *__restrict__ g_cnt, int32_t *__restrict__ h_cnt,
     const int64_t *__restrict__ g_off, const int64_t *__restrict__ h_off,
     uint32_t *__restrict__ g_list, uint32_t *__restrict__ h_list,
-    int64_t g_cap, int64_t h_cap, int *__restrict__ err) {
+    int64_t g_cap, int64_t h_cap, const int32_t *__restrict__ act_leaf,
+    int *__restrict__ err) {
     const int lane = threadIdx.x & 63;
     const int64_t I = (int64_t)blockIdx.x * (LB / 64) + (threadIdx.x >> 6);
     const int64_t nn = *nn_ptr;
     if (I >= nn) return;  // whole wavefront leaves together
+    // with an active subset only the active leaves get lists (the others
+    // keep the zero counts filled before the launch)
+    if (act_leaf && !act_leaf[I]) return;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int key = leaf_key[I];
     const bool gasI = key < total_bins;
@@ -219,7 +223,7 @@ int lists_impl(crk_ctx *ctx, crk_tree *t) {
                            t->h_cnt.as<int32_t>(), t->g_off.as<int64_t>(),
                            t->h_off.as<int64_t>(), t->g_list.as<uint32_t>(),
                            t->h_list.as<uint32_t>(), t->grav_cap, t->hydro_cap,
-                           err);
+                           t->act_on ? t->act_leaf.as<int32_t>() : nullptr, err);
         CRK_HIP(hipGetLastError());
         return CRK_OK;
     };

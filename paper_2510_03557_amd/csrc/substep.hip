@@ -153,33 +153,23 @@ __global__ void refit_pos_kernel(int64_t n, int64_t n_gas,
     }
 }
 
-// grows the box of slots [st, st + c) (three planes of stride ld, entry k)
-template <typename T>
-__device__ inline void grow_box(const T *p0, const T *p1, const T *p2, int st,
-                                int c, T *lo, T *hi, int64_t ld, int64_t k) {
-    T l0 = lo[k], l1 = lo[ld + k], l2 = lo[2 * ld + k];
-    T u0 = hi[k], u1 = hi[ld + k], u2 = hi[2 * ld + k];
-    for (int q = st; q < st + c; ++q) {
-        l0 = fmin(l0, p0[q]);
-        u0 = fmax(u0, p0[q]);
-        l1 = fmin(l1, p1[q]);
-        u1 = fmax(u1, p1[q]);
-        l2 = fmin(l2, p2[q]);
-        u2 = fmax(u2, p2[q]);
-    }
-    lo[k] = l0;
-    lo[ld + k] = l1;
-    lo[2 * ld + k] = l2;
-    hi[k] = u0;
-    hi[ld + k] = u1;
-    hi[2 * ld + k] = u2;
+template <typename T> __device__ inline T wmin(T v, int width) {
+    for (int off = width >> 1; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+    return v;
+}
+template <typename T> __device__ inline T wmax(T v, int width) {
+    for (int off = width >> 1; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
 }
 
-// One thread per leaf: grow the leaf box and its sub-leaf boxes to the
-// current positions (boxes never shrink), and record per box the largest
-// distance by which a leaf box reaches out of its chaining-mesh bin.
+// One wavefront per leaf (four per workgroup): grow the leaf box and its
+// sub-leaf boxes to the current positions (boxes never shrink; sub-leaf g
+// on lanes 16g..16g+15).  Every pair the lists could miss has a particle
+// that left its bin: while each leaf box reaches at most d out of its bin
+// with 2 d + range <= bin width, the 27-bin stencil still holds every
+// partner; a leaf breaking that sets *stale.
 template <typename T>
-__global__ void refit_box_kernel(
+__global__ __launch_bounds__(256) void refit_box_kernel(
     const int32_t *__restrict__ nn_ptr, int64_t lcap,
     const int32_t *__restrict__ lst, const int32_t *__restrict__ lct,
     const int32_t *__restrict__ lkey, const int32_t *__restrict__ lbox,
@@ -188,33 +178,83 @@ __global__ void refit_box_kernel(
     const int32_t *__restrict__ nsub, const int32_t *__restrict__ sst,
     const int32_t *__restrict__ scnt, T *__restrict__ slo, T *__restrict__ shi,
     int64_t total_bins, const int *__restrict__ ncm,
-    const int64_t *__restrict__ bin_base, float *__restrict__ overhang) {
+    const int64_t *__restrict__ bin_base, const double *__restrict__ rc,
+    const double *__restrict__ hmax, int *__restrict__ stale) {
     const int64_t nn = *nn_ptr;
-    GRID_LOOP(I, nn) {
-        grow_box(p0, p1, p2, lst[I], lct[I], lo, hi, lcap, I);
-        if (has_sub) {
-            const int ns = nsub[I];
-            for (int g = 0; g < ns; ++g) {
-                const int64_t sl = 4 * I + g;
-                grow_box(p0, p1, p2, sst[sl], scnt[sl], slo, shi, 4 * lcap, sl);
-            }
-        }
+    const int lane = threadIdx.x & 63;
+    const int64_t I = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (I >= nn) return;  // the whole wavefront leaves together
+    const int st = lst[I], c = lct[I];
+    T l0 = lo[I], l1 = lo[lcap + I], l2 = lo[2 * lcap + I];
+    T u0 = hi[I], u1 = hi[lcap + I], u2 = hi[2 * lcap + I];
+    for (int q = st + lane; q < st + c; q += 64) {
+        l0 = fmin(l0, p0[q]);
+        u0 = fmax(u0, p0[q]);
+        l1 = fmin(l1, p1[q]);
+        u1 = fmax(u1, p1[q]);
+        l2 = fmin(l2, p2[q]);
+        u2 = fmax(u2, p2[q]);
+    }
+    l0 = wmin(l0, 64);
+    l1 = wmin(l1, 64);
+    l2 = wmin(l2, 64);
+    u0 = wmax(u0, 64);
+    u1 = wmax(u1, 64);
+    u2 = wmax(u2, 64);
+    if (lane == 0) {
+        lo[I] = l0;
+        lo[lcap + I] = l1;
+        lo[2 * lcap + I] = l2;
+        hi[I] = u0;
+        hi[lcap + I] = u1;
+        hi[2 * lcap + I] = u2;
         const int key = lkey[I];
         const int64_t gbin = key < total_bins ? key : key - total_bins;
         const int b = lbox[I];
         const int nc = ncm[b];
         const int64_t lb = gbin - bin_base[b];
         const int64_t cc[3] = {lb / ((int64_t)nc * nc), (lb / nc) % nc, lb % nc};
+        const double L[3] = {(double)l0, (double)l1, (double)l2};
+        const double U[3] = {(double)u0, (double)u1, (double)u2};
         double ov = 0.0;
         for (int a = 0; a < 3; ++a) {
             const double cl = 1.0 + (double)cc[a] / nc;
             const double ch = 1.0 + (double)(cc[a] + 1) / nc;
-            ov = fmax(ov, fmax(cl - (double)lo[a * lcap + I],
-                               (double)hi[a * lcap + I] - ch));
+            ov = fmax(ov, fmax(cl - L[a], U[a] - ch));
         }
-        // non-negative floats order like their bit patterns
-        atomicMax(reinterpret_cast<int *>(overhang) + b,
-                  __float_as_int((float)(ov * (1.0 + 1e-6))));
+        const double R = fmax(rc[b], 2.0 * hmax[b]) * (1.0 + 1e-5);
+        if (2.0 * ov * (1.0 + 1e-6) + R > 1.0 / nc) atomicOr(stale, 1);
+    }
+    if (has_sub) {
+        const int g = lane >> 4, u = lane & 15;
+        const int ns = nsub[I];
+        const int64_t sl = 4 * I + (g < ns ? g : 0);
+        const bool v = g < ns && u < scnt[sl];
+        const int q = v ? sst[sl] + u : st;
+        T a0 = slo[sl], a1 = slo[4 * lcap + sl], a2 = slo[8 * lcap + sl];
+        T b0 = shi[sl], b1 = shi[4 * lcap + sl], b2 = shi[8 * lcap + sl];
+        if (v) {
+            a0 = fmin(a0, p0[q]);
+            b0 = fmax(b0, p0[q]);
+            a1 = fmin(a1, p1[q]);
+            b1 = fmax(b1, p1[q]);
+            a2 = fmin(a2, p2[q]);
+            b2 = fmax(b2, p2[q]);
+        }
+        a0 = wmin(a0, 16);
+        a1 = wmin(a1, 16);
+        a2 = wmin(a2, 16);
+        b0 = wmax(b0, 16);
+        b1 = wmax(b1, 16);
+        b2 = wmax(b2, 16);
+        if (u == 0 && g < ns) {
+            slo[sl] = a0;
+            slo[4 * lcap + sl] = a1;
+            slo[8 * lcap + sl] = a2;
+            shi[sl] = b0;
+            shi[4 * lcap + sl] = b1;
+            shi[8 * lcap + sl] = b2;
+        }
     }
 }
 
@@ -311,11 +351,11 @@ int refit_impl(crk_ctx *ctx, crk_tree *t, const void *gx, const void *gy,
                        cp<T>(gz), cp<T>(dx), cp<T>(dy), cp<T>(dz),
                        t->pos[0].as<T>(), t->pos[1].as<T>(), t->pos[2].as<T>());
     CRK_HIP(hipGetLastError());
-    const int nb = t->n_boxes;
-    CRK_TRY(t->overhang.ensure((size_t)nb * 4, false));
-    CRK_HIP(fill_i32(t->overhang.as<int32_t>(), 0, nb, s));
+    CRK_TRY(t->overhang.ensure(4, false));
+    CRK_HIP(fill_i32(t->overhang.as<int32_t>(), 0, 1, s));
     const int cur = t->cur_nodes;
-    hipLaunchKernelGGL((refit_box_kernel<T>), dim3(grid_n(t->n_leaves)), dim3(256),
+    const unsigned nwg = (unsigned)std::max<int64_t>(1, (t->n_leaves + 3) / 4);
+    hipLaunchKernelGGL((refit_box_kernel<T>), dim3(nwg), dim3(256),
                        0, s, t->counters.as<int32_t>() + C_NN, t->leaf_cap,
                        t->nd_start[cur].as<int32_t>(), t->nd_count[cur].as<int32_t>(),
                        t->nd_key[cur].as<int32_t>(), t->leaf_box.as<int32_t>(),
@@ -324,24 +364,17 @@ int refit_impl(crk_ctx *ctx, crk_tree *t, const void *gx, const void *gy,
                        t->sub_nsub.as<int32_t>(), t->sub_start.as<int32_t>(),
                        t->sub_count.as<int32_t>(), t->sub_lo.as<T>(),
                        t->sub_hi.as<T>(), t->total_bins, t->d_ncm.as<int>(),
-                       t->d_bin_base.as<int64_t>(), t->overhang.as<float>());
+                       t->d_bin_base.as<int64_t>(), t->d_rc.as<double>(),
+                       t->d_hmax.as<double>(), t->overhang.as<int>());
     CRK_HIP(hipGetLastError());
-    // every pair the lists miss has a particle that left its bin: with the
-    // largest excursion d of a box out of its bin, pairs stay inside the
-    // 27-bin stencil while 2 d + range <= bin width
-    std::vector<float> ov(nb);
-    CRK_HIP(hipMemcpyAsync(ov.data(), t->overhang.p, (size_t)nb * 4,
-                           hipMemcpyDeviceToHost, s));
+    int32_t *hb = ctx->err_host.as<int32_t>() + 12;
+    CRK_HIP(hipMemcpyAsync(hb, t->overhang.p, 4, hipMemcpyDeviceToHost, s));
     CRK_HIP(hipStreamSynchronize(s));
-    for (int b = 0; b < nb; ++b) {
-        const double w = 1.0 / t->h_ncm[b];
-        const double R = std::max(t->cur_rc[b], 2.0 * t->cur_hmax[b]) * (1.0 + 1e-5);
-        if (2.0 * (double)ov[b] + R > w)
-            return set_error(CRK_ESTALE,
-                             "tree_refit: particles moved too far out of their "
-                             "chaining-mesh bins for the interaction stencil; "
-                             "rebuild the tree");
-    }
+    if (*hb)
+        return set_error(CRK_ESTALE,
+                         "tree_refit: particles moved too far out of their "
+                         "chaining-mesh bins for the interaction stencil; "
+                         "rebuild the tree");
     return CRK_OK;
 }
 
@@ -387,6 +420,8 @@ int timestep_bins(crk_ctx *ctx, int64_t n, double dt, int max_level, double eps,
 int tree_set_active(crk_ctx *ctx, crk_tree *t, const int32_t *bins_gas,
                     const int32_t *bins_dm, int max_level, int64_t substep) {
     hipStream_t s = ctx->stream;
+    // lists belong to one subset: the next passes need a list build
+    t->lists_built = false;
     if (substep < 0) {
         t->act_on = false;
         return CRK_OK;

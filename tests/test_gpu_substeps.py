@@ -123,6 +123,7 @@ def test_active_passes_write_active_particles_only(step_cls):
     act_d = ((s + 1) % (2 ** (L - bd))) == 0
     assert 0 < act_g.sum() < st.ng and 0 < act_d.sum() < st.nd
     c.tree_set_active(t, st.bins_g, st.bins_d, L, s)
+    c.build_interaction_lists(t)
     sentinel = -7.25
     groups = {
         "density": (("V", "rho_t"), ("V", "rho_tilde")),
@@ -163,7 +164,12 @@ def test_active_passes_write_active_particles_only(step_cls):
         with torch.cuda.stream(c.stream):
             for k in attrs:
                 getattr(st, k).copy_(saved[k])
+    # a new subset invalidates the lists until they are rebuilt
     c.tree_set_active(t, None, None, 0, -1)
+    from paper_2510_03557_amd.binding import CrkError, CRK_ESTATE
+    with pytest.raises(CrkError) as e:
+        c.density(t, st.gm, st.V, st.rho_t)
+    assert e.value.status == CRK_ESTATE
     st.close()
 
 
