@@ -652,6 +652,14 @@ __global__ __launch_bounds__(64) void pair_kernel_split(const TreeView<T> tv,
                                : (int)blockIdx.x;
     const int I = item_leaf(tv, b >> 2), g = b & 3;
     if (g >= tv.nsub[I]) return;
+    if (tv.act) {
+        // active subset: a sub-leaf without active particles has nothing
+        // to write (the whole wavefront leaves together)
+        const int64_t sl = 4 * (int64_t)I + g;
+        const int lane = threadIdx.x;
+        const bool a = lane < min(tv.scnt[sl], 16) && tv.act[tv.sst[sl] + lane];
+        if (__ballot(a) == 0) return;
+    }
     process_subleaf<T, P>(tv, pa, I, g, sj, sjid);
 }
 
