@@ -10,5 +10,5 @@ depend on.
 from .oracle import (  # noqa: F401
     PARAMS, build, coefficients, density, gravity, hydro, integrate,
     kernel, grav_g, s2_force, neighbours, num_threads, step, step_sampled,
-    STEP_PARAMS, timestep_bins, substep_cycle,
+    STEP_PARAMS, timestep_bins, substep_cycle, s2_form_factor, pm_long_range,
 )

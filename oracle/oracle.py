@@ -480,3 +480,91 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
     out = dict(xg=_wrap(xg), vg=vg, u=u, xd=_wrap(xd), vd=vd)
     out.update(st)
     return out
+
+
+# ----------------------------------------------------------------------------
+# long-range gravity on a mesh, matched to the short-range split (the
+# spectral particle-mesh part of Sec. IV-A; the paper's filtered PM method
+# and SWFFT are not printed, so the steps below are the textbook
+# particle-mesh method with the S2 split of Hockney & Eastwood).
+# ----------------------------------------------------------------------------
+
+def s2_form_factor(k, r_c):
+    """Fourier transform of the S2 cloud of diameter r_c (unit mass, density
+    falling linearly from the centre to radius r_c / 2): with x = k r_c / 2,
+    12 (2 - 2 cos x - x sin x) / x^4, 1 at k = 0 (series below x = 1e-2)."""
+    x = np.asarray(k, np.float64) * (0.5 * r_c)
+    out = np.ones_like(x)
+    big = x > 1e-2
+    xb = x[big]
+    out[big] = 12.0 * (2.0 - 2.0 * np.cos(xb) - xb * np.sin(xb)) / xb ** 4
+    xs = x[~big]
+    out[~big] = 1.0 - xs ** 2 / 15.0 + xs ** 4 / 560.0
+    return out
+
+
+def pm_long_range(x, y, z, m, n_mesh, r_c, G=PARAMS["G"]):
+    """Long-range acceleration of every particle of one periodic unit box
+    (coordinates in [1, 2)): the force between S2 clouds of diameter r_c,
+    i.e. the complement of the short-range force, on an n_mesh^3 mesh.
+    Steps: cloud-in-cell deposit of the masses on the nodes j / n_mesh;
+    FFT; multiplication by -4 pi G S2(k)^2 / k^2 (the mean removed) divided
+    by the squared CIC window prod_a sinc^4(k_a / (2 n_mesh)) (deposit and
+    interpolation); spectral gradient i k (Nyquist planes zeroed); three
+    inverse FFTs; cloud-in-cell interpolation back to the particles."""
+    N = int(n_mesh)
+    P = np.stack([np.asarray(a, np.float64) for a in (x, y, z)])
+    m = np.asarray(m, np.float64)
+    u = (P - 1.0) * N
+    i0 = np.floor(u).astype(np.int64)
+    f = u - i0
+    i0 %= N
+    i1 = (i0 + 1) % N
+    rho = np.zeros((N, N, N))
+    for cx in (0, 1):
+        wx = f[0] if cx else 1.0 - f[0]
+        ix = i1[0] if cx else i0[0]
+        for cy in (0, 1):
+            wy = f[1] if cy else 1.0 - f[1]
+            iy = i1[1] if cy else i0[1]
+            for cz in (0, 1):
+                wz = f[2] if cz else 1.0 - f[2]
+                iz = i1[2] if cz else i0[2]
+                np.add.at(rho, (ix, iy, iz), m * wx * wy * wz)
+    rho *= N ** 3  # mass per cell volume
+    rk = np.fft.rfftn(rho)
+    n1 = np.fft.fftfreq(N, 1.0 / N)
+    nz = np.fft.rfftfreq(N, 1.0 / N)
+    KX, KY, KZ = np.meshgrid(2 * np.pi * n1, 2 * np.pi * n1, 2 * np.pi * nz,
+                             indexing="ij")
+    k2 = KX ** 2 + KY ** 2 + KZ ** 2
+    k = np.sqrt(k2)
+    h = 0.5 / N
+
+    def sinc(t):
+        return np.where(t == 0, 1.0, np.sin(t) / np.where(t == 0, 1.0, t))
+
+    W = (sinc(KX * h) * sinc(KY * h) * sinc(KZ * h)) ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        gk = np.where(k2 > 0, 4 * np.pi * G * s2_form_factor(k, r_c) ** 2
+                      / (k2 * W * W), 0.0)
+    nyq = N // 2
+    acc = []
+    for K, axis_ny in ((KX, np.abs(n1)[:, None, None] == nyq),
+                       (KY, np.abs(n1)[None, :, None] == nyq),
+                       (KZ, (nz == nyq)[None, None, :])):
+        Kd = np.where(axis_ny, 0.0, K)
+        field = np.fft.irfftn(1j * Kd * gk * rk, s=(N, N, N), axes=(0, 1, 2))
+        a = np.zeros(P.shape[1])
+        for cx in (0, 1):
+            wx = f[0] if cx else 1.0 - f[0]
+            ix = i1[0] if cx else i0[0]
+            for cy in (0, 1):
+                wy = f[1] if cy else 1.0 - f[1]
+                iy = i1[1] if cy else i0[1]
+                for cz in (0, 1):
+                    wz = f[2] if cz else 1.0 - f[2]
+                    iz = i1[2] if cz else i0[2]
+                    a += wx * wy * wz * field[ix, iy, iz]
+        acc.append(a)
+    return np.stack(acc)
