@@ -316,6 +316,30 @@ int crk_drift(crk_ctx *ctx, int64_t n, double delta, int32_t wrap,
               double *x64, const double *v64, void *const x[3]);
 
 /* ------------------------------------------------------------------------ */
+/* long-range gravity on a mesh                                              */
+/* ------------------------------------------------------------------------ */
+
+/* The spectral particle-mesh half of the force split of Sec. IV-A, for one
+ * periodic unit box: the long-range acceleration that shortrange_gravity
+ * leaves out, i.e. the force between S2 clouds of diameter r_c, so that the
+ * two add up to the periodic Newtonian force (up to the mesh error, below
+ * 1 % for r_c >= 6 mesh cells, tested against an Ewald sum).  Cloud-in-cell
+ * deposit of all masses on the nodes j / n_mesh (double atomics), FFT,
+ * multiplication by 4 pi G S2(k)^2 / (k^2 W(k)^2) with W the CIC window
+ * prod_a sinc^2(k_a / (2 n_mesh)), spectral gradient i k (k = 0 and each
+ * component's Nyquist plane removed), three inverse FFTs, cloud-in-cell
+ * interpolation.  Positions (context precision, periodic, wrapped into the
+ * box by the deposit), masses; outputs a_gas (3 pointers, n_gas values) and
+ * a_dm (3 pointers, n_dm values), overwritten.  n_mesh even in [4, 2048];
+ * the mesh workspace and FFT plans live in the context and are reused for
+ * the same n_mesh. */
+int crk_pm_gravity(crk_ctx *ctx, int32_t n_mesh, double r_c, int64_t n_gas,
+                   const void *gx, const void *gy, const void *gz,
+                   const void *m_gas, int64_t n_dm, const void *dx,
+                   const void *dy, const void *dz, const void *m_dm,
+                   void *const a_gas[3], void *const a_dm[3]);
+
+/* ------------------------------------------------------------------------ */
 /* tree queries, graph capture, release                                      */
 /* ------------------------------------------------------------------------ */
 

@@ -32,7 +32,7 @@ EXPORTS = (
     "crk_tree_get_leaves", "crk_count_pairs", "crk_graph_begin", "crk_graph_end",
     "crk_graph_launch", "crk_tree_free", "crk_timing_enable",
     "crk_pass_times", "crk_timestep_bins", "crk_tree_set_active",
-    "crk_tree_refit", "crk_kick", "crk_drift",
+    "crk_tree_refit", "crk_kick", "crk_drift", "crk_pm_gravity",
 )
 
 
@@ -148,6 +148,8 @@ def load(path: Path | str | None = None):
     lib.crk_kick.argtypes = [vp, i64, f64, i32, i64, i32, vp, vp, vp, P, P, vp,
                              P, vp]
     lib.crk_drift.argtypes = [vp, i64, f64, i32, vp, vp, P]
+    lib.crk_pm_gravity.argtypes = [vp, i32, f64, i64, vp, vp, vp, vp, i64, vp,
+                                   vp, vp, vp, P, P]
     for name in EXPORTS:
         getattr(lib, name).restype = (ctypes.c_char_p if name == "crk_last_error"
                                       else ctypes.c_int)
@@ -313,6 +315,13 @@ class Context:
         check(self.lib.crk_drift(self.handle, int(n), float(delta),
                                  int(bool(wrap)), _ptr(x64), _ptr(v64),
                                  self._p3(x)))
+
+    def pm_gravity(self, n_mesh, r_c, n_gas, gx, gy, gz, m_gas, n_dm, dx, dy,
+                   dz, m_dm, a_gas, a_dm):
+        check(self.lib.crk_pm_gravity(
+            self.handle, int(n_mesh), float(r_c), int(n_gas), _ptr(gx),
+            _ptr(gy), _ptr(gz), _ptr(m_gas), int(n_dm), _ptr(dx), _ptr(dy),
+            _ptr(dz), _ptr(m_dm), self._p3(a_gas), self._p3(a_dm)))
 
     def count_pairs(self, tree):
         """In-range ordered pairs (gather, hydro, gravity), then the swept

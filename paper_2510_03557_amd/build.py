@@ -11,7 +11,7 @@ HERE = Path(__file__).resolve().parent
 CSRC = HERE / "csrc"
 OUT = HERE / "libcrk.so"
 SOURCES = ["capi.hip", "primitives.hip", "tree.hip", "lists.hip",
-           "passes.hip", "integrate.hip", "substep.hip"]
+           "passes.hip", "integrate.hip", "substep.hip", "pm.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("CRK_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -37,7 +37,8 @@ def build(verbose: bool = False) -> Path:
         objs = list(ex.map(lambda s: _compile(s, objdir), SOURCES))
     tmp = OUT.with_suffix(".so.tmp%d" % os.getpid())
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp),
-           *map(str, objs)]
+           *map(str, objs), "-L/opt/rocm/lib", "-lhipfft",
+           "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

@@ -202,6 +202,7 @@ int crk_ctx_destroy(crk_ctx *ctx) {
     }
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    pm_release(ctx->pm);
     ctx->err.release();
     ctx->err_host.release();
     ctx->scratch.release();
@@ -525,6 +526,38 @@ int crk_drift(crk_ctx *ctx, int64_t n, double delta, int32_t wrap, double *x64,
     for (int a = 0; a < 3; ++a) CRK_TRY(check_ptr(x[a], el, "x", true));
     PassSpan sp(ctx, P_INTEG);
     return drift(ctx, n, delta, wrap ? 1 : 0, x64, v64, x);
+}
+
+int crk_pm_gravity(crk_ctx *ctx, int32_t n_mesh, double r_c, int64_t n_gas,
+                   const void *gx, const void *gy, const void *gz,
+                   const void *m_gas, int64_t n_dm, const void *dx,
+                   const void *dy, const void *dz, const void *m_dm,
+                   void *const a_gas[3], void *const a_dm[3]) {
+    CRK_TRY(check_ctx(ctx));
+    if (n_mesh < 4 || n_mesh > 2048 || (n_mesh & 1))
+        return set_error(CRK_EINVAL, "n_mesh must be even, in [4, 2048]");
+    if (!(r_c > 0.0) || !(r_c < 0.5) || !std::isfinite(r_c))
+        return set_error(CRK_EINVAL, "r_c must be in (0, 0.5)");
+    if (n_gas < 0 || n_dm < 0) return set_error(CRK_EINVAL, "counts must be >= 0");
+    if (ctx->capturing) return set_error(CRK_ESTATE, "pm_gravity during capture");
+    const size_t el = ctx->elem();
+    const bool g = n_gas > 0, d = n_dm > 0;
+    CRK_TRY(check_ptr(gx, el, "gx", g));
+    CRK_TRY(check_ptr(gy, el, "gy", g));
+    CRK_TRY(check_ptr(gz, el, "gz", g));
+    CRK_TRY(check_ptr(m_gas, el, "m_gas", g));
+    CRK_TRY(check_ptr(dx, el, "dx", d));
+    CRK_TRY(check_ptr(dy, el, "dy", d));
+    CRK_TRY(check_ptr(dz, el, "dz", d));
+    CRK_TRY(check_ptr(m_dm, el, "m_dm", d));
+    if ((g && !a_gas) || (d && !a_dm)) return set_error(CRK_EINVAL, "null pointer array");
+    for (int a = 0; a < 3; ++a) {
+        if (g) CRK_TRY(check_ptr(a_gas[a], el, "a_gas", true));
+        if (d) CRK_TRY(check_ptr(a_dm[a], el, "a_dm", true));
+    }
+    PassSpan sp(ctx, P_GRAV);
+    return pm_gravity(ctx, n_mesh, r_c, n_gas, gx, gy, gz, m_gas, n_dm, dx, dy,
+                      dz, m_dm, a_gas, a_dm);
 }
 
 int crk_count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[6]) {

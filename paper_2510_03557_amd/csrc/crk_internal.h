@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <cstdint>
 #include <cstring>
@@ -70,6 +71,16 @@ struct HostBuf {
 
 enum PassId { P_TREE = 0, P_LISTS, P_DENSITY, P_COEFF, P_HYDRO, P_GRAV, P_INTEG, P_COUNT };
 
+// long-range mesh workspace (pm.hip): double deposit mesh, real mesh and
+// two half-spectra of the context precision, and the FFT plans of one size
+struct crk_pm {
+    DevBuf rho, real, rhok, tmpk;
+    int n = 0, elem = 0;
+    bool plans = false;
+    hipfftHandle fwd = nullptr, inv = nullptr;
+};
+void pm_release(crk_pm &pm);
+
 struct TimedSpan {
     int pass;
     bool kernel;  // true: the pass's main kernel only
@@ -92,6 +103,7 @@ struct crk_ctx {
     crk::HostBuf err_host;
     crk::DevBuf scratch;      // primitives' temporary storage
     bool timing = false;
+    crk::crk_pm pm;
     std::vector<crk::TimedSpan> spans;
     std::vector<hipEvent_t> event_pool;
     size_t elem() const { return precision == CRK_FP64 ? 8 : 4; }
@@ -260,6 +272,11 @@ int block_kick(crk_ctx *ctx, int64_t n, double dt, int max_level,
                void *const v[3], void *u);
 int drift(crk_ctx *ctx, int64_t n, double delta, int wrap, double *x64,
           const double *v64, void *const x[3]);
+// long-range gravity on a mesh (pm.hip)
+int pm_gravity(crk_ctx *ctx, int n_mesh, double r_c, int64_t n_gas,
+               const void *gx, const void *gy, const void *gz, const void *m_gas,
+               int64_t n_dm, const void *dx, const void *dy, const void *dz,
+               const void *m_dm, void *const a_gas[3], void *const a_dm[3]);
 
 // timing helpers (capi.cpp): bracket a span on the context stream
 void span_begin(crk_ctx *ctx, int pass, bool kernel, hipEvent_t *ev);

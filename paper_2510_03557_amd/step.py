@@ -220,6 +220,32 @@ class ShortRangeStep:
                     u=self.gu64[:ng].cpu().numpy() if ng else np.zeros(0),
                     xd=h3(self.dx64, nd), vd=h3(self.dv64, nd))
 
+    def pm_gravity(self, n_mesh: int | None = None):
+        """Long-range accelerations of a single-box workload on an n_mesh^3
+        mesh (default: r_c = 6 mesh cells), into self.pm_gas / self.pm_dm
+        (3 tensors each); returns them as numpy (3, n) arrays."""
+        wl, c, torch = self.wl, self.ctx, self.torch
+        if wl.n_boxes != 1:
+            raise ValueError("the mesh solver takes one periodic box")
+        rc = float(wl.r_c[0])
+        if n_mesh is None:
+            n_mesh = int(2 * np.ceil(3.0 / rc))
+        T = c.dtype
+        if getattr(self, "pm_gas", None) is None:
+            with torch.cuda.stream(c.stream):
+                self.pm_gas = [torch.zeros(max(self.ng, 1), dtype=T,
+                                           device="cuda") for _ in range(3)]
+                self.pm_dm = [torch.zeros(max(self.nd, 1), dtype=T,
+                                          device="cuda") for _ in range(3)]
+        c.pm_gravity(n_mesh, rc, self.ng, self.gx, self.gy, self.gz, self.gm,
+                     self.nd, self.dx, self.dy, self.dz, self.dm,
+                     self.pm_gas if self.ng else None,
+                     self.pm_dm if self.nd else None)
+        c.stream.synchronize()
+        g = np.stack([t[:self.ng].double().cpu().numpy() for t in self.pm_gas])
+        d = np.stack([t[:self.nd].double().cpu().numpy() for t in self.pm_dm])
+        return g, d
+
     def capture(self, integrate: bool = True):
         """Runs the step once eagerly (sizes), then captures it in a graph."""
         self.run(integrate=integrate)
