@@ -163,6 +163,35 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
             "launch": "eager"}
 
 
+def measure_pm(wl, reps, log):
+    """Long-range mesh gravity of the whole box (crk_pm_gravity) on the mesh
+    with r_c = 6 cells, float32; HIP-event time of one call on the
+    library's stream, averaged over reps calls after a warm-up."""
+    import numpy as np
+    import torch
+    from paper_2510_03557_amd.step import ShortRangeStep
+    if wl.n_boxes != 1:
+        return None
+    st = ShortRangeStep(wl, precision="fp32")
+    n_mesh = int(2 * np.ceil(3.0 / float(wl.r_c[0])))
+    st.pm_gravity(n_mesh)  # warm-up: workspace and FFT plans
+    st.ctx.timing(True)
+    sec = time_steps(lambda: st.ctx.pm_gravity(
+        n_mesh, float(wl.r_c[0]), st.ng, st.gx, st.gy, st.gz, st.gm, st.nd,
+        st.dx, st.dy, st.dz, st.dm, st.pm_gas, st.pm_dm),
+        lambda: (torch.cuda.synchronize(), st.ctx.stream.synchronize()),
+        reps, 0)
+    pass_ms, _, launches = st.ctx.pass_times()
+    st.ctx.timing(False)
+    st.close()
+    n = wl.n_total
+    log(f"[bench] mesh gravity: {n_mesh}^3 mesh, {sec * 1e3:.3f} ms")
+    return {"n_mesh": n_mesh, "ms_per_call": sec * 1e3,
+            "ms_per_call_events": pass_ms["gravity"] / max(reps, 1),
+            "particles_per_s": n / sec, "reps": reps, "dtype": "f32",
+            "deposit": "cic, double atomics", "fft": "hipfft r2c/c2r"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +218,10 @@ def main():
     ap.add_argument("--cycle-only", action="store_true",
                     help="time only the hierarchical time-step cycle and "
                          "print its JSON object")
+    ap.add_argument("--pm-only", action="store_true",
+                    help="time only the long-range mesh gravity and print "
+                         "its JSON object")
+    ap.add_argument("--no-pm", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times "
                          "(reference kernel for scaling HBM byte counters)")
@@ -227,6 +260,9 @@ def main():
                   xcd_remap=args.xcd_remap, walk_mask=args.walk_mask,
                   sub_sweep=args.sub_sweep, tree_lds=args.tree_lds)
 
+    if args.pm_only:
+        print(json.dumps(measure_pm(wl, 10, log)), flush=True)
+        return
     if args.cycle_only:
         print(json.dumps(measure_cycle(wl, tuning, max(args.substep_levels, 1),
                                        args.cycles, None, log)), flush=True)
@@ -310,6 +346,11 @@ def main():
         cycle = measure_cycle(wl, tuning, args.substep_levels, args.cycles,
                               sec * 1e3, log)
 
+    pm = None
+    if not args.no_pm:
+        st.close()
+        pm = measure_pm(wl, 10, log)
+
     # ---------------- CPU baseline: the FP64 oracle ---------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -360,6 +401,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "substep_cycle": cycle,
+        "pm_long_range": pm,
         "context": "paper: 46.6e9 particles/s on 9,000 Frontier nodes for the"
                    " whole solver per PM step (not like-for-like)",
     }

@@ -101,10 +101,12 @@ __device__ inline double s2_form(double k, double rc) {
 
 __device__ inline double sinc_pm(double t) { return t == 0.0 ? 1.0 : sin(t) / t; }
 
-// out = i K_a G(k) in, component a; layout [N][N][N/2+1]
+// o_a = i K_a G(k) in for the three components at once (G evaluated once
+// per mode); layout [N][N][N/2+1]
 template <typename C, typename T>
-__global__ void green_kernel(int N, int a, double rc, double G,
-                             const C *__restrict__ in, C *__restrict__ out) {
+__global__ void green_kernel(int N, double rc, double G, const C *__restrict__ in,
+                             C *__restrict__ o0, C *__restrict__ o1,
+                             C *__restrict__ o2) {
     const int Nh = N / 2 + 1;
     const int64_t total = (int64_t)N * N * Nh;
     PM_LOOP(q, total) {
@@ -117,20 +119,26 @@ __global__ void green_kernel(int N, int a, double rc, double G,
         const double kx = 2.0 * PI_PM * nx, ky = 2.0 * PI_PM * ny,
                      kz = 2.0 * PI_PM * nz;
         const double k2 = kx * kx + ky * ky + kz * kz;
-        const int na = a == 0 ? nx : (a == 1 ? ny : nz);
-        const double ka = a == 0 ? kx : (a == 1 ? ky : kz);
         double g = 0.0;
-        if (k2 > 0.0 && (na < 0 ? -na : na) != N / 2) {
+        if (k2 > 0.0) {
             const double h = 0.5 / N;
             const double w = sinc_pm(kx * h) * sinc_pm(ky * h) * sinc_pm(kz * h);
             const double W = w * w;
             const double s = s2_form(sqrt(k2), rc);
-            g = ka * 4.0 * PI_PM * G * s * s / (k2 * W * W);
+            g = 4.0 * PI_PM * G * s * s / (k2 * W * W);
         }
+        // each component's Nyquist plane carries no gradient
+        const double gx = (nx == N / 2 || nx == -N / 2) ? 0.0 : g * kx;
+        const double gy = (ny == N / 2 || ny == -N / 2) ? 0.0 : g * ky;
+        const double gz = (nz == N / 2) ? 0.0 : g * kz;
+        const double re = (double)in[q].x, im = (double)in[q].y;
         // i g (re + i im) = -g im + i g re
-        const T re = in[q].x, im = in[q].y;
-        out[q].x = (T)(-g * (double)im);
-        out[q].y = (T)(g * (double)re);
+        o0[q].x = (T)(-gx * im);
+        o0[q].y = (T)(gx * re);
+        o1[q].x = (T)(-gy * im);
+        o1[q].y = (T)(gy * re);
+        o2[q].x = (T)(-gz * im);
+        o2[q].y = (T)(gz * re);
     }
 }
 
@@ -219,7 +227,7 @@ int pm_impl(crk_ctx *ctx, int N, double rc, int64_t ng, const void *gx,
     CRK_TRY(pm.rho.ensure((size_t)n3 * 8, false));
     CRK_TRY(pm.real.ensure((size_t)n3 * sizeof(T), false));
     CRK_TRY(pm.rhok.ensure((size_t)nc * sizeof(C), false));
-    CRK_TRY(pm.tmpk.ensure((size_t)nc * sizeof(C), false));
+    CRK_TRY(pm.tmpk.ensure((size_t)3 * nc * sizeof(C), false));
     if (pm.n != N || pm.elem != (int)sizeof(T)) {
         if (pm.plans) {
             (void)hipfftDestroy(pm.fwd);
@@ -250,11 +258,11 @@ int pm_impl(crk_ctx *ctx, int N, double rc, int64_t ng, const void *gx,
                        rho, real, n3);
     CRK_HIP(hipGetLastError());
     CRK_FFT(F::fwd(pm.fwd, real, rhok));
+    hipLaunchKernelGGL((green_kernel<C, T>), dim3(grid_pm(nc)), dim3(256), 0, s, N,
+                       rc, ctx->params.G, rhok, tmpk, tmpk + nc, tmpk + 2 * nc);
+    CRK_HIP(hipGetLastError());
     for (int a = 0; a < 3; ++a) {
-        hipLaunchKernelGGL((green_kernel<C, T>), dim3(grid_pm(nc)), dim3(256), 0, s,
-                           N, a, rc, ctx->params.G, rhok, tmpk);
-        CRK_HIP(hipGetLastError());
-        CRK_FFT(F::inv(pm.inv, tmpk, real));
+        CRK_FFT(F::inv(pm.inv, tmpk + a * nc, real));
         if (ng)
             hipLaunchKernelGGL((interp_kernel<T>), dim3(grid_pm(ng)), dim3(256), 0,
                                s, ng, N, cp(gx), cp(gy), cp(gz), real,
