@@ -192,6 +192,35 @@ def measure_pm(wl, reps, log):
             "deposit": "cic, double atomics", "fft": "hipfft r2c/c2r"}
 
 
+def measure_fof(wl, tuning, reps, log):
+    """Friends-of-friends groups of the whole workload (crk_fof) with the
+    linking length 0.2 of the mean inter-particle spacing, over the step's
+    tree and gravity lists (built once, outside the timed calls)."""
+    import numpy as np
+    import torch
+    from paper_2510_03557_amd.step import ShortRangeStep
+    st = ShortRangeStep(wl, precision="fp32", tuning=tuning)
+    st.run()
+    b = 0.2 * wl.n_total ** (-1.0 / 3.0)
+    lg, ld = st.fof(b)  # warm-up
+    with torch.cuda.stream(st.ctx.stream):
+        tg = torch.zeros(max(st.ng, 1), dtype=torch.int32, device="cuda")
+        td = torch.zeros(max(st.nd, 1), dtype=torch.int32, device="cuda")
+    sec = time_steps(lambda: st.ctx.fof(st.tree, b, tg if st.ng else None,
+                                        td if st.nd else None),
+                     lambda: (torch.cuda.synchronize(),
+                              st.ctx.stream.synchronize()), reps, 0)
+    st.close()
+    lab = np.concatenate([lg, ld])
+    sizes = np.bincount(lab)
+    sizes = sizes[sizes > 0]
+    log(f"[bench] fof: b {b:.4g}, {len(sizes)} groups, {sec * 1e3:.3f} ms")
+    return {"linking_length": b, "ms_per_call": sec * 1e3,
+            "particles_per_s": wl.n_total / sec, "groups": int(len(sizes)),
+            "groups_20_or_more": int(np.sum(sizes >= 20)),
+            "largest_group": int(sizes.max()), "reps": reps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +251,10 @@ def main():
                     help="time only the long-range mesh gravity and print "
                          "its JSON object")
     ap.add_argument("--no-pm", action="store_true")
+    ap.add_argument("--no-fof", action="store_true")
+    ap.add_argument("--fof-only", action="store_true",
+                    help="time only the friends-of-friends groups and print "
+                         "their JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times "
                          "(reference kernel for scaling HBM byte counters)")
@@ -260,6 +293,9 @@ def main():
                   xcd_remap=args.xcd_remap, walk_mask=args.walk_mask,
                   sub_sweep=args.sub_sweep, tree_lds=args.tree_lds)
 
+    if args.fof_only:
+        print(json.dumps(measure_fof(wl, tuning, 5, log)), flush=True)
+        return
     if args.pm_only:
         print(json.dumps(measure_pm(wl, 10, log)), flush=True)
         return
@@ -351,6 +387,11 @@ def main():
         st.close()
         pm = measure_pm(wl, 10, log)
 
+    fof = None
+    if not args.no_fof:
+        st.close()
+        fof = measure_fof(wl, tuning, 5, log)
+
     # ---------------- CPU baseline: the FP64 oracle ---------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -402,6 +443,7 @@ def main():
         "cpu_baseline": cpu,
         "substep_cycle": cycle,
         "pm_long_range": pm,
+        "fof": fof,
         "context": "paper: 46.6e9 particles/s on 9,000 Frontier nodes for the"
                    " whole solver per PM step (not like-for-like)",
     }

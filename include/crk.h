@@ -316,6 +316,22 @@ int crk_drift(crk_ctx *ctx, int64_t n, double delta, int32_t wrap,
               double *x64, const double *v64, void *const x[3]);
 
 /* ------------------------------------------------------------------------ */
+/* friends-of-friends groups                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Friends-of-friends groups of every box (the in-situ halo finding of
+ * Sec. IV-B.3, here as a second pair workload over the same tree and
+ * gravity lists): two particles of a box closer than the linking length b
+ * (strictly; squared separations in double from the exact float32
+ * separations) are friends; groups are the connected components, both
+ * species together.  labels_gas (n_gas) and labels_dm (n_dm) receive, per
+ * particle, the smallest combined caller index of its group (gas index, or
+ * n_gas + dm index): deterministic whatever the order of the links.
+ * Needs built lists, no active subset, 0 < b <= r_c of every box. */
+int crk_fof(crk_ctx *ctx, crk_tree *tree, double b, int32_t *labels_gas,
+            int32_t *labels_dm);
+
+/* ------------------------------------------------------------------------ */
 /* long-range gravity on a mesh                                              */
 /* ------------------------------------------------------------------------ */
 

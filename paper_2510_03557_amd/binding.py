@@ -32,7 +32,7 @@ EXPORTS = (
     "crk_tree_get_leaves", "crk_count_pairs", "crk_graph_begin", "crk_graph_end",
     "crk_graph_launch", "crk_tree_free", "crk_timing_enable",
     "crk_pass_times", "crk_timestep_bins", "crk_tree_set_active",
-    "crk_tree_refit", "crk_kick", "crk_drift", "crk_pm_gravity",
+    "crk_tree_refit", "crk_kick", "crk_drift", "crk_pm_gravity", "crk_fof",
 )
 
 
@@ -150,6 +150,7 @@ def load(path: Path | str | None = None):
     lib.crk_drift.argtypes = [vp, i64, f64, i32, vp, vp, P]
     lib.crk_pm_gravity.argtypes = [vp, i32, f64, i64, vp, vp, vp, vp, i64, vp,
                                    vp, vp, vp, P, P]
+    lib.crk_fof.argtypes = [vp, vp, f64, vp, vp]
     for name in EXPORTS:
         getattr(lib, name).restype = (ctypes.c_char_p if name == "crk_last_error"
                                       else ctypes.c_int)
@@ -322,6 +323,10 @@ class Context:
             self.handle, int(n_mesh), float(r_c), int(n_gas), _ptr(gx),
             _ptr(gy), _ptr(gz), _ptr(m_gas), int(n_dm), _ptr(dx), _ptr(dy),
             _ptr(dz), _ptr(m_dm), self._p3(a_gas), self._p3(a_dm)))
+
+    def fof(self, tree, b, labels_gas, labels_dm):
+        check(self.lib.crk_fof(self.handle, tree.handle, float(b),
+                               _ptr(labels_gas), _ptr(labels_dm)))
 
     def count_pairs(self, tree):
         """In-range ordered pairs (gather, hydro, gravity), then the swept

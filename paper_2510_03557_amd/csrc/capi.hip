@@ -560,6 +560,24 @@ int crk_pm_gravity(crk_ctx *ctx, int32_t n_mesh, double r_c, int64_t n_gas,
                       dz, m_dm, a_gas, a_dm);
 }
 
+int crk_fof(crk_ctx *ctx, crk_tree *t, double b, int32_t *labels_gas,
+            int32_t *labels_dm) {
+    CRK_TRY(check_tree_ready(ctx, t, true));
+    if (ctx->capturing) return set_error(CRK_ESTATE, "fof during capture");
+    if (t->act_on) return set_error(CRK_ESTATE, "fof with an active subset set");
+    if (!(b > 0.0) || !std::isfinite(b))
+        return set_error(CRK_EINVAL, "linking length must be > 0");
+    for (double rc : t->cur_rc)
+        if (b > rc)
+            return set_error(CRK_EINVAL,
+                             "linking length above r_c (the gravity lists' range)");
+    if (t->n >= ((int64_t)1 << 31) - 1)
+        return set_error(CRK_EINVAL, "fof: too many particles for int32 labels");
+    CRK_TRY(check_ptr(labels_gas, 4, "labels_gas", t->n_gas > 0));
+    CRK_TRY(check_ptr(labels_dm, 4, "labels_dm", t->n_dm > 0));
+    return fof_groups(ctx, t, b, labels_gas, labels_dm);
+}
+
 int crk_count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[6]) {
     CRK_TRY(check_tree_ready(ctx, t, true));
     if (!totals) return set_error(CRK_EINVAL, "null totals");

@@ -272,6 +272,9 @@ int block_kick(crk_ctx *ctx, int64_t n, double dt, int max_level,
                void *const v[3], void *u);
 int drift(crk_ctx *ctx, int64_t n, double delta, int wrap, double *x64,
           const double *v64, void *const x[3]);
+// friends-of-friends groups over the gravity lists (passes.hip)
+int fof_groups(crk_ctx *ctx, crk_tree *t, double b, int32_t *labels_gas,
+               int32_t *labels_dm);
 // long-range gravity on a mesh (pm.hip)
 int pm_gravity(crk_ctx *ctx, int n_mesh, double r_c, int64_t n_gas,
                const void *gx, const void *gy, const void *gz, const void *m_gas,

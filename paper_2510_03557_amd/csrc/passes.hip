@@ -1363,6 +1363,141 @@ template <typename T> struct CountPass {
     }
 };
 
+// --------------------------------------------------------------------------
+// friends-of-friends links (the in-situ halo finding of Sec. IV-B.3 as a
+// second pair workload): union-find over caller indices
+// --------------------------------------------------------------------------
+// Roots always hook under smaller roots (compare-and-swap on the parent
+// word), so every union loop ends and each group's root is its smallest
+// index whatever the order of the links.  Parent words are read with
+// device-scope atomic loads (the L1 of another compute unit may hold a
+// stale copy).
+__device__ inline int fof_load(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int fof_find(int32_t *parent, int x) {
+    int p = fof_load(parent + x);
+    while (p != x) {
+        x = p;
+        p = fof_load(parent + x);
+    }
+    return x;
+}
+__device__ inline void fof_unite(int32_t *parent, int a, int b) {
+    while (true) {
+        a = fof_find(parent, a);
+        b = fof_find(parent, b);
+        if (a == b) return;
+        if (a < b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        // hook root a under the smaller root b
+        if (atomicCAS(parent + a, a, b) == a) return;
+    }
+}
+
+template <typename T> struct FofPass {
+    struct Args {
+        int32_t *parent;  // caller index space (gas, then dm)
+        double b;         // linking length
+    };
+    static constexpr int NJ = 4;  // fx fy fz, caller index of j
+    static constexpr int CAPF = 4;
+    static constexpr int ID = 5;
+    static constexpr bool MASKED = false;
+    __device__ static T range(const Args &a, const TreeView<T> &, int, T, T) {
+        return widen<T>(a.b);
+    }
+    __device__ static T sub_range(const Args &a, const TreeView<T> &, int, T,
+                                  const T *) {
+        return widen<T>(a.b);
+    }
+    struct I {
+        T ex, ey, ez;
+        int c;
+        int32_t *parent;
+        double b2;
+    };
+    struct Tile {
+        __device__ void zero() {}
+    };
+    struct Acc {
+        __device__ void zero() {}
+        __device__ void fold(Tile &) {}
+        __device__ void quad_reduce() {}
+    };
+    __device__ static void load_i(I &is, const Args &a, const TreeView<T> &tv,
+                                  int i, T ex, T ey, T ez, int) {
+        is.ex = ex;
+        is.ey = ey;
+        is.ez = ez;
+        is.c = tv.perm[i];
+        is.parent = a.parent;
+        is.b2 = a.b * a.b;
+    }
+    // the caller index travels with the position (bit copy for float,
+    // exact value for double)
+    static constexpr int NP = 1;
+    __device__ static void fetch_j(T *f, const Args &, const TreeView<T> &tv,
+                                   int j) {
+        f[0] = enc(tv.perm[j]);
+    }
+    __device__ static void store_j(T *d, const T *f, const Args &,
+                                   const TreeView<T> &, int, T fx, T fy, T fz) {
+        d[0] = fx;
+        d[1] = fy;
+        d[2] = fz;
+        d[3] = f[0];
+    }
+    __device__ static T enc(int c) {
+        if constexpr (sizeof(T) == 4) return __int_as_float(c);
+        else return (T)c;
+    }
+    __device__ static int dec(T v) {
+        if constexpr (sizeof(T) == 4) return __float_as_int(v);
+        else return (int)v;
+    }
+    // r^2 in double from the exact float separations, summed in a fixed
+    // order (no contraction): the same decision as a double evaluation of
+    // the minimum-image separations
+    __device__ static double r2_of(const I &is, const T *jd) {
+#pragma clang fp contract(off)
+        const double dx = (double)(is.ex - jd[0]);
+        const double dy = (double)(is.ey - jd[1]);
+        const double dz = (double)(is.ez - jd[2]);
+        const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+        return (xx + yy) + zz;
+    }
+    __device__ static bool test(const I &is, const T *jd, bool self) {
+        return !self && r2_of(is, jd) < is.b2;
+    }
+    __device__ static void pair(Tile &, const I &is, const T *jd, bool self) {
+        if (!self && r2_of(is, jd) < is.b2) fof_unite(is.parent, is.c, dec(jd[3]));
+    }
+    __device__ static void finish(const Acc &, const I &, const Args &,
+                                  const TreeView<T> &, int) {}
+};
+
+__global__ void fof_init_kernel(int32_t *__restrict__ parent, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        parent[i] = (int32_t)i;
+}
+
+// final labels: every index's root (its group's smallest index)
+__global__ void fof_label_kernel(int32_t *__restrict__ parent, int64_t n,
+                                 int64_t n_gas, int32_t *__restrict__ lg,
+                                 int32_t *__restrict__ ld) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = fof_find(parent, (int)i);
+        if (i < n_gas) lg[i] = r;
+        else ld[i - n_gas] = r;
+    }
+}
+
 __global__ void sum_counts_kernel(const int32_t *__restrict__ c, int64_t n,
                                   unsigned long long *__restrict__ total) {
     __shared__ unsigned long long part[256];
@@ -1684,7 +1819,31 @@ int count_impl(crk_ctx *ctx, crk_tree *t, int64_t totals[6]) {
     return CRK_OK;
 }
 
+template <typename T>
+int fof_impl(crk_ctx *ctx, crk_tree *t, double b, int32_t *lg, int32_t *ld) {
+    const int64_t n = t->n;
+    CRK_TRY(t->pf[10].ensure(std::max<int64_t>(n, 1) * 4, ctx->capturing));
+    int32_t *parent = t->pf[10].as<int32_t>();
+    hipLaunchKernelGGL(fof_init_kernel, dim3(grid_for(n)), dim3(256), 0,
+                       ctx->stream, parent, n);
+    CRK_HIP(hipGetLastError());
+    typename FofPass<T>::Args pa{parent, b};
+    CRK_TRY((launch_pair<T, FofPass<T>>(ctx, t,
+                                         tree_view<T>(t, false, all_leaf_count(t)),
+                                         pa, all_bound(ctx, t), -1, false)));
+    hipLaunchKernelGGL(fof_label_kernel, dim3(grid_for(n)), dim3(256), 0,
+                       ctx->stream, parent, n, t->n_gas, lg, ld);
+    CRK_HIP(hipGetLastError());
+    return CRK_OK;
+}
+
 }  // namespace
+
+int fof_groups(crk_ctx *ctx, crk_tree *t, double b, int32_t *labels_gas,
+               int32_t *labels_dm) {
+    if (ctx->precision == CRK_FP64) return fof_impl<double>(ctx, t, b, labels_gas, labels_dm);
+    return fof_impl<float>(ctx, t, b, labels_gas, labels_dm);
+}
 
 int pass_density(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
                  void *rho_tilde) {

@@ -246,6 +246,18 @@ class ShortRangeStep:
         d = np.stack([t[:self.nd].double().cpu().numpy() for t in self.pm_dm])
         return g, d
 
+    def fof(self, b: float):
+        """Friends-of-friends labels (gas, dm) with linking length b over the
+        current tree and lists (crk_fof); numpy int arrays, the smallest
+        combined caller index of each group."""
+        torch, c = self.torch, self.ctx
+        with torch.cuda.stream(c.stream):
+            lg = torch.zeros(max(self.ng, 1), dtype=torch.int32, device="cuda")
+            ld = torch.zeros(max(self.nd, 1), dtype=torch.int32, device="cuda")
+        c.fof(self.tree, b, lg if self.ng else None, ld if self.nd else None)
+        c.stream.synchronize()
+        return lg[:self.ng].cpu().numpy(), ld[:self.nd].cpu().numpy()
+
     def capture(self, integrate: bool = True):
         """Runs the step once eagerly (sizes), then captures it in a graph."""
         self.run(integrate=integrate)
