@@ -294,7 +294,12 @@ def main():
                   sub_sweep=args.sub_sweep, tree_lds=args.tree_lds)
 
     if args.fof_only:
-        print(json.dumps(measure_fof(wl, tuning, 5, log)), flush=True)
+        out = measure_fof(wl, tuning, 5, log)
+        half = n // 2
+        out["clustered"] = measure_fof(
+            workloads.random_uniform(half, n - half, 77, clustered=True,
+                                     h_rule="global"), tuning, 5, log)
+        print(json.dumps(out), flush=True)
         return
     if args.pm_only:
         print(json.dumps(measure_pm(wl, 10, log)), flush=True)
@@ -391,6 +396,14 @@ def main():
     if not args.no_fof:
         st.close()
         fof = measure_fof(wl, tuning, 5, log)
+        # the Zel'dovich box is nearly uniform at this linking length (no
+        # friends at all): a clustered set of the same size exercises the
+        # unions as well
+        log("[bench] fof on a clustered set of the same size")
+        half = n // 2
+        fof["clustered"] = measure_fof(
+            workloads.random_uniform(half, n - half, 77, clustered=True,
+                                     h_rule="global"), tuning, 5, log)
 
     # ---------------- CPU baseline: the FP64 oracle ---------------------------
     cpu = None
