@@ -374,7 +374,7 @@ def _wrap(x):
 
 
 def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
-                  counts=None, forces_at="float64"):
+                  counts=None, forces_at="float64", pm_mesh=None):
     """One interval dt of hierarchical block steps (kick-drift-kick) with
     2^max_level substeps of dt / 2^max_level.  A particle of bin b takes
     steps tau_b = dt / 2^b, starting at substeps s with s % 2^(L-b) == 0
@@ -393,9 +393,13 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
     float32 roundings of the double positions (not wrapped inside the
     interval), velocities and energies: the mixed-precision split of
     Sec. IV-A, where the short-range solver works on float32 copies of a
-    double state.  Returns the final x, v, u (float64, (3, n) / n per
-    species) and the state of the last evaluation.  counts, if a dict,
-    receives the number of evaluations of every particle."""
+    double state.  pm_mesh (single box): the long-range mesh force brackets
+    the interval, a half-kick v += a_long dt / 2 of every particle before
+    the first substep (positions at the start) and after the last one
+    (positions at the end, wrapped), as a long PM step encloses the short
+    subcycles.  Returns the final x, v, u (float64, (3, n) / n per species)
+    and the state of the last evaluation.  counts, if a dict, receives the
+    number of evaluations of every particle."""
     f32 = forces_at == "float32"
 
     def q(a):
@@ -462,6 +466,17 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
         u[act_g] += st["dudt"][act_g] * tg
         vd[:, act_d] += st["a_grav_dm"][:, act_d] * td
 
+    def long_kick():
+        X = q(np.concatenate([xg, xd], axis=1))
+        X = _wrap(X)
+        M = np.concatenate([g.m, d.m])
+        a = pm_long_range(X[0], X[1], X[2], M, pm_mesh, float(wl.r_c[0]),
+                          params["G"])
+        vg[:] += a[:, :ng] * (0.5 * dt)
+        vd[:] += a[:, ng:] * (0.5 * dt)
+
+    if pm_mesh:
+        long_kick()
     evaluate(np.ones(ng, bool), np.ones(nd, bool))
     delta = dt * 2.0 ** (-L)
     for s in range(2 ** L):
@@ -474,6 +489,10 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
         end_d = ((s + 1) % (2 ** (L - bd))) == 0
         evaluate(end_g, end_d)
         kick(end_g, end_d)
+    if pm_mesh:
+        xg[:] = _wrap(xg)
+        xd[:] = _wrap(xd)
+        long_kick()
     if counts is not None:
         counts["gas"] = ev_g
         counts["dm"] = ev_d

@@ -182,16 +182,36 @@ class ShortRangeStep:
         c.stream.synchronize()
         return (bg[:self.ng].cpu().numpy(), bd[:self.nd].cpu().numpy())
 
-    def substep_cycle(self, dt, max_level):
+    def _long_kick(self, dt, n_mesh):
+        """v += a_long dt / 2 for every particle (crk_pm_gravity, then
+        crk_kick with one level: every particle selected, tau = dt)."""
+        torch, c = self.torch, self.ctx
+        self.pm_gravity(n_mesh)
+        if getattr(self, "_zero_bins", None) is None:
+            with torch.cuda.stream(c.stream):
+                self._zero_bins = torch.zeros(max(self.ng, self.nd, 1),
+                                              dtype=torch.int32, device="cuda")
+        if self.ng:
+            c.kick(self.ng, dt, 0, 0, 0, self._zero_bins, self.gv64, None,
+                   self.pm_gas, None, None, (self.gvx, self.gvy, self.gvz), None)
+        if self.nd:
+            c.kick(self.nd, dt, 0, 0, 0, self._zero_bins, self.dv64, None,
+                   self.pm_dm, None, None, (self.dvx, self.dvy, self.dvz), None)
+
+    def substep_cycle(self, dt, max_level, pm_mesh: int | None = None):
         """One interval dt of hierarchical block steps with 2^max_level
         substeps on one tree (built here at the start): every particle is
         evaluated first; each substep kicks the particles starting a step,
         drifts all, refits the leaf boxes, rebuilds the lists, evaluates the
         particles ending a step (active leaves only) and kicks them; the
         positions are wrapped at the end.  Bins come from set_bins or
-        timestep_bins."""
+        timestep_bins.  With pm_mesh (single box), the long-range mesh
+        force brackets the interval: a half-kick of every particle before
+        the first substep and after the last one (positions wrapped)."""
         c, t, wl = self.ctx, self.tree, self.wl
         L = int(max_level)
+        if pm_mesh:
+            self._long_kick(dt, pm_mesh)
         c.build_tree(t, wl.gas_off, wl.dm_off, wl.r_c, wl.eps, self.h_max,
                      self.gx, self.gy, self.gz, self.gh, self.dx, self.dy,
                      self.dz)
@@ -207,6 +227,8 @@ class ShortRangeStep:
             self._kick(dt, L, s, 1)
         c.tree_set_active(t, None, None, 0, -1)
         self._drift(0.0, True)
+        if pm_mesh:
+            self._long_kick(dt, pm_mesh)
 
     def state(self) -> dict:
         """The double-precision state (numpy, (3, n) / n)."""

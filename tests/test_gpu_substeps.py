@@ -232,6 +232,31 @@ def test_substep_cycle_matches_oracle(orc, step_cls, precision, clustered, L,
     st.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_cycle_with_long_range_matches_oracle(orc, step_cls, precision):
+    """The cycle bracketed by long-range mesh half-kicks (the whole force
+    split: mesh long range, subcycled short range)."""
+    print(f"case cycle + mesh long range {precision}", flush=True)
+    wl = W.random_uniform(12000, 10000, 505, n_ngb=48.0, h_spread=0.15)
+    rng = np.random.default_rng(505)
+    L = 2
+    bg = rng.integers(0, L + 1, wl.gas.n)
+    bd = rng.integers(0, L + 1, wl.dm.n)
+    n_mesh = 2 * int(np.ceil(3.0 / float(wl.r_c[0])))
+    dt = 0.02
+    st = step_cls(wl, precision)
+    st.set_bins(bg, bd)
+    st.substep_cycle(dt, L, pm_mesh=n_mesh)
+    got = st.state()
+    ref = orc.substep_cycle(wl, bg, bd, dt, L, pm_mesh=n_mesh, forces_at=(
+        "float32" if precision == "fp32" else "float64"))
+    errs = _cycle_errors(wl, got, ref)
+    print(f"mesh {n_mesh}", {k: f"{v:.2e}" for k, v in errs.items()},
+          flush=True)
+    tol = FP32_TOL if precision == "fp32" else FP64_TOL
+    assert all(v <= tol for v in errs.values()), errs
+
+
 def test_cycle_bins_from_accelerations(orc, step_cls):
     """Bins from crk_timestep_bins on the step's own accelerations (gas:
     Courant and acceleration; dm: acceleration), then a cycle: the bins

@@ -214,3 +214,54 @@ def test_cycle_evaluation_counts(orc):
     orc.substep_cycle(wl, bg, bd, 0.001, 2, counts=counts)
     assert np.array_equal(counts["gas"], 1 + 2 ** bg)
     assert np.array_equal(counts["dm"], 1 + 2 ** bd)
+
+
+def test_cycle_with_long_range_is_split_leapfrog(orc):
+    """One level (L = 0) with the long-range mesh force coupled: the cycle
+    is the split composition long half-kick, short-range kick-drift-kick of
+    dt (forces evaluated after the long kick: the viscosity sees the kicked
+    velocities), long half-kick at the new positions."""
+    wl = wl_mod.jittered_lattice(5, seed=14)
+    n_mesh = 2 * int(np.ceil(3.0 / float(wl.r_c[0])))
+    dt = 0.004
+    out = orc.substep_cycle(wl, np.zeros(wl.gas.n, np.int64),
+                            np.zeros(wl.dm.n, np.int64), dt, 0,
+                            pm_mesh=n_mesh)
+    g, d = wl.gas, wl.dm
+    xg = np.array([g.x, g.y, g.z], np.float64)
+    vg = np.array([g.vx, g.vy, g.vz], np.float64)
+    xd = np.array([d.x, d.y, d.z], np.float64)
+    vd = np.array([d.vx, d.vy, d.vz], np.float64)
+    u = np.asarray(g.u, np.float64).copy()
+
+    def long_kick():
+        X = np.concatenate([_wrap(xg), _wrap(xd)], axis=1)
+        a = orc.pm_long_range(X[0], X[1], X[2], np.concatenate([g.m, d.m]),
+                              n_mesh, float(wl.r_c[0]))
+        vg[:] += 0.5 * dt * a[:, :g.n]
+        vd[:] += 0.5 * dt * a[:, g.n:]
+
+    def short():
+        return orc.step(_f64_copy(wl, _wrap(xg), vg, u, _wrap(xd), vd))
+
+    long_kick()
+    s = short()
+    vg += 0.5 * dt * (s["a_grav_gas"] + s["a_hydro"])
+    vd += 0.5 * dt * s["a_grav_dm"]
+    u += 0.5 * dt * s["dudt"]
+    xg += dt * vg
+    xd += dt * vd
+    s = short()
+    vg += 0.5 * dt * (s["a_grav_gas"] + s["a_hydro"])
+    vd += 0.5 * dt * s["a_grav_dm"]
+    u += 0.5 * dt * s["dudt"]
+    long_kick()
+    # the long-range kicks moved velocities noticeably
+    no_long = orc.substep_cycle(wl, np.zeros(wl.gas.n, np.int64),
+                                np.zeros(wl.dm.n, np.int64), dt, 0)
+    assert np.max(np.abs(out["vd"] - no_long["vd"])) > 1e-4
+    assert _periodic_close(out["xg"], _wrap(xg), 1e-13)
+    assert _periodic_close(out["xd"], _wrap(xd), 1e-13)
+    assert np.allclose(out["vg"], vg, rtol=0, atol=1e-11)
+    assert np.allclose(out["vd"], vd, rtol=0, atol=1e-11)
+    assert np.allclose(out["u"], u, rtol=1e-12, atol=0)
