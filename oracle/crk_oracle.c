@@ -23,17 +23,23 @@
  *     coefficients A, B, grad A, grad B that make the corrected kernel
  *     A(1 + B.x)W reproduce constant and linear fields exactly (CRKSPH,
  *     Sec. IV-A), then rho = A (rho~ + B.M1), ideal-gas P and c;
+ *   - orc_velocity_gradient: the corrected-kernel gradient of the velocity
+ *     field (exact for linear fields);
  *   - orc_hydro: the antisymmetric CRKSPH pair force F_ij = -F_ji (Eq. (2)
  *     and its (anti)symmetry, Sec. IV-B.2) and the work-split du/dt, which
- *     conserve momentum and energy (Sec. IV-A);
+ *     conserve momentum and energy (Sec. IV-A); optionally with the
+ *     viscosity acting on a limited linear reconstruction of both velocities
+ *     at the pair midpoint (CRKSPH's viscosity, named in Sec. IV-A);
  *   - orc_gravity: the short-range remainder of Newtonian gravity inside the
  *     handover scale r_c (Sec. IV-A): Plummer-softened 1/r^2 minus the force
  *     between two S2 clouds of diameter r_c (Hockney & Eastwood), zero
  *     beyond r_c.
  * Parity-pinned by the tests under tests/ (normalisation, reproducing
  * conditions, lattice symmetry, conservation, closed forms, quadrature,
- * brute force versus the tree).  The viscosity form and constants are a
- * reading: parity unpinned beyond conservation and Galilean invariance.
+ * brute force versus the tree, exact gradients of linear fields).  The
+ * viscosity form and constants are a reading: pinned only by conservation,
+ * Galilean invariance and the cases where the reconstruction removes the
+ * viscosity of a linear flow or reduces to the plain form.
  */
 #include <math.h>
 #include <stdint.h>
@@ -640,12 +646,74 @@ static void grad_rk(const double y[3], double hk, double Ak, const double *Bk,
     }
 }
 
+/* Velocity gradient with the corrected kernel (the CRKSPH gradient of a
+ * field, Sec. IV-A):
+ *   dv[a][b]_i = sum_j V_j (v_j^a - v_i^a) g_i^b(x_ij)
+ * over gas j with r_ij < 2 h_i (j = i adds zero).  The corrected kernel
+ * reproduces constants, so sum_j V_j g_i(x_ij) = 0 and this is the gradient
+ * of the reproduced field; a linear field comes back exactly. */
+int orc_velocity_gradient(int64_t n, const double *x, const double *y,
+                          const double *z, const double *vx, const double *vy,
+                          const double *vz, const double *h, const double *V,
+                          const double *A, const double *B,
+                          const double *gradA, const double *gradB,
+                          int64_t nt, const int64_t *targets, int brute,
+                          double *dv)
+{
+    search_t cl;
+    if (search_build(&cl, n, x, y, z, h, brute)) return -1;
+#pragma omp parallel
+    {
+    nbr_t nb = {0, 0, NULL, NULL, 0};
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = target_index(targets, k);
+        double hi = h[i];
+        double D[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        find_neighbours(&cl, x, y, z, h, x[i], y[i], z[i], 2.0 * hi, 0.0, &nb);
+        for (int64_t q = 0; q < nb.n; ++q) {
+            int64_t j = nb.r[q].j;
+            double xij[3] = {nb.r[q].dx, nb.r[q].dy, nb.r[q].dz};
+            double gi[3];
+            grad_rk(xij, hi, A[i], &B[3 * i], &gradA[3 * i], &gradB[9 * i], gi);
+            double dvj[3] = {vx[j] - vx[i], vy[j] - vy[i], vz[j] - vz[i]};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) D[3 * a + b] += V[j] * dvj[a] * gi[b];
+        }
+        for (int e = 0; e < 9; ++e) dv[9 * k + e] = D[e];
+    }
+    nbr_free(&nb);
+    }
+    search_free(&cl);
+    return 0;
+}
+
+/* Limiter of the linear velocity reconstruction for the pair (i, j), with
+ * s_k = x_ij . (dv_k x_ij) the velocity gradient of each side projected on
+ * the pair axis: van Leer's limiter of their ratio, 4 s_i s_j / (s_i + s_j)^2
+ * when they agree in sign, else 0 (symmetric in i and j); a close pair,
+ * eta = r / max(h_i, h_j) below eta_crit, is damped further by
+ * exp(-((eta - eta_crit) / eta_fold)^2). */
+static double recon_limiter(double si, double sj, double r, double hmax,
+                            double eta_crit, double eta_fold)
+{
+    double phi = 0.0;
+    if (si * sj > 0.0) phi = 4.0 * si * sj / ((si + sj) * (si + sj));
+    double eta = r / hmax;
+    if (eta < eta_crit) {
+        double t = (eta - eta_crit) / eta_fold;
+        phi *= exp(-t * t);
+    }
+    return phi;
+}
+
 int orc_hydro(int64_t n, const double *x, const double *y, const double *z,
               const double *vx, const double *vy, const double *vz,
               const double *h, const double *m, const double *V,
               const double *rho, const double *P, const double *cs,
               const double *A, const double *B, const double *gradA,
               const double *gradB, double Cl, double Cq, double epsQ,
+              const double *dv, double eta_crit, double eta_fold,
               int64_t nt, const int64_t *targets, int brute, double *ax,
               double *ay, double *az, double *dudt)
 {
@@ -672,7 +740,26 @@ int orc_hydro(int64_t n, const double *x, const double *y, const double *z,
                 grad_rk(xij, hi, A[i], &B[3 * i], &gradA[3 * i], &gradB[9 * i], gi);
                 grad_rk(xji, h[j], A[j], &B[3 * j], &gradA[3 * j], &gradB[9 * j], gj);
                 double vij[3] = {vx[i] - vx[j], vy[i] - vy[j], vz[i] - vz[j]};
-                double vdx = vij[0] * dx + vij[1] * dy + vij[2] * dz;
+                /* velocity difference seen by the viscosity: the actual one,
+                 * or (dv given) both sides' velocities extrapolated linearly
+                 * to the pair midpoint, limited */
+                double vt[3] = {vij[0], vij[1], vij[2]};
+                if (dv) {
+                    const double *Di = &dv[9 * i], *Dj = &dv[9 * j];
+                    double ei[3], ej[3];
+                    for (int a = 0; a < 3; ++a) {
+                        ei[a] = Di[3 * a] * dx + Di[3 * a + 1] * dy + Di[3 * a + 2] * dz;
+                        ej[a] = Dj[3 * a] * dx + Dj[3 * a + 1] * dy + Dj[3 * a + 2] * dz;
+                    }
+                    double si = ei[0] * dx + ei[1] * dy + ei[2] * dz;
+                    double sj = ej[0] * dx + ej[1] * dy + ej[2] * dz;
+                    double phi = recon_limiter(si, sj, sqrt(r2),
+                                               hi > h[j] ? hi : h[j],
+                                               eta_crit, eta_fold);
+                    for (int a = 0; a < 3; ++a)
+                        vt[a] = vij[a] - 0.5 * phi * (ei[a] + ej[a]);
+                }
+                double vdx = vt[0] * dx + vt[1] * dy + vt[2] * dz;
                 double mui = hi * vdx / (r2 + epsQ * hi * hi);
                 double muj = h[j] * vdx / (r2 + epsQ * h[j] * h[j]);
                 if (mui > 0.0) mui = 0.0;

@@ -23,6 +23,12 @@ _LIB = _HERE / "libcrk_oracle.so"
 # gravitational constant G = 1.
 PARAMS = dict(gamma=5.0 / 3.0, Cl=1.0, Cq=2.0, epsQ=0.01, G=1.0)
 
+# Limiter of the reconstructed viscosity (a reading; CRKSPH is named in
+# Sec. IV-A without its constants): close pairs, r / max(h_i, h_j) below
+# eta_crit (about the mean spacing at ~64 neighbours inside 2h), are damped
+# with a Gaussian of width eta_fold.
+RECON = dict(eta_crit=0.8, eta_fold=0.2)
+
 _lib = None
 
 
@@ -149,23 +155,50 @@ def coefficients(x, y, z, h, m, V, u, gamma=PARAMS["gamma"], targets=None,
     return out
 
 
+def velocity_gradient(x, y, z, vx, vy, vz, h, V, A, B, gradA, gradB,
+                      targets=None, brute=False):
+    """Corrected-kernel velocity gradient at the targets, (nt, 3, 3) with
+    dv[:, a, b] = d v^a / d x^b."""
+    lib = _load()
+    arrs = [_d(a) for a in (x, y, z, vx, vy, vz, h, V, A)]
+    B = _d(np.reshape(B, (-1, 3)))
+    gradA = _d(np.reshape(gradA, (-1, 3)))
+    gradB = _d(np.reshape(gradB, (-1, 3, 3)))
+    n = arrs[0].shape[0]
+    nt, t = _targets(targets, n)
+    dv = np.zeros((nt, 3, 3))
+    if lib.orc_velocity_gradient(_i64(n), *[_p(a) for a in arrs], _p(B),
+                                 _p(gradA), _p(gradB), _i64(nt), _p(t),
+                                 ctypes.c_int(int(brute)), _p(dv)):
+        raise MemoryError("oracle velocity gradient failed")
+    return dv
+
+
 def hydro(x, y, z, vx, vy, vz, h, m, V, rho, P, cs, A, B, gradA, gradB,
           Cl=PARAMS["Cl"], Cq=PARAMS["Cq"], epsQ=PARAMS["epsQ"],
-          targets=None, brute=False):
-    """a_hydro (3 arrays) and du/dt at the targets."""
+          targets=None, brute=False, dv=None, eta_crit=RECON["eta_crit"],
+          eta_fold=RECON["eta_fold"]):
+    """a_hydro (3 arrays) and du/dt at the targets.  With ``dv`` (the
+    velocity gradient of every particle, (n, 3, 3)) the viscosity acts on the
+    limited linear reconstruction of the two velocities at the pair
+    midpoint."""
     lib = _load()
     arrs = [_d(a) for a in (x, y, z, vx, vy, vz, h, m, V, rho, P, cs, A)]
     B = _d(np.reshape(B, (-1, 3)))
     gradA = _d(np.reshape(gradA, (-1, 3)))
     gradB = _d(np.reshape(gradB, (-1, 3, 3)))
     n = arrs[0].shape[0]
+    if dv is not None:
+        dv = _d(np.reshape(dv, (n, 3, 3)))
     nt, t = _targets(targets, n)
     ax, ay, az, du = (np.zeros(nt) for _ in range(4))
     if lib.orc_hydro(_i64(n), *[_p(a) for a in arrs], _p(B), _p(gradA),
                      _p(gradB), ctypes.c_double(Cl), ctypes.c_double(Cq),
-                     ctypes.c_double(epsQ), _i64(nt), _p(t),
-                     ctypes.c_int(int(brute)), _p(ax), _p(ay), _p(az),
-                     _p(du)):
+                     ctypes.c_double(epsQ),
+                     _p(dv) if dv is not None else None,
+                     ctypes.c_double(eta_crit), ctypes.c_double(eta_fold),
+                     _i64(nt), _p(t), ctypes.c_int(int(brute)), _p(ax),
+                     _p(ay), _p(az), _p(du)):
         raise MemoryError("oracle hydro failed")
     return ax, ay, az, du
 
@@ -213,9 +246,12 @@ def _box_slices(wl):
 
 
 def step(wl, params=PARAMS, brute=False, passes=("density", "coefficients",
-                                                   "hydro", "gravity")):
+                                                   "hydro", "gravity"),
+         recon=False):
     """Every output of the short-range step for every particle, box by box,
-    each pass fed with the previous passes' FP64 results."""
+    each pass fed with the previous passes' FP64 results.  With ``recon``
+    the velocity gradient is computed after the coefficients and the
+    viscosity acts on the limited midpoint reconstruction."""
     g, d = wl.gas, wl.dm
     ng, nd = g.n, d.n
     out = {k: np.zeros(ng) for k in ("V", "rho_tilde", "A", "rho", "P", "cs",
@@ -223,7 +259,7 @@ def step(wl, params=PARAMS, brute=False, passes=("density", "coefficients",
     out.update(B=np.zeros((ng, 3)), gradA=np.zeros((ng, 3)),
                gradB=np.zeros((ng, 3, 3)), a_hydro=np.zeros((3, ng)),
                a_grav_gas=np.zeros((3, ng)), a_grav_dm=np.zeros((3, nd)),
-               degenerate=np.zeros(ng, np.int32))
+               degenerate=np.zeros(ng, np.int32), dv=np.zeros((ng, 3, 3)))
     for b, gs, ds in _box_slices(wl):
         if "density" in passes and gs.stop > gs.start:
             V, rt = density(g.x[gs], g.y[gs], g.z[gs], g.h[gs], g.m[gs],
@@ -236,13 +272,18 @@ def step(wl, params=PARAMS, brute=False, passes=("density", "coefficients",
             for k in ("A", "B", "gradA", "gradB", "rho", "P", "cs",
                       "degenerate"):
                 out[k][gs] = c[k]
+        if recon and gs.stop > gs.start:
+            out["dv"][gs] = velocity_gradient(
+                g.x[gs], g.y[gs], g.z[gs], g.vx[gs], g.vy[gs], g.vz[gs],
+                g.h[gs], out["V"][gs], out["A"][gs], out["B"][gs],
+                out["gradA"][gs], out["gradB"][gs], brute=brute)
         if "hydro" in passes and gs.stop > gs.start:
             ax, ay, az, du = hydro(
                 g.x[gs], g.y[gs], g.z[gs], g.vx[gs], g.vy[gs], g.vz[gs],
                 g.h[gs], g.m[gs], out["V"][gs], out["rho"][gs], out["P"][gs],
                 out["cs"][gs], out["A"][gs], out["B"][gs], out["gradA"][gs],
                 out["gradB"][gs], params["Cl"], params["Cq"], params["epsQ"],
-                brute=brute)
+                brute=brute, dv=out["dv"][gs] if recon else None)
             out["a_hydro"][:, gs] = (ax, ay, az)
             out["dudt"][gs] = du
         if "gravity" in passes:
@@ -260,11 +301,12 @@ def step(wl, params=PARAMS, brute=False, passes=("density", "coefficients",
     return out
 
 
-def step_sampled(wl, gas_targets, dm_targets, params=PARAMS):
+def step_sampled(wl, gas_targets, dm_targets, params=PARAMS, recon=False):
     """The step's outputs at sampled particles only (global indices into the
     gas and dm arrays).  Each sampled gas particle pulls in the
-    neighbourhoods its outputs depend on: coefficients at its force
-    neighbours, and volumes at their gather neighbours."""
+    neighbourhoods its outputs depend on: coefficients (and, with
+    ``recon``, velocity gradients) at its force neighbours, and volumes at
+    their gather neighbours."""
     g, d = wl.gas, wl.dm
     gas_targets = np.asarray(gas_targets, np.int64)
     dm_targets = np.asarray(dm_targets, np.int64)
@@ -275,7 +317,8 @@ def step_sampled(wl, gas_targets, dm_targets, params=PARAMS):
                dudt=np.zeros(nt), B=np.zeros((nt, 3)), gradA=np.zeros((nt, 3)),
                gradB=np.zeros((nt, 3, 3)), a_hydro=np.zeros((3, nt)),
                a_grav_gas=np.zeros((3, nt)),
-               a_grav_dm=np.zeros((3, dm_targets.shape[0])))
+               a_grav_dm=np.zeros((3, dm_targets.shape[0])),
+               dv=np.zeros((nt, 3, 3)))
     for b, gs, ds in _box_slices(wl):
         sel = np.nonzero((gas_targets >= gs.start) & (gas_targets < gs.stop))[0]
         dsel = np.nonzero((dm_targets >= ds.start) & (dm_targets < ds.stop))[0]
@@ -302,11 +345,21 @@ def step_sampled(wl, gas_targets, dm_targets, params=PARAMS):
             for k, shp in (("B", (3,)), ("gradA", (3,)), ("gradB", (3, 3))):
                 full[k] = np.full((n,) + shp, np.nan)
                 full[k][S1] = c[k]
+            dvf = None
+            if recon:
+                # gradients at the force neighbours: their own coefficients
+                # and the volumes of their gather neighbours (inside S2)
+                dvf = np.full((n, 3, 3), np.nan)
+                dvf[S1] = velocity_gradient(
+                    gx, gy, gz, g.vx[gs], g.vy[gs], g.vz[gs], gh, V,
+                    full["A"], full["B"], full["gradA"], full["gradB"],
+                    targets=S1)
+                res["dv"][sel] = dvf[T]
             ax, ay, az, du = hydro(
                 gx, gy, gz, g.vx[gs], g.vy[gs], g.vz[gs], gh, gm, V,
                 full["rho"], full["P"], full["cs"], full["A"], full["B"],
                 full["gradA"], full["gradB"], params["Cl"], params["Cq"],
-                params["epsQ"], targets=T)
+                params["epsQ"], targets=T, dv=dvf)
             res["V"][sel], res["rho_tilde"][sel] = V[T], rt[T]
             for k in ("A", "rho", "P", "cs", "B", "gradA", "gradB"):
                 res[k][sel] = full[k][T]
