@@ -33,6 +33,9 @@ if ROOT not in sys.path:
 # gravity: 33 for r < r_c/2, 39 beyond; 38 is the uniform-density mean.
 FLOP_PER_PAIR = {"density": 20, "coefficients": 89, "hydro": 178,
                  "gravity": 38}
+# with the reconstructed viscosity: the gradient pass (the corrected-kernel
+# gradient and nine products per pair) and the hydro pass with the limiter
+RECON_FLOP_PER_PAIR = {"velocity_gradient": 86, "hydro": 220}
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector, published (packed)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 PASS_TYPES = {"density": "DensityPass", "coefficients": "CoeffPass",
@@ -43,18 +46,21 @@ def kernel_name(p: str, tuning: dict) -> str:
     """The float32 kernel a pass launches under a tuning (as rocprofv3 names
     it, namespaces dropped)."""
     t = PASS_TYPES[p]
+    # (the hydro pass is a template on the reconstruction; the step's plain
+    # form is the "false" instance)
+    t = t + "<float, false>" if p == "hydro" else t + "<float>"
     L = tuning.get("leaf_max", 64)
     if tuning.get("grid_mult", 0) > 0:
         b = 64 if L <= 64 else (128 if L <= 128 else 256)
-        return f"pair_kernel_queue<float, {t}<float>, {b}>"
+        return f"pair_kernel_queue<float, {t}, {b}>"
     if L <= 64 and (tuning.get("walk_mask", 0) >> list(PASS_TYPES).index(p)) & 1:
-        return f"pair_kernel<float, {t}<float>, 64, 1>"
+        return f"pair_kernel<float, {t}, 64, 1>"
     if L <= 64 and tuning.get("sub_sweep", 2) == 2:
-        return f"pair_kernel_split<float, {t}<float> >"
+        return f"pair_kernel_split<float, {t} >"
     if L <= 64 and tuning.get("sub_sweep", 2) == 1:
-        return f"pair_kernel<float, {t}<float>, 64, 2>"
+        return f"pair_kernel<float, {t}, 64, 2>"
     b = 64 if L <= 64 else (128 if L <= 128 else 256)
-    return f"pair_kernel<float, {t}<float>, {b}, 0>"
+    return f"pair_kernel<float, {t}, {b}, 0>"
 
 
 def log(*a):
@@ -163,6 +169,49 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
             "launch": "eager"}
 
 
+def measure_recon(wl, tuning, steps, warmup, gather_pairs, hydro_pairs,
+                  log):
+    """The whole step with the viscosity on the limited midpoint
+    reconstruction: the velocity-gradient pass added before the hydro
+    forces, which then read the gradients of both sides.  Per-kernel HIP
+    event times over eager steps, then graph replays of the step."""
+    import torch
+    from paper_2510_03557_amd.step import ShortRangeStep
+    n = wl.n_total
+    log("[bench] step with the reconstructed viscosity")
+    st = ShortRangeStep(wl, precision="fp32", tuning=tuning, dt=1e-5,
+                        recon=True)
+    try:
+        st.run(integrate=True)
+        st.sync()
+        st.ctx.timing(True)
+        n_eager = max(steps // 4, 3)
+        for _ in range(n_eager):
+            st.run(integrate=True)
+        pass_ms, kern_ms, launches = st.ctx.pass_times()
+        st.ctx.timing(False)
+        st.sync()
+        st.capture(integrate=True)
+        sec = time_steps(st.replay, lambda: (torch.cuda.synchronize(),
+                                             st.ctx.stream.synchronize()),
+                         steps, warmup)
+        st.sync()
+    finally:
+        st.close()
+    kern = {}
+    for p, pairs in (("velocity_gradient", gather_pairs),
+                     ("hydro", hydro_pairs)):
+        avg = kern_ms[p] / max(launches[p], 1)
+        kern[p] = {"avg_ms": round(avg, 4), "pairs": pairs,
+                   "flop_per_pair": RECON_FLOP_PER_PAIR[p],
+                   "tflops": round(pairs * RECON_FLOP_PER_PAIR[p]
+                                   / (avg * 1e-3) / 1e12, 3)}
+    return {"value": n / sec, "ms_per_step": sec * 1e3, "launch": "hip_graph",
+            "eta_crit": 0.8, "eta_fold": 0.2,
+            "pass_ms": {k: round(v / n_eager, 4) for k, v in pass_ms.items()},
+            "kernels": kern}
+
+
 def measure_pm(wl, reps, log):
     """Long-range mesh gravity of the whole box (crk_pm_gravity) on the mesh
     with r_c = 6 cells, float32; HIP-event time of one call on the
@@ -255,6 +304,8 @@ def main():
     ap.add_argument("--fof-only", action="store_true",
                     help="time only the friends-of-friends groups and print "
                          "their JSON object")
+    ap.add_argument("--no-recon", action="store_true",
+                    help="skip the step with the reconstructed viscosity")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times "
                          "(reference kernel for scaling HBM byte counters)")
@@ -380,6 +431,13 @@ def main():
                 "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
                 "frac_unpacked": round(ach / PEAK_FP32_UNPACKED_TFLOPS, 4)}
 
+    # ---------------- the step with the reconstructed viscosity -------------
+    recon = None
+    if not args.no_recon:
+        st.close()
+        recon = measure_recon(wl, tuning, args.steps, args.warmup, pairs[0],
+                              pairs[1], log)
+
     # ---------------- hierarchical time steps ---------------------------------
     cycle = None
     if args.substep_levels > 0:
@@ -454,6 +512,7 @@ def main():
         "kernels": kern,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "recon_viscosity": recon,
         "substep_cycle": cycle,
         "pm_long_range": pm,
         "fof": fof,

@@ -217,6 +217,44 @@ int crk_hydro_forces(crk_ctx *ctx, crk_tree *tree, const void *m,
                      const void *gradA, const void *gradB, void *ax,
                      void *ay, void *az, void *dudt);
 
+/* Velocity gradient with the corrected kernel (the CRKSPH gradient of a
+ * field, Sec. IV-A; the input of the reconstructed viscosity below):
+ *   dv[a][b]_i = sum_j V_j (v_j^a - v_i^a) g_i(x_ij)_b
+ * over gas j with r_ij < 2 h_i, g_i the corrected-kernel gradient at h_i
+ * (as in crk_hydro_forces).  The corrected kernel reproduces linear fields,
+ * so a linear velocity field returns its gradient exactly wherever the
+ * moment matrix is regular.
+ * Inputs (n_gas each): vx, vy, vz, V, A; B, gradA (3 planes), gradB
+ * (9 planes), from crk_density and crk_coefficients.  Output dv: 9 planes
+ * of n_gas, plane 3a + b = d v^a / d x^b.  Timed as index 7 of
+ * crk_pass_times. */
+int crk_velocity_gradient(crk_ctx *ctx, crk_tree *tree, const void *vx,
+                          const void *vy, const void *vz, const void *V,
+                          const void *A, const void *B, const void *gradA,
+                          const void *gradB, void *dv);
+
+/* crk_hydro_forces with the viscosity acting on a limited linear
+ * reconstruction of the velocities at the pair midpoint (CRKSPH's
+ * viscosity, Sec. IV-A; the limiter is a reading):
+ *   v~_ij = v_ij - phi_ij/2 (dv_i + dv_j) x_ij,
+ *   phi_ij = 4 s_i s_j / (s_i + s_j)^2 if s_i s_j > 0 else 0,
+ *   s_k = x_ij . dv_k x_ij  (van Leer's limiter of the ratio s_i / s_j),
+ * times exp(-((eta - eta_crit) / eta_fold)^2) when
+ * eta = r_ij / max(h_i, h_j) < eta_crit; mu_ij takes v~_ij in place of
+ * v_ij.  phi is symmetric in the pair, so F_ij = -F_ji still; du/dt keeps
+ * the actual v_ij, so the energy rate is conserved.  A linear flow whose
+ * pairs all lie beyond eta_crit gets no viscous force.
+ * Arguments as crk_hydro_forces, plus dv (9 planes from
+ * crk_velocity_gradient), eta_crit >= 0 and eta_fold > 0 (finite, else
+ * CRK_EINVAL; usual values 0.8 and 0.2). */
+int crk_hydro_forces_limited(crk_ctx *ctx, crk_tree *tree, const void *m,
+                             const void *vx, const void *vy, const void *vz,
+                             const void *V, const void *rho, const void *P,
+                             const void *cs, const void *A, const void *B,
+                             const void *gradA, const void *gradB,
+                             const void *dv, double eta_crit, double eta_fold,
+                             void *ax, void *ay, void *az, void *dudt);
+
 /* Short-range gravity inside the handover scale (Sec. IV-A, with the
  * long-range part left to a spectral particle-mesh solver):
  *   a_i = -G sum_{j != i, r_ij < r_c} m_j g(r_ij) x_ij / r_ij,
@@ -398,12 +436,13 @@ int crk_tree_free(crk_tree *tree);
  * enable = 1 starts recording; crk_pass_times waits for the stream and
  * returns, per operation since the last query, the summed milliseconds of
  * the whole call (pass_ms) and of its main kernel alone (kernel_ms: the pair
- * kernel of the four passes and the integrate kernel), and the number of
+ * kernel of each pass and the integrate kernel), and the number of
  * main-kernel launches.  Index order: 0 build_tree, 1 lists, 2 density,
- * 3 coefficients, 4 hydro, 5 gravity, 6 integrate.  Any array may be NULL. */
+ * 3 coefficients, 4 hydro, 5 gravity, 6 integrate, 7 velocity gradient.
+ * Any array may be NULL. */
 int crk_timing_enable(crk_ctx *ctx, int enable);
-int crk_pass_times(crk_ctx *ctx, double pass_ms[7], double kernel_ms[7],
-                   int64_t launches[7]);
+int crk_pass_times(crk_ctx *ctx, double pass_ms[8], double kernel_ms[8],
+                   int64_t launches[8]);
 
 #ifdef __cplusplus
 }

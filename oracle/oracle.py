@@ -427,7 +427,8 @@ def _wrap(x):
 
 
 def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
-                  counts=None, forces_at="float64", pm_mesh=None):
+                  counts=None, forces_at="float64", pm_mesh=None,
+                  recon=False):
     """One interval dt of hierarchical block steps (kick-drift-kick) with
     2^max_level substeps of dt / 2^max_level.  A particle of bin b takes
     steps tau_b = dt / 2^b, starting at substeps s with s % 2^(L-b) == 0
@@ -452,7 +453,10 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
     (positions at the end, wrapped), as a long PM step encloses the short
     subcycles.  Returns the final x, v, u (float64, (3, n) / n per species)
     and the state of the last evaluation.  counts, if a dict, receives the
-    number of evaluations of every particle."""
+    number of evaluations of every particle.  recon: the hydro forces use
+    the viscosity on the limited midpoint reconstruction, with the velocity
+    gradients evaluated with the coefficients (latest values of inactive
+    neighbours, like every other field)."""
     f32 = forces_at == "float32"
 
     def q(a):
@@ -471,7 +475,8 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
                                      "dudt")}
     st.update(B=np.zeros((ng, 3)), gradA=np.zeros((ng, 3)),
               gradB=np.zeros((ng, 3, 3)), a_hydro=np.zeros((3, ng)),
-              a_grav_gas=np.zeros((3, ng)), a_grav_dm=np.zeros((3, nd)))
+              a_grav_gas=np.zeros((3, ng)), a_grav_dm=np.zeros((3, nd)),
+              dv=np.zeros((ng, 3, 3)))
     ev_g = np.zeros(ng, np.int64)
     ev_d = np.zeros(nd, np.int64)
 
@@ -492,12 +497,18 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
                 for k in ("A", "B", "gradA", "gradB", "rho", "P", "cs"):
                     st[k][gs.start + Tg] = c[k]
                 V3 = q(vg[:, gs])
+                if recon:
+                    st["dv"][gs.start + Tg] = velocity_gradient(
+                        X[0], X[1], X[2], V3[0], V3[1], V3[2], hh,
+                        st["V"][gs], st["A"][gs], st["B"][gs],
+                        st["gradA"][gs], st["gradB"][gs], targets=Tg)
                 ax, ay, az, du = hydro(
                     X[0], X[1], X[2], V3[0], V3[1], V3[2], hh, mm,
                     st["V"][gs], st["rho"][gs], st["P"][gs], st["cs"][gs],
                     st["A"][gs], st["B"][gs], st["gradA"][gs],
                     st["gradB"][gs], params["Cl"], params["Cq"],
-                    params["epsQ"], targets=Tg)
+                    params["epsQ"], targets=Tg,
+                    dv=st["dv"][gs] if recon else None)
                 st["a_hydro"][:, gs.start + Tg] = (ax, ay, az)
                 st["dudt"][gs.start + Tg] = du
             Td = np.nonzero(act_d[ds])[0]

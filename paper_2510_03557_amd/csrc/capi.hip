@@ -370,7 +370,50 @@ int crk_hydro_forces(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
     if (!g) return CRK_OK;
     PassSpan sp(ctx, P_HYDRO);
     return pass_hydro(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gradA, gradB,
-                      ax, ay, az, dudt);
+                      nullptr, 0.0, 1.0, ax, ay, az, dudt);
+}
+
+int crk_velocity_gradient(crk_ctx *ctx, crk_tree *t, const void *vx,
+                          const void *vy, const void *vz, const void *V,
+                          const void *A, const void *B, const void *gradA,
+                          const void *gradB, void *dv) {
+    CRK_TRY(check_tree_ready(ctx, t, true));
+    const size_t el = ctx->elem();
+    const bool g = t->n_gas > 0;
+    const void *ins[] = {vx, vy, vz, V, A, B, gradA, gradB};
+    const char *in_names[] = {"vx", "vy", "vz", "V", "A", "B", "gradA", "gradB"};
+    for (int k = 0; k < 8; ++k) CRK_TRY(check_ptr(ins[k], el, in_names[k], g));
+    CRK_TRY(check_ptr(dv, el, "dv", g));
+    if (!g) return CRK_OK;
+    PassSpan sp(ctx, P_VGRAD);
+    return pass_velocity_gradient(ctx, t, vx, vy, vz, V, A, B, gradA, gradB, dv);
+}
+
+int crk_hydro_forces_limited(crk_ctx *ctx, crk_tree *t, const void *m,
+                             const void *vx, const void *vy, const void *vz,
+                             const void *V, const void *rho, const void *P,
+                             const void *cs, const void *A, const void *B,
+                             const void *gradA, const void *gradB,
+                             const void *dv, double eta_crit, double eta_fold,
+                             void *ax, void *ay, void *az, void *dudt) {
+    CRK_TRY(check_tree_ready(ctx, t, true));
+    const size_t el = ctx->elem();
+    const bool g = t->n_gas > 0;
+    const void *ins[] = {m, vx, vy, vz, V, rho, P, cs, A, B, gradA, gradB, dv};
+    const char *in_names[] = {"m", "vx", "vy", "vz", "V", "rho", "P", "cs",
+                              "A", "B", "gradA", "gradB", "dv"};
+    for (int k = 0; k < 13; ++k) CRK_TRY(check_ptr(ins[k], el, in_names[k], g));
+    void *outs[] = {ax, ay, az, dudt};
+    const char *out_names[] = {"ax", "ay", "az", "dudt"};
+    for (int k = 0; k < 4; ++k) CRK_TRY(check_ptr(outs[k], el, out_names[k], g));
+    if (!(eta_crit >= 0.0) || !std::isfinite(eta_crit) || !(eta_fold > 0.0) ||
+        !std::isfinite(eta_fold))
+        return set_error(CRK_EINVAL,
+                         "eta_crit must be finite and >= 0, eta_fold finite and > 0");
+    if (!g) return CRK_OK;
+    PassSpan sp(ctx, P_HYDRO);
+    return pass_hydro(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gradA, gradB,
+                      dv, eta_crit, eta_fold, ax, ay, az, dudt);
 }
 
 int shortrange_gravity(crk_ctx *ctx, crk_tree *t, const void *m_gas,
@@ -695,8 +738,8 @@ int crk_timing_enable(crk_ctx *ctx, int enable) {
     return CRK_OK;
 }
 
-int crk_pass_times(crk_ctx *ctx, double pass_ms[7], double kernel_ms[7],
-                   int64_t launches[7]) {
+int crk_pass_times(crk_ctx *ctx, double pass_ms[8], double kernel_ms[8],
+                   int64_t launches[8]) {
     CRK_TRY(check_ctx(ctx));
     if (ctx->capturing) return set_error(CRK_ESTATE, "query during capture");
     CRK_HIP(hipStreamSynchronize(ctx->stream));

@@ -69,7 +69,10 @@ struct HostBuf {
 // context and tree
 // --------------------------------------------------------------------------
 
-enum PassId { P_TREE = 0, P_LISTS, P_DENSITY, P_COEFF, P_HYDRO, P_GRAV, P_INTEG, P_COUNT };
+enum PassId {
+    P_TREE = 0, P_LISTS, P_DENSITY, P_COEFF, P_HYDRO, P_GRAV, P_INTEG, P_VGRAD,
+    P_COUNT
+};
 
 // long-range mesh workspace (pm.hip): double deposit mesh, real mesh and
 // two half-spectra of the context precision, and the FFT plans of one size
@@ -245,8 +248,13 @@ int pass_coefficients(crk_ctx *ctx, crk_tree *t, const void *m,
 int pass_hydro(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                const void *vy, const void *vz, const void *V,
                const void *rho, const void *P, const void *cs, const void *A,
-               const void *B, const void *gradA, const void *gradB, void *ax,
+               const void *B, const void *gradA, const void *gradB,
+               const void *dv, double eta_crit, double eta_fold, void *ax,
                void *ay, void *az, void *dudt);
+int pass_velocity_gradient(crk_ctx *ctx, crk_tree *t, const void *vx,
+                           const void *vy, const void *vz, const void *V,
+                           const void *A, const void *B, const void *gradA,
+                           const void *gradB, void *dv);
 int pass_gravity(crk_ctx *ctx, crk_tree *t, const void *m_gas,
                  const void *m_dm, void *ax_gas, void *ay_gas, void *az_gas,
                  void *ax_dm, void *ay_dm, void *az_dm);

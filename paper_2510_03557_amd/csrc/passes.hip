@@ -36,6 +36,8 @@ __device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double rsq(double x) { return 1.0 / sqrt(x); }
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double rcp(double x) { return 1.0 / x; }
+__device__ inline float fexp(float x) { return __expf(x); }
+__device__ inline double fexp(double x) { return exp(x); }
 
 // compensated running sum (float) / plain sum (double)
 template <typename T> struct Comp;
@@ -1012,22 +1014,35 @@ template <typename T> struct CoeffPass {
 //   0 vx 1 vy 2 vz 3 ih2=1/h^2 4 a=A N 5..7 da=dA N 8..10 B
 //   11..13 ab=A N B  14..22 adb=A N dB [g][x]  23 h  24 V  25 P  26 rho
 //   27 cs   (N = 1/(pi h^3))
+//   with the reconstruction: 28..33 the symmetric part of the velocity
+//   gradient as the quadratic form x.dv x needs it: dv00 dv11 dv22
+//   dv01+dv10 dv02+dv20 dv12+dv21
 // The corrected-kernel gradient of particle k at separation y:
 //   g_k(y)_g = (1 + B.y)(da_g w + a wq ih2 y_g) + w (sum_x adb[g][x] y_x + ab_g)
 constexpr int HF = 28;
+constexpr int HF_RECON = HF + 6;
 
-template <typename T> struct HydroPass {
+// RECON: the viscosity acts on both velocities extrapolated linearly to the
+// pair midpoint, v~_ij = v_ij - phi/2 (dv_i + dv_j) x_ij, with the limiter
+// phi = 4 s_i s_j / (s_i + s_j)^2 (0 unless s_i s_j > 0), s_k = x.dv_k x,
+// damped by exp(-((eta - eta_c) / eta_f)^2) for eta = r / max(h) < eta_c
+template <typename T, bool RECON = false> struct HydroPass {
     struct Args {
-        const T *f;       // HF planes of n_gas, tree order
+        const T *f;       // HFN planes of n_gas, tree order
         int64_t n_gas;
         T *ax, *ay, *az, *dudt;  // caller order
         const T *m;       // tree order
         T Cl, Cq, epsQ;
+        T eta_c, ieta_f;  // close-pair scale and 1 / its width (RECON)
     };
-    // candidate record: fx fy fz, one pad, the HF fields from float FO on
-    // (16-byte aligned, so they load as 128-bit LDS reads), pad to 36
+    static constexpr int HFN = RECON ? HF_RECON : HF;
+    // candidate record: fx fy fz, one pad, the HFN fields from float FO on
+    // (16-byte aligned, so they load as 128-bit LDS reads), padded to an odd
+    // number of 16-byte units (36 or 44 floats): records read by different
+    // lanes at once then start in different 16-byte bank groups
     static constexpr int FO = 4;
-    static constexpr int NJ = 36;
+    static constexpr int NJ = (((FO + HFN + 3) / 4) | 1) * 4;
+    static_assert(NJ == (RECON ? 44 : 36), "hydro record layout");
     static constexpr int CAPF = 1;
     static constexpr int ID = 2;
     // split sweep: one phase.  The in-range candidates of one buffer are
@@ -1044,8 +1059,8 @@ template <typename T> struct HydroPass {
     }
     struct I {
         T ex, ey, ez;
-        T Cl, Cq, epsQ;
-        T f[HF];
+        T Cl, Cq, epsQ, eta_c, ieta_f;
+        T f[HFN];
     };
     struct Tile {
         T s[4];
@@ -1065,8 +1080,10 @@ template <typename T> struct HydroPass {
         is.Cl = a.Cl;
         is.Cq = a.Cq;
         is.epsQ = a.epsQ;
+        is.eta_c = a.eta_c;
+        is.ieta_f = a.ieta_f;
 #pragma unroll
-        for (int k = 0; k < HF; ++k) is.f[k] = a.f[k * a.n_gas + i];
+        for (int k = 0; k < HFN; ++k) is.f[k] = a.f[k * a.n_gas + i];
     }
     // the fields are many: loaded for the culling survivors only
     static constexpr int NP = 1;
@@ -1080,7 +1097,9 @@ template <typename T> struct HydroPass {
         d[2] = fz;
         d[3] = T(0);
 #pragma unroll
-        for (int k = 0; k < HF; ++k) d[FO + k] = a.f[k * a.n_gas + j];
+        for (int k = 0; k < HFN; ++k) d[FO + k] = a.f[k * a.n_gas + j];
+#pragma unroll
+        for (int k = FO + HFN; k < NJ; ++k) d[k] = T(0);
     }
     // gradient of the corrected kernel of particle with fields f at y
     __device__ static void grad_rk(const T *f, T y0, T y1, T y2, T r2, T out[3],
@@ -1119,8 +1138,26 @@ template <typename T> struct HydroPass {
             grad_rk(fi, x0, x1, x2, r2, gi, oi);
             grad_rk(fj, -x0, -x1, -x2, r2, gj, oj);
             const T v0 = fi[0] - fj[0], v1 = fi[1] - fj[1], v2 = fi[2] - fj[2];
-            const T vdx = v0 * x0 + v1 * x1 + v2 * x2;
+            T vdx = v0 * x0 + v1 * x1 + v2 * x2;
             const T hi_ = fi[23], hj_ = fj[23];
+            if constexpr (RECON) {
+                // x.v~ = x.v_ij - phi/2 (s_i + s_j): only the projections
+                // of the two extrapolations on the pair axis enter mu
+                const T *Di = fi + HF, *Dj = fj + HF;
+                const T q00 = x0 * x0, q11 = x1 * x1, q22 = x2 * x2;
+                const T q01 = x0 * x1, q02 = x0 * x2, q12 = x1 * x2;
+                const T si = fma(Di[0], q00, fma(Di[1], q11, fma(Di[2], q22,
+                             fma(Di[3], q01, fma(Di[4], q02, Di[5] * q12)))));
+                const T sj = fma(Dj[0], q00, fma(Dj[1], q11, fma(Dj[2], q22,
+                             fma(Dj[3], q01, fma(Dj[4], q02, Dj[5] * q12)))));
+                const T sp = si + sj;
+                T phi = si * sj > T(0) ? T(4) * si * sj * rcp(sp * sp) : T(0);
+                const T r = r2 > T(0) ? r2 * rsq(r2) : T(0);
+                const T eta = r * rcp(hi_ > hj_ ? hi_ : hj_);
+                const T te = (eta - is.eta_c) * is.ieta_f;
+                phi = eta < is.eta_c ? phi * fexp(-te * te) : phi;
+                vdx = fma(T(-0.5) * phi, sp, vdx);
+            }
             T mui = hi_ * vdx * rcp(fma(is.epsQ * hi_, hi_, r2));
             T muj = hj_ * vdx * rcp(fma(is.epsQ * hj_, hj_, r2));
             mui = mui < T(0) ? mui : T(0);
@@ -1147,6 +1184,108 @@ template <typename T> struct HydroPass {
         a.ay[c] = (T)(ac.a.c[1].value() * im);
         a.az[c] = (T)(ac.a.c[2].value() * im);
         a.dudt[c] = (T)(-0.5 * ac.a.c[3].value() * im);
+    }
+};
+
+// --------------------------------------------------------------------------
+// velocity gradient
+// --------------------------------------------------------------------------
+// dv[a][b]_i = sum_j V_j (v_j^a - v_i^a) g_i(x_ij)_b over gas j with
+// r_ij < 2 h_i, with the corrected-kernel gradient g_i of the hydro fields
+// (planes 0..22 and 24 of the hydro gather); j = i adds zero.
+template <typename T> struct VGradPass {
+    struct Args {
+        const T *f;   // hydro field planes of n_gas, tree order
+        int64_t n_gas;
+        T *dv;        // 9 planes [a][b] of n_gas, caller order
+    };
+    static constexpr int NJ = 8;  // fx fy fz V vx vy vz pad
+    static constexpr int CAPF = 4;
+    static constexpr int ID = 6;
+    static constexpr bool MASKED = false;
+    static constexpr int NI = 23;  // i fields: v, 1/h^2, coefficients
+    __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
+        return widen<T>(2.0 * (double)hI);
+    }
+    __device__ static T sub_range(const Args &, const TreeView<T> &, int, T hg,
+                                  const T *) {
+        return widen<T>(2.0 * (double)hg);
+    }
+    struct I {
+        T ex, ey, ez;
+        T f[NI];
+    };
+    struct Tile {
+        T s[9];
+        __device__ void zero() {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) s[k] = T(0);
+        }
+    };
+    struct Acc {
+        CompArr<T, 9> a;
+        __device__ void zero() { a.zero(); }
+        __device__ void fold(Tile &t) { a.fold(t.s); }
+        __device__ void quad_reduce() { a.quad_reduce(); }
+    };
+    __device__ static void load_i(I &is, const Args &a, const TreeView<T> &,
+                                  int i, T ex, T ey, T ez, int) {
+        is.ex = ex;
+        is.ey = ey;
+        is.ez = ez;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) is.f[k] = a.f[k * a.n_gas + i];
+    }
+    static constexpr int NP = 4;  // prefetched with the position: V, v
+    __device__ static void fetch_j(T *f, const Args &a, const TreeView<T> &,
+                                   int j) {
+        f[0] = a.f[24 * a.n_gas + j];
+        f[1] = a.f[0 * a.n_gas + j];
+        f[2] = a.f[1 * a.n_gas + j];
+        f[3] = a.f[2 * a.n_gas + j];
+    }
+    __device__ static void store_j(T *d, const T *f, const Args &,
+                                   const TreeView<T> &, int, T fx, T fy, T fz) {
+        d[0] = fx;
+        d[1] = fy;
+        d[2] = fz;
+        d[3] = f[0];
+        d[4] = f[1];
+        d[5] = f[2];
+        d[6] = f[3];
+        d[7] = T(0);
+    }
+    __device__ static bool test(const I &is, const T *jd, bool) {
+        const T x0 = is.ex - jd[0], x1 = is.ey - jd[1], x2 = is.ez - jd[2];
+        return (x0 * x0 + x1 * x1 + x2 * x2) * is.f[3] < T(4);
+    }
+    __device__ static void pair(Tile &tl, const I &is, const T *jd, bool) {
+        const T x0 = is.ex - jd[0], x1 = is.ey - jd[1], x2 = is.ez - jd[2];
+        const T r2 = x0 * x0 + x1 * x1 + x2 * x2;
+        T g[3];
+        bool on;
+        HydroPass<T>::grad_rk(is.f, x0, x1, x2, r2, g, on);
+        if (on) {
+            const T d0 = jd[3] * (jd[4] - is.f[0]);
+            const T d1 = jd[3] * (jd[5] - is.f[1]);
+            const T d2 = jd[3] * (jd[6] - is.f[2]);
+            T *s = tl.s;
+            s[0] = fma(d0, g[0], s[0]);
+            s[1] = fma(d0, g[1], s[1]);
+            s[2] = fma(d0, g[2], s[2]);
+            s[3] = fma(d1, g[0], s[3]);
+            s[4] = fma(d1, g[1], s[4]);
+            s[5] = fma(d1, g[2], s[5]);
+            s[6] = fma(d2, g[0], s[6]);
+            s[7] = fma(d2, g[1], s[7]);
+            s[8] = fma(d2, g[2], s[8]);
+        }
+    }
+    __device__ static void finish(const Acc &ac, const I &, const Args &a,
+                                  const TreeView<T> &tv, int i) {
+        const int c = tv.perm[i];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a.dv[k * a.n_gas + c] = (T)ac.a.c[k].value();
     }
 };
 
@@ -1556,7 +1695,8 @@ __global__ void hydro_gather_kernel(
     const T *__restrict__ rho, const T *__restrict__ P,
     const T *__restrict__ cs, const T *__restrict__ A,
     const T *__restrict__ B, const T *__restrict__ gA,
-    const T *__restrict__ gB, T *__restrict__ f, T *__restrict__ mt) {
+    const T *__restrict__ gB, const T *__restrict__ dv, T *__restrict__ f,
+    T *__restrict__ mt) {
     GRID_STRIDE(p, n) {
         const int c = perm[p];
         const T hh = h[p];
@@ -1576,10 +1716,22 @@ __global__ void hydro_gather_kernel(
         }
         f[23 * n + p] = hh;
         f[24 * n + p] = V[c];
-        f[25 * n + p] = P[c];
-        f[26 * n + p] = rho[c];
-        f[27 * n + p] = cs[c];
-        mt[p] = m[c];
+        // (the velocity-gradient pass needs neither the state nor the mass)
+        if (P) {
+            f[25 * n + p] = P[c];
+            f[26 * n + p] = rho[c];
+            f[27 * n + p] = cs[c];
+            mt[p] = m[c];
+        }
+        if (dv) {
+            const T *d = dv + c;
+            f[(HF + 0) * n + p] = d[0];
+            f[(HF + 1) * n + p] = d[4 * n];
+            f[(HF + 2) * n + p] = d[8 * n];
+            f[(HF + 3) * n + p] = d[1 * n] + d[3 * n];
+            f[(HF + 4) * n + p] = d[2 * n] + d[6 * n];
+            f[(HF + 5) * n + p] = d[5 * n] + d[7 * n];
+        }
     }
 }
 
@@ -1742,17 +1894,18 @@ int coeff_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *V,
                                         pa, gas_bound(ctx, t), P_COEFF, true);
 }
 
+// the hydro field planes of every gas particle in tree order (pf[7]);
+// P == nullptr: the kinematic and coefficient planes only (no state, no
+// masses); dv != nullptr: also the reconstruction planes
 template <typename T>
-int hydro_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
-               const void *vy, const void *vz, const void *V, const void *rho,
-               const void *P, const void *cs, const void *A, const void *B,
-               const void *gA, const void *gB, void *ax, void *ay, void *az,
-               void *dudt) {
+int hydro_fields(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
+                 const void *vy, const void *vz, const void *V, const void *rho,
+                 const void *P, const void *cs, const void *A, const void *B,
+                 const void *gA, const void *gB, const void *dv) {
     const int64_t ng = t->n_gas;
     const size_t n1 = std::max<int64_t>(ng, 1);
-    CRK_TRY(t->pf[7].ensure(n1 * HF * sizeof(T), ctx->capturing));
+    CRK_TRY(t->pf[7].ensure(n1 * HF_RECON * sizeof(T), ctx->capturing));
     CRK_TRY(t->pf[4].ensure(n1 * sizeof(T), ctx->capturing));
-    T *f = t->pf[7].as<T>(), *mt = t->pf[4].as<T>();
     hipLaunchKernelGGL((hydro_gather_kernel<T>), dim3(grid_for(ng)), dim3(256),
                        0, ctx->stream, t->perm.as<int32_t>(), ng, t->hsm.as<T>(),
                        static_cast<const T *>(m), static_cast<const T *>(vx),
@@ -1760,16 +1913,52 @@ int hydro_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                        static_cast<const T *>(V), static_cast<const T *>(rho),
                        static_cast<const T *>(P), static_cast<const T *>(cs),
                        static_cast<const T *>(A), static_cast<const T *>(B),
-                       static_cast<const T *>(gA), static_cast<const T *>(gB), f,
-                       mt);
+                       static_cast<const T *>(gA), static_cast<const T *>(gB),
+                       static_cast<const T *>(dv), t->pf[7].as<T>(),
+                       t->pf[4].as<T>());
     CRK_HIP(hipGetLastError());
+    return CRK_OK;
+}
+
+template <typename T>
+int hydro_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
+               const void *vy, const void *vz, const void *V, const void *rho,
+               const void *P, const void *cs, const void *A, const void *B,
+               const void *gA, const void *gB, const void *dv, double eta_c,
+               double eta_f, void *ax, void *ay, void *az, void *dudt) {
+    CRK_TRY(hydro_fields<T>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB,
+                            dv));
+    const int64_t ng = t->n_gas;
+    T *f = t->pf[7].as<T>(), *mt = t->pf[4].as<T>();
+    const TreeView<T> tv = tree_view<T>(t, true, gas_leaf_count(t));
+    if (dv) {
+        typename HydroPass<T, true>::Args pa{
+            f, ng, static_cast<T *>(ax), static_cast<T *>(ay),
+            static_cast<T *>(az), static_cast<T *>(dudt), mt,
+            (T)ctx->params.Cl, (T)ctx->params.Cq, (T)ctx->params.epsQ,
+            (T)eta_c, (T)(1.0 / eta_f)};
+        return launch_pair<T, HydroPass<T, true>>(ctx, t, tv, pa,
+                                                  gas_bound(ctx, t), P_HYDRO, true);
+    }
     typename HydroPass<T>::Args pa{f, ng, static_cast<T *>(ax),
                                    static_cast<T *>(ay), static_cast<T *>(az),
                                    static_cast<T *>(dudt), mt,
                                    (T)ctx->params.Cl, (T)ctx->params.Cq,
-                                   (T)ctx->params.epsQ};
-    return launch_pair<T, HydroPass<T>>(ctx, t, tree_view<T>(t, true, gas_leaf_count(t)),
-                                        pa, gas_bound(ctx, t), P_HYDRO, true);
+                                   (T)ctx->params.epsQ, T(0), T(0)};
+    return launch_pair<T, HydroPass<T>>(ctx, t, tv, pa, gas_bound(ctx, t),
+                                        P_HYDRO, true);
+}
+
+template <typename T>
+int vgrad_impl(crk_ctx *ctx, crk_tree *t, const void *vx, const void *vy,
+               const void *vz, const void *V, const void *A, const void *B,
+               const void *gA, const void *gB, void *dv) {
+    CRK_TRY(hydro_fields<T>(ctx, t, nullptr, vx, vy, vz, V, nullptr, nullptr,
+                            nullptr, A, B, gA, gB, nullptr));
+    typename VGradPass<T>::Args pa{t->pf[7].as<T>(), t->n_gas,
+                                   static_cast<T *>(dv)};
+    return launch_pair<T, VGradPass<T>>(ctx, t, tree_view<T>(t, true, gas_leaf_count(t)),
+                                        pa, gas_bound(ctx, t), P_VGRAD, true);
 }
 
 template <typename T>
@@ -1862,13 +2051,24 @@ int pass_coefficients(crk_ctx *ctx, crk_tree *t, const void *m, const void *V,
 int pass_hydro(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                const void *vy, const void *vz, const void *V, const void *rho,
                const void *P, const void *cs, const void *A, const void *B,
-               const void *gradA, const void *gradB, void *ax, void *ay,
-               void *az, void *dudt) {
+               const void *gradA, const void *gradB, const void *dv,
+               double eta_crit, double eta_fold, void *ax, void *ay, void *az,
+               void *dudt) {
     if (ctx->precision == CRK_FP64)
         return hydro_impl<double>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B,
-                                  gradA, gradB, ax, ay, az, dudt);
+                                  gradA, gradB, dv, eta_crit, eta_fold, ax, ay,
+                                  az, dudt);
     return hydro_impl<float>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gradA,
-                             gradB, ax, ay, az, dudt);
+                             gradB, dv, eta_crit, eta_fold, ax, ay, az, dudt);
+}
+
+int pass_velocity_gradient(crk_ctx *ctx, crk_tree *t, const void *vx,
+                           const void *vy, const void *vz, const void *V,
+                           const void *A, const void *B, const void *gradA,
+                           const void *gradB, void *dv) {
+    if (ctx->precision == CRK_FP64)
+        return vgrad_impl<double>(ctx, t, vx, vy, vz, V, A, B, gradA, gradB, dv);
+    return vgrad_impl<float>(ctx, t, vx, vy, vz, V, A, B, gradA, gradB, dv);
 }
 
 int count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[6]) {

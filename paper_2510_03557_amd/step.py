@@ -17,14 +17,20 @@ class ShortRangeStep:
     """Device-resident inputs, outputs and double-precision state of one
     workload.  ``run()`` enqueues build_tree, build_interaction_lists and the
     four passes (and crk_integrate when ``integrate`` is set) on the
-    context's stream."""
+    context's stream.  With ``recon`` the hydro forces take the velocity
+    gradient and the viscosity on the limited midpoint reconstruction
+    (crk_velocity_gradient, then crk_hydro_forces_limited)."""
 
     def __init__(self, wl, precision: str = "fp32", tuning: dict | None = None,
-                 dt: float = 0.0, device: str = "cuda", params=None):
+                 dt: float = 0.0, device: str = "cuda", params=None,
+                 recon: bool = False, eta_crit: float = 0.8,
+                 eta_fold: float = 0.2):
         import torch
         self.torch = torch
         self.wl = wl
         self.dt = float(dt)
+        self.recon = bool(recon)
+        self.eta_crit, self.eta_fold = float(eta_crit), float(eta_fold)
         self.ctx = Context(precision, params=params)
         if tuning:
             self.ctx.set_tuning(**tuning)
@@ -64,6 +70,7 @@ class ShortRangeStep:
             self.V, self.rho_t = zeros(ng), zeros(ng)
             self.A, self.rho, self.P, self.cs = (zeros(ng) for _ in range(4))
             self.B, self.gA, self.gB = zeros(3 * ng), zeros(3 * ng), zeros(9 * ng)
+            self.dv = zeros(9 * ng)
             self.ahx, self.ahy, self.ahz, self.dudt = (zeros(ng) for _ in range(4))
             self.agx, self.agy, self.agz = (zeros(ng) for _ in range(3))
             self.adx, self.ady, self.adz = (zeros(nd) for _ in range(3))
@@ -86,9 +93,7 @@ class ShortRangeStep:
             c.coefficients(t, self.gm, self.V, self.gu, self.A, self.B,
                            self.gA, self.gB, self.rho, self.P, self.cs)
         if "hydro" in passes:
-            c.hydro_forces(t, self.gm, self.gvx, self.gvy, self.gvz, self.V,
-                           self.rho, self.P, self.cs, self.A, self.B, self.gA,
-                           self.gB, self.ahx, self.ahy, self.ahz, self.dudt)
+            self._hydro()
         if "gravity" in passes:
             c.shortrange_gravity(t, self.gm, self.dm, self.agx, self.agy,
                                  self.agz, self.adx, self.ady, self.adz)
@@ -117,11 +122,24 @@ class ShortRangeStep:
             c.density(t, self.gm, self.V, self.rho_t)
             c.coefficients(t, self.gm, self.V, self.gu, self.A, self.B,
                            self.gA, self.gB, self.rho, self.P, self.cs)
+            self._hydro()
+        c.shortrange_gravity(t, self.gm, self.dm, self.agx, self.agy,
+                             self.agz, self.adx, self.ady, self.adz)
+
+    def _hydro(self):
+        c, t = self.ctx, self.tree
+        if not self.recon:
             c.hydro_forces(t, self.gm, self.gvx, self.gvy, self.gvz, self.V,
                            self.rho, self.P, self.cs, self.A, self.B, self.gA,
                            self.gB, self.ahx, self.ahy, self.ahz, self.dudt)
-        c.shortrange_gravity(t, self.gm, self.dm, self.agx, self.agy,
-                             self.agz, self.adx, self.ady, self.adz)
+            return
+        c.velocity_gradient(t, self.gvx, self.gvy, self.gvz, self.V, self.A,
+                            self.B, self.gA, self.gB, self.dv)
+        c.hydro_forces_limited(t, self.gm, self.gvx, self.gvy, self.gvz,
+                               self.V, self.rho, self.P, self.cs, self.A,
+                               self.B, self.gA, self.gB, self.dv,
+                               self.eta_crit, self.eta_fold, self.ahx,
+                               self.ahy, self.ahz, self.dudt)
 
     def _kick(self, dt, L, s, phase):
         c = self.ctx
@@ -322,6 +340,7 @@ class ShortRangeStep:
         out["B"] = h(self.B, 3 * ng).reshape(3, ng).T
         out["gradA"] = h(self.gA, 3 * ng).reshape(3, ng).T
         out["gradB"] = h(self.gB, 9 * ng).reshape(3, 3, ng).transpose(2, 0, 1)
+        out["dv"] = h(self.dv, 9 * ng).reshape(3, 3, ng).transpose(2, 0, 1)
         out["a_hydro"] = np.stack([h(self.ahx, ng), h(self.ahy, ng),
                                    h(self.ahz, ng)])
         out["a_grav_gas"] = np.stack([h(self.agx, ng), h(self.agy, ng),

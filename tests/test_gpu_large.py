@@ -36,20 +36,24 @@ def pick_gas(wl, rng, n_random, n_dense):
     return g
 
 
-@pytest.mark.parametrize("name,n_gas_rand,n_dense,n_dm,sub", [
-    ("uneven_boxes512", 60, 0, 200, 0),
-    ("uneven_boxes512", 40, 0, 100, 2),
-    ("plummer64M", 24, 8, 200, 2),
-    ("zeldovich448", 32, 0, 200, 2),
+@pytest.mark.parametrize("name,n_gas_rand,n_dense,n_dm,sub,recon", [
+    ("uneven_boxes512", 60, 0, 200, 0, False),
+    ("uneven_boxes512", 40, 0, 100, 2, False),
+    ("plummer64M", 24, 8, 200, 2, False),
+    ("zeldovich448", 32, 0, 200, 2, False),
+    # with the velocity gradient and the reconstructed viscosity
+    ("uneven_boxes512", 40, 0, 50, 2, True),
+    ("plummer64M", 16, 8, 50, 2, True),
 ])
-def test_large_config_sampled(orc, name, n_gas_rand, n_dense, n_dm, sub):
+def test_large_config_sampled(orc, name, n_gas_rand, n_dense, n_dm, sub,
+                              recon):
     from paper_2510_03557_amd.step import ShortRangeStep
-    print(f"case {name} sub_sweep={sub}: generating", flush=True)
+    print(f"case {name} sub_sweep={sub} recon={recon}: generating", flush=True)
     wl = W.make(name)
     print(f"case {name}: {wl.n_total} particles in {wl.n_boxes} boxes, GPU "
           "step", flush=True)
     st = ShortRangeStep(wl, precision="fp32",
-                        tuning=dict(leaf_max=64, sub_sweep=sub))
+                        tuning=dict(leaf_max=64, sub_sweep=sub), recon=recon)
     st.run()
     got = st.outputs()
     pairs = st.ctx.count_pairs(st.tree)
@@ -63,9 +67,9 @@ def test_large_config_sampled(orc, name, n_gas_rand, n_dense, n_dm, sub):
     di = np.sort(rng.choice(wl.dm.n, n_dm, replace=False))
     print(f"case {name}: oracle on {gi.size} gas + {di.size} dm samples",
           flush=True)
-    ref = orc.step_sampled(wl, gi, di)
+    ref = orc.step_sampled(wl, gi, di, recon=recon)
     errs = {}
-    for k in GAS_KEYS:
+    for k in GAS_KEYS + (("dv",) if recon else ()):
         g = got[k][:, gi] if k.startswith("a_") else got[k][gi]
         errs[k] = rel_rms(g, ref[k])
     errs["a_grav_dm"] = rel_rms(got["a_grav_dm"][:, di], ref["a_grav_dm"])

@@ -257,6 +257,39 @@ def test_cycle_with_long_range_matches_oracle(orc, step_cls, precision):
     assert all(v <= tol for v in errs.values()), errs
 
 
+@pytest.mark.parametrize("precision,L,seed", [("fp32", 3, 507),
+                                               ("fp64", 2, 508)])
+def test_cycle_with_reconstructed_viscosity(orc, step_cls, precision, L,
+                                            seed):
+    """The cycle with the velocity-gradient pass and the reconstructed
+    viscosity: gradients of active particles only, the latest gradients of
+    inactive neighbours in the limiter."""
+    print(f"case cycle + reconstructed viscosity {precision} L={L}",
+          flush=True)
+    wl = W.random_uniform(12000, 8000, seed, n_ngb=48.0, h_spread=0.15)
+    rng = np.random.default_rng(seed)
+    bg = rng.integers(0, L + 1, wl.gas.n)
+    bd = rng.integers(0, L + 1, wl.dm.n)
+    dt = 0.02
+    st = step_cls(wl, precision, recon=True)
+    try:
+        st.set_bins(bg, bd)
+        st.substep_cycle(dt, L)
+        got = st.state()
+        outs = st.outputs()
+    finally:
+        st.close()
+    ref = orc.substep_cycle(wl, bg, bd, dt, L, recon=True, forces_at=(
+        "float32" if precision == "fp32" else "float64"))
+    errs = _cycle_errors(wl, got, ref)
+    errs.update({k: rel_rms(outs[k], ref[k]) for k in ("dv", "a_hydro",
+                                                        "dudt")})
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    tol = FP32_TOL if precision == "fp32" else FP64_TOL
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, bad
+
+
 def test_cycle_bins_from_accelerations(orc, step_cls):
     """Bins from crk_timestep_bins on the step's own accelerations (gas:
     Courant and acceleration; dm: acceleration), then a cycle: the bins
