@@ -11,5 +11,5 @@ from .oracle import (  # noqa: F401
     PARAMS, build, coefficients, density, gravity, hydro, integrate,
     kernel, grav_g, s2_force, neighbours, num_threads, step, step_sampled,
     STEP_PARAMS, timestep_bins, substep_cycle, s2_form_factor, pm_long_range,
-    fof_labels, velocity_gradient, RECON,
+    fof_labels, velocity_gradient, RECON, compatible_update,
 )

@@ -29,7 +29,10 @@
  *     and its (anti)symmetry, Sec. IV-B.2) and the work-split du/dt, which
  *     conserve momentum and energy (Sec. IV-A); optionally with the
  *     viscosity acting on a limited linear reconstruction of both velocities
- *     at the pair midpoint (CRKSPH's viscosity, named in Sec. IV-A);
+ *     at the pair midpoint (CRKSPH's viscosity, named in Sec. IV-A), and
+ *     optionally with the pair work taken at the time-centred velocities of
+ *     a kick (the compatible energy update, which makes one kick conserve
+ *     the total energy exactly);
  *   - orc_gravity: the short-range remainder of Newtonian gravity inside the
  *     handover scale r_c (Sec. IV-A): Plummer-softened 1/r^2 minus the force
  *     between two S2 clouds of diameter r_c (Hockney & Eastwood), zero
@@ -714,6 +717,7 @@ int orc_hydro(int64_t n, const double *x, const double *y, const double *z,
               const double *A, const double *B, const double *gradA,
               const double *gradB, double Cl, double Cq, double epsQ,
               const double *dv, double eta_crit, double eta_fold,
+              const double *v1x, const double *v1y, const double *v1z,
               int64_t nt, const int64_t *targets, int brute, double *ax,
               double *ay, double *az, double *dudt)
 {
@@ -772,7 +776,15 @@ int orc_hydro(int64_t n, const double *x, const double *y, const double *z,
                     Fij[g] = -0.5 * V[i] * V[j]
                              * (pp * (gi[g] - gj[g]) + Qi * gi[g] - Qj * gj[g]);
                 for (int g = 0; g < 3; ++g) f[g] += Fij[g];
-                work += vij[0] * Fij[0] + vij[1] * Fij[1] + vij[2] * Fij[2];
+                /* the pair's work: with the velocities after the kick (v1)
+                 * given, at the time-centred velocities (v + v1)/2 */
+                double wv[3] = {vij[0], vij[1], vij[2]};
+                if (v1x) {
+                    wv[0] = 0.5 * (vij[0] + (v1x[i] - v1x[j]));
+                    wv[1] = 0.5 * (vij[1] + (v1y[i] - v1y[j]));
+                    wv[2] = 0.5 * (vij[2] + (v1z[i] - v1z[j]));
+                }
+                work += wv[0] * Fij[0] + wv[1] * Fij[1] + wv[2] * Fij[2];
             }
         }
         ax[k] = f[0] / m[i];

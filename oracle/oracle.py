@@ -177,11 +177,13 @@ def velocity_gradient(x, y, z, vx, vy, vz, h, V, A, B, gradA, gradB,
 def hydro(x, y, z, vx, vy, vz, h, m, V, rho, P, cs, A, B, gradA, gradB,
           Cl=PARAMS["Cl"], Cq=PARAMS["Cq"], epsQ=PARAMS["epsQ"],
           targets=None, brute=False, dv=None, eta_crit=RECON["eta_crit"],
-          eta_fold=RECON["eta_fold"]):
+          eta_fold=RECON["eta_fold"], v1=None):
     """a_hydro (3 arrays) and du/dt at the targets.  With ``dv`` (the
     velocity gradient of every particle, (n, 3, 3)) the viscosity acts on the
     limited linear reconstruction of the two velocities at the pair
-    midpoint."""
+    midpoint.  With ``v1`` (the velocities after a kick, (3, n)) du/dt takes
+    the pair work at the time-centred velocities (v + v1)/2 (the forces
+    stay those of the state at v)."""
     lib = _load()
     arrs = [_d(a) for a in (x, y, z, vx, vy, vz, h, m, V, rho, P, cs, A)]
     B = _d(np.reshape(B, (-1, 3)))
@@ -190,6 +192,9 @@ def hydro(x, y, z, vx, vy, vz, h, m, V, rho, P, cs, A, B, gradA, gradB,
     n = arrs[0].shape[0]
     if dv is not None:
         dv = _d(np.reshape(dv, (n, 3, 3)))
+    w1 = [None, None, None]
+    if v1 is not None:
+        w1 = [_d(a) for a in v1]
     nt, t = _targets(targets, n)
     ax, ay, az, du = (np.zeros(nt) for _ in range(4))
     if lib.orc_hydro(_i64(n), *[_p(a) for a in arrs], _p(B), _p(gradA),
@@ -197,6 +202,7 @@ def hydro(x, y, z, vx, vy, vz, h, m, V, rho, P, cs, A, B, gradA, gradB,
                      ctypes.c_double(epsQ),
                      _p(dv) if dv is not None else None,
                      ctypes.c_double(eta_crit), ctypes.c_double(eta_fold),
+                     *[_p(a) for a in w1],
                      _i64(nt), _p(t), ctypes.c_int(int(brute)), _p(ax),
                      _p(ay), _p(az), _p(du)):
         raise MemoryError("oracle hydro failed")
@@ -214,6 +220,32 @@ def gravity(x, y, z, m, r_c, eps, G=PARAMS["G"], targets=None, brute=False):
                        ctypes.c_int(int(brute)), _p(ax), _p(ay), _p(az)):
         raise MemoryError("oracle gravity failed")
     return ax, ay, az
+
+
+def compatible_update(wl, out, dt, params=PARAMS, recon=False,
+                      brute=False):
+    """The compatible energy update of one kick of the gas of a step whose
+    passes gave ``out`` (from step()): v1 = v + dt (a_grav + a_hydro), the
+    specific-energy rate from the same pair forces with the pair work at
+    the time-centred velocities (v + v1)/2, and u1 = u + dt du/dt.
+    Returns dict(v1 (3, n), dudt, u1)."""
+    g = wl.gas
+    v = np.array([g.vx, g.vy, g.vz], np.float64)
+    v1 = v + dt * (out["a_grav_gas"] + out["a_hydro"])
+    dudt = np.zeros(g.n)
+    for b, gs, ds in _box_slices(wl):
+        if gs.stop == gs.start:
+            continue
+        _, _, _, du = hydro(
+            g.x[gs], g.y[gs], g.z[gs], g.vx[gs], g.vy[gs], g.vz[gs],
+            g.h[gs], g.m[gs], out["V"][gs], out["rho"][gs], out["P"][gs],
+            out["cs"][gs], out["A"][gs], out["B"][gs], out["gradA"][gs],
+            out["gradB"][gs], params["Cl"], params["Cq"], params["epsQ"],
+            brute=brute, dv=out["dv"][gs] if recon else None,
+            v1=v1[:, gs])
+        dudt[gs] = du
+    return dict(v1=v1, dudt=dudt,
+                u1=np.asarray(g.u, np.float64) + dt * dudt)
 
 
 def integrate(dt, x, v, u, a_grav, a_hydro=None, dudt=None):
