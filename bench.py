@@ -198,6 +198,27 @@ def measure_recon(wl, tuning, steps, warmup, gather_pairs, hydro_pairs,
         st.sync()
     finally:
         st.close()
+    # the same step with the compatible energy update before the kick
+    log("[bench] step with the reconstructed viscosity and the compatible "
+        "energy update")
+    st = ShortRangeStep(wl, precision="fp32", tuning=tuning, dt=1e-5,
+                        recon=True, compatible=True)
+    try:
+        st.run(integrate=True)
+        st.sync()
+        st.ctx.timing(True)
+        for _ in range(n_eager):
+            st.run(integrate=True)
+        cpass_ms, ckern_ms, claunch = st.ctx.pass_times()
+        st.ctx.timing(False)
+        st.sync()
+        st.capture(integrate=True)
+        csec = time_steps(st.replay, lambda: (torch.cuda.synchronize(),
+                                              st.ctx.stream.synchronize()),
+                          steps, warmup)
+        st.sync()
+    finally:
+        st.close()
     kern = {}
     for p, pairs in (("velocity_gradient", gather_pairs),
                      ("hydro", hydro_pairs)):
@@ -209,7 +230,13 @@ def measure_recon(wl, tuning, steps, warmup, gather_pairs, hydro_pairs,
     return {"value": n / sec, "ms_per_step": sec * 1e3, "launch": "hip_graph",
             "eta_crit": 0.8, "eta_fold": 0.2,
             "pass_ms": {k: round(v / n_eager, 4) for k, v in pass_ms.items()},
-            "kernels": kern}
+            "kernels": kern,
+            "compatible_energy": {
+                "value": n / csec, "ms_per_step": csec * 1e3,
+                "launch": "hip_graph",
+                "energy_pass_ms": round(cpass_ms["energy"] / n_eager, 4),
+                "energy_kernel_ms": round(ckern_ms["energy"]
+                                          / max(claunch["energy"], 1), 4)}}
 
 
 def measure_pm(wl, reps, log):

@@ -255,6 +255,30 @@ int crk_hydro_forces_limited(crk_ctx *ctx, crk_tree *tree, const void *m,
                              const void *dv, double eta_crit, double eta_fold,
                              void *ax, void *ay, void *az, void *dudt);
 
+/* Compatible specific-energy rate for the kick that crk_integrate applies
+ * next (CRKSPH's energy-conserving update, Sec. IV-A; the form is a
+ * reading): with the pair forces F_ij of the current state (exactly those
+ * of crk_hydro_forces, or of crk_hydro_forces_limited when dv is given) and
+ * the velocities after the kick v1 = v + dt (a_grav + a_hydro),
+ *   du_i/dt = -sum_j F_ij . (v^c_i - v^c_j) / (2 m_i),  v^c = (v + v1)/2,
+ * over the same pairs.  A kick v1, u1 = u + dt du/dt with the hydro forces
+ * alone then conserves sum m (v^2/2 + u) to rounding (the plain rate, the
+ * pair work at v, only to O(dt^2)); dt = 0 gives the plain rate.
+ * Arguments as crk_hydro_forces_limited (dv may be NULL: plain viscosity;
+ * eta_crit, eta_fold are checked only with dv), plus dt (finite) and the
+ * accelerations of the kick: a_grav 3 planes (required), a_hydro 3 planes
+ * or NULL.  Output dudt (n_gas) only; the accelerations are not rewritten.
+ * Timed as index 8 of crk_pass_times. */
+int crk_hydro_energy_compatible(crk_ctx *ctx, crk_tree *tree, const void *m,
+                                const void *vx, const void *vy, const void *vz,
+                                const void *V, const void *rho, const void *P,
+                                const void *cs, const void *A, const void *B,
+                                const void *gradA, const void *gradB,
+                                const void *dv, double eta_crit,
+                                double eta_fold, double dt,
+                                const void *const a_grav[3],
+                                const void *const a_hydro[3], void *dudt);
+
 /* Short-range gravity inside the handover scale (Sec. IV-A, with the
  * long-range part left to a spectral particle-mesh solver):
  *   a_i = -G sum_{j != i, r_ij < r_c} m_j g(r_ij) x_ij / r_ij,
@@ -438,11 +462,11 @@ int crk_tree_free(crk_tree *tree);
  * the whole call (pass_ms) and of its main kernel alone (kernel_ms: the pair
  * kernel of each pass and the integrate kernel), and the number of
  * main-kernel launches.  Index order: 0 build_tree, 1 lists, 2 density,
- * 3 coefficients, 4 hydro, 5 gravity, 6 integrate, 7 velocity gradient.
- * Any array may be NULL. */
+ * 3 coefficients, 4 hydro, 5 gravity, 6 integrate, 7 velocity gradient,
+ * 8 compatible energy rate.  Any array may be NULL. */
 int crk_timing_enable(crk_ctx *ctx, int enable);
-int crk_pass_times(crk_ctx *ctx, double pass_ms[8], double kernel_ms[8],
-                   int64_t launches[8]);
+int crk_pass_times(crk_ctx *ctx, double pass_ms[9], double kernel_ms[9],
+                   int64_t launches[9]);
 
 #ifdef __cplusplus
 }

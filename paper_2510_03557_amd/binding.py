@@ -22,7 +22,7 @@ CRK_OK, CRK_EINVAL, CRK_ECAPACITY, CRK_EDEVICE, CRK_ESTATE = 0, -1, -2, -3, -4
 CRK_ESTALE = -5
 CRK_FP64, CRK_FP32 = 0, 1
 PASS_NAMES = ("tree", "lists", "density", "coefficients", "hydro", "gravity",
-              "integrate", "velocity_gradient")
+              "integrate", "velocity_gradient", "energy")
 
 EXPORTS = (
     "crk_ctx_create", "crk_ctx_destroy", "crk_set_tuning", "crk_get_tuning",
@@ -34,6 +34,7 @@ EXPORTS = (
     "crk_pass_times", "crk_timestep_bins", "crk_tree_set_active",
     "crk_tree_refit", "crk_kick", "crk_drift", "crk_pm_gravity", "crk_fof",
     "crk_velocity_gradient", "crk_hydro_forces_limited",
+    "crk_hydro_energy_compatible",
 )
 
 
@@ -127,6 +128,8 @@ def load(path: Path | str | None = None):
     lib.crk_velocity_gradient.argtypes = [vp] * 11
     lib.crk_hydro_forces_limited.argtypes = [vp] * 15 + [ctypes.c_double] * 2 \
         + [vp] * 4
+    lib.crk_hydro_energy_compatible.argtypes = [vp] * 15 + \
+        [ctypes.c_double] * 3 + [ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.shortrange_gravity.argtypes = [vp] * 10
     lib.crk_integrate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp, vp,
                                   vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -282,6 +285,18 @@ class Context:
             _ptr(gB), _ptr(dv), float(eta_crit), float(eta_fold), _ptr(ax),
             _ptr(ay), _ptr(az), _ptr(dudt)))
 
+    def hydro_energy_compatible(self, tree, m, vx, vy, vz, V, rho, P, cs, A,
+                                B, gA, gB, dv, eta_crit, eta_fold, dt, a_grav,
+                                a_hydro, dudt):
+        P3 = ctypes.c_void_p * 3
+        ag = P3(*[t.data_ptr() for t in a_grav]) if a_grav is not None else None
+        ah = P3(*[t.data_ptr() for t in a_hydro]) if a_hydro is not None else None
+        check(self.lib.crk_hydro_energy_compatible(
+            self.handle, tree.handle, _ptr(m), _ptr(vx), _ptr(vy), _ptr(vz),
+            _ptr(V), _ptr(rho), _ptr(P), _ptr(cs), _ptr(A), _ptr(B), _ptr(gA),
+            _ptr(gB), _ptr(dv), float(eta_crit), float(eta_fold), float(dt),
+            ag, ah, _ptr(dudt)))
+
     def shortrange_gravity(self, tree, m_gas, m_dm, axg, ayg, azg, axd, ayd,
                            azd):
         check(self.lib.shortrange_gravity(
@@ -365,9 +380,9 @@ class Context:
         check(self.lib.crk_timing_enable(self.handle, int(bool(enable))))
 
     def pass_times(self):
-        a = (ctypes.c_double * 8)()
-        b = (ctypes.c_double * 8)()
-        c = (ctypes.c_int64 * 8)()
+        a = (ctypes.c_double * 9)()
+        b = (ctypes.c_double * 9)()
+        c = (ctypes.c_int64 * 9)()
         check(self.lib.crk_pass_times(self.handle, a, b, c))
         return ({k: a[i] for i, k in enumerate(PASS_NAMES)},
                 {k: b[i] for i, k in enumerate(PASS_NAMES)},

@@ -373,6 +373,43 @@ int crk_hydro_forces(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                       nullptr, 0.0, 1.0, ax, ay, az, dudt);
 }
 
+int crk_hydro_energy_compatible(crk_ctx *ctx, crk_tree *t, const void *m,
+                                const void *vx, const void *vy, const void *vz,
+                                const void *V, const void *rho, const void *P,
+                                const void *cs, const void *A, const void *B,
+                                const void *gradA, const void *gradB,
+                                const void *dv, double eta_crit,
+                                double eta_fold, double dt,
+                                const void *const a_grav[3],
+                                const void *const a_hydro[3], void *dudt) {
+    CRK_TRY(check_tree_ready(ctx, t, true));
+    const size_t el = ctx->elem();
+    const bool g = t->n_gas > 0;
+    const void *ins[] = {m, vx, vy, vz, V, rho, P, cs, A, B, gradA, gradB};
+    const char *in_names[] = {"m", "vx", "vy", "vz", "V", "rho", "P", "cs",
+                              "A", "B", "gradA", "gradB"};
+    for (int k = 0; k < 12; ++k) CRK_TRY(check_ptr(ins[k], el, in_names[k], g));
+    CRK_TRY(check_ptr(dudt, el, "dudt", g));
+    if (!std::isfinite(dt)) return set_error(CRK_EINVAL, "dt must be finite");
+    if (g && !a_grav) return set_error(CRK_EINVAL, "null pointer array a_grav");
+    for (int a = 0; a < 3 && g; ++a) {
+        CRK_TRY(check_ptr(a_grav[a], el, "a_grav", true));
+        if (a_hydro) CRK_TRY(check_ptr(a_hydro[a], el, "a_hydro", true));
+    }
+    if (dv) {
+        CRK_TRY(check_ptr(dv, el, "dv", g));
+        if (!(eta_crit >= 0.0) || !std::isfinite(eta_crit) ||
+            !(eta_fold > 0.0) || !std::isfinite(eta_fold))
+            return set_error(CRK_EINVAL,
+                             "eta_crit must be finite and >= 0, eta_fold finite and > 0");
+    }
+    if (!g) return CRK_OK;
+    PassSpan sp(ctx, P_ENERGY);
+    return pass_energy_compatible(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B,
+                                  gradA, gradB, dv, eta_crit, eta_fold, dt,
+                                  a_grav, a_hydro, dudt);
+}
+
 int crk_velocity_gradient(crk_ctx *ctx, crk_tree *t, const void *vx,
                           const void *vy, const void *vz, const void *V,
                           const void *A, const void *B, const void *gradA,
@@ -738,8 +775,8 @@ int crk_timing_enable(crk_ctx *ctx, int enable) {
     return CRK_OK;
 }
 
-int crk_pass_times(crk_ctx *ctx, double pass_ms[8], double kernel_ms[8],
-                   int64_t launches[8]) {
+int crk_pass_times(crk_ctx *ctx, double pass_ms[9], double kernel_ms[9],
+                   int64_t launches[9]) {
     CRK_TRY(check_ctx(ctx));
     if (ctx->capturing) return set_error(CRK_ESTATE, "query during capture");
     CRK_HIP(hipStreamSynchronize(ctx->stream));

@@ -71,7 +71,7 @@ struct HostBuf {
 
 enum PassId {
     P_TREE = 0, P_LISTS, P_DENSITY, P_COEFF, P_HYDRO, P_GRAV, P_INTEG, P_VGRAD,
-    P_COUNT
+    P_ENERGY, P_COUNT
 };
 
 // long-range mesh workspace (pm.hip): double deposit mesh, real mesh and
@@ -251,6 +251,14 @@ int pass_hydro(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                const void *B, const void *gradA, const void *gradB,
                const void *dv, double eta_crit, double eta_fold, void *ax,
                void *ay, void *az, void *dudt);
+int pass_energy_compatible(crk_ctx *ctx, crk_tree *t, const void *m,
+                           const void *vx, const void *vy, const void *vz,
+                           const void *V, const void *rho, const void *P,
+                           const void *cs, const void *A, const void *B,
+                           const void *gradA, const void *gradB, const void *dv,
+                           double eta_crit, double eta_fold, double dt,
+                           const void *const a_grav[3],
+                           const void *const a_hydro[3], void *dudt);
 int pass_velocity_gradient(crk_ctx *ctx, crk_tree *t, const void *vx,
                            const void *vy, const void *vz, const void *V,
                            const void *A, const void *B, const void *gradA,

@@ -1017,16 +1017,31 @@ template <typename T> struct CoeffPass {
 //   with the reconstruction: 28..33 the symmetric part of the velocity
 //   gradient as the quadratic form x.dv x needs it: dv00 dv11 dv22
 //   dv01+dv10 dv02+dv20 dv12+dv21
+//   for the compatible energy update, after those: the velocities after the
+//   kick, v1 = v + dt (a_grav + a_hydro) (3 planes)
 // The corrected-kernel gradient of particle k at separation y:
 //   g_k(y)_g = (1 + B.y)(da_g w + a wq ih2 y_g) + w (sum_x adb[g][x] y_x + ab_g)
 constexpr int HF = 28;
 constexpr int HF_RECON = HF + 6;
+constexpr int HF_MAX = HF_RECON + 3;
+
+// optional inputs of the hydro field gather
+template <typename T> struct GatherExtra {
+    const T *dv = nullptr;           // velocity gradient, 9 caller planes
+    const T *ag[3] = {nullptr, nullptr, nullptr};  // kick accelerations
+    const T *ah[3] = {nullptr, nullptr, nullptr};
+    double dt = 0.0;
+    int w0 = HF;                     // first plane of v1
+};
 
 // RECON: the viscosity acts on both velocities extrapolated linearly to the
 // pair midpoint, v~_ij = v_ij - phi/2 (dv_i + dv_j) x_ij, with the limiter
 // phi = 4 s_i s_j / (s_i + s_j)^2 (0 unless s_i s_j > 0), s_k = x.dv_k x,
-// damped by exp(-((eta - eta_c) / eta_f)^2) for eta = r / max(h) < eta_c
-template <typename T, bool RECON = false> struct HydroPass {
+// damped by exp(-((eta - eta_c) / eta_f)^2) for eta = r / max(h) < eta_c.
+// WORK: the same pair forces, but only du/dt, with the pair work taken at
+// the time-centred velocities (v + v1)/2 of the kick v1 (the compatible
+// energy update)
+template <typename T, bool RECON = false, bool WORK = false> struct HydroPass {
     struct Args {
         const T *f;       // HFN planes of n_gas, tree order
         int64_t n_gas;
@@ -1035,7 +1050,8 @@ template <typename T, bool RECON = false> struct HydroPass {
         T Cl, Cq, epsQ;
         T eta_c, ieta_f;  // close-pair scale and 1 / its width (RECON)
     };
-    static constexpr int HFN = RECON ? HF_RECON : HF;
+    static constexpr int W0 = RECON ? HF_RECON : HF;  // v1 planes (WORK)
+    static constexpr int HFN = W0 + (WORK ? 3 : 0);
     // candidate record: fx fy fz, one pad, the HFN fields from float FO on
     // (16-byte aligned, so they load as 128-bit LDS reads), padded to an odd
     // number of 16-byte units (36 or 44 floats): records read by different
@@ -1170,19 +1186,29 @@ template <typename T, bool RECON = false> struct HydroPass {
             const T F0 = k * (ci * gi[0] - cj * gj[0]);
             const T F1 = k * (ci * gi[1] - cj * gj[1]);
             const T F2 = k * (ci * gi[2] - cj * gj[2]);
-            tl.s[0] += F0;
-            tl.s[1] += F1;
-            tl.s[2] += F2;
-            tl.s[3] = fma(v0, F0, fma(v1, F1, fma(v2, F2, tl.s[3])));
+            if constexpr (WORK) {
+                const T *wi = fi + W0, *wj = fj + W0;
+                const T c0 = T(0.5) * (v0 + (wi[0] - wj[0]));
+                const T c1 = T(0.5) * (v1 + (wi[1] - wj[1]));
+                const T c2 = T(0.5) * (v2 + (wi[2] - wj[2]));
+                tl.s[3] = fma(c0, F0, fma(c1, F1, fma(c2, F2, tl.s[3])));
+            } else {
+                tl.s[0] += F0;
+                tl.s[1] += F1;
+                tl.s[2] += F2;
+                tl.s[3] = fma(v0, F0, fma(v1, F1, fma(v2, F2, tl.s[3])));
+            }
         }
     }
     __device__ static void finish(const Acc &ac, const I &, const Args &a,
                                   const TreeView<T> &tv, int i) {
         const int c = tv.perm[i];
         const double im = 1.0 / (double)a.m[i];
-        a.ax[c] = (T)(ac.a.c[0].value() * im);
-        a.ay[c] = (T)(ac.a.c[1].value() * im);
-        a.az[c] = (T)(ac.a.c[2].value() * im);
+        if constexpr (!WORK) {
+            a.ax[c] = (T)(ac.a.c[0].value() * im);
+            a.ay[c] = (T)(ac.a.c[1].value() * im);
+            a.az[c] = (T)(ac.a.c[2].value() * im);
+        }
         a.dudt[c] = (T)(-0.5 * ac.a.c[3].value() * im);
     }
 };
@@ -1695,7 +1721,7 @@ __global__ void hydro_gather_kernel(
     const T *__restrict__ rho, const T *__restrict__ P,
     const T *__restrict__ cs, const T *__restrict__ A,
     const T *__restrict__ B, const T *__restrict__ gA,
-    const T *__restrict__ gB, const T *__restrict__ dv, T *__restrict__ f,
+    const T *__restrict__ gB, const GatherExtra<T> ex, T *__restrict__ f,
     T *__restrict__ mt) {
     GRID_STRIDE(p, n) {
         const int c = perm[p];
@@ -1723,14 +1749,23 @@ __global__ void hydro_gather_kernel(
             f[27 * n + p] = cs[c];
             mt[p] = m[c];
         }
-        if (dv) {
-            const T *d = dv + c;
+        if (ex.dv) {
+            const T *d = ex.dv + c;
             f[(HF + 0) * n + p] = d[0];
             f[(HF + 1) * n + p] = d[4 * n];
             f[(HF + 2) * n + p] = d[8 * n];
             f[(HF + 3) * n + p] = d[1 * n] + d[3 * n];
             f[(HF + 4) * n + p] = d[2 * n] + d[6 * n];
             f[(HF + 5) * n + p] = d[5 * n] + d[7 * n];
+        }
+        if (ex.ag[0]) {
+            const T *vv[3] = {vx, vy, vz};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                double acc = (double)ex.ag[a][c];
+                if (ex.ah[a]) acc += (double)ex.ah[a][c];
+                f[(ex.w0 + a) * n + p] = (T)((double)vv[a][c] + ex.dt * acc);
+            }
         }
     }
 }
@@ -1901,10 +1936,10 @@ template <typename T>
 int hydro_fields(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                  const void *vy, const void *vz, const void *V, const void *rho,
                  const void *P, const void *cs, const void *A, const void *B,
-                 const void *gA, const void *gB, const void *dv) {
+                 const void *gA, const void *gB, const GatherExtra<T> &ex) {
     const int64_t ng = t->n_gas;
     const size_t n1 = std::max<int64_t>(ng, 1);
-    CRK_TRY(t->pf[7].ensure(n1 * HF_RECON * sizeof(T), ctx->capturing));
+    CRK_TRY(t->pf[7].ensure(n1 * HF_MAX * sizeof(T), ctx->capturing));
     CRK_TRY(t->pf[4].ensure(n1 * sizeof(T), ctx->capturing));
     hipLaunchKernelGGL((hydro_gather_kernel<T>), dim3(grid_for(ng)), dim3(256),
                        0, ctx->stream, t->perm.as<int32_t>(), ng, t->hsm.as<T>(),
@@ -1914,8 +1949,7 @@ int hydro_fields(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                        static_cast<const T *>(P), static_cast<const T *>(cs),
                        static_cast<const T *>(A), static_cast<const T *>(B),
                        static_cast<const T *>(gA), static_cast<const T *>(gB),
-                       static_cast<const T *>(dv), t->pf[7].as<T>(),
-                       t->pf[4].as<T>());
+                       ex, t->pf[7].as<T>(), t->pf[4].as<T>());
     CRK_HIP(hipGetLastError());
     return CRK_OK;
 }
@@ -1926,8 +1960,10 @@ int hydro_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                const void *P, const void *cs, const void *A, const void *B,
                const void *gA, const void *gB, const void *dv, double eta_c,
                double eta_f, void *ax, void *ay, void *az, void *dudt) {
+    GatherExtra<T> ex;
+    ex.dv = static_cast<const T *>(dv);
     CRK_TRY(hydro_fields<T>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB,
-                            dv));
+                            ex));
     const int64_t ng = t->n_gas;
     T *f = t->pf[7].as<T>(), *mt = t->pf[4].as<T>();
     const TreeView<T> tv = tree_view<T>(t, true, gas_leaf_count(t));
@@ -1950,11 +1986,48 @@ int hydro_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
 }
 
 template <typename T>
+int energy_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
+                const void *vy, const void *vz, const void *V, const void *rho,
+                const void *P, const void *cs, const void *A, const void *B,
+                const void *gA, const void *gB, const void *dv, double eta_c,
+                double eta_f, double dt, const void *const ag[3],
+                const void *const ah[3], void *dudt) {
+    GatherExtra<T> ex;
+    ex.dv = static_cast<const T *>(dv);
+    for (int a = 0; a < 3; ++a) {
+        ex.ag[a] = static_cast<const T *>(ag[a]);
+        ex.ah[a] = ah ? static_cast<const T *>(ah[a]) : nullptr;
+    }
+    ex.dt = dt;
+    ex.w0 = dv ? HF_RECON : HF;
+    CRK_TRY(hydro_fields<T>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB,
+                            ex));
+    const int64_t ng = t->n_gas;
+    T *f = t->pf[7].as<T>(), *mt = t->pf[4].as<T>();
+    const TreeView<T> tv = tree_view<T>(t, true, gas_leaf_count(t));
+    if (dv) {
+        typename HydroPass<T, true, true>::Args pa{
+            f, ng, nullptr, nullptr, nullptr, static_cast<T *>(dudt), mt,
+            (T)ctx->params.Cl, (T)ctx->params.Cq, (T)ctx->params.epsQ,
+            (T)eta_c, (T)(1.0 / eta_f)};
+        return launch_pair<T, HydroPass<T, true, true>>(ctx, t, tv, pa,
+                                                        gas_bound(ctx, t), P_ENERGY,
+                                                        true);
+    }
+    typename HydroPass<T, false, true>::Args pa{
+        f, ng, nullptr, nullptr, nullptr, static_cast<T *>(dudt), mt,
+        (T)ctx->params.Cl, (T)ctx->params.Cq, (T)ctx->params.epsQ, T(0), T(0)};
+    return launch_pair<T, HydroPass<T, false, true>>(ctx, t, tv, pa,
+                                                     gas_bound(ctx, t), P_ENERGY,
+                                                     true);
+}
+
+template <typename T>
 int vgrad_impl(crk_ctx *ctx, crk_tree *t, const void *vx, const void *vy,
                const void *vz, const void *V, const void *A, const void *B,
                const void *gA, const void *gB, void *dv) {
     CRK_TRY(hydro_fields<T>(ctx, t, nullptr, vx, vy, vz, V, nullptr, nullptr,
-                            nullptr, A, B, gA, gB, nullptr));
+                            nullptr, A, B, gA, gB, GatherExtra<T>()));
     typename VGradPass<T>::Args pa{t->pf[7].as<T>(), t->n_gas,
                                    static_cast<T *>(dv)};
     return launch_pair<T, VGradPass<T>>(ctx, t, tree_view<T>(t, true, gas_leaf_count(t)),
@@ -2060,6 +2133,23 @@ int pass_hydro(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                                   az, dudt);
     return hydro_impl<float>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gradA,
                              gradB, dv, eta_crit, eta_fold, ax, ay, az, dudt);
+}
+
+int pass_energy_compatible(crk_ctx *ctx, crk_tree *t, const void *m,
+                           const void *vx, const void *vy, const void *vz,
+                           const void *V, const void *rho, const void *P,
+                           const void *cs, const void *A, const void *B,
+                           const void *gradA, const void *gradB, const void *dv,
+                           double eta_crit, double eta_fold, double dt,
+                           const void *const a_grav[3],
+                           const void *const a_hydro[3], void *dudt) {
+    if (ctx->precision == CRK_FP64)
+        return energy_impl<double>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B,
+                                   gradA, gradB, dv, eta_crit, eta_fold, dt,
+                                   a_grav, a_hydro, dudt);
+    return energy_impl<float>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gradA,
+                              gradB, dv, eta_crit, eta_fold, dt, a_grav,
+                              a_hydro, dudt);
 }
 
 int pass_velocity_gradient(crk_ctx *ctx, crk_tree *t, const void *vx,

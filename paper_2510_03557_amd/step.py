@@ -19,17 +19,20 @@ class ShortRangeStep:
     four passes (and crk_integrate when ``integrate`` is set) on the
     context's stream.  With ``recon`` the hydro forces take the velocity
     gradient and the viscosity on the limited midpoint reconstruction
-    (crk_velocity_gradient, then crk_hydro_forces_limited)."""
+    (crk_velocity_gradient, then crk_hydro_forces_limited).  With
+    ``compatible`` the integration's energy update takes the compatible rate
+    (crk_hydro_energy_compatible before crk_integrate; flat steps only)."""
 
     def __init__(self, wl, precision: str = "fp32", tuning: dict | None = None,
                  dt: float = 0.0, device: str = "cuda", params=None,
                  recon: bool = False, eta_crit: float = 0.8,
-                 eta_fold: float = 0.2):
+                 eta_fold: float = 0.2, compatible: bool = False):
         import torch
         self.torch = torch
         self.wl = wl
         self.dt = float(dt)
         self.recon = bool(recon)
+        self.compatible = bool(compatible)
         self.eta_crit, self.eta_fold = float(eta_crit), float(eta_fold)
         self.ctx = Context(precision, params=params)
         if tuning:
@@ -102,6 +105,13 @@ class ShortRangeStep:
 
     def integrate(self):
         c = self.ctx
+        if self.ng and self.compatible:
+            c.hydro_energy_compatible(
+                self.tree, self.gm, self.gvx, self.gvy, self.gvz, self.V,
+                self.rho, self.P, self.cs, self.A, self.B, self.gA, self.gB,
+                self.dv if self.recon else None, self.eta_crit, self.eta_fold,
+                self.dt, (self.agx, self.agy, self.agz),
+                (self.ahx, self.ahy, self.ahz), self.dudt)
         if self.ng:
             c.integrate(self.ng, self.dt, self.gx64, self.gv64, self.gu64,
                         (self.agx, self.agy, self.agz),
@@ -226,6 +236,9 @@ class ShortRangeStep:
         timestep_bins.  With pm_mesh (single box), the long-range mesh
         force brackets the interval: a half-kick of every particle before
         the first substep and after the last one (positions wrapped)."""
+        if self.compatible:
+            raise ValueError("the compatible energy update is built for flat "
+                             "steps only")
         c, t, wl = self.ctx, self.tree, self.wl
         L = int(max_level)
         if pm_mesh:
