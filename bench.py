@@ -46,9 +46,9 @@ def kernel_name(p: str, tuning: dict) -> str:
     """The float32 kernel a pass launches under a tuning (as rocprofv3 names
     it, namespaces dropped)."""
     t = PASS_TYPES[p]
-    # (the hydro pass is a template on the reconstruction; the step's plain
-    # form is the "false" instance)
-    t = t + "<float, false>" if p == "hydro" else t + "<float>"
+    # (the hydro pass is a template on the reconstruction and the
+    # compatible-energy form; the step's plain form is <false, false>)
+    t = t + "<float, false, false>" if p == "hydro" else t + "<float>"
     L = tuning.get("leaf_max", 64)
     if tuning.get("grid_mult", 0) > 0:
         b = 64 if L <= 64 else (128 if L <= 128 else 256)
@@ -236,7 +236,11 @@ def measure_recon(wl, tuning, steps, warmup, gather_pairs, hydro_pairs,
                 "launch": "hip_graph",
                 "energy_pass_ms": round(cpass_ms["energy"] / n_eager, 4),
                 "energy_kernel_ms": round(ckern_ms["energy"]
-                                          / max(claunch["energy"], 1), 4)}}
+                                          / max(claunch["energy"], 1), 4),
+                "energy_tflops": round(
+                    hydro_pairs * RECON_FLOP_PER_PAIR["hydro"]
+                    / (ckern_ms["energy"] / max(claunch["energy"], 1) * 1e-3)
+                    / 1e12, 3)}}
 
 
 def measure_pm(wl, reps, log):

@@ -1117,13 +1117,15 @@ template <typename T, bool RECON = false, bool WORK = false> struct HydroPass {
 #pragma unroll
         for (int k = FO + HFN; k < NJ; ++k) d[k] = T(0);
     }
-    // gradient of the corrected kernel of particle with fields f at y
+    // gradient of the corrected kernel of particle with fields f at y (and
+    // q = r / h of that particle)
     __device__ static void grad_rk(const T *f, T y0, T y1, T y2, T r2, T out[3],
-                                   bool &on) {
+                                   bool &on, T &qo) {
         const T q2 = r2 * f[3];
         on = q2 < T(4);
         const T rq = rsq(q2);
         const T q = q2 > T(0) ? q2 * rq : T(0);
+        qo = q;
         T w, wq;
         spline(q, rq, w, wq);
         const T by1 = T(1) + f[8] * y0 + f[9] * y1 + f[10] * y2;
@@ -1149,10 +1151,10 @@ template <typename T, bool RECON = false, bool WORK = false> struct HydroPass {
         // LDS read of the j-side 1/h^2)
         const bool near = (r2 * fi[3] < T(4)) | (r2 * fj[3] < T(4));
         if (near & !self) {
-            T gi[3], gj[3];
+            T gi[3], gj[3], qi, qj;
             bool oi, oj;
-            grad_rk(fi, x0, x1, x2, r2, gi, oi);
-            grad_rk(fj, -x0, -x1, -x2, r2, gj, oj);
+            grad_rk(fi, x0, x1, x2, r2, gi, oi, qi);
+            grad_rk(fj, -x0, -x1, -x2, r2, gj, oj, qj);
             const T v0 = fi[0] - fj[0], v1 = fi[1] - fj[1], v2 = fi[2] - fj[2];
             T vdx = v0 * x0 + v1 * x1 + v2 * x2;
             const T hi_ = fi[23], hj_ = fj[23];
@@ -1168,8 +1170,8 @@ template <typename T, bool RECON = false, bool WORK = false> struct HydroPass {
                              fma(Dj[3], q01, fma(Dj[4], q02, Dj[5] * q12)))));
                 const T sp = si + sj;
                 T phi = si * sj > T(0) ? T(4) * si * sj * rcp(sp * sp) : T(0);
-                const T r = r2 > T(0) ? r2 * rsq(r2) : T(0);
-                const T eta = r * rcp(hi_ > hj_ ? hi_ : hj_);
+                // eta = r / max(h_i, h_j) = min(q_i, q_j)
+                const T eta = qi < qj ? qi : qj;
                 const T te = (eta - is.eta_c) * is.ieta_f;
                 phi = eta < is.eta_c ? phi * fexp(-te * te) : phi;
                 vdx = fma(T(-0.5) * phi, sp, vdx);
@@ -1288,9 +1290,9 @@ template <typename T> struct VGradPass {
     __device__ static void pair(Tile &tl, const I &is, const T *jd, bool) {
         const T x0 = is.ex - jd[0], x1 = is.ey - jd[1], x2 = is.ez - jd[2];
         const T r2 = x0 * x0 + x1 * x1 + x2 * x2;
-        T g[3];
+        T g[3], q;
         bool on;
-        HydroPass<T>::grad_rk(is.f, x0, x1, x2, r2, g, on);
+        HydroPass<T>::grad_rk(is.f, x0, x1, x2, r2, g, on, q);
         if (on) {
             const T d0 = jd[3] * (jd[4] - is.f[0]);
             const T d1 = jd[3] * (jd[5] - is.f[1]);

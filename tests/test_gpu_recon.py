@@ -163,6 +163,33 @@ def test_zeldovich128_fp32_graph(orc, step_cls):
         st.close()
 
 
+@pytest.mark.parametrize("tuning", [dict(grid_mult=16), dict(xcd_remap=1),
+                                    dict(walk_mask=1 << 2),
+                                    dict(grid_mult=8, leaf_max=128)])
+def test_launch_shapes_are_bitwise_identical(step_cls, tuning):
+    """The queue, the XCD remap and the per-lane hit walk change only which
+    workgroup or lane runs a leaf: the gradient and the reconstructed forces
+    are bitwise those of one workgroup per leaf with the broadcast sweep."""
+    print(f"case recon launch shape {tuning}", flush=True)
+    wl = W.random_uniform(6000, 3000, 1601, n_ngb=48.0, clustered=True)
+    L = tuning.get("leaf_max", 64)
+    base = dict(leaf_max=L, sub_sweep=0, xcd_remap=0)
+    ref = run(step_cls, wl, "fp32", tuning=base)
+    got = run(step_cls, wl, "fp32", tuning=dict(base, **tuning))
+    for k in ("dv", "a_hydro", "dudt"):
+        assert np.array_equal(ref[k], got[k]), k
+
+
+def test_sub_leaf_sweep_matches_whole_leaf_sweep(orc, step_cls):
+    """The benchmark's split sweep (a wavefront per sub-leaf) against the
+    whole-leaf sweep: only the summation order differs."""
+    print("case recon split sweep vs whole-leaf sweep fp32", flush=True)
+    wl = W.random_uniform(6000, 3000, 1602, n_ngb=48.0, clustered=True)
+    a = run(step_cls, wl, "fp32", tuning=dict(leaf_max=64, sub_sweep=0))
+    b = run(step_cls, wl, "fp32", tuning=dict(leaf_max=64, sub_sweep=2))
+    compare(b, a, 2e-6, ("dv", "a_hydro", "dudt"))
+
+
 def test_argument_errors(step_cls):
     from paper_2510_03557_amd.binding import CrkError, CRK_EINVAL
     print("case recon argument errors", flush=True)
