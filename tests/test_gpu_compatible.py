@@ -73,6 +73,48 @@ def test_compatible_step_matches_oracle(orc, step_cls, seed, ng, nd, recon,
     assert rel_rms(r["dudt"], ref["dudt"]) > 1e-3
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_tiny_and_empty_boxes(orc, step_cls, precision):
+    """Boxes with one, two, three or no gas particles (a lone particle, and
+    singular moments: the degenerate coefficient branch feeds the gradient
+    and the limiter) and an empty box, batched with ordinary ones, with the
+    reconstruction and the compatible update."""
+    print(f"case compatible + recon tiny and empty boxes {precision}",
+          flush=True)
+    sizes = [(1, 0), (0, 1), (0, 0), (2, 1), (3, 2), (40, 30), (2000, 1500)]
+    boxes = [W.random_uniform(n, m, 1750 + k, n_ngb=20.0 if n < 100 else 48.0,
+                              h_spread=0.15,
+                              h_rule="knn" if n > 22 else "global")
+             for k, (n, m) in enumerate(sizes)]
+    wl = W.concat_boxes("tiny", boxes)
+    ref = orc.step(wl, recon=True)
+    assert (ref["degenerate"][:6] == 1).all()
+    dt = kick_dt(wl, ref)
+    r = orc.compatible_update(wl, ref, dt, recon=True)
+    st = step_cls(wl, precision=precision, dt=dt, recon=True,
+                  compatible=True)
+    try:
+        st.run(integrate=True)
+        got = st.state()
+        out = st.outputs()
+    finally:
+        st.close()
+    g = wl.gas
+    v0 = np.array([g.vx, g.vy, g.vz], np.float64)
+    u0 = np.asarray(g.u, np.float64)
+    errs = dict(dv=rel_rms(out["dv"], ref["dv"]),
+                a_hydro=rel_rms(out["a_hydro"], ref["a_hydro"]),
+                dudt=rel_rms(out["dudt"], r["dudt"]),
+                du=rel_rms(got["u"] - u0, r["u1"] - u0),
+                dvel=rel_rms(got["vg"] - v0, r["v1"] - v0))
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    tol = FP64_TOL if precision == "fp64" else FP32_TOL
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, bad
+    # a lone gas particle: no neighbour, no gradient, no force
+    assert np.all(out["dv"][0] == 0) and np.all(out["a_hydro"][:, 0] == 0)
+
+
 def test_hydro_kick_conserves_energy_fp64(step_cls):
     """Hydro forces alone (no gravity in the kick): the compatible rate from
     the GPU makes sum m (v^2/2 + u) constant to rounding."""
@@ -83,9 +125,11 @@ def test_hydro_kick_conserves_energy_fp64(step_cls):
     try:
         st.run(passes=("density", "coefficients", "hydro"))
         c, t = st.ctx, st.tree
-        zeros = [torch.zeros_like(st.ahx) for _ in range(3)]
-        a = np.stack([st.ahx.cpu().numpy(), st.ahy.cpu().numpy(),
-                      st.ahz.cpu().numpy()])
+        # (outputs() waits for the library's stream)
+        a = st.outputs()["a_hydro"]
+        with torch.cuda.stream(c.stream):
+            zeros = [torch.zeros_like(st.ahx) for _ in range(3)]
+        c.stream.synchronize()
         g = wl.gas
         v = np.array([g.vx, g.vy, g.vz], np.float64)
         dt = 0.2 * np.abs(v).max() / np.abs(a).max()

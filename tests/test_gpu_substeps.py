@@ -80,6 +80,9 @@ def _bins_case(orc, ctx, n, dt, L, eps, c_cfl, eta, ag, ah, h, cs):
     dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda()
            for a in (*ag, *ah, h, cs)]
     bins = torch.zeros(n, dtype=torch.int32, device="cuda")
+    # (the inputs and the zero fill are on torch's stream, the library works
+    # on its own)
+    torch.cuda.synchronize()
     ctx.timestep_bins(n, dt, L, eps, c_cfl, eta, dev[0:3], dev[3:6], dev[6],
                       dev[7], bins)
     ctx.stream.synchronize()
