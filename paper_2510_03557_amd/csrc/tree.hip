@@ -760,7 +760,7 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
             lmn[2] = min(lmn[2], kz);
             lmx[2] = max(lmx[2], kz);
         }
-        if (t < 3 * 64) (&hist[0][0])[t] = 0;
+        for (int k = t; k < 3 * 64; k += SEG_TB) (&hist[0][0])[k] = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             for (int off = 32; off > 0; off >>= 1) {
