@@ -25,7 +25,9 @@
  *   per-box offsets of the gas and dm arrays; boxes do not interact.
  * - All work is enqueued asynchronously on the context's stream; no entry
  *   point synchronises except build_tree / build_interaction_lists outside
- *   graph capture (they read back sizes) and crk_sync.
+ *   graph capture (they read back sizes), crk_sync, and the calls whose
+ *   comment says so (crk_tree_set_active, crk_tree_refit, crk_count_pairs,
+ *   crk_pass_times, crk_tree_get_info after a synchronising build).
  * - Return value: CRK_OK or a negative crk_status; the message of the last
  *   failure on the calling thread is returned by crk_last_error().
  *   Argument errors are detected on the host before anything is enqueued.
