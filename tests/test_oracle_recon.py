@@ -71,10 +71,11 @@ def test_gradient_of_linear_field_is_exact(orc):
     assert ok.sum() > 0.98 * ok.size
     err = np.abs(dv[ok] - M[None]).max()
     assert err < 1e-10 * np.abs(M).max(), err
-    # the oracle's gradient is the gradient of the field, not a plain SPH
-    # estimate: that one (with the uncorrected kernel) misses at the edge
+    # particles within h of the patch edge (truncated neighbourhoods, where
+    # an uncorrected kernel estimate would be far off) are among those held
+    # to the bound above
     d_edge = np.min(np.minimum(P - 1.3, 1.7 - P), axis=0) < h
-    assert d_edge.any()
+    assert (ok & d_edge).sum() > 50
 
 
 def test_gradient_of_rotation_and_uniform_flow(orc):
@@ -184,3 +185,21 @@ def test_recon_step_tree_equals_brute_and_sampled(orc):
         assert np.abs(s[k] - a[k][gt]).max() <= 1e-12 * np.abs(a[k]).max(), k
     assert np.abs(s["a_hydro"] - a["a_hydro"][:, gt]).max() <= \
         1e-12 * np.abs(a["a_hydro"]).max()
+
+
+def test_golden_tiny_recon(orc):
+    """The oracle still reproduces the reconstructed-viscosity and
+    compatible-update outputs stored by tests/golden/make_golden.py."""
+    import json
+    import os
+    import sys
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    sys.path.insert(0, here)
+    import make_golden
+    with open(os.path.join(here, "tiny_recon.json")) as f:
+        ref = json.load(f)["outputs"]
+    out = make_golden.recon_outputs()
+    for k, v in ref.items():
+        v = np.asarray(v)
+        assert np.abs(np.asarray(out[k]) - v).max() <= \
+            1e-12 * max(np.abs(v).max(), 1e-300), k
