@@ -156,6 +156,29 @@ def test_hydro_kick_conserves_energy_fp64(step_cls):
     assert abs(E1p - E0) > 1e-7 * E0
 
 
+@pytest.mark.parametrize("recon", [False, True])
+def test_no_kick_gives_the_force_pass_rate_bitwise(step_cls, recon):
+    """dt = 0: v1 = v, the centred velocity difference is the actual one
+    and the compatible pass returns the force pass's du/dt to the bit."""
+    print(f"case compatible dt=0 recon={recon}", flush=True)
+    wl = W.random_uniform(3000, 1000, 841, n_ngb=48.0, h_spread=0.15,
+                          clustered=True)
+    st = step_cls(wl, precision="fp32", recon=recon)
+    try:
+        st.run()
+        ref = st.outputs()["dudt"]
+        c, t = st.ctx, st.tree
+        c.hydro_energy_compatible(t, st.gm, st.gvx, st.gvy, st.gvz, st.V,
+                                  st.rho, st.P, st.cs, st.A, st.B, st.gA,
+                                  st.gB, st.dv if recon else None, 0.8, 0.2,
+                                  0.0, (st.agx, st.agy, st.agz),
+                                  (st.ahx, st.ahy, st.ahz), st.dudt)
+        got = st.outputs()["dudt"]
+    finally:
+        st.close()
+    assert np.array_equal(got, ref)
+
+
 def test_compatible_graph_replay_equals_eager(step_cls):
     """Two steps with the compatible update: eager, and one eager step plus
     a captured step replayed, give the same state to the last bit."""
