@@ -1384,12 +1384,14 @@ template <typename T> struct GravityPass {
         const T r2 = dx * dx + dy * dy + dz * dz;
         return (r2 > T(0)) && (r2 < is.rc2);
     }
-    // the mass is read under the range test, so the compiler skips the
-    // arithmetic when no lane of the wave is in range (frequent here: the
-    // candidates fill the leaf box widened by r_c)
+    // out-of-range pairs leave before the arithmetic: the wave skips it when
+    // no lane is in range (frequent here: the candidates fill the leaf box
+    // widened by r_c), and in-range lanes accumulate under the mask with no
+    // zero weight kept for the others
     __device__ static void pair(Tile &tl, const I &is, const T *jd, bool) {
         const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
         const T r2 = dx * dx + dy * dy + dz * dz;
+        if (!((r2 > T(0)) && (r2 < is.rc2))) return;
         const T rs = rsq(r2);
         const T r = r2 * rs;
         const T xi = r * is.two_rc;
@@ -1411,8 +1413,7 @@ template <typename T> struct GravityPass {
         const T rs3 = rs * rs * rs;
         const T gout = fma(rs3, val, plum);
         const T gr = xi < T(1) ? gin : gout;
-        const bool on = (r2 > T(0)) && (r2 < is.rc2);
-        const T w = on ? jd[3] * gr : T(0);
+        const T w = jd[3] * gr;
         tl.s[0] = fma(-w, dx, tl.s[0]);
         tl.s[1] = fma(-w, dy, tl.s[1]);
         tl.s[2] = fma(-w, dz, tl.s[2]);
