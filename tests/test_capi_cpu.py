@@ -60,3 +60,24 @@ def test_context_without_device_fails_cleanly(lib):
     st = lib.crk_ctx_create(ctypes.byref(h), binding.CRK_FP32, None, None)
     assert st == binding.CRK_EDEVICE
     assert not h.value
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """The binding refuses to run without the built HIP library (there is
+    no fallback path)."""
+    with pytest.raises(ImportError):
+        binding.load(tmp_path / "libcrk.so")
+
+
+def test_package_never_touches_the_oracle():
+    """The library, its binding and the step driver share no code with the
+    oracle: no import, include or link of anything under oracle/."""
+    pkg = ROOT / "paper_2510_03557_amd"
+    offenders = []
+    for f in list(pkg.rglob("*.py")) + list(pkg.rglob("*.hip")) + \
+            list(pkg.rglob("*.h")) + list((ROOT / "include").rglob("*.h")):
+        text = f.read_text()
+        if re.search(r"^\s*(import|from)\s+oracle\b", text, re.M) or \
+                "crk_oracle" in text or "libcrk_oracle" in text:
+            offenders.append(str(f.relative_to(ROOT)))
+    assert not offenders, offenders
