@@ -12,4 +12,5 @@ from .oracle import (  # noqa: F401
     kernel, grav_g, s2_force, neighbours, num_threads, step, step_sampled,
     STEP_PARAMS, timestep_bins, substep_cycle, s2_form_factor, pm_long_range,
     fof_labels, velocity_gradient, RECON, compatible_update,
+    fof_properties,
 )

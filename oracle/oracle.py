@@ -729,3 +729,29 @@ def fof_labels(x, y, z, b, brute=False):
     first = np.full(comp.max() + 1, n, np.int64)
     np.minimum.at(first, comp, np.arange(n))
     return first[comp]
+
+
+def fof_properties(x, y, z, m, labels):
+    """Per group of a friends-of-friends labelling (groups indexed by their
+    label, the smallest member index; Sec. IV-B.3 finds halos in situ):
+    member count, total mass and the periodic centre of mass -- every member
+    taken at its minimum image about the labelling particle, the
+    mass-weighted mean of those images, wrapped into [1, 2).  Returns
+    count (n,), mass (n,) and centre (3, n), zero at indices that label no
+    group."""
+    P = np.stack([np.asarray(a, np.float64) for a in (x, y, z)])
+    m = np.asarray(m, np.float64)
+    lab = np.asarray(labels, np.int64)
+    n = lab.shape[0]
+    count = np.bincount(lab, minlength=n).astype(np.int64)
+    mass = np.bincount(lab, weights=m, minlength=n)
+    com = np.zeros((3, n))
+    has = count > 0
+    for a in range(3):
+        d = P[a] - P[a][lab]
+        d = d - np.round(d)
+        s = np.bincount(lab, weights=m * d, minlength=n)
+        c = P[a] + np.where(has, s / np.where(has, mass, 1.0), 0.0)
+        c = np.where(c >= 2.0, c - 1.0, np.where(c < 1.0, c + 1.0, c))
+        com[a] = np.where(has, c, 0.0)
+    return count, mass, com

@@ -46,3 +46,55 @@ def test_labels_are_group_minima(orc):
     for g in np.unique(lab):
         members = np.nonzero(lab == g)[0]
         assert members.min() == g
+
+
+# ---------------------------------------------------------------------------
+# group properties
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("xa,xb,centre", [(1.995, 1.003, 1.999),
+                                         (1.998, 1.004, 1.001)])
+def test_properties_of_a_group_across_the_boundary(orc, xa, xb, centre):
+    """Two equal masses linked through the periodic boundary: the centre is
+    the midpoint of the minimum-image pair, wrapped into [1, 2)."""
+    x = np.array([xa, xb])
+    y = np.array([1.5, 1.5])
+    z = np.array([1.25, 1.25])
+    m = np.array([2.0, 2.0])
+    lab = orc.fof_labels(x, y, z, 0.02, brute=True)
+    assert lab.tolist() == [0, 0]
+    count, mass, com = orc.fof_properties(x, y, z, m, lab)
+    assert count.tolist() == [2, 0] and mass.tolist() == [4.0, 0.0]
+    assert abs(com[0, 0] - centre) < 1e-12
+    assert com[1, 0] == 1.5 and com[2, 0] == 1.25
+    assert np.all(com[:, 1] == 0.0)
+
+
+def test_properties_totals_singletons_and_translation(orc):
+    rng = np.random.default_rng(17)
+    n = 3000
+    P = 1.0 + rng.random((3, n))
+    # a few tight clumps, one of them across a corner of the box
+    for k, c in enumerate(([1.02, 1.97, 1.5], [1.5, 1.5, 1.5],
+                           [1.999, 1.001, 1.998])):
+        P[:, k * 40:(k + 1) * 40] = (np.asarray(c)[:, None] - 1.0 + 0.004
+                                     * rng.standard_normal((3, 40))) % 1.0 + 1.0
+    m = rng.uniform(0.5, 1.5, n)
+    lab = orc.fof_labels(*P, 0.005)
+    count, mass, com = orc.fof_properties(*P, m, lab)
+    assert count.sum() == n and abs(mass.sum() - m.sum()) < 1e-9
+    roots = np.unique(lab)
+    assert np.all(count[roots] > 0)
+    others = np.setdiff1d(np.arange(n), roots)
+    assert np.all(count[others] == 0) and np.all(mass[others] == 0)
+    assert count.max() >= 30
+    single = roots[count[roots] == 1]
+    assert np.array_equal(com[:, single], P[:, single])
+    # a periodic translation moves every centre by the same amount
+    s = np.array([0.3125, 0.625, 0.875])[:, None]
+    Q = (P - 1.0 + s) % 1.0 + 1.0
+    count2, mass2, com2 = orc.fof_properties(*Q, m, lab)
+    assert np.array_equal(count2, count)
+    d = (com2[:, roots] - com[:, roots] - s[:, :]) % 1.0
+    d = np.minimum(d, 1.0 - d)
+    assert d.max() < 1e-12
