@@ -433,6 +433,25 @@ typedef struct {
 } crk_tree_info;
 int crk_tree_get_info(const crk_tree *tree, crk_tree_info *info);
 
+/* Group properties of a friends-of-friends labelling (the in-situ halo
+ * finding of Sec. IV-B.3), for the labels crk_fof returns (group label =
+ * smallest combined caller index of its members: gas index, or n_gas + dm
+ * index).  Per index q of [0, n_gas + n_dm): count[q] members, mass[q]
+ * their total mass and centre (3 planes of n_gas + n_dm doubles, plane a at
+ * offset a (n_gas + n_dm)) the periodic centre of mass -- every member at
+ * its minimum image about particle q, the mass-weighted mean of the images,
+ * wrapped into [1, 2) -- at the indices that label a group; 0 elsewhere.
+ * Sums in double with atomics (their order, so the last bits, may vary).
+ * gas_x, dm_x: 3 pointers each to positions (context precision, caller
+ * order); m_gas, m_dm: masses; labels: int32, caller order.  Labels outside
+ * [0, n_gas + n_dm) are skipped and reported by crk_sync (CRK_EINVAL).
+ * Outputs are overwritten (cleared by the call).  Needs no tree. */
+int crk_fof_properties(crk_ctx *ctx, int64_t n_gas, int64_t n_dm,
+                       const int32_t *labels_gas, const int32_t *labels_dm,
+                       const void *const gas_x[3], const void *m_gas,
+                       const void *const dm_x[3], const void *m_dm,
+                       int32_t *count, double *mass, double *centre);
+
 /* Pair counts under each pass's own pair test (a diagnostic for throughput
  * accounting; synchronises).  totals[0]: gas pairs with r_ij < 2 h_i, i = j
  * included (density and coefficients); totals[1]: gas pairs i != j with

@@ -34,7 +34,7 @@ EXPORTS = (
     "crk_pass_times", "crk_timestep_bins", "crk_tree_set_active",
     "crk_tree_refit", "crk_kick", "crk_drift", "crk_pm_gravity", "crk_fof",
     "crk_velocity_gradient", "crk_hydro_forces_limited",
-    "crk_hydro_energy_compatible",
+    "crk_hydro_energy_compatible", "crk_fof_properties",
 )
 
 
@@ -158,6 +158,8 @@ def load(path: Path | str | None = None):
     lib.crk_pm_gravity.argtypes = [vp, i32, f64, i64, vp, vp, vp, vp, i64, vp,
                                    vp, vp, vp, P, P]
     lib.crk_fof.argtypes = [vp, vp, f64, vp, vp]
+    lib.crk_fof_properties.argtypes = [vp, i64, i64, vp, vp, P, vp, P, vp,
+                                       vp, vp, vp]
     for name in EXPORTS:
         getattr(lib, name).restype = (ctypes.c_char_p if name == "crk_last_error"
                                       else ctypes.c_int)
@@ -359,6 +361,13 @@ class Context:
     def fof(self, tree, b, labels_gas, labels_dm):
         check(self.lib.crk_fof(self.handle, tree.handle, float(b),
                                _ptr(labels_gas), _ptr(labels_dm)))
+
+    def fof_properties(self, n_gas, n_dm, labels_gas, labels_dm, gas_x, m_gas,
+                       dm_x, m_dm, count, mass, centre):
+        check(self.lib.crk_fof_properties(
+            self.handle, int(n_gas), int(n_dm), _ptr(labels_gas),
+            _ptr(labels_dm), self._p3(gas_x), _ptr(m_gas), self._p3(dm_x),
+            _ptr(m_dm), _ptr(count), _ptr(mass), _ptr(centre)))
 
     def count_pairs(self, tree):
         """In-range ordered pairs (gather, hydro, gravity), then the swept

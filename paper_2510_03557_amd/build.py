@@ -11,7 +11,7 @@ HERE = Path(__file__).resolve().parent
 CSRC = HERE / "csrc"
 OUT = HERE / "libcrk.so"
 SOURCES = ["capi.hip", "primitives.hip", "tree.hip", "lists.hip",
-           "passes.hip", "integrate.hip", "substep.hip", "pm.hip"]
+           "passes.hip", "integrate.hip", "substep.hip", "pm.hip", "halo.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("CRK_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -99,6 +99,15 @@ void span_end(crk_ctx *ctx, int pass, bool kernel, hipEvent_t ev) {
 
 using namespace crk;
 
+namespace crk {
+// halo.hip
+int fof_properties(crk_ctx *ctx, int64_t n_gas, int64_t n_dm,
+                   const int32_t *labels_gas, const int32_t *labels_dm,
+                   const void *const g[3], const void *m_gas,
+                   const void *const d[3], const void *m_dm, int32_t *count,
+                   double *mass, double *centre);
+}  // namespace crk
+
 namespace {
 
 int check_ctx(const crk_ctx *ctx) {
@@ -253,7 +262,8 @@ int crk_sync(crk_ctx *ctx, int64_t *required) {
         if (word & DEV_ERR_INPUT)
             return set_error(CRK_EINVAL,
                              "device check: a position outside [1,2), a "
-                             "non-finite value or a non-positive h");
+                             "non-finite value, a non-positive h or a group "
+                             "label outside the particle range");
         if (word & DEV_ERR_HMAX)
             return set_error(CRK_EINVAL,
                              "device check: a smoothing length above the "
@@ -656,6 +666,36 @@ int crk_fof(crk_ctx *ctx, crk_tree *t, double b, int32_t *labels_gas,
     CRK_TRY(check_ptr(labels_gas, 4, "labels_gas", t->n_gas > 0));
     CRK_TRY(check_ptr(labels_dm, 4, "labels_dm", t->n_dm > 0));
     return fof_groups(ctx, t, b, labels_gas, labels_dm);
+}
+
+int crk_fof_properties(crk_ctx *ctx, int64_t n_gas, int64_t n_dm,
+                       const int32_t *labels_gas, const int32_t *labels_dm,
+                       const void *const gas_x[3], const void *m_gas,
+                       const void *const dm_x[3], const void *m_dm,
+                       int32_t *count, double *mass, double *centre) {
+    CRK_TRY(check_ctx(ctx));
+    if (n_gas < 0 || n_dm < 0) return set_error(CRK_EINVAL, "counts must be >= 0");
+    if (n_gas + n_dm >= ((int64_t)1 << 31) - 1)
+        return set_error(CRK_EINVAL, "fof_properties: too many particles for int32 labels");
+    const size_t el = ctx->elem();
+    const bool g = n_gas > 0, d = n_dm > 0;
+    if ((g && !gas_x) || (d && !dm_x)) return set_error(CRK_EINVAL, "null pointer array");
+    for (int a = 0; a < 3; ++a) {
+        if (g) CRK_TRY(check_ptr(gas_x[a], el, "gas_x", true));
+        if (d) CRK_TRY(check_ptr(dm_x[a], el, "dm_x", true));
+    }
+    CRK_TRY(check_ptr(labels_gas, 4, "labels_gas", g));
+    CRK_TRY(check_ptr(labels_dm, 4, "labels_dm", d));
+    CRK_TRY(check_ptr(m_gas, el, "m_gas", g));
+    CRK_TRY(check_ptr(m_dm, el, "m_dm", d));
+    const bool any = g || d;
+    CRK_TRY(check_ptr(count, 4, "count", any));
+    CRK_TRY(check_ptr(mass, 8, "mass", any));
+    CRK_TRY(check_ptr(centre, 8, "centre", any));
+    if (!any) return CRK_OK;
+    return fof_properties(ctx, n_gas, n_dm, labels_gas, labels_dm,
+                          g ? gas_x : nullptr, m_gas, d ? dm_x : nullptr, m_dm,
+                          count, mass, centre);
 }
 
 int crk_count_pairs(crk_ctx *ctx, crk_tree *t, int64_t totals[6]) {

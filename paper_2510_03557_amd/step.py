@@ -311,6 +311,31 @@ class ShortRangeStep:
         c.stream.synchronize()
         return lg[:self.ng].cpu().numpy(), ld[:self.nd].cpu().numpy()
 
+    def fof_properties(self, b: float):
+        """Friends-of-friends groups with linking length b and their
+        properties (crk_fof, then crk_fof_properties): labels (gas, dm) and,
+        per combined index, member count, mass and periodic centre of mass
+        (numpy; zero at indices that label no group)."""
+        torch, c = self.torch, self.ctx
+        n = self.ng + self.nd
+        with torch.cuda.stream(c.stream):
+            lg = torch.zeros(max(self.ng, 1), dtype=torch.int32, device="cuda")
+            ld = torch.zeros(max(self.nd, 1), dtype=torch.int32, device="cuda")
+            cnt = torch.zeros(max(n, 1), dtype=torch.int32, device="cuda")
+            mass = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")
+            cen = torch.zeros(3 * max(n, 1), dtype=torch.float64, device="cuda")
+        c.fof(self.tree, b, lg if self.ng else None, ld if self.nd else None)
+        c.fof_properties(self.ng, self.nd, lg if self.ng else None,
+                         ld if self.nd else None,
+                         (self.gx, self.gy, self.gz) if self.ng else None,
+                         self.gm if self.ng else None,
+                         (self.dx, self.dy, self.dz) if self.nd else None,
+                         self.dm if self.nd else None, cnt, mass, cen)
+        c.stream.synchronize()
+        return (lg[:self.ng].cpu().numpy(), ld[:self.nd].cpu().numpy(),
+                cnt[:n].cpu().numpy(), mass[:n].cpu().numpy(),
+                cen[:3 * n].cpu().numpy().reshape(3, n))
+
     def capture(self, integrate: bool = True):
         """Runs the step once eagerly (sizes), then captures it in a graph."""
         self.run(integrate=integrate)

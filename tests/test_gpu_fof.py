@@ -109,3 +109,72 @@ def test_fof_argument_errors(step_cls):
     assert e.value.status == CRK_EINVAL
     with pytest.raises(CrkError):
         st.fof(0.0)
+
+
+# ---------------------------------------------------------------------------
+# group properties
+# ---------------------------------------------------------------------------
+
+def _check_properties(orc, st, wl, b):
+    st.run()
+    lg, ld, cnt, mass, cen = st.fof_properties(b)
+    rg, rd = _oracle_labels(orc, wl, b)
+    assert np.array_equal(lg, rg) and np.array_equal(ld, rd)
+    g, d = wl.gas, wl.dm
+    X, Y, Z, M = (np.concatenate([getattr(g, k), getattr(d, k)]).astype(
+        np.float64) for k in ("x", "y", "z", "m"))
+    rc, rm, rcen = orc.fof_properties(X, Y, Z, M, np.concatenate([rg, rd]))
+    assert np.array_equal(cnt.astype(np.int64), rc)
+    assert np.abs(mass - rm).max() <= 1e-12 * np.abs(rm).max()
+    dd = cen - rcen
+    dd -= np.round(dd)
+    print(f"groups {np.count_nonzero(rc)}, largest {rc.max()}, centre error "
+          f"{np.abs(dd).max():.2e}", flush=True)
+    assert np.abs(dd).max() < 1e-12
+    assert rc.max() > 5
+
+
+@pytest.mark.parametrize("precision,ng,nd,seed,frac", [
+    ("fp32", 8000, 6000, 931, 0.25), ("fp64", 5000, 4000, 932, 0.3)])
+def test_fof_properties_match_oracle(orc, step_cls, precision, ng, nd, seed,
+                                     frac):
+    wl = W.random_uniform(ng, nd, seed, n_ngb=48.0, clustered=True)
+    b = frac * (ng + nd) ** (-1.0 / 3.0)
+    print(f"case fof properties {precision} random({ng},{nd}) b={b:.4g}",
+          flush=True)
+    _check_properties(orc, step_cls(wl, precision), wl, b)
+
+
+def test_fof_properties_batched_boxes(orc, step_cls):
+    boxes = [W.random_uniform(1500 + 300 * k, 1200, 940 + k, n_ngb=48.0,
+                              clustered=True) for k in range(4)]
+    wl = W.concat_boxes("fof_props_batch", boxes)
+    b = 0.4 * 2700 ** (-1.0 / 3.0)
+    print(f"case fof properties batch of 4 boxes b={b:.4g}", flush=True)
+    _check_properties(orc, step_cls(wl, "fp32"), wl, b)
+
+
+def test_fof_properties_reject_foreign_labels(step_cls):
+    """A label outside the particle range is skipped on the device (no
+    access out of bounds) and reported by crk_sync."""
+    from paper_2510_03557_amd.binding import CrkError, CRK_EINVAL
+    print("case fof properties foreign label", flush=True)
+    wl = W.random_uniform(500, 400, 950)
+    st = step_cls(wl, "fp32")
+    st.run()
+    c = st.ctx
+    n = wl.n_total
+    with torch.cuda.stream(c.stream):
+        lg = torch.arange(500, dtype=torch.int32, device="cuda")
+        ld = torch.arange(500, 900, dtype=torch.int32, device="cuda")
+        ld[7] = n + 5
+        cnt = torch.zeros(n, dtype=torch.int32, device="cuda")
+        mass = torch.zeros(n, dtype=torch.float64, device="cuda")
+        cen = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    c.fof_properties(500, 400, lg, ld, (st.gx, st.gy, st.gz), st.gm,
+                     (st.dx, st.dy, st.dz), st.dm, cnt, mass, cen)
+    with pytest.raises(CrkError) as e:
+        st.sync()
+    assert e.value.status == CRK_EINVAL
+    c.stream.synchronize()
+    assert int(cnt.sum().item()) == n - 1
