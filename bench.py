@@ -290,13 +290,30 @@ def measure_fof(wl, tuning, reps, log):
                                         td if st.nd else None),
                      lambda: (torch.cuda.synchronize(),
                               st.ctx.stream.synchronize()), reps, 0)
+    # group properties (count, mass, centre of mass) from those labels
+    n = wl.n_total
+    with torch.cuda.stream(st.ctx.stream):
+        cnt = torch.zeros(max(n, 1), dtype=torch.int32, device="cuda")
+        mass = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")
+        cen = torch.zeros(3 * max(n, 1), dtype=torch.float64, device="cuda")
+
+    def props():
+        st.ctx.fof_properties(
+            st.ng, st.nd, tg if st.ng else None, td if st.nd else None,
+            (st.gx, st.gy, st.gz) if st.ng else None, st.gm if st.ng else None,
+            (st.dx, st.dy, st.dz) if st.nd else None, st.dm if st.nd else None,
+            cnt, mass, cen)
+    psec = time_steps(props, lambda: (torch.cuda.synchronize(),
+                                      st.ctx.stream.synchronize()), reps, 1)
+    st.sync()
     st.close()
     lab = np.concatenate([lg, ld])
     sizes = np.bincount(lab)
     sizes = sizes[sizes > 0]
     log(f"[bench] fof: b {b:.4g}, {len(sizes)} groups, {sec * 1e3:.3f} ms")
     return {"linking_length": b, "ms_per_call": sec * 1e3,
-            "particles_per_s": wl.n_total / sec, "groups": int(len(sizes)),
+            "particles_per_s": wl.n_total / sec,
+            "properties_ms_per_call": psec * 1e3, "groups": int(len(sizes)),
             "groups_20_or_more": int(np.sum(sizes >= 20)),
             "largest_group": int(sizes.max()), "reps": reps}
 
