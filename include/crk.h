@@ -470,10 +470,19 @@ int crk_tree_get_leaves(crk_ctx *ctx, const crk_tree *tree, int64_t *perm,
  * end into a HIP graph (build_tree and build_interaction_lists then use
  * the capacities of the previous eager build and read nothing back);
  * crk_graph_launch replays it.  Capacities exceeded during a replay are
- * reported by crk_sync as CRK_ECAPACITY. */
+ * reported by crk_sync as CRK_ECAPACITY; the recovery is an eager call at
+ * the new size followed by a new capture.  The graph holds the addresses of
+ * the library's buffers at capture time: once any library buffer of the
+ * process has been grown (moved) or freed since then (an eager call that
+ * needs more room, crk_tree_free, crk_ctx_destroy of any context),
+ * crk_graph_launch returns CRK_ESTATE without launching anything, and the
+ * caller captures again. */
 int crk_graph_begin(crk_ctx *ctx);
 int crk_graph_end(crk_ctx *ctx);
 int crk_graph_launch(crk_ctx *ctx);
+/* Drops the captured graph, if any (a later crk_graph_launch returns
+ * CRK_ESTATE until the next capture). */
+int crk_graph_reset(crk_ctx *ctx);
 
 int crk_tree_free(crk_tree *tree);
 

@@ -482,9 +482,10 @@ int orc_density(int64_t n, const double *x, const double *y, const double *z,
 /* m2 counts as singular when det(m2) <= DEGENERATE (tr(m2)/3)^3, i.e. its
  * eigenvalues multiply to less than 1e-5 of the cube of their mean: such a
  * neighbourhood (a single particle, a pair, three points, a sheet) cannot fix
- * the linear correction, and the bound lies far above the rounding noise
- * of float32 moment sums (about 1e-7 relative), so that float32 and float64
- * evaluations take the same branch. */
+ * the linear correction.  The bound lies far above the rounding noise of
+ * float32 moment sums (about 1e-7 relative), so float32 and float64
+ * evaluations take the same branch except in a narrow band, a few 1e-7
+ * relative wide, around the bound itself. */
 #define DEGENERATE 1e-5
 
 /* Solve the reproducing conditions at one particle from its moments.

@@ -72,6 +72,8 @@ def tune(step, candidates=None, reps: int = 5, use_cache: bool = True,
     cache = _load_cache() if use_cache else {}
     if key in cache:
         best = cache[key]["tuning"]
+        if step.graph:
+            step.drop_graph()
         step.ctx.set_tuning(**best)
         return {"tuning": best, "ms": cache[key]["ms"], "cached": True}
     results = {}
@@ -93,6 +95,9 @@ def tune(step, candidates=None, reps: int = 5, use_cache: bool = True,
             log(f"[tune] {name}: {ms:.3f} ms")
     best_name = min(results, key=results.get)
     best = next(c for c in (candidates or CANDIDATES) if _name(c) == best_name)
+    # the last candidate's graph holds that candidate's launch shape: drop
+    # it, so that the step is left eager at the chosen tuning
+    step.drop_graph()
     step.ctx.set_tuning(**best)
     if use_cache:
         cache = _load_cache()

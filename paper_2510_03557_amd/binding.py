@@ -30,7 +30,7 @@ EXPORTS = (
     "crk_density", "crk_coefficients", "crk_hydro_forces",
     "shortrange_gravity", "crk_integrate", "crk_tree_get_info",
     "crk_tree_get_leaves", "crk_count_pairs", "crk_graph_begin", "crk_graph_end",
-    "crk_graph_launch", "crk_tree_free", "crk_timing_enable",
+    "crk_graph_launch", "crk_graph_reset", "crk_tree_free", "crk_timing_enable",
     "crk_pass_times", "crk_timestep_bins", "crk_tree_set_active",
     "crk_tree_refit", "crk_kick", "crk_drift", "crk_pm_gravity", "crk_fof",
     "crk_velocity_gradient", "crk_hydro_forces_limited",
@@ -141,6 +141,7 @@ def load(path: Path | str | None = None):
     lib.crk_graph_begin.argtypes = [vp]
     lib.crk_graph_end.argtypes = [vp]
     lib.crk_graph_launch.argtypes = [vp]
+    lib.crk_graph_reset.argtypes = [vp]
     lib.crk_tree_free.argtypes = [vp]
     lib.crk_timing_enable.argtypes = [vp, ctypes.c_int]
     lib.crk_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
@@ -178,10 +179,36 @@ def check(status: int):
 
 
 def _ptr(t):
-    """Device address of a torch tensor (None -> NULL)."""
+    """Device address of a torch tensor (None -> NULL), unchecked: for
+    buffers the caller of this module never supplies."""
     if t is None:
         return None
     return ctypes.c_void_p(t.data_ptr())
+
+
+def check_tensor(t, dtype, n: int, name: str):
+    """Raises CrkError(CRK_EINVAL) unless t is a contiguous device tensor of
+    dtype with at least n elements; the library reads and writes raw
+    addresses, so a wrong type or a short array would be misread or
+    overrun rather than reported.  None passes (a NULL argument, which the
+    library checks)."""
+    if t is None:
+        return
+    if t.dtype != dtype:
+        raise CrkError(CRK_EINVAL, f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise CrkError(CRK_EINVAL, f"{name}: not contiguous")
+    if t.numel() < n:
+        raise CrkError(CRK_EINVAL,
+                       f"{name}: {t.numel()} elements, at least {n} needed")
+    if not t.is_cuda:
+        raise CrkError(CRK_EINVAL, f"{name}: not a device tensor")
+
+
+def _dev(t, dtype, n, name):
+    """check_tensor, then the device address (None -> NULL)."""
+    check_tensor(t, dtype, n, name)
+    return _ptr(t)
 
 
 def _arr(ctype, vals):
@@ -228,6 +255,11 @@ class Context:
                        int(xcd_remap), int(walk_mask), int(sub_sweep),
                        int(tree_lds)))))
 
+    def get_tuning(self) -> dict:
+        t = crk_tuning()
+        check(self.lib.crk_get_tuning(self.handle, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in crk_tuning._fields_}
+
     def sync(self):
         req = ctypes.c_int64()
         check(self.lib.crk_sync(self.handle, ctypes.byref(req)))
@@ -249,125 +281,190 @@ class Context:
                       ep.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                       hm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         self._boxes_keep = (keep, b)
-        check(self.lib.build_tree(self.handle, ctypes.byref(b), _ptr(gx),
-                                  _ptr(gy), _ptr(gz), _ptr(gh), _ptr(dx),
-                                  _ptr(dy), _ptr(dz),
+        F = self.dtype
+        ng, nd = int(go[-1]), int(do[-1])
+        args = [_dev(gx, F, ng, "gx"), _dev(gy, F, ng, "gy"),
+                _dev(gz, F, ng, "gz"), _dev(gh, F, ng, "gh"),
+                _dev(dx, F, nd, "dx"), _dev(dy, F, nd, "dy"),
+                _dev(dz, F, nd, "dz")]
+        check(self.lib.build_tree(self.handle, ctypes.byref(b), *args,
                                   ctypes.byref(tree.handle)))
+        tree.n_gas, tree.n_dm = ng, nd
 
     def build_interaction_lists(self, tree):
         check(self.lib.build_interaction_lists(self.handle, tree.handle))
 
+    # argument checks: F is the context precision; gas arrays hold n_gas
+    # values per plane, dm arrays n_dm (from the tree)
+    def _g(self, tree, t, planes, name, dtype=None):
+        return _dev(t, dtype or self.dtype, planes * tree.n_gas, name)
+
+    def _p3(self, ts, n, name, dtype=None):
+        """Three plane pointers (None -> NULL), each checked for n values."""
+        if ts is None:
+            return None
+        ts = list(ts)
+        if len(ts) != 3:
+            raise CrkError(CRK_EINVAL, f"{name}: three planes expected")
+        for k, t in enumerate(ts):
+            if t is None:
+                raise CrkError(CRK_EINVAL, f"{name}[{k}]: null plane")
+        for k, t in enumerate(ts):
+            check_tensor(t, dtype or self.dtype, n, f"{name}[{k}]")
+        return (ctypes.c_void_p * 3)(*[t.data_ptr() for t in ts])
+
     def density(self, tree, m, V, rho_t):
-        check(self.lib.crk_density(self.handle, tree.handle, _ptr(m), _ptr(V),
-                                   _ptr(rho_t)))
+        g = lambda t, k, nm: self._g(tree, t, k, nm)
+        check(self.lib.crk_density(self.handle, tree.handle, g(m, 1, "m"),
+                                   g(V, 1, "V"), g(rho_t, 1, "rho_tilde")))
 
     def coefficients(self, tree, m, V, u, A, B, gA, gB, rho, P, cs):
-        check(self.lib.crk_coefficients(self.handle, tree.handle, _ptr(m),
-                                        _ptr(V), _ptr(u), _ptr(A), _ptr(B),
-                                        _ptr(gA), _ptr(gB), _ptr(rho), _ptr(P),
-                                        _ptr(cs)))
+        g = lambda t, k, nm: self._g(tree, t, k, nm)
+        check(self.lib.crk_coefficients(
+            self.handle, tree.handle, g(m, 1, "m"), g(V, 1, "V"), g(u, 1, "u"),
+            g(A, 1, "A"), g(B, 3, "B"), g(gA, 3, "gradA"), g(gB, 9, "gradB"),
+            g(rho, 1, "rho"), g(P, 1, "P"), g(cs, 1, "cs")))
+
+    def _hydro_in(self, tree, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB):
+        g = lambda t, k, nm: self._g(tree, t, k, nm)
+        return [g(m, 1, "m"), g(vx, 1, "vx"), g(vy, 1, "vy"), g(vz, 1, "vz"),
+                g(V, 1, "V"), g(rho, 1, "rho"), g(P, 1, "P"), g(cs, 1, "cs"),
+                g(A, 1, "A"), g(B, 3, "B"), g(gA, 3, "gradA"),
+                g(gB, 9, "gradB")]
 
     def hydro_forces(self, tree, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB,
                      ax, ay, az, dudt):
+        g = lambda t, k, nm: self._g(tree, t, k, nm)
         check(self.lib.crk_hydro_forces(
-            self.handle, tree.handle, _ptr(m), _ptr(vx), _ptr(vy), _ptr(vz),
-            _ptr(V), _ptr(rho), _ptr(P), _ptr(cs), _ptr(A), _ptr(B), _ptr(gA),
-            _ptr(gB), _ptr(ax), _ptr(ay), _ptr(az), _ptr(dudt)))
+            self.handle, tree.handle,
+            *self._hydro_in(tree, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB),
+            g(ax, 1, "ax"), g(ay, 1, "ay"), g(az, 1, "az"),
+            g(dudt, 1, "dudt")))
 
     def velocity_gradient(self, tree, vx, vy, vz, V, A, B, gA, gB, dv):
+        g = lambda t, k, nm: self._g(tree, t, k, nm)
         check(self.lib.crk_velocity_gradient(
-            self.handle, tree.handle, _ptr(vx), _ptr(vy), _ptr(vz), _ptr(V),
-            _ptr(A), _ptr(B), _ptr(gA), _ptr(gB), _ptr(dv)))
+            self.handle, tree.handle, g(vx, 1, "vx"), g(vy, 1, "vy"),
+            g(vz, 1, "vz"), g(V, 1, "V"), g(A, 1, "A"), g(B, 3, "B"),
+            g(gA, 3, "gradA"), g(gB, 9, "gradB"), g(dv, 9, "dv")))
 
     def hydro_forces_limited(self, tree, m, vx, vy, vz, V, rho, P, cs, A, B,
                              gA, gB, dv, eta_crit, eta_fold, ax, ay, az, dudt):
+        g = lambda t, k, nm: self._g(tree, t, k, nm)
         check(self.lib.crk_hydro_forces_limited(
-            self.handle, tree.handle, _ptr(m), _ptr(vx), _ptr(vy), _ptr(vz),
-            _ptr(V), _ptr(rho), _ptr(P), _ptr(cs), _ptr(A), _ptr(B), _ptr(gA),
-            _ptr(gB), _ptr(dv), float(eta_crit), float(eta_fold), _ptr(ax),
-            _ptr(ay), _ptr(az), _ptr(dudt)))
+            self.handle, tree.handle,
+            *self._hydro_in(tree, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB),
+            g(dv, 9, "dv"), float(eta_crit), float(eta_fold), g(ax, 1, "ax"),
+            g(ay, 1, "ay"), g(az, 1, "az"), g(dudt, 1, "dudt")))
 
     def hydro_energy_compatible(self, tree, m, vx, vy, vz, V, rho, P, cs, A,
                                 B, gA, gB, dv, eta_crit, eta_fold, dt, a_grav,
                                 a_hydro, dudt):
-        P3 = ctypes.c_void_p * 3
-        ag = P3(*[t.data_ptr() for t in a_grav]) if a_grav is not None else None
-        ah = P3(*[t.data_ptr() for t in a_hydro]) if a_hydro is not None else None
+        g = lambda t, k, nm: self._g(tree, t, k, nm)
+        n = tree.n_gas
         check(self.lib.crk_hydro_energy_compatible(
-            self.handle, tree.handle, _ptr(m), _ptr(vx), _ptr(vy), _ptr(vz),
-            _ptr(V), _ptr(rho), _ptr(P), _ptr(cs), _ptr(A), _ptr(B), _ptr(gA),
-            _ptr(gB), _ptr(dv), float(eta_crit), float(eta_fold), float(dt),
-            ag, ah, _ptr(dudt)))
+            self.handle, tree.handle,
+            *self._hydro_in(tree, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB),
+            g(dv, 9, "dv"), float(eta_crit), float(eta_fold), float(dt),
+            self._p3(a_grav, n, "a_grav"), self._p3(a_hydro, n, "a_hydro"),
+            g(dudt, 1, "dudt")))
 
     def shortrange_gravity(self, tree, m_gas, m_dm, axg, ayg, azg, axd, ayd,
                            azd):
+        F, ng, nd = self.dtype, tree.n_gas, tree.n_dm
         check(self.lib.shortrange_gravity(
-            self.handle, tree.handle, _ptr(m_gas), _ptr(m_dm), _ptr(axg),
-            _ptr(ayg), _ptr(azg), _ptr(axd), _ptr(ayd), _ptr(azd)))
+            self.handle, tree.handle, _dev(m_gas, F, ng, "m_gas"),
+            _dev(m_dm, F, nd, "m_dm"), _dev(axg, F, ng, "ax_gas"),
+            _dev(ayg, F, ng, "ay_gas"), _dev(azg, F, ng, "az_gas"),
+            _dev(axd, F, nd, "ax_dm"), _dev(ayd, F, nd, "ay_dm"),
+            _dev(azd, F, nd, "az_dm")))
 
     def integrate(self, n, dt, x64, v64, u64, a_grav, a_hydro, dudt, x, v, u):
-        P3 = ctypes.c_void_p * 3
-        ag = P3(*[t.data_ptr() for t in a_grav])
-        ah = P3(*[t.data_ptr() for t in a_hydro]) if a_hydro is not None else None
-        xo = P3(*[t.data_ptr() for t in x])
-        vo = P3(*[t.data_ptr() for t in v])
+        import torch
+        F, D, n = self.dtype, torch.float64, int(n)
         check(self.lib.crk_integrate(
-            self.handle, int(n), float(dt), _ptr(x64), _ptr(v64), _ptr(u64),
-            ag, ah, _ptr(dudt), xo, vo, _ptr(u)))
+            self.handle, n, float(dt), _dev(x64, D, 3 * n, "x64"),
+            _dev(v64, D, 3 * n, "v64"), _dev(u64, D, n, "u64"),
+            self._p3(a_grav, n, "a_grav"), self._p3(a_hydro, n, "a_hydro"),
+            _dev(dudt, F, n, "dudt"), self._p3(x, n, "x"), self._p3(v, n, "v"),
+            _dev(u, F, n, "u")))
 
     # hierarchical time steps ------------------------------------------------
-    @staticmethod
-    def _p3(ts):
-        if ts is None:
-            return None
-        return (ctypes.c_void_p * 3)(*[t.data_ptr() for t in ts])
-
     def timestep_bins(self, n, dt, max_level, eps, c_cfl, eta, a_grav,
                       a_hydro, h, cs, bins):
+        import torch
+        F, n = self.dtype, int(n)
         check(self.lib.crk_timestep_bins(
-            self.handle, int(n), float(dt), int(max_level), float(eps),
-            float(c_cfl), float(eta), self._p3(a_grav), self._p3(a_hydro),
-            _ptr(h), _ptr(cs), _ptr(bins)))
+            self.handle, n, float(dt), int(max_level), float(eps),
+            float(c_cfl), float(eta), self._p3(a_grav, n, "a_grav"),
+            self._p3(a_hydro, n, "a_hydro"), _dev(h, F, n, "h"),
+            _dev(cs, F, n, "cs"), _dev(bins, torch.int32, n, "bins")))
 
     def tree_set_active(self, tree, bins_gas, bins_dm, max_level, substep):
+        import torch
+        I = torch.int32
         check(self.lib.crk_tree_set_active(
-            self.handle, tree.handle, _ptr(bins_gas), _ptr(bins_dm),
-            int(max_level), int(substep)))
+            self.handle, tree.handle, _dev(bins_gas, I, tree.n_gas, "bins_gas"),
+            _dev(bins_dm, I, tree.n_dm, "bins_dm"), int(max_level),
+            int(substep)))
 
     def tree_refit(self, tree, gx, gy, gz, dx, dy, dz):
-        check(self.lib.crk_tree_refit(self.handle, tree.handle, _ptr(gx),
-                                      _ptr(gy), _ptr(gz), _ptr(dx), _ptr(dy),
-                                      _ptr(dz)))
+        F, ng, nd = self.dtype, tree.n_gas, tree.n_dm
+        check(self.lib.crk_tree_refit(
+            self.handle, tree.handle, _dev(gx, F, ng, "gx"),
+            _dev(gy, F, ng, "gy"), _dev(gz, F, ng, "gz"),
+            _dev(dx, F, nd, "dx"), _dev(dy, F, nd, "dy"),
+            _dev(dz, F, nd, "dz")))
 
     def kick(self, n, dt, max_level, substep, phase, bins, v64, u64, a_grav,
              a_hydro, dudt, v, u):
+        import torch
+        F, D, n = self.dtype, torch.float64, int(n)
         check(self.lib.crk_kick(
-            self.handle, int(n), float(dt), int(max_level), int(substep),
-            int(phase), _ptr(bins), _ptr(v64), _ptr(u64), self._p3(a_grav),
-            self._p3(a_hydro), _ptr(dudt), self._p3(v), _ptr(u)))
+            self.handle, n, float(dt), int(max_level), int(substep),
+            int(phase), _dev(bins, torch.int32, n, "bins"),
+            _dev(v64, D, 3 * n, "v64"), _dev(u64, D, n, "u64"),
+            self._p3(a_grav, n, "a_grav"), self._p3(a_hydro, n, "a_hydro"),
+            _dev(dudt, F, n, "dudt"), self._p3(v, n, "v"), _dev(u, F, n, "u")))
 
     def drift(self, n, delta, wrap, x64, v64, x):
-        check(self.lib.crk_drift(self.handle, int(n), float(delta),
-                                 int(bool(wrap)), _ptr(x64), _ptr(v64),
-                                 self._p3(x)))
+        import torch
+        D, n = torch.float64, int(n)
+        check(self.lib.crk_drift(self.handle, n, float(delta),
+                                 int(bool(wrap)), _dev(x64, D, 3 * n, "x64"),
+                                 _dev(v64, D, 3 * n, "v64"),
+                                 self._p3(x, n, "x")))
 
     def pm_gravity(self, n_mesh, r_c, n_gas, gx, gy, gz, m_gas, n_dm, dx, dy,
                    dz, m_dm, a_gas, a_dm):
+        F, ng, nd = self.dtype, int(n_gas), int(n_dm)
         check(self.lib.crk_pm_gravity(
-            self.handle, int(n_mesh), float(r_c), int(n_gas), _ptr(gx),
-            _ptr(gy), _ptr(gz), _ptr(m_gas), int(n_dm), _ptr(dx), _ptr(dy),
-            _ptr(dz), _ptr(m_dm), self._p3(a_gas), self._p3(a_dm)))
+            self.handle, int(n_mesh), float(r_c), ng, _dev(gx, F, ng, "gx"),
+            _dev(gy, F, ng, "gy"), _dev(gz, F, ng, "gz"),
+            _dev(m_gas, F, ng, "m_gas"), nd, _dev(dx, F, nd, "dx"),
+            _dev(dy, F, nd, "dy"), _dev(dz, F, nd, "dz"),
+            _dev(m_dm, F, nd, "m_dm"), self._p3(a_gas, ng, "a_gas"),
+            self._p3(a_dm, nd, "a_dm")))
 
     def fof(self, tree, b, labels_gas, labels_dm):
+        import torch
+        I = torch.int32
         check(self.lib.crk_fof(self.handle, tree.handle, float(b),
-                               _ptr(labels_gas), _ptr(labels_dm)))
+                               _dev(labels_gas, I, tree.n_gas, "labels_gas"),
+                               _dev(labels_dm, I, tree.n_dm, "labels_dm")))
 
     def fof_properties(self, n_gas, n_dm, labels_gas, labels_dm, gas_x, m_gas,
                        dm_x, m_dm, count, mass, centre):
+        import torch
+        F, I, D = self.dtype, torch.int32, torch.float64
+        ng, nd = int(n_gas), int(n_dm)
+        n = ng + nd
         check(self.lib.crk_fof_properties(
-            self.handle, int(n_gas), int(n_dm), _ptr(labels_gas),
-            _ptr(labels_dm), self._p3(gas_x), _ptr(m_gas), self._p3(dm_x),
-            _ptr(m_dm), _ptr(count), _ptr(mass), _ptr(centre)))
+            self.handle, ng, nd, _dev(labels_gas, I, ng, "labels_gas"),
+            _dev(labels_dm, I, nd, "labels_dm"), self._p3(gas_x, ng, "gas_x"),
+            _dev(m_gas, F, ng, "m_gas"), self._p3(dm_x, nd, "dm_x"),
+            _dev(m_dm, F, nd, "m_dm"), _dev(count, I, n, "count"),
+            _dev(mass, D, n, "mass"), _dev(centre, D, 3 * n, "centre")))
 
     def count_pairs(self, tree):
         """In-range ordered pairs (gather, hydro, gravity), then the swept
@@ -384,6 +481,9 @@ class Context:
 
     def graph_launch(self):
         check(self.lib.crk_graph_launch(self.handle))
+
+    def graph_reset(self):
+        check(self.lib.crk_graph_reset(self.handle))
 
     def timing(self, enable=True):
         check(self.lib.crk_timing_enable(self.handle, int(bool(enable))))
@@ -404,6 +504,7 @@ class Tree:
     def __init__(self, ctx: Context):
         self.ctx = ctx
         self.handle = ctypes.c_void_p()
+        self.n_gas = self.n_dm = 0  # set by Context.build_tree
         _live_trees.add(self)
 
     def info(self):

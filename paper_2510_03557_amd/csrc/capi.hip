@@ -2,6 +2,7 @@
 // device-error latching, graph capture and event timing.  The arithmetic
 // lives in tree.hip, lists.hip, passes.hip and integrate.hip.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -23,6 +24,13 @@ int set_error(int status, const std::string &msg) {
     return status;
 }
 
+namespace {
+std::atomic<uint64_t> g_alloc_gen{1};
+}
+
+uint64_t alloc_generation() { return g_alloc_gen.load(std::memory_order_acquire); }
+void alloc_generation_bump() { g_alloc_gen.fetch_add(1, std::memory_order_acq_rel); }
+
 int DevBuf::ensure(size_t n, bool capturing) {
     if (n <= bytes && p) return CRK_OK;
     if (capturing)
@@ -30,6 +38,7 @@ int DevBuf::ensure(size_t n, bool capturing) {
                          "a buffer would have to grow during graph capture; "
                          "run the step once eagerly at this size first");
     if (p) {
+        alloc_generation_bump();
         (void)hipFree(p);
         p = nullptr;
         bytes = 0;
@@ -46,14 +55,20 @@ int DevBuf::ensure(size_t n, bool capturing) {
 }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+        alloc_generation_bump();
+        (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
 }
 
 int HostBuf::ensure(size_t n) {
     if (n <= bytes && p) return CRK_OK;
-    if (p) (void)hipHostFree(p);
+    if (p) {
+        alloc_generation_bump();
+        (void)hipHostFree(p);
+    }
     p = nullptr;
     bytes = 0;
     size_t want = std::max<size_t>((n + 255) & ~size_t(255), 256);
@@ -67,7 +82,10 @@ int HostBuf::ensure(size_t n) {
 }
 
 void HostBuf::release() {
-    if (p) (void)hipHostFree(p);
+    if (p) {
+        alloc_generation_bump();
+        (void)hipHostFree(p);
+    }
     p = nullptr;
     bytes = 0;
 }
@@ -764,12 +782,30 @@ int crk_graph_end(crk_ctx *ctx) {
     ctx->graph = g;
     ctx->graph_exec = nullptr;
     CRK_HIP(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+    ctx->graph_gen = alloc_generation();
+    return CRK_OK;
+}
+
+int crk_graph_reset(crk_ctx *ctx) {
+    CRK_TRY(check_ctx(ctx));
+    if (ctx->capturing) return set_error(CRK_ESTATE, "graph reset during capture");
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
     return CRK_OK;
 }
 
 int crk_graph_launch(crk_ctx *ctx) {
     CRK_TRY(check_ctx(ctx));
     if (!ctx->graph_exec) return set_error(CRK_ESTATE, "no graph captured");
+    // the graph's kernels hold raw pointers: a buffer grown, moved or freed
+    // since the capture (an eager build at a larger size, crk_tree_free)
+    // would be a use after free, so such a graph is never launched
+    if (ctx->graph_gen != alloc_generation())
+        return set_error(CRK_ESTATE,
+                         "library buffers were reallocated or freed since the "
+                         "graph was captured; capture it again");
     CRK_HIP(hipGraphLaunch(ctx->graph_exec, ctx->stream));
     return CRK_OK;
 }

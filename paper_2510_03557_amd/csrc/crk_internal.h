@@ -47,9 +47,20 @@ enum : int {
 // device buffers
 // --------------------------------------------------------------------------
 
+// Every release of library memory (device or pinned host), including the
+// old block of a buffer that grows, advances a process-wide generation.  A
+// captured graph holds raw pointers, so it may be replayed only while the
+// generation it was captured at is current (checked by crk_graph_launch).
+uint64_t alloc_generation();
+void alloc_generation_bump();
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
     // Grows to at least n bytes (contents are not preserved).  Fails when
     // growth is needed during graph capture.
     int ensure(size_t n, bool capturing);
@@ -60,6 +71,10 @@ struct DevBuf {
 struct HostBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf() { release(); }
     int ensure(size_t n);
     void release();
     template <typename T> T *as() const { return static_cast<T *>(p); }
@@ -102,6 +117,7 @@ struct crk_ctx {
     bool capturing = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_gen = 0;   // allocation generation at the last capture
     crk::DevBuf err;          // int error word + int64 required capacity
     crk::HostBuf err_host;
     crk::DevBuf scratch;      // primitives' temporary storage

@@ -950,8 +950,11 @@ template <typename T> struct CoeffPass {
         double det = m2[0][0] * c00 + m2[0][1] * c01 + m2[0][2] * c02;
         double tr = m2[0][0] + m2[1][1] + m2[2][2];
         double A, B[3], dA[3], dB[3][3];
-        // singular when det <= 1e-5 (tr/3)^3: far above the float32 noise of
-        // the moment sums, so both precisions take the same branch
+        // singular when det <= 1e-5 (tr/3)^3.  The bound sits far above the
+        // float32 noise of the moment sums (about 1e-7 relative), so the two
+        // precisions take the same branch except for neighbourhoods whose
+        // det / (tr/3)^3 lies within a few 1e-7 of the bound, a narrow band
+        // where either branch may be taken
         if (!(fabs(det) > 1e-5 * tr * tr * tr / 27.0) || !(tr > 0.0)) {
             A = 1.0 / m0;
             for (int g = 0; g < 3; ++g) {

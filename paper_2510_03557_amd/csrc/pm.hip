@@ -230,6 +230,7 @@ int pm_impl(crk_ctx *ctx, int N, double rc, int64_t ng, const void *gx,
     CRK_TRY(pm.tmpk.ensure((size_t)3 * nc * sizeof(C), false));
     if (pm.n != N || pm.elem != (int)sizeof(T)) {
         if (pm.plans) {
+            alloc_generation_bump();  // the plans' work areas go with them
             (void)hipfftDestroy(pm.fwd);
             (void)hipfftDestroy(pm.inv);
             pm.plans = false;
@@ -280,6 +281,7 @@ int pm_impl(crk_ctx *ctx, int N, double rc, int64_t ng, const void *gx,
 
 void pm_release(crk_pm &pm) {
     if (pm.plans) {
+        alloc_generation_bump();
         (void)hipfftDestroy(pm.fwd);
         (void)hipfftDestroy(pm.inv);
         pm.plans = false;

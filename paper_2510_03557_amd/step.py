@@ -348,7 +348,14 @@ class ShortRangeStep:
         self.graph = True
 
     def replay(self):
+        if not self.graph:
+            raise RuntimeError("no step captured: call capture() first")
         self.ctx.graph_launch()
+
+    def drop_graph(self):
+        """Forgets the captured step (a later replay() raises)."""
+        self.ctx.graph_reset()
+        self.graph = False
 
     def sync(self):
         return self.ctx.sync()
@@ -385,6 +392,42 @@ class ShortRangeStep:
                                       h(self.agz, ng)])
         out["a_grav_dm"] = np.stack([h(self.adx, nd), h(self.ady, nd),
                                      h(self.adz, nd)])
+        return out
+
+    def outputs_at(self, gas_idx, dm_idx) -> dict:
+        """outputs() at the listed gas and dm indices only (gathered on the
+        device: at 180 M particles the full outputs would not fit a host
+        copy comfortably).  Same layout as outputs(), n = len(indices)."""
+        self.ctx.sync()
+        torch = self.torch
+        dev = self.V.device
+        gi = torch.as_tensor(np.asarray(gas_idx, np.int64), device=dev)
+        di = torch.as_tensor(np.asarray(dm_idx, np.int64), device=dev)
+        ng, nd = self.ng, self.nd
+        k = int(gi.numel())
+
+        def h(t, planes, n, idx):
+            if idx.numel() == 0:
+                return np.zeros((planes, 0))
+            v = t[:planes * n].view(planes, n)[:, idx]
+            return v.double().cpu().numpy()
+
+        with torch.cuda.stream(self.ctx.stream):
+            out = {key: h(getattr(self, a), 1, ng, gi)[0]
+                   for key, a in (("V", "V"), ("rho_tilde", "rho_t"), ("A", "A"),
+                                  ("rho", "rho"), ("P", "P"), ("cs", "cs"),
+                                  ("dudt", "dudt"))}
+            out["B"] = h(self.B, 3, ng, gi).T
+            out["gradA"] = h(self.gA, 3, ng, gi).T
+            out["gradB"] = h(self.gB, 9, ng, gi).reshape(3, 3, k).transpose(2, 0, 1)
+            out["dv"] = h(self.dv, 9, ng, gi).reshape(3, 3, k).transpose(2, 0, 1)
+            out["a_hydro"] = np.concatenate([h(t, 1, ng, gi) for t in
+                                             (self.ahx, self.ahy, self.ahz)])
+            out["a_grav_gas"] = np.concatenate([h(t, 1, ng, gi) for t in
+                                                (self.agx, self.agy, self.agz)])
+            out["a_grav_dm"] = np.concatenate([h(t, 1, nd, di) for t in
+                                               (self.adx, self.ady, self.adz)])
+        self.ctx.stream.synchronize()
         return out
 
     def close(self):

@@ -81,3 +81,47 @@ def test_package_never_touches_the_oracle():
                 "crk_oracle" in text or "libcrk_oracle" in text:
             offenders.append(str(f.relative_to(ROOT)))
     assert not offenders, offenders
+
+
+def test_binding_rejects_mismatched_tensors():
+    """The binding hands raw addresses to the library, so it checks every
+    tensor first: dtype, contiguity, length, then that it lives on the
+    device.  Each mismatch raises CRK_EINVAL before any library call."""
+    import torch
+    ok = torch.zeros(8, dtype=torch.float32)
+    cases = [
+        (torch.zeros(8, dtype=torch.float64), torch.float32, 8, "dtype"),
+        (torch.zeros(8, dtype=torch.int64), torch.int32, 8, "dtype"),
+        (torch.zeros(4, 4, dtype=torch.float32).t(), torch.float32, 8,
+         "contiguous"),
+        (torch.zeros(7, dtype=torch.float32), torch.float32, 8, "elements"),
+        (ok, torch.float32, 8, "device"),  # host tensor
+    ]
+    for t, dtype, n, what in cases:
+        with pytest.raises(binding.CrkError) as e:
+            binding.check_tensor(t, dtype, n, "arg")
+        assert e.value.status == binding.CRK_EINVAL
+        assert what in str(e.value), (what, str(e.value))
+    binding.check_tensor(None, torch.float32, 8, "arg")  # NULL passes
+
+
+def test_context_checks_plane_triples_before_the_library():
+    """Three-plane arguments (accelerations, positions) are checked plane by
+    plane; the check needs no device (it fails on the host tensor)."""
+    import torch
+    ctx = binding.Context.__new__(binding.Context)  # no device context
+    ctx.dtype = torch.float32
+    planes = [torch.zeros(5, dtype=torch.float32) for _ in range(3)]
+    with pytest.raises(binding.CrkError) as e:
+        ctx._p3(planes[:2], 5, "a")
+    assert "three planes" in str(e.value)
+    with pytest.raises(binding.CrkError) as e:
+        ctx._p3([planes[0], None, planes[2]], 5, "a")
+    assert "null plane" in str(e.value)
+    with pytest.raises(binding.CrkError) as e:
+        ctx._p3(planes, 6, "a")
+    assert "elements" in str(e.value)
+    with pytest.raises(binding.CrkError) as e:
+        ctx._p3(planes, 5, "a")
+    assert "device" in str(e.value)
+    assert ctx._p3(None, 5, "a") is None

@@ -21,24 +21,33 @@ KEYS = ("V", "rho_tilde", "A", "B", "gradA", "gradB", "rho", "P", "cs",
         "a_hydro", "dudt", "a_grav_gas", "a_grav_dm")
 
 
-def rel_rms(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    den = np.sqrt(np.sum(b * b))
-    num = np.sqrt(np.sum((a - b) ** 2))
-    return num / den if den > 0 else num
+from parity_util import (PER_PARTICLE_FP32, PER_PARTICLE_FP64,  # noqa: E402
+                         degenerate_disagreements, rel_rms, worst_particle)
 
 
-def compare(got, ref, tol, keys=KEYS, sel=None):
-    errs = {}
+def compare(got, ref, tol, keys=KEYS, sel=None, per_particle=None):
+    """Relative RMS per output within tol, the worst particle of every
+    output within the per-particle bound (by default the one of the
+    precision that tol belongs to), and no particle on a different
+    coefficient branch than the oracle."""
+    if per_particle is None:
+        per_particle = PER_PARTICLE_FP64 if tol < 1e-8 else PER_PARTICLE_FP32
+    errs, worst = {}, {}
     for k in keys:
         g, r = got[k], ref[k]
         if sel is not None:
             g = g[..., sel] if k.startswith("a_") else g[sel]
         errs[k] = rel_rms(g, r)
+        worst[k] = worst_particle(k, g, r)
     bad = {k: v for k, v in errs.items() if not v <= tol}
+    badw = {k: v for k, v in worst.items() if not v[0] <= per_particle}
+    flips = degenerate_disagreements(got, ref, sel) if "B" in keys else 0
     print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    print("worst particle:", {k: f"{v[0]:.2e}@{v[1]}" for k, v in worst.items()},
+          "branch flips:", flips, flush=True)
     assert not bad, bad
+    assert not badw, badw
+    assert flips == 0, flips
     return errs
 
 
@@ -316,7 +325,7 @@ def test_host_argument_errors(step_cls):
 
 
 def test_capacity_overflow_in_graph_is_reported(step_cls):
-    from paper_2510_03557_amd.binding import CrkError, CRK_ECAPACITY
+    from paper_2510_03557_amd.binding import CrkError, CRK_ECAPACITY, CRK_ESTATE
     print("case graph capacity overflow", flush=True)
     wl = W.random_uniform(3000, 2000, 1101, n_ngb=48.0, h_spread=0.15)
     st = step_cls(wl, precision="fp32")
@@ -332,6 +341,55 @@ def test_capacity_overflow_in_graph_is_reported(step_cls):
         with pytest.raises(CrkError) as e:
             st.sync()
         assert e.value.status == CRK_ECAPACITY
+        # the documented recovery: an eager step at the new size, then a
+        # new capture.  The old graph is never replayed past that step
+        # unnoticed: if the eager step grew (moved) a buffer the graph
+        # refuses to launch (CRK_ESTATE); if every buffer was large enough
+        # it still carries the capacities of its capture and reports the
+        # overflow again
+        st.run(integrate=False)
+        st.sync()
+        try:
+            st.replay()
+        except CrkError as e:
+            assert e.value.status == CRK_ESTATE
+        else:
+            with pytest.raises(CrkError) as e:
+                st.sync()
+            assert e.value.status == CRK_ECAPACITY
+        st.capture(integrate=False)
+        st.replay()
+        st.sync()
+    finally:
+        st.close()
+
+
+def test_graph_refuses_launch_after_buffers_are_freed(step_cls):
+    """A captured graph is not launched once library buffers it may hold
+    were freed (here: another context and its tree destroyed); a new
+    capture launches again."""
+    from paper_2510_03557_amd.binding import CrkError, CRK_ESTATE
+    print("case graph invalidated by freed buffers", flush=True)
+    wl = W.random_uniform(2000, 1500, 1111, n_ngb=48.0, h_spread=0.15)
+    st = step_cls(wl, precision="fp32")
+    try:
+        st.capture(integrate=False)
+        st.replay()
+        st.sync()
+        other = step_cls(W.random_uniform(500, 400, 1112, n_ngb=32.0),
+                         precision="fp32")
+        other.run()
+        other.sync()
+        other.close()
+        with pytest.raises(CrkError) as e:
+            st.replay()
+        assert e.value.status == CRK_ESTATE
+        st.drop_graph()
+        with pytest.raises(RuntimeError):
+            st.replay()
+        st.capture(integrate=False)
+        st.replay()
+        st.sync()
     finally:
         st.close()
 
@@ -427,6 +485,14 @@ def test_autotune_keeps_results(orc, step_cls):
     cands = [dict(leaf_max=32, sub_sweep=0), dict(leaf_max=64, sub_sweep=2)]
     res = autotune.tune(st, candidates=cands, reps=2, use_cache=False)
     assert res["tuning"] in cands and len(res["ms"]) == 2
+    # the tuner leaves the step eager at the chosen shape: no stale graph
+    # of the last candidate can be replayed
+    assert not st.graph
+    with pytest.raises(RuntimeError):
+        st.replay()
+    got = st.ctx.get_tuning()
+    for k, v in res["tuning"].items():
+        assert got[k] == v, k
     st.run()
     compare(st.outputs(), orc.step(wl), FP32_TOL)
     st.close()
