@@ -2,9 +2,10 @@
 """Throughput of one full short-range step (build_tree, lists, density,
 coefficients, hydro forces, gravity, integrate) on one MI355X.
 
-Workload (default): 128^3 dm + 128^3 gas particles, Zel'dovich displacements
-of a Gaussian random field with P(k) ~ k^-2 (rms 0.5 grid spacing),
-~64 hydro neighbours, r_c = 3/128, leaf size <= 128; synthetic, seeded.
+Workload (default): the one-GPU share at its real shape, 448^3 dm + 448^3
+gas particles (179,830,784), Zel'dovich displacements of a Gaussian random
+field with P(k) ~ k^-1.5 (rms 1.0 grid spacing), ~64 hydro neighbours,
+r_c = 3/448; synthetic, seeded.
 
 value = particles / s of the float32 path (pair sums in float32 with
 compensated accumulation, double moment solve and integration), replayed as
@@ -12,7 +13,13 @@ one HIP graph per step.  The plain float64 path (same kernels in double,
 launched eagerly) is timed beside it and reported as fp64_plain; the
 speedup is their ratio.  The roofline entry covers the pass kernel with
 the largest average duration, timed with HIP events on the library's stream.
-The CPU baseline is the FP64 oracle (C, OpenMP) on the same workload.
+The CPU baseline is the FP64 oracle (C, OpenMP) on a bounded sample of the
+same workload (a central cube with the halo its outputs depend on); the
+float32 outputs at the cube's inner particles are compared with it, per
+output (parity_vs_oracle).  A secondary workload (128^3 + 128^3, P(k) ~
+k^-2) is measured after the headline together with the next rows: the
+reconstructed viscosity, the hierarchical substep cycle, the long-range
+mesh gravity and friends-of-friends groups.
 Progress goes to stderr; stdout carries one JSON line.
 """
 from __future__ import annotations
@@ -318,13 +325,240 @@ def measure_fof(wl, tuning, reps, log):
             "largest_group": int(sizes.max()), "reps": reps}
 
 
+def host_info() -> dict:
+    """CPU model, logical CPUs and RAM of the host (Linux /proc)."""
+    model, ram = None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "ram_gib": ram}
+
+
+def measure_step(wl, workload, tuning, args, log, sample=None, tune=False):
+    """The whole step on one workload: float32 kernel times (HIP events over
+    eager steps), eager steps, graph replays (the value), the plain float64
+    path, and the roofline of the dominant pass kernel.  With a sample
+    (gas and dm indices), also the float32 outputs of the first step at
+    those particles (before any integration)."""
+    import torch
+    from paper_2510_03557_amd.step import ShortRangeStep
+    n = wl.n_total
+    st = ShortRangeStep(wl, precision="fp32", tuning=tuning, dt=args.dt)
+    tuned = None
+    if tune:
+        from paper_2510_03557_amd import autotune
+        log(f"[bench] {workload}: tuning the launch shape")
+        tuned = autotune.tune(st, log=log)
+        tuning = dict(tuning, **tuned["tuning"])
+    log(f"[bench] {workload}: fp32 path with {tuning}: first step, kernel timing")
+    st.run(integrate=False)
+    st.sync()
+    got = st.outputs_at(*sample) if sample is not None else None
+    pairs = st.ctx.count_pairs(st.tree)
+    info = st.tree.info()
+    st.run(integrate=True)
+    st.sync()
+    # per-kernel HIP-event timing over eager steps on the library stream
+    st.ctx.timing(True)
+    n_eager = max(args.steps // 4, 3)
+    for _ in range(n_eager):
+        st.run(integrate=True)
+    pass_ms, kern_ms, launches = st.ctx.pass_times()
+    st.ctx.timing(False)
+    st.sync()
+    # the same float32 step launched eagerly (no graph): separates the gain
+    # of graph replay from that of the precision
+    sec_eager = time_steps(lambda: st.run(integrate=True),
+                           lambda: st.ctx.stream.synchronize(),
+                           max(args.steps // 2, 3), 1)
+    st.sync()
+    log(f"[bench] {workload}: fp32 path: graph capture and timed replays")
+    st.capture(integrate=True)
+    sec = time_steps(st.replay, lambda: (torch.cuda.synchronize(),
+                                         st.ctx.stream.synchronize()),
+                     args.steps, args.warmup)
+    st.sync()
+    st.close()
+    value = n / sec
+
+    fp64 = None
+    if not args.no_fp64:
+        log(f"[bench] {workload}: fp64 plain path")
+        st64 = ShortRangeStep(wl, precision="fp64", tuning=dict(leaf_max=64),
+                              dt=args.dt)
+        sec64 = time_steps(lambda: st64.run(integrate=True),
+                           lambda: st64.ctx.stream.synchronize(),
+                           args.fp64_steps, 1)
+        st64.sync()
+        fp64 = {"value": n / sec64, "ms_per_step": sec64 * 1e3,
+                "dtype": "f64", "launch": "eager", "leaf_max": 64}
+        st64.close()
+
+    pair_of = {"density": pairs[0], "coefficients": pairs[0],
+               "hydro": pairs[1], "gravity": pairs[2]}
+    kern = {}
+    for p in ("density", "coefficients", "hydro", "gravity"):
+        if launches[p]:
+            avg = kern_ms[p] / launches[p]
+            flop = pair_of[p] * FLOP_PER_PAIR[p]
+            kern[p] = {"avg_ms": avg, "pairs": pair_of[p],
+                       "flop_per_pair": FLOP_PER_PAIR[p],
+                       "tflops": flop / (avg * 1e-3) / 1e12}
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"])
+    ach = kern[dom]["tflops"]
+    traffic = measured_traffic(dom, kernel_name(dom, tuning), workload)
+    roofline = {"bound": "alu", "achieved": round(ach, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                "traffic": traffic, "kernel": kernel_name(dom, tuning),
+                "avg_launch_ms": round(kern[dom]["avg_ms"], 4),
+                "flop_per_unit": FLOP_PER_PAIR[dom],
+                "units_per_launch": pair_of[dom],
+                "unit_of_work": "in-range ordered pair",
+                "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                "frac_unpacked": round(ach / PEAK_FP32_UNPACKED_TFLOPS, 4)}
+    res = {
+        "value": value, "ms_per_step": sec * 1e3,
+        "config": {"workload": workload, "description": wl.name,
+                   "n_particles": n, "boxes": wl.n_boxes,
+                   "leaf_max": tuning["leaf_max"],
+                   "grid_mult": tuning.get("grid_mult", 0),
+                   "xcd_remap": tuning.get("xcd_remap", 1),
+                   "walk_mask": tuning.get("walk_mask", 0),
+                   "sub_sweep": tuning.get("sub_sweep", 2),
+                   "tree_lds": tuning.get("tree_lds", 1), "launch": "hip_graph",
+                   "leaves": info["n_leaves"],
+                   "list_entries": {"gravity": info["grav_entries"],
+                                    "hydro": info["hydro_entries"]}},
+        "fp32_eager": {"value": n / sec_eager, "ms_per_step": sec_eager * 1e3,
+                       "launch": "eager"},
+        "fp64_plain": fp64,
+        "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "pairs": {"gather": pairs[0], "hydro": pairs[1], "gravity": pairs[2]},
+        "swept_pairs": {"gather": pairs[3], "hydro": pairs[4],
+                        "gravity": pairs[5]},
+        "tuning": tuned,
+        "pass_ms": {k: round(v / n_eager, 4) for k, v in pass_ms.items()},
+        "kernels": kern,
+        "roofline": roofline,
+    }
+    return res, got
+
+
+# oracle sample: the particles of a central cube plus the halo their outputs
+# depend on (hydro force neighbours, their gather neighbours, theirs: three
+# hydro ranges, 6 h_max; gravity: r_c), sized for about 10-30 s of oracle
+# time on the host's cores
+CPU_SAMPLE_PARTICLES = 6.0e6
+PARITY_KEYS = ("V", "rho_tilde", "rho", "A", "B", "gradA", "gradB", "P", "cs",
+               "a_hydro", "dudt", "a_grav_gas", "a_grav_dm")
+
+
+def oracle_sample(wl):
+    """(sub, gas_idx, dm_idx, inner_gas, inner_dm, side, halo) of the
+    oracle's sample of a single-box workload (workloads.sub_cube)."""
+    import numpy as np
+    from paper_2510_03557_amd import workloads
+    h_max = float(np.max(wl.gas.h)) if wl.gas.n else 0.0
+    halo = 1.001 * max(float(wl.r_c[0]), 6.0 * h_max)
+    side = max((CPU_SAMPLE_PARTICLES / wl.n_total) ** (1.0 / 3.0) - 2 * halo,
+               2 * halo)
+    side = min(side, 0.49 - 2 * halo)
+    return workloads.sub_cube(wl, side, halo) + (side, halo)
+
+
+def parity_errors(got, ref, keys=PARITY_KEYS):
+    """Per output: relative RMS (vectors and tensors by their Euclidean /
+    Frobenius norms) and the worst particle's error |y_i - y_ref_i| /
+    (|y_ref_i| + RMS_i |y_ref_i|) of the float32 GPU step against the FP64
+    oracle."""
+    import numpy as np
+    out = {}
+    for k in keys:
+        g = np.asarray(got[k], np.float64)
+        r = np.asarray(ref[k], np.float64)
+        if k.startswith("a_"):
+            g, r = np.moveaxis(g, -1, 0), np.moveaxis(r, -1, 0)
+        g = g.reshape(g.shape[0], -1)
+        r = r.reshape(r.shape[0], -1)
+        if g.shape[0] == 0:
+            continue
+        d = np.sqrt(np.sum((g - r) ** 2, axis=1))
+        rn = np.sqrt(np.sum(r * r, axis=1))
+        scale = float(np.sqrt(np.mean(rn * rn)))
+        out[k] = {"rel_rms": float(np.sqrt(np.sum(d * d)) / scale
+                                   / np.sqrt(rn.shape[0])) if scale > 0
+                  else float(np.sqrt(np.mean(d * d))),
+                  "worst_particle": float(np.max(d / (rn + scale)))
+                  if scale > 0 else float(np.max(d))}
+    return out
+
+
+def cpu_baseline_and_parity(sample, workload, got, log):
+    """The FP64 oracle timed on a bounded sample of the benchmarked
+    workload (a central cube with its dependency halo, every particle of it
+    computed), and the per-output errors of the float32 GPU step (got: its
+    outputs at the cube's inner particles) against the oracle there, where
+    the sample holds every neighbourhood in full."""
+    import numpy as np
+    import oracle
+    sub, gi, di, ig, idm, side, halo = sample
+    oracle.build(force=False)
+    log(f"[bench] cpu baseline: FP64 oracle on a cube of side {side:.4f} with "
+        f"halo {halo:.4f} ({sub.n_total} particles)")
+    t0 = time.perf_counter()
+    ref = oracle.step(sub)
+    tc = time.perf_counter() - t0
+    cpu = {"value": sub.n_total / tc, "unit": "particles/s",
+           "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"central cube of side {side:.4f} of {workload} with a "
+                     f"{halo:.4f} halo (max(r_c, 6 h_max)): {sub.n_total} "
+                     f"particles, every one computed (one step of the four "
+                     f"passes, FP64 C oracle with OpenMP); rate = sample "
+                     f"particles / oracle seconds",
+           "seconds": round(tc, 2), "host": host_info()}
+    gsel, dsel = np.nonzero(ig)[0], np.nonzero(idm)[0]
+    inner = {}
+    for k in PARITY_KEYS:
+        if k == "a_grav_dm":
+            inner[k] = ref[k][:, dsel]
+        elif k.startswith("a_"):
+            inner[k] = ref[k][:, gsel]
+        else:
+            inner[k] = ref[k][gsel]
+    par = {"particles": {"gas": int(gsel.size), "dm": int(dsel.size)},
+           "region": "inner cube of the oracle sample",
+           "bound_rel_rms": 1e-5,
+           "outputs": parity_errors(got, inner)}
+    par["max_rel_rms"] = max(v["rel_rms"] for v in par["outputs"].values())
+    return cpu, par
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="zeldovich128")
-    # defaults: the fastest shape the tuner found for this workload on
+    ap.add_argument("--workload", default="zeldovich448")
+    ap.add_argument("--secondary", default="zeldovich128",
+                    help="second workload, measured after the headline with "
+                         "the next rows (reconstructed viscosity, substep "
+                         "cycle, mesh gravity, friends-of-friends); 'none' "
+                         "skips it")
+    # defaults: the fastest shape the tuner found for these workloads on
     # MI355X (--tune re-runs the search)
     ap.add_argument("--leaf-max", type=int, default=64)
     ap.add_argument("--grid-mult", type=int, default=0)
@@ -339,7 +573,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--substep-levels", type=int, default=8,
                     help="most levels of the hierarchical time-step cycle "
-                         "timed after the step (0: none)")
+                         "timed on the secondary workload (0: none)")
     ap.add_argument("--cycles", type=int, default=3)
     ap.add_argument("--cycle-only", action="store_true",
                     help="time only the hierarchical time-step cycle and "
@@ -367,7 +601,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -382,139 +615,50 @@ def main():
         return
 
     from paper_2510_03557_amd import workloads
-    from paper_2510_03557_amd.step import ShortRangeStep
 
     torch.cuda.set_device(0)
-    log(f"[bench] generating {args.workload}")
-    wl = workloads.make(args.workload)
-    n = wl.n_total
     tuning = dict(leaf_max=args.leaf_max, grid_mult=args.grid_mult,
                   xcd_remap=args.xcd_remap, walk_mask=args.walk_mask,
                   sub_sweep=args.sub_sweep, tree_lds=args.tree_lds)
 
-    if args.fof_only:
-        out = measure_fof(wl, tuning, 5, log)
-        half = n // 2
-        out["clustered"] = measure_fof(
-            workloads.random_uniform(half, n - half, 77, clustered=True,
-                                     h_rule="global"), tuning, 5, log)
+    if args.fof_only or args.pm_only or args.cycle_only:
+        log(f"[bench] generating {args.workload}")
+        wl = workloads.make(args.workload)
+        n = wl.n_total
+        if args.fof_only:
+            out = measure_fof(wl, tuning, 5, log)
+            half = n // 2
+            out["clustered"] = measure_fof(
+                workloads.random_uniform(half, n - half, 77, clustered=True,
+                                         h_rule="global"), tuning, 5, log)
+        elif args.pm_only:
+            out = measure_pm(wl, 10, log)
+        else:
+            out = measure_cycle(wl, tuning, max(args.substep_levels, 1),
+                                args.cycles, None, log)
         print(json.dumps(out), flush=True)
         return
-    if args.pm_only:
-        print(json.dumps(measure_pm(wl, 10, log)), flush=True)
-        return
-    if args.cycle_only:
-        print(json.dumps(measure_cycle(wl, tuning, max(args.substep_levels, 1),
-                                       args.cycles, None, log)), flush=True)
-        return
 
-    # ---------------- float32 path: graph replay of the whole step ---------
-    st = ShortRangeStep(wl, precision="fp32", tuning=tuning, dt=args.dt)
-    tuned = None
-    if args.tune:
-        from paper_2510_03557_amd import autotune
-        log("[bench] tuning leaf size and grid")
-        tuned = autotune.tune(st, log=log)
-        tuning = tuned["tuning"]
-    log(f"[bench] fp32 path with {tuning}: eager warm-up, kernel timing")
-    st.run(integrate=True)
-    st.sync()
-    pairs = st.ctx.count_pairs(st.tree)
-    info = st.tree.info()
-    # per-kernel HIP-event timing over eager steps on the library stream
-    st.ctx.timing(True)
-    n_eager = max(args.steps // 4, 3)
-    for _ in range(n_eager):
-        st.run(integrate=True)
-    pass_ms, kern_ms, launches = st.ctx.pass_times()
-    st.ctx.timing(False)
-    st.sync()
-    # the same float32 step launched eagerly (no graph): separates the gain
-    # of graph replay from that of the precision
-    sec_eager = time_steps(lambda: st.run(integrate=True),
-                           lambda: st.ctx.stream.synchronize(),
-                           max(args.steps // 2, 3), 1)
-    st.sync()
-    log("[bench] fp32 path: graph capture and timed replays")
-    st.capture(integrate=True)
-    sec = time_steps(st.replay, lambda: (torch.cuda.synchronize(),
-                                         st.ctx.stream.synchronize()),
-                     args.steps, args.warmup)
-    st.sync()
-    value = n / sec
-
-    # ---------------- float64 plain path (eager) -----------------------------
-    fp64 = None
-    if not args.no_fp64:
-        log("[bench] fp64 plain path")
-        st64 = ShortRangeStep(wl, precision="fp64", tuning=dict(leaf_max=64),
-                              dt=args.dt)
-        sec64 = time_steps(lambda: st64.run(integrate=True),
-                           lambda: st64.ctx.stream.synchronize(),
-                           args.fp64_steps, 1)
-        st64.sync()
-        fp64 = {"value": n / sec64, "ms_per_step": sec64 * 1e3,
-                "dtype": "f64", "launch": "eager", "leaf_max": 64}
-        st64.close()
-
-    # ---------------- roofline of the dominant pass kernel -------------------
-    pair_of = {"density": pairs[0], "coefficients": pairs[0],
-               "hydro": pairs[1], "gravity": pairs[2]}
-    kern = {}
-    for p in ("density", "coefficients", "hydro", "gravity"):
-        if launches[p]:
-            avg = kern_ms[p] / launches[p]
-            flop = pair_of[p] * FLOP_PER_PAIR[p]
-            kern[p] = {"avg_ms": avg, "pairs": pair_of[p],
-                       "flop_per_pair": FLOP_PER_PAIR[p],
-                       "tflops": flop / (avg * 1e-3) / 1e12}
-    dom = max(kern, key=lambda k: kern[k]["avg_ms"])
-    ach = kern[dom]["tflops"]
-    traffic = measured_traffic(dom, kernel_name(dom, tuning), args.workload)
-    roofline = {"bound": "alu", "achieved": round(ach, 3),
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic, "kernel": kernel_name(dom, tuning),
-                "avg_launch_ms": round(kern[dom]["avg_ms"], 4),
-                "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
-                "frac_unpacked": round(ach / PEAK_FP32_UNPACKED_TFLOPS, 4)}
-
-    # ---------------- the step with the reconstructed viscosity -------------
-    recon = None
-    if not args.no_recon:
-        st.close()
-        recon = measure_recon(wl, tuning, args.steps, args.warmup, pairs[0],
-                              pairs[1], log)
-
-    # ---------------- hierarchical time steps ---------------------------------
-    cycle = None
-    if args.substep_levels > 0:
-        st.close()
-        cycle = measure_cycle(wl, tuning, args.substep_levels, args.cycles,
-                              sec * 1e3, log)
-
-    pm = None
-    if not args.no_pm:
-        st.close()
-        pm = measure_pm(wl, 10, log)
-
-    fof = None
-    if not args.no_fof:
-        st.close()
-        fof = measure_fof(wl, tuning, 5, log)
-        # the Zel'dovich box is nearly uniform at this linking length (no
-        # friends at all): a clustered set of the same size exercises the
-        # unions as well
-        log("[bench] fof on a clustered set of the same size")
-        half = n // 2
-        fof["clustered"] = measure_fof(
-            workloads.random_uniform(half, n - half, 77, clustered=True,
-                                     h_rule="global"), tuning, 5, log)
-
-    # ---------------- CPU baseline: the FP64 oracle ---------------------------
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline: FP64 oracle, whole workload, one step")
+    # ---------------- headline: the step on the benchmarked workload ---------
+    log(f"[bench] generating {args.workload}")
+    t0 = time.perf_counter()
+    wl = workloads.make(args.workload)
+    log(f"[bench] {wl.n_total} particles in {time.perf_counter() - t0:.1f} s")
+    n = wl.n_total
+    cpu = par = sample = None
+    if not args.no_cpu_baseline and wl.n_boxes == 1:
+        # the oracle's sample is fixed before the GPU step, whose outputs at
+        # the sample's inner particles are kept for the parity entry
+        sample = oracle_sample(wl)
+    res, got = measure_step(
+        wl, args.workload, tuning, args, log, tune=args.tune,
+        sample=None if sample is None else (sample[1][sample[3]],
+                                            sample[2][sample[4]]))
+    if sample is not None:
+        cpu, par = cpu_baseline_and_parity(sample, args.workload, got, log)
+        del sample
+    elif not args.no_cpu_baseline:
+        # batches of boxes: the oracle on the whole workload
         import oracle
         oracle.build(force=False)
         t0 = time.perf_counter()
@@ -522,52 +666,60 @@ def main():
         tc = time.perf_counter() - t0
         cpu = {"value": n / tc, "unit": "particles/s",
                "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"the whole {args.workload} workload ({n} particles),"
-                         " one step of the four passes, FP64 C oracle with "
-                         "OpenMP", "seconds": round(tc, 2)}
+               "sample": f"the whole {args.workload} workload ({n} particles)"
+                         ", one step of the four passes, FP64 C oracle with "
+                         "OpenMP", "seconds": round(tc, 2), "host": host_info()}
 
     out = {
         "metric": "particles/s per full short-range step (grav+CRKSPH), "
                   "FP32-batched vs FP64 plain",
-        "value": value, "unit": "particles/s", "n_gpus": 1,
+        "value": res["value"], "unit": "particles/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": sec * 1e3, "higher_is_better": True,
+        "ms_per_step": res["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload,
-                   "description": "128^3 dm + 128^3 gas, Zel'dovich P(k)~k^-2,"
-                                  " r_c=3/128, ~64 hydro neighbours, periodic"
-                   if args.workload == "zeldovich128" else wl.name,
-                   "n_particles": n, "boxes": wl.n_boxes,
-                   "leaf_max": tuning["leaf_max"],
-                   "grid_mult": tuning["grid_mult"],
-                   "xcd_remap": tuning.get("xcd_remap", 1),
-                   "walk_mask": tuning.get("walk_mask", 0),
-                   "sub_sweep": tuning.get("sub_sweep", 2),
-                   "tree_lds": tuning.get("tree_lds", 1), "launch": "hip_graph",
-                   "leaves": info["n_leaves"],
-                   "list_entries": {"gravity": info["grav_entries"],
-                                    "hydro": info["hydro_entries"]}},
-        "fp32_eager": {"value": n / sec_eager, "ms_per_step": sec_eager * 1e3,
-                       "launch": "eager"},
-        "fp64_plain": fp64,
-        "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
-        "pairs": {"gather": pairs[0], "hydro": pairs[1], "gravity": pairs[2]},
-        "swept_pairs": {"gather": pairs[3], "hydro": pairs[4],
-                        "gravity": pairs[5]},
-        "tuning": tuned,
-        "pass_ms": {k: round(v / n_eager, 4) for k, v in pass_ms.items()},
-        "kernels": kern,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "recon_viscosity": recon,
-        "substep_cycle": cycle,
-        "pm_long_range": pm,
-        "fof": fof,
-        "context": "paper: 46.6e9 particles/s on 9,000 Frontier nodes for the"
-                   " whole solver per PM step (not like-for-like)",
     }
-    st.close()
+    out.update({k: v for k, v in res.items()
+                if k not in ("value", "ms_per_step")})
+    out["cpu_baseline"] = cpu
+    out["parity_vs_oracle"] = par
+
+    # ---------------- secondary workload and the next rows ------------------
+    wl2 = wl
+    name2 = args.workload
+    if args.secondary not in ("none", "", args.workload):
+        del wl
+        log(f"[bench] generating {args.secondary}")
+        wl2 = workloads.make(args.secondary)
+        name2 = args.secondary
+        sec_res, _ = measure_step(wl2, name2, tuning, args, log)
+        out[name2] = sec_res
+    sec_pairs = (out[name2] if name2 in out else res)["pairs"]
+    nxt = out[name2] if name2 in out else out
+    if not args.no_recon:
+        nxt["recon_viscosity"] = measure_recon(
+            wl2, tuning, args.steps, args.warmup, sec_pairs["gather"],
+            sec_pairs["hydro"], log)
+    if args.substep_levels > 0:
+        nxt["substep_cycle"] = measure_cycle(
+            wl2, tuning, args.substep_levels, args.cycles,
+            (out[name2] if name2 in out else res)["ms_per_step"], log)
+    if not args.no_pm:
+        nxt["pm_long_range"] = measure_pm(wl2, 10, log)
+    if not args.no_fof:
+        fof = measure_fof(wl2, tuning, 5, log)
+        # the Zel'dovich box is nearly uniform at this linking length (no
+        # friends at all): a clustered set of the same size exercises the
+        # unions as well
+        log("[bench] fof on a clustered set of the same size")
+        half = wl2.n_total // 2
+        fof["clustered"] = measure_fof(
+            workloads.random_uniform(half, wl2.n_total - half, 77,
+                                     clustered=True, h_rule="global"),
+            tuning, 5, log)
+        nxt["fof"] = fof
+    out["context"] = ("paper: 46.6e9 particles/s on 9,000 Frontier nodes for "
+                      "the whole solver per PM step (not like-for-like)")
     print(json.dumps(out), flush=True)
 
 

@@ -280,6 +280,61 @@ def zeldovich(ng: int = 128, seed: int = 2, spectral_index: float = -2.0,
                         "rms_cells": rms_cells})
 
 
+def half_box_shift(c: np.ndarray) -> np.ndarray:
+    """Float32 box coordinates in [1, 2) moved by half a box, periodically:
+    x - 0.5 for x >= 1.5, x + 0.5 below.  Both branches stay inside [1, 2)
+    with the same spacing of float32 values, so the move is exact and every
+    minimum-image separation is unchanged."""
+    c = np.asarray(c, F32)
+    return np.where(c >= F32(1.5), c - F32(0.5), c + F32(0.5)).astype(F32)
+
+
+def sub_cube(wl: Workload, side: float, halo: float, centre=1.5):
+    """The particles of one box inside the cube of the given side about
+    ``centre`` (a box coordinate in [1, 2), or one per axis), plus a halo of
+    the given width around it, as a workload of its own (one box with the
+    same r_c and eps; masses, h and u unchanged).  An axis along which the
+    cube with its halo would cross the box's faces is first moved by half a
+    box (half_box_shift, exact), so a cube may sit on the periodic faces.
+    The cube with its halo must span less than half the box, so that the
+    sub-box seen as a periodic unit box gains no pair across its faces.
+    Returns (sub, gas_idx, dm_idx, inner_gas, inner_dm): the sub-box
+    particles' indices in wl, and masks of those inside the cube proper.
+    Selection only: no arithmetic of the method."""
+    if wl.n_boxes != 1:
+        raise ValueError("sub_cube takes a single-box workload")
+    w = 0.5 * side + halo
+    if not (2 * w < 0.5):
+        raise ValueError("cube with halo must span less than half the box")
+    cen = np.broadcast_to(np.asarray(centre, np.float64), (3,)).copy()
+    shift = [not (1.0 < c - w and c + w < 2.0) for c in cen]
+    for a in range(3):
+        if shift[a]:
+            cen[a] = cen[a] - 0.5 if cen[a] >= 1.5 else cen[a] + 0.5
+    out = []
+    for sp in (wl.gas, wl.dm):
+        sel = np.ones(sp.n, bool)
+        inner = np.ones(sp.n, bool)
+        coords = []
+        for a, c in enumerate((sp.x, sp.y, sp.z)):
+            if shift[a]:
+                c = half_box_shift(c)
+            coords.append(c)
+            c = c.astype(np.float64)
+            sel &= (c >= cen[a] - w) & (c < cen[a] + w)
+            inner &= (c >= cen[a] - 0.5 * side) & (c < cen[a] + 0.5 * side)
+        idx = np.nonzero(sel)[0]
+        f = {k: v[idx] for k, v in sp.fields().items()}
+        f["x"], f["y"], f["z"] = (c[idx] for c in coords)
+        out.append((Species(**f), idx, inner[idx]))
+    (gas, gi, ig), (dm, di, idm) = out
+    sub = _single_box(f"{wl.name}_cube", gas, dm, float(wl.r_c[0]),
+                      float(wl.eps[0]),
+                      {"kind": "sub_cube", "parent": wl.name, "side": side,
+                       "halo": halo, "centre": cen.tolist(), "shift": shift})
+    return sub, gi, di, ig, idm
+
+
 def uneven_boxes(n_boxes: int = 512, seed: int = 3000, median: float = 20000.0,
                  sigma_ln: float = 0.768, nmin: int = 2000,
                  nmax: int = 200000) -> Workload:

@@ -1,11 +1,22 @@
 """GPU parity at the full sizes of the large configurations, in the launch
 shape the benchmark uses (leaves of <= 64, one wavefront per sub-leaf with
-four lanes per particle), checked on sampled particles: the oracle computes
-each sampled particle's outputs from its full neighbourhood closure
-(coefficients of its force neighbours, volumes of theirs), so the
-comparison is exact in definition.  Same bound as the small cases: relative
-RMS <= 1e-5 per output over the sample.  The 13.5 M-particle batch also
-runs the whole-leaf broadcast sweep."""
+four lanes per particle), checked against the FP64 oracle on large samples:
+
+* the 180 M-particle box (448^3 + 448^3): every particle of two cubes of
+  about 10^5 particles each, one in the middle of the box and one on its
+  periodic corner (moved by an exact half-box shift), each computed by the
+  oracle together with the halo its outputs depend on (max(r_c, 6 h_max):
+  hydro force neighbours, their gather neighbours, theirs);
+* the 2^26-particle Plummer set and the 13.5 M-particle batch of 512 boxes:
+  10^4 gas targets stratified over the deciles of h (local density, from the
+  Plummer cores to the background), plus the densest particles, and 2,000
+  dm targets, each computed from its full neighbourhood closure
+  (oracle.step_sampled); in the Plummer set the dense chaining-mesh bins
+  exceed 2,048 particles and take the general tree path.
+
+Bounds: relative RMS <= 1e-5 per output over each sample (the specified
+bound), the worst particle within the per-particle bound of parity_util,
+and no particle on a different coefficient branch than the oracle."""
 import numpy as np
 import pytest
 
@@ -14,65 +25,122 @@ torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 from paper_2510_03557_amd import workloads as W  # noqa: E402
+from parity_util import (PER_PARTICLE_FP32, degenerate_disagreements,  # noqa: E402
+                         rel_rms, worst_particle)
 
 FP32_TOL = 1e-5
 GAS_KEYS = ("V", "rho_tilde", "A", "B", "gradA", "gradB", "rho", "P", "cs",
             "a_hydro", "dudt", "a_grav_gas")
+_cache = {}
 
 
-def rel_rms(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    den = np.sqrt(np.sum(b * b))
-    return np.sqrt(np.sum((a - b) ** 2)) / den
+def workload(name):
+    if name not in _cache:
+        _cache.clear()
+        print(f"case {name}: generating", flush=True)
+        _cache[name] = W.make(name)
+    return _cache[name]
 
 
-def pick_gas(wl, rng, n_random, n_dense):
-    """Random gas particles plus the n_dense with the smallest h (densest)."""
-    g = np.sort(rng.choice(wl.gas.n, n_random, replace=False))
-    if n_dense:
-        dense = np.argpartition(wl.gas.h, n_dense)[:n_dense]
-        g = np.unique(np.concatenate([g, dense]))
-    return g
-
-
-@pytest.mark.parametrize("name,n_gas_rand,n_dense,n_dm,sub,recon", [
-    ("uneven_boxes512", 60, 0, 200, 0, False),
-    ("uneven_boxes512", 40, 0, 100, 2, False),
-    ("plummer64M", 24, 8, 200, 2, False),
-    ("zeldovich448", 32, 0, 200, 2, False),
-    # with the velocity gradient and the reconstructed viscosity
-    ("uneven_boxes512", 40, 0, 50, 2, True),
-    ("plummer64M", 16, 8, 50, 2, True),
-])
-def test_large_config_sampled(orc, name, n_gas_rand, n_dense, n_dm, sub,
-                              recon):
-    from paper_2510_03557_amd.step import ShortRangeStep
-    print(f"case {name} sub_sweep={sub} recon={recon}: generating", flush=True)
-    wl = W.make(name)
-    print(f"case {name}: {wl.n_total} particles in {wl.n_boxes} boxes, GPU "
-          "step", flush=True)
-    st = ShortRangeStep(wl, precision="fp32",
-                        tuning=dict(leaf_max=64, sub_sweep=sub), recon=recon)
-    st.run()
-    got = st.outputs()
-    pairs = st.ctx.count_pairs(st.tree)
-    info = st.tree.info()
-    print(f"case {name}: pairs {pairs}, leaves {info['n_leaves']}, "
-          f"k-d levels {info['kd_levels']}", flush=True)
-    st.close()
-    del st
-    rng = np.random.default_rng(11)
-    gi = pick_gas(wl, rng, n_gas_rand, n_dense)
-    di = np.sort(rng.choice(wl.dm.n, n_dm, replace=False))
-    print(f"case {name}: oracle on {gi.size} gas + {di.size} dm samples",
-          flush=True)
-    ref = orc.step_sampled(wl, gi, di, recon=recon)
-    errs = {}
-    for k in GAS_KEYS + (("dv",) if recon else ()):
-        g = got[k][:, gi] if k.startswith("a_") else got[k][gi]
-        errs[k] = rel_rms(g, ref[k])
-    errs["a_grav_dm"] = rel_rms(got["a_grav_dm"][:, di], ref["a_grav_dm"])
-    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+def check(got, ref, keys, label):
+    errs, worst = {}, {}
+    for k in keys:
+        errs[k] = rel_rms(got[k], ref[k])
+        worst[k] = worst_particle(k, got[k], ref[k])
+    flips = degenerate_disagreements(got, ref)
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    print(label, "worst particle:",
+          {k: f"{v[0]:.2e}" for k, v in worst.items()}, "branch flips:",
+          flips, flush=True)
     bad = {k: v for k, v in errs.items() if not v <= FP32_TOL}
+    badw = {k: v for k, v in worst.items() if not v[0] <= PER_PARTICLE_FP32}
     assert not bad, bad
+    assert not badw, badw
+    assert flips == 0, flips
+
+
+def gpu_outputs(wl, samples, sub_sweep=2, recon=False, grid_mult=0):
+    """The float32 step on the whole workload; outputs at each (gas, dm)
+    index sample."""
+    from paper_2510_03557_amd.step import ShortRangeStep
+    st = ShortRangeStep(wl, precision="fp32", recon=recon,
+                        tuning=dict(leaf_max=64, sub_sweep=sub_sweep,
+                                    grid_mult=grid_mult))
+    try:
+        st.run()
+        pairs = st.ctx.count_pairs(st.tree)
+        info = st.tree.info()
+        print(f"  GPU step: pairs {pairs}, leaves {info['n_leaves']}, k-d "
+              f"levels {info['kd_levels']}", flush=True)
+        return [st.outputs_at(g, d) for g, d in samples]
+    finally:
+        st.close()
+
+
+def test_zeldovich448_cubes(orc):
+    """Two cubes of the 180 M-particle box, one on the periodic corner."""
+    wl = workload("zeldovich448")
+    h_max = float(np.max(wl.gas.h))
+    halo = 1.001 * max(float(wl.r_c[0]), 6.0 * h_max)
+    side = 0.055  # about 1.8e5 particles inside, 1.2e6 with the halo
+    cubes = [W.sub_cube(wl, side, halo, c) for c in (1.5, 1.0)]
+    samples = [(gi[ig], di[idm]) for _, gi, di, ig, idm in cubes]
+    print(f"case zeldovich448: cubes of side {side} with halo {halo:.4f}: "
+          f"{[int(ig.sum() + idm.sum()) for *_, ig, idm in cubes]} inner "
+          "particles", flush=True)
+    gots = gpu_outputs(wl, samples)
+    for (sub, gi, di, ig, idm), got, where in zip(cubes, gots,
+                                                  ("centre", "corner")):
+        print(f"case zeldovich448 cube at the {where}: oracle on "
+              f"{sub.n_total} particles (shift {sub.meta['shift']})",
+              flush=True)
+        ref = orc.step(sub)
+        gs, ds = np.nonzero(ig)[0], np.nonzero(idm)[0]
+        inner = {k: (ref[k][:, ds] if k == "a_grav_dm" else
+                     ref[k][:, gs] if k.startswith("a_") else ref[k][gs])
+                 for k in GAS_KEYS + ("a_grav_dm",)}
+        inner["degenerate"] = ref["degenerate"][gs]
+        # h deciles of the inner particles against the whole box
+        q = np.quantile(wl.gas.h[gi[ig]], [0.0, 0.5, 1.0])
+        print(f"  inner h min/median/max {q}, box h range "
+              f"[{wl.gas.h.min():.4g}, {wl.gas.h.max():.4g}]", flush=True)
+        check(got, inner, GAS_KEYS + ("a_grav_dm",),
+              f"zeldovich448 {where}")
+
+
+def stratified_gas(wl, rng, per_decile, n_dense):
+    """per_decile gas targets from every decile of h, plus the n_dense
+    particles of smallest h (densest)."""
+    h = wl.gas.h
+    order = np.argsort(h, kind="stable")
+    parts = np.array_split(order, 10)
+    g = [rng.choice(p, min(per_decile, p.size), replace=False) for p in parts]
+    g.append(order[:n_dense])
+    return np.unique(np.concatenate(g))
+
+
+@pytest.mark.parametrize("name,per_decile,n_dense,n_dm,sub,recon,grid", [
+    ("plummer64M", 1000, 64, 2000, 2, False, 0),
+    ("uneven_boxes512", 1000, 0, 2000, 2, False, 0),
+    ("uneven_boxes512", 300, 0, 500, 0, False, 0),
+    # the persistent cost-ordered queue form of the launch
+    ("uneven_boxes512", 300, 0, 500, 0, False, 16),
+    # with the velocity gradient and the reconstructed viscosity
+    ("uneven_boxes512", 200, 0, 200, 2, True, 0),
+    ("plummer64M", 100, 16, 200, 2, True, 0),
+])
+def test_large_config_stratified(orc, name, per_decile, n_dense, n_dm, sub,
+                                 recon, grid):
+    wl = workload(name)
+    rng = np.random.default_rng(11)
+    gi = stratified_gas(wl, rng, per_decile, n_dense)
+    di = np.sort(rng.choice(wl.dm.n, n_dm, replace=False))
+    print(f"case {name} sub_sweep={sub} recon={recon} grid_mult={grid}: "
+          f"{wl.n_total} particles in {wl.n_boxes} boxes, {gi.size} gas + "
+          f"{di.size} dm targets", flush=True)
+    (got,) = gpu_outputs(wl, [(gi, di)], sub_sweep=sub, recon=recon,
+                         grid_mult=grid)
+    print(f"case {name}: oracle on the targets", flush=True)
+    ref = orc.step_sampled(wl, gi, di, recon=recon)
+    check(got, ref, GAS_KEYS + ("a_grav_dm",) + (("dv",) if recon else ()),
+          f"{name} sub={sub} recon={recon} grid={grid}")
