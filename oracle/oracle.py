@@ -333,12 +333,15 @@ def step(wl, params=PARAMS, brute=False, passes=("density", "coefficients",
     return out
 
 
-def step_sampled(wl, gas_targets, dm_targets, params=PARAMS, recon=False):
+def step_sampled(wl, gas_targets, dm_targets, params=PARAMS, recon=False,
+                 progress=None):
     """The step's outputs at sampled particles only (global indices into the
     gas and dm arrays).  Each sampled gas particle pulls in the
     neighbourhoods its outputs depend on: coefficients (and, with
     ``recon``, velocity gradients) at its force neighbours, and volumes at
-    their gather neighbours."""
+    their gather neighbours.  ``progress(msg)``, if given, is called after
+    each stage (large sets take minutes)."""
+    say = progress or (lambda msg: None)
     g, d = wl.gas, wl.dm
     gas_targets = np.asarray(gas_targets, np.int64)
     dm_targets = np.asarray(dm_targets, np.int64)
@@ -363,13 +366,18 @@ def step_sampled(wl, gas_targets, dm_targets, params=PARAMS, recon=False):
             T = gas_targets[sel] - gs.start
             off, idx = neighbours(gx, gy, gz, gh, 1, targets=T)
             S1 = np.unique(np.concatenate([T, idx]))
+            say(f"oracle box {b}: {T.size} targets, {S1.size} force "
+                "neighbours")
             off2, idx2 = neighbours(gx, gy, gz, gh, 0, targets=S1)
             S2 = np.unique(np.concatenate([S1, idx2]))
+            say(f"oracle box {b}: {S2.size} particles of the volume closure")
             V = np.full(n, np.nan)
             rt = np.full(n, np.nan)
             V[S2], rt[S2] = density(gx, gy, gz, gh, gm, targets=S2)
+            say(f"oracle box {b}: volumes done")
             c = coefficients(gx, gy, gz, gh, gm, V, g.u[gs], params["gamma"],
                              targets=S1)
+            say(f"oracle box {b}: coefficients done")
             full = {}
             for k in ("A", "rho", "P", "cs"):
                 full[k] = np.full(n, np.nan)
@@ -397,6 +405,7 @@ def step_sampled(wl, gas_targets, dm_targets, params=PARAMS, recon=False):
                 res[k][sel] = full[k][T]
             res["a_hydro"][:, sel] = (ax, ay, az)
             res["dudt"][sel] = du
+            say(f"oracle box {b}: hydro forces done")
         X = np.concatenate([gx, d.x[ds]])
         Y = np.concatenate([gy, d.y[ds]])
         Z = np.concatenate([gz, d.z[ds]])
@@ -408,6 +417,7 @@ def step_sampled(wl, gas_targets, dm_targets, params=PARAMS, recon=False):
         k = sel.size
         res["a_grav_gas"][:, sel] = (ax[:k], ay[:k], az[:k])
         res["a_grav_dm"][:, dsel] = (ax[k:], ay[k:], az[k:])
+        say(f"oracle box {b}: gravity done")
     return res
 
 

@@ -3,14 +3,14 @@ shape the benchmark uses (leaves of <= 64, one wavefront per sub-leaf with
 four lanes per particle), checked against the FP64 oracle on large samples:
 
 * the 180 M-particle box (448^3 + 448^3): every particle of two cubes of
-  about 10^5 particles each, one in the middle of the box and one on its
+  about 1.8 x 10^5 particles each, one in the middle of the box and one on its
   periodic corner (moved by an exact half-box shift), each computed by the
   oracle together with the halo its outputs depend on (max(r_c, 6 h_max):
   hydro force neighbours, their gather neighbours, theirs);
 * the 2^26-particle Plummer set and the 13.5 M-particle batch of 512 boxes:
-  10^4 gas targets stratified over the deciles of h (local density, from the
-  Plummer cores to the background), plus the densest particles, and 2,000
-  dm targets, each computed from its full neighbourhood closure
+  about 10^4 gas targets stratified over the deciles of h (local density,
+  from the Plummer cores to the background; 200 from the densest decile of
+  the Plummer set), plus the densest particles, and 2,000 dm targets, each computed from its full neighbourhood closure
   (oracle.step_sampled); in the Plummer set the dense chaining-mesh bins
   exceed 2,048 particles and take the general tree path.
 
@@ -82,7 +82,7 @@ def test_zeldovich448_cubes(orc):
     wl = workload("zeldovich448")
     h_max = float(np.max(wl.gas.h))
     halo = 1.001 * max(float(wl.r_c[0]), 6.0 * h_max)
-    side = 0.055  # about 1.8e5 particles inside, 1.2e6 with the halo
+    side = 0.1  # about 1.8e5 particles inside, 5e5 with the halo
     cubes = [W.sub_cube(wl, side, halo, c) for c in (1.5, 1.0)]
     samples = [(gi[ig], di[idm]) for _, gi, di, ig, idm in cubes]
     print(f"case zeldovich448: cubes of side {side} with halo {halo:.4f}: "
@@ -108,17 +108,25 @@ def test_zeldovich448_cubes(orc):
               f"zeldovich448 {where}")
 
 
-def stratified_gas(wl, rng, per_decile, n_dense):
-    """per_decile gas targets from every decile of h, plus the n_dense
-    particles of smallest h (densest)."""
+def stratified_gas(wl, rng, per_decile, n_dense, per_top=None):
+    """per_decile gas targets from every decile of h (per_top from the
+    first, densest decile, if given), plus the n_dense particles of
+    smallest h (densest)."""
     h = wl.gas.h
     order = np.argsort(h, kind="stable")
     parts = np.array_split(order, 10)
-    g = [rng.choice(p, min(per_decile, p.size), replace=False) for p in parts]
+    counts = [per_decile] * 10
+    if per_top is not None:
+        counts[0] = per_top
+    g = [rng.choice(p, min(c, p.size), replace=False)
+         for p, c in zip(parts, counts)]
     g.append(order[:n_dense])
     return np.unique(np.concatenate(g))
 
 
+# (the densest decile of the Plummer set holds the sphere cores, whose
+# particles have up to ~10^6 gravity neighbours each: fewer of them keep the
+# oracle's share of the test within a minute or two)
 @pytest.mark.parametrize("name,per_decile,n_dense,n_dm,sub,recon,grid", [
     ("plummer64M", 1000, 64, 2000, 2, False, 0),
     ("uneven_boxes512", 1000, 0, 2000, 2, False, 0),
@@ -133,7 +141,9 @@ def test_large_config_stratified(orc, name, per_decile, n_dense, n_dm, sub,
                                  recon, grid):
     wl = workload(name)
     rng = np.random.default_rng(11)
-    gi = stratified_gas(wl, rng, per_decile, n_dense)
+    gi = stratified_gas(wl, rng, per_decile, n_dense,
+                        per_top=min(per_decile, 200)
+                        if name.startswith("plummer") else None)
     di = np.sort(rng.choice(wl.dm.n, n_dm, replace=False))
     print(f"case {name} sub_sweep={sub} recon={recon} grid_mult={grid}: "
           f"{wl.n_total} particles in {wl.n_boxes} boxes, {gi.size} gas + "
@@ -141,6 +151,9 @@ def test_large_config_stratified(orc, name, per_decile, n_dense, n_dm, sub,
     (got,) = gpu_outputs(wl, [(gi, di)], sub_sweep=sub, recon=recon,
                          grid_mult=grid)
     print(f"case {name}: oracle on the targets", flush=True)
-    ref = orc.step_sampled(wl, gi, di, recon=recon)
+    ref = orc.step_sampled(
+        wl, gi, di, recon=recon,
+        progress=(lambda msg: print("  " + msg, flush=True))
+        if wl.n_boxes == 1 else None)
     check(got, ref, GAS_KEYS + ("a_grav_dm",) + (("dv",) if recon else ()),
           f"{name} sub={sub} recon={recon} grid={grid}")
