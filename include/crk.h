@@ -182,6 +182,23 @@ int build_interaction_lists(crk_ctx *ctx, crk_tree *tree);
 int crk_density(crk_ctx *ctx, crk_tree *tree, const void *m, void *V,
                 void *rho_tilde);
 
+/* crk_density that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * crk_density (bitwise the same outputs), but the masses in tree order, the
+ * one scratch buffer of that pass, live in a static device array of the
+ * library (CRK_NOALLOC_MAX_GAS values of the context precision, 16 MiB,
+ * held on every GPU the library runs on until the process ends) instead of
+ * library-allocated memory, and no timing events are recorded.  The tree
+ * (built by build_tree) must already exist.  More than CRK_NOALLOC_MAX_GAS
+ * gas particles: CRK_EINVAL.  Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents: calls that overlap on one
+ * GPU (several streams or threads at once) race and must be serialised by
+ * the caller.  Nothing in the array needs to start at zero. */
+#define CRK_NOALLOC_MAX_GAS 2097152
+int crk_density_noalloc(crk_ctx *ctx, crk_tree *tree, const void *m, void *V,
+                        void *rho_tilde);
+
 /* Reproducing-kernel correction coefficients (CRKSPH, Sec. IV-A; the
  * paper's highest-throughput kernel, Sec. V-B).  Gathers the moments
  * m0, m1, m2 of V_j W(r_ij, h_i) and their gradients, then solves, per
@@ -196,6 +213,7 @@ int crk_density(crk_ctx *ctx, crk_tree *tree, const void *m, void *V,
  * A = 1/m0, grad A = -grad m0 / m0^2.
  * Inputs m, V, u (n_gas); outputs A, rho, P, cs (n_gas), B and gradA
  * (3 planes), gradB (9 planes). */
+
 int crk_coefficients(crk_ctx *ctx, crk_tree *tree, const void *m,
                      const void *V, const void *u, void *A, void *B,
                      void *gradA, void *gradB, void *rho, void *P, void *cs);

@@ -27,7 +27,8 @@ PASS_NAMES = ("tree", "lists", "density", "coefficients", "hydro", "gravity",
 EXPORTS = (
     "crk_ctx_create", "crk_ctx_destroy", "crk_set_tuning", "crk_get_tuning",
     "crk_last_error", "crk_sync", "build_tree", "build_interaction_lists",
-    "crk_density", "crk_coefficients", "crk_hydro_forces",
+    "crk_density", "crk_density_noalloc", "crk_coefficients",
+    "crk_hydro_forces",
     "shortrange_gravity", "crk_integrate", "crk_tree_get_info",
     "crk_tree_get_leaves", "crk_count_pairs", "crk_graph_begin", "crk_graph_end",
     "crk_graph_launch", "crk_graph_reset", "crk_tree_free", "crk_timing_enable",
@@ -123,6 +124,7 @@ def load(path: Path | str | None = None):
         [ctypes.POINTER(vp)]
     lib.build_interaction_lists.argtypes = [vp, vp]
     lib.crk_density.argtypes = [vp, vp, vp, vp, vp]
+    lib.crk_density_noalloc.argtypes = [vp, vp, vp, vp, vp]
     lib.crk_coefficients.argtypes = [vp] * 12
     lib.crk_hydro_forces.argtypes = [vp] * 18
     lib.crk_velocity_gradient.argtypes = [vp] * 11
@@ -317,6 +319,13 @@ class Context:
         g = lambda t, k, nm: self._g(tree, t, k, nm)
         check(self.lib.crk_density(self.handle, tree.handle, g(m, 1, "m"),
                                    g(V, 1, "V"), g(rho_t, 1, "rho_tilde")))
+
+    def density_noalloc(self, tree, m, V, rho_t):
+        """crk_density with the library's static scratch (no allocation)."""
+        g = lambda t, k, nm: self._g(tree, t, k, nm)
+        check(self.lib.crk_density_noalloc(self.handle, tree.handle,
+                                           g(m, 1, "m"), g(V, 1, "V"),
+                                           g(rho_t, 1, "rho_tilde")))
 
     def coefficients(self, tree, m, V, u, A, B, gA, gB, rho, P, cs):
         g = lambda t, k, nm: self._g(tree, t, k, nm)

@@ -5,9 +5,20 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "crk_internal.h"
+
+// Scratch of crk_density_noalloc: the masses of the gas particles in tree
+// order (up to CRK_NOALLOC_MAX_GAS values of the context precision), as a
+// file-scope device array so that the entry point allocates nothing.  Each
+// GPU holds its own copy until the process ends.  In host code the name is
+// only a stand-in for the symbol, not a device address: its address on a
+// device comes from hipGetSymbolAddress, once per device (at the first
+// crk_ctx_create on it), and only that address is ever passed to kernels.
+static __device__ __align__(256) unsigned char
+    scratch[(size_t)CRK_NOALLOC_MAX_GAS * sizeof(double)];
 
 namespace crk {
 
@@ -26,7 +37,38 @@ int set_error(int status, const std::string &msg) {
 
 namespace {
 std::atomic<uint64_t> g_alloc_gen{1};
+
+// per-device address of the scratch array (null until looked up; a failed
+// lookup is remembered with its message)
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+std::string g_scratch_err[MAX_DEVICES];
+bool g_scratch_done[MAX_DEVICES] = {};
+
+// Looks the scratch array up on the current device (which must be dev).
+void *scratch_address(int dev, std::string *err) {
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        *err = "device index beyond the scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e == hipSuccess && p) {
+            g_scratch_ptr[dev] = p;
+        } else {
+            g_scratch_ptr[dev] = nullptr;
+            g_scratch_err[dev] = std::string("hipGetSymbolAddress(scratch): ") +
+                                 hipGetErrorString(e);
+        }
+        g_scratch_done[dev] = true;
+    }
+    *err = g_scratch_err[dev];
+    return g_scratch_ptr[dev];
 }
+}  // namespace
 
 uint64_t alloc_generation() { return g_alloc_gen.load(std::memory_order_acquire); }
 void alloc_generation_bump() { g_alloc_gen.fetch_add(1, std::memory_order_acq_rel); }
@@ -202,6 +244,8 @@ int crk_ctx_create(crk_ctx **out, int precision, void *stream,
         delete c;
         return set_error(CRK_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
     }
+    // the allocation-free entry point's scratch on this (current) device
+    c->noalloc_scratch = scratch_address(c->device, &c->noalloc_error);
     int s = c->err.ensure(64, false);
     if (s == CRK_OK) s = c->err_host.ensure(4096);
     if (s != CRK_OK) {
@@ -360,6 +404,27 @@ int crk_density(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
     if (!g) return CRK_OK;
     PassSpan sp(ctx, P_DENSITY);
     return pass_density(ctx, t, m, V, rho_tilde);
+}
+
+int crk_density_noalloc(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
+                        void *rho_tilde) {
+    CRK_TRY(check_tree_ready(ctx, t, true));
+    const size_t el = ctx->elem();
+    const bool g = t->n_gas > 0;
+    CRK_TRY(check_ptr(m, el, "m", g));
+    CRK_TRY(check_ptr(V, el, "V", g));
+    CRK_TRY(check_ptr(rho_tilde, el, "rho_tilde", g));
+    if (t->n_gas > (int64_t)CRK_NOALLOC_MAX_GAS)
+        return set_error(CRK_EINVAL,
+                         "crk_density_noalloc: " + std::to_string(t->n_gas) +
+                             " gas particles exceed its scratch of " +
+                             std::to_string((int64_t)CRK_NOALLOC_MAX_GAS) +
+                             "; use crk_density");
+    if (!ctx->noalloc_scratch)
+        return set_error(CRK_EDEVICE, "crk_density_noalloc: no scratch on this "
+                                      "device (" + ctx->noalloc_error + ")");
+    if (!g) return CRK_OK;
+    return pass_density_scratch(ctx, t, m, V, rho_tilde, ctx->noalloc_scratch);
 }
 
 int crk_coefficients(crk_ctx *ctx, crk_tree *t, const void *m, const void *V,

@@ -118,6 +118,8 @@ struct crk_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     uint64_t graph_gen = 0;   // allocation generation at the last capture
+    void *noalloc_scratch = nullptr;  // this device's static scratch array
+    std::string noalloc_error;        // why it is missing, if it is
     crk::DevBuf err;          // int error word + int64 required capacity
     crk::HostBuf err_host;
     crk::DevBuf scratch;      // primitives' temporary storage
@@ -257,6 +259,10 @@ int tree_build(crk_ctx *ctx, crk_tree *t, const crk_boxes *boxes,
 int lists_build(crk_ctx *ctx, crk_tree *t);
 int pass_density(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
                  void *rho_tilde);
+// crk_density with the tree-order masses in caller-provided scratch (at
+// least n_gas values of the context precision); allocates nothing
+int pass_density_scratch(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
+                         void *rho_tilde, void *scratch);
 int pass_coefficients(crk_ctx *ctx, crk_tree *t, const void *m,
                       const void *V, const void *u, void *A, void *B,
                       void *gradA, void *gradB, void *rho, void *P,

@@ -1896,10 +1896,15 @@ inline int64_t all_bound(crk_ctx *, crk_tree *t) {
 
 template <typename T>
 int density_impl(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
-                 void *rho_t) {
+                 void *rho_t, void *scratch) {
     const int64_t ng = t->n_gas;
-    CRK_TRY(t->pf[4].ensure(std::max<int64_t>(ng, 1) * sizeof(T), ctx->capturing));
-    T *mt = t->pf[4].as<T>();
+    // masses in tree order: the tree's pass scratch, or (allocation-free
+    // form) the caller's scratch, timed by no event either
+    T *mt = static_cast<T *>(scratch);
+    if (!mt) {
+        CRK_TRY(t->pf[4].ensure(std::max<int64_t>(ng, 1) * sizeof(T), ctx->capturing));
+        mt = t->pf[4].as<T>();
+    }
     hipLaunchKernelGGL((gather1_kernel<T>), dim3(grid_for(ng)), dim3(256), 0,
                        ctx->stream, t->perm.as<int32_t>(),
                        static_cast<const T *>(m), ng, mt);
@@ -1907,7 +1912,8 @@ int density_impl(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
     typename DensityPass<T>::Args pa{mt, static_cast<T *>(V),
                                      static_cast<T *>(rho_t)};
     return launch_pair<T, DensityPass<T>>(ctx, t, tree_view<T>(t, true, gas_leaf_count(t)),
-                                          pa, gas_bound(ctx, t), P_DENSITY, true);
+                                          pa, gas_bound(ctx, t),
+                                          scratch ? -1 : P_DENSITY, true);
 }
 
 template <typename T>
@@ -2115,8 +2121,16 @@ int fof_groups(crk_ctx *ctx, crk_tree *t, double b, int32_t *labels_gas,
 
 int pass_density(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
                  void *rho_tilde) {
-    if (ctx->precision == CRK_FP64) return density_impl<double>(ctx, t, m, V, rho_tilde);
-    return density_impl<float>(ctx, t, m, V, rho_tilde);
+    if (ctx->precision == CRK_FP64)
+        return density_impl<double>(ctx, t, m, V, rho_tilde, nullptr);
+    return density_impl<float>(ctx, t, m, V, rho_tilde, nullptr);
+}
+
+int pass_density_scratch(crk_ctx *ctx, crk_tree *t, const void *m, void *V,
+                         void *rho_tilde, void *scratch) {
+    if (ctx->precision == CRK_FP64)
+        return density_impl<double>(ctx, t, m, V, rho_tilde, scratch);
+    return density_impl<float>(ctx, t, m, V, rho_tilde, scratch);
 }
 
 int pass_coefficients(crk_ctx *ctx, crk_tree *t, const void *m, const void *V,
