@@ -98,8 +98,11 @@ typedef struct {
                            [1, 64]; 0 (default) widens the bins until each
                            holds about 4 leaf_max particles of the denser
                            species (never narrower than max(r_c, 2 h_max)) */
-    int32_t grid_mult;  /* persistent grid = grid_mult x CU count; 0 = one
-                           workgroup per leaf (default 0)                    */
+    int32_t grid_mult;  /* persistent grid = grid_mult x CU count
+                           workgroups (four times that for the 64-thread
+                           split form) popping items from a cost-ordered
+                           atomic queue; 0 = one workgroup per leaf or
+                           sub-leaf (default 0)                             */
     int32_t xcd_remap;  /* 1: with one workgroup per leaf or sub-leaf, give
                            each of the 8 XCDs a contiguous range of them
                            (default 1)                                       */
@@ -112,12 +115,19 @@ typedef struct {
                            1: each 16-lane group sweeps only the candidates
                            near its sub-leaf; 2: one wavefront per sub-leaf,
                            culled against the sub-leaf box, four lanes per
-                           particle (default); 0: whole-leaf sweep          */
+                           particle (default); 3: four wavefronts per leaf
+                           staging the leaf's candidates once in shared LDS,
+                           each then culling them against its sub-leaf box
+                           and sweeping as in 2; 0: whole-leaf sweep        */
     int32_t tree_lds;   /* 1: after one sort by bin, sort every bin along the
                            three axes and run its k-d levels in LDS (bins of
                            up to 4096 particles; larger bins fall back to
                            the per-axis global sorts); 0: always the global
                            sorts.  Both give the same tree (default 1)      */
+    int32_t tile;       /* j-tile width of the split form (sub_sweep 2): the
+                           LDS candidate buffer holds tile x 64 records
+                           (capped per pass at 64 KiB); 0: the pass's own
+                           width (default); 1, 2, 4 or 8                    */
 } crk_tuning;
 
 /* ------------------------------------------------------------------------ */

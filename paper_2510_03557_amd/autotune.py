@@ -1,10 +1,21 @@
 """Launch-shape tuner of the short-range step.
 
-Times the whole captured step for a small grid of (leaf_max, sweep form,
-launch shape) choices on the workload itself and keeps the fastest.  Every choice gives
-the same results up to floating-point rounding order (tested), so the tuner
-can only change speed.  Results are cached per (workload signature, GPU
-architecture) in ~/.cache/crk_mi355x/tuning.json.
+Times the whole captured step on the workload itself and keeps the fastest
+shape.  The search runs one dimension at a time from a starting shape
+(coordinate descent), each dimension's best value kept for the next:
+
+* leaf_max (k-d leaf size bound): 32, 48, 64;
+* sub_sweep (wavefronts per leaf): 2 = one wavefront per sub-leaf, each
+  staging its own candidates; 3 = four wavefronts per leaf sharing one
+  staging of the leaf's candidates;
+* tile (j-tile width of the split form): the candidate buffer of 64 x
+  {pass default, 2, 8} records;
+* grid_mult (persistent cost-ordered queue): 0 = one workgroup per item,
+  or 32 x the CU count workgroups popping items.
+
+Every shape gives the same results up to floating-point rounding order
+(tested), so the tuner can only change speed.  Results are cached per
+(workload signature, GPU architecture) in ~/.cache/crk_mi355x/tuning.json.
 """
 from __future__ import annotations
 
@@ -13,11 +24,9 @@ import json
 import os
 import time
 
-CANDIDATES = ([dict(leaf_max=L, sub_sweep=s) for L in (32, 48, 64)
-               for s in (0, 2)]
-              + [dict(leaf_max=64, sub_sweep=2, xcd_remap=0),
-                 dict(leaf_max=128, sub_sweep=0),
-                 dict(leaf_max=64, sub_sweep=0, grid_mult=16)])
+START = dict(leaf_max=64, sub_sweep=2, tile=0, grid_mult=0, xcd_remap=1)
+DIMENSIONS = (("leaf_max", (32, 48, 64)), ("sub_sweep", (2, 3)),
+              ("tile", (0, 2, 8)), ("grid_mult", (0, 32)))
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "crk_mi355x",
                      "tuning.json")
 
@@ -58,16 +67,34 @@ def _store_cache(d: dict):
 
 
 def _name(c) -> str:
-    return (f"L{c['leaf_max']}_g{c.get('grid_mult', 0)}_x{c.get('xcd_remap', 0)}"
-            f"_s{c.get('sub_sweep', 2)}")
+    return (f"L{c['leaf_max']}_s{c.get('sub_sweep', 2)}_t{c.get('tile', 0)}"
+            f"_g{c.get('grid_mult', 0)}_x{c.get('xcd_remap', 1)}")
+
+
+def _time(step, cand, reps):
+    """Milliseconds per replay of the captured step at one shape."""
+    import torch
+    step.ctx.set_tuning(**cand)
+    step.capture(integrate=False)
+    step.replay()
+    step.ctx.stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step.replay()
+    step.ctx.stream.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    step.sync()
+    return ms
 
 
 def tune(step, candidates=None, reps: int = 5, use_cache: bool = True,
          log=None) -> dict:
     """Picks the fastest tuning for an existing ShortRangeStep (which is
-    left set to it, with no graph captured).  Returns
-    {"tuning": {...}, "ms": {...}, "cached": bool}."""
-    import torch
+    left set to it, eager, with no graph captured).  With ``candidates``
+    (a list of tuning dicts) those are timed; otherwise the coordinate
+    search over DIMENSIONS from START.  Returns
+    {"tuning": {...}, "ms": {name: ms}, "cached": bool}."""
     key = signature(step.wl, step.ctx.precision) + "@" + _arch()
     cache = _load_cache() if use_cache else {}
     if key in cache:
@@ -77,24 +104,28 @@ def tune(step, candidates=None, reps: int = 5, use_cache: bool = True,
         step.ctx.set_tuning(**best)
         return {"tuning": best, "ms": cache[key]["ms"], "cached": True}
     results = {}
-    for cand in candidates or CANDIDATES:
-        step.ctx.set_tuning(**cand)
-        step.capture(integrate=False)
-        step.replay()
-        step.ctx.stream.synchronize()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            step.replay()
-        step.ctx.stream.synchronize()
-        ms = (time.perf_counter() - t0) / reps * 1e3
-        step.sync()
+
+    def measure(cand):
         name = _name(cand)
-        results[name] = ms
-        if log:
-            log(f"[tune] {name}: {ms:.3f} ms")
-    best_name = min(results, key=results.get)
-    best = next(c for c in (candidates or CANDIDATES) if _name(c) == best_name)
+        if name not in results:
+            results[name] = _time(step, cand, reps)
+            if log:
+                log(f"[tune] {name}: {results[name]:.3f} ms")
+        return results[name]
+
+    if candidates:
+        for cand in candidates:
+            measure(cand)
+        best_name = min(results, key=results.get)
+        best = next(c for c in candidates if _name(c) == best_name)
+    else:
+        best = dict(START)
+        for dim, values in DIMENSIONS:
+            timed = []
+            for v in values:
+                cand = dict(best, **{dim: v})
+                timed.append((measure(cand), v))
+            best[dim] = min(timed)[1]
     # the last candidate's graph holds that candidate's launch shape: drop
     # it, so that the step is left eager at the chosen tuning
     step.drop_graph()

@@ -64,7 +64,7 @@ class crk_tuning(ctypes.Structure):
     _fields_ = [("leaf_max", ctypes.c_int32), ("cm_factor", ctypes.c_double),
                 ("grid_mult", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("walk_mask", ctypes.c_int32), ("sub_sweep", ctypes.c_int32),
-                ("tree_lds", ctypes.c_int32)]
+                ("tree_lds", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
 class crk_tree_info(ctypes.Structure):
@@ -251,11 +251,11 @@ class Context:
             pass
 
     def set_tuning(self, leaf_max=64, cm_factor=0.0, grid_mult=0, xcd_remap=1,
-                   walk_mask=0, sub_sweep=2, tree_lds=1):
+                   walk_mask=0, sub_sweep=2, tree_lds=1, tile=0):
         check(self.lib.crk_set_tuning(self.handle, ctypes.byref(
             crk_tuning(int(leaf_max), float(cm_factor), int(grid_mult),
                        int(xcd_remap), int(walk_mask), int(sub_sweep),
-                       int(tree_lds)))))
+                       int(tree_lds), int(tile)))))
 
     def get_tuning(self) -> dict:
         t = crk_tuning()

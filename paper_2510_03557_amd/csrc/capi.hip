@@ -236,6 +236,7 @@ int crk_ctx_create(crk_ctx **out, int precision, void *stream,
     c->tuning.walk_mask = 0;
     c->tuning.sub_sweep = 2;
     c->tuning.tree_lds = 1;
+    c->tuning.tile = 0;
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount,
@@ -294,10 +295,13 @@ int crk_set_tuning(crk_ctx *ctx, const crk_tuning *t) {
         return set_error(CRK_EINVAL, "xcd_remap must be 0 or 1");
     if (t->walk_mask < 0 || t->walk_mask > 31)
         return set_error(CRK_EINVAL, "walk_mask must be in [0, 31]");
-    if (t->sub_sweep < 0 || t->sub_sweep > 2)
-        return set_error(CRK_EINVAL, "sub_sweep must be 0, 1 or 2");
+    if (t->sub_sweep < 0 || t->sub_sweep > 3)
+        return set_error(CRK_EINVAL, "sub_sweep must be 0, 1, 2 or 3");
     if (t->tree_lds != 0 && t->tree_lds != 1)
         return set_error(CRK_EINVAL, "tree_lds must be 0 or 1");
+    if (!(t->tile == 0 || t->tile == 1 || t->tile == 2 || t->tile == 4 ||
+          t->tile == 8))
+        return set_error(CRK_EINVAL, "tile must be 0, 1, 2, 4 or 8");
     if (ctx->capturing) return set_error(CRK_ESTATE, "tuning change during capture");
     ctx->tuning = *t;
     return CRK_OK;

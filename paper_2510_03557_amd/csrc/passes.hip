@@ -21,6 +21,7 @@
 // plain double throughout.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "crk_internal.h"
 
@@ -123,6 +124,8 @@ template <typename T> struct TreeView {
     const T *lo, *hi, *hmax;  // leaf boxes (3 planes of lcap) and h_max
     int64_t lcap;
     int xcd_remap;            // map blocks to contiguous leaf ranges per XCD
+    int tile;                 // split forms: candidate buffer of tile x 64
+                              // (0: the pass's own CAPF)
     int walk_mask;            // passes (bit P::ID) that use the hit walk
     int groups;               // sub-leaf sweep: 1 lane groups, 2 split
     const int32_t *nsub, *sst, *scnt;  // sub-leaves (slots 4*leaf + k)
@@ -155,13 +158,48 @@ __device__ inline double uni(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// lane k's value (k wave-uniform, in a scalar register): one readlane, no
+// LDS round trip as a shuffle would take
+__device__ inline int lane_val(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ inline float lane_val(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ inline double lane_val(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // sweep forms of the pair kernels
-enum { SWEEP_BROADCAST = 0, SWEEP_WALK = 1, SWEEP_GROUPED = 2, SWEEP_SPLIT = 3 };
+enum { SWEEP_BROADCAST = 0, SWEEP_WALK = 1, SWEEP_GROUPED = 2, SWEEP_SPLIT = 3,
+       SWEEP_LEAF = 4 };
 
 __device__ inline void decode_shift(uint32_t code, int &sx, int &sy, int &sz) {
     sx = (int)(code / 9u) - 1;
     sy = (int)((code / 3u) % 3u) - 1;
     sz = (int)(code % 3u) - 1;
+}
+
+// Position and the P::NP prefetched fields of slot j: one 16-byte load from
+// the pass's packed (x, y, z, field) records where it has them (P::PK),
+// else the position planes and P::fetch_j.
+template <typename T, typename P>
+__device__ __forceinline__ void load_j(T &x, T &y, T &z, T *f,
+                                       const typename P::Args &pa,
+                                       const TreeView<T> &tv, int j) {
+    if constexpr (P::PK) {
+        const float4 r = P::packed(pa)[j];
+        x = r.x;
+        y = r.y;
+        z = r.z;
+        f[0] = r.w;
+    } else {
+        x = tv.px[j];
+        y = tv.py[j];
+        z = tv.pz[j];
+        P::fetch_j(f, pa, tv, j);
+    }
 }
 
 // Walks the list entries [e0, e1) of one leaf.  Each wavefront loads the
@@ -197,35 +235,25 @@ __device__ __forceinline__ void walk_list(const TreeView<T> &tv,
                 }
             }
         }
-        // entry values are wave-uniform: keep them in scalar registers
-        int js = uni(__shfl(bjs, 0)), jc = uni(__shfl(bjc, 0));
+        // entry values are wave-uniform: read into scalar registers
+        int js = lane_val(bjs, 0), jc = lane_val(bjc, 0);
         T nx = T(0), ny = T(0), nz = T(0);
         T nf[P::NP];
 #pragma unroll
         for (int u = 0; u < P::NP; ++u) nf[u] = T(0);
-        if (t < jc) {
-            nx = tv.px[js + t];
-            ny = tv.py[js + t];
-            nz = tv.pz[js + t];
-            P::fetch_j(nf, pa, tv, js + t);
-        }
+        if (t < jc) load_j<T, P>(nx, ny, nz, nf, pa, tv, js + t);
         for (int k = 0; k < nb; ++k) {
             const int cjs = js, cjc = jc;
             const T cx = nx, cy = ny, cz = nz;
             T cf[P::NP];
 #pragma unroll
             for (int u = 0; u < P::NP; ++u) cf[u] = nf[u];
-            const int code = uni(__shfl(bcode, k));
-            const T hJ = uni(__shfl(bh, k));
+            const int code = lane_val(bcode, k);
+            const T hJ = lane_val(bh, k);
             if (k + 1 < nb) {
-                js = uni(__shfl(bjs, k + 1));
-                jc = uni(__shfl(bjc, k + 1));
-                if (t < jc) {
-                    nx = tv.px[js + t];
-                    ny = tv.py[js + t];
-                    nz = tv.pz[js + t];
-                    P::fetch_j(nf, pa, tv, js + t);
-                }
+                js = lane_val(bjs, k + 1);
+                jc = lane_val(bjc, k + 1);
+                if (t < jc) load_j<T, P>(nx, ny, nz, nf, pa, tv, js + t);
             }
             if (cjc == 0) continue;
             visit(cjs, cjc, (uint32_t)code, hJ, cx, cy, cz, cf);
@@ -480,6 +508,17 @@ __global__ __launch_bounds__(BLOCK) void pair_kernel(const TreeView<T> tv,
     process_leaf<T, P, BLOCK, MODE>(tv, pa, I, sj, sjid, wcnt, smask, glist);
 }
 
+// Candidate buffer of the split forms: tile x 64 records (the pass's CAPF
+// when no tile is set), capped at 64 KiB of LDS with the record ids.
+template <typename T, typename P> __host__ __device__ constexpr int split_cap_of(int tile) {
+    const int want = (tile > 0 ? tile : P::CAPF) * 64;
+    const int most = 65536 / (P::NJ * (int)sizeof(T) + 4) / 64 * 64;
+    return want < most ? want : most;
+}
+template <typename T, typename P> __device__ inline int split_cap(const TreeView<T> &tv) {
+    return split_cap_of<T, P>(tv.tile);
+}
+
 // Split forms: one wavefront per sub-leaf (<= 16 particles).  The wave
 // walks the parent leaf's list, skips j-leaves out of range of the
 // sub-leaf's box, culls every j particle against that box (smaller than the
@@ -491,7 +530,7 @@ __device__ __forceinline__ void stage_subleaf(const TreeView<T> &tv,
                                               const typename P::Args &pa,
                                               const int I, const int64_t slot,
                                               T *sj, int *sjid, Sweep &&sweep) {
-    constexpr int CAP = P::CAPF * 64;
+    const int CAP = split_cap<T, P>(tv);
     const int lane = threadIdx.x;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int st = tv.leaf_start[I];
@@ -521,43 +560,74 @@ __device__ __forceinline__ void stage_subleaf(const TreeView<T> &tv,
         const T R = P::range(pa, tv, box, hmS, hJ) * T(1.0001) + T(1e-6);
         return gx * gx + gy * gy + gz * gz < R * R;
     };
+    // with P::FARNEAR, candidates at least P::far_range from the box go to
+    // the front of the buffer ([0, nbuf)), the others to its back
+    // ([CAP - nnear, CAP)), and sweep(nbuf, nnear) takes both ranges
+    int nnear = 0;
+    T Rf2 = T(0);
+    if constexpr (P::FARNEAR) {
+        const T Rf = P::far_range(tv, box);
+        Rf2 = Rf * Rf;
+    }
+    // the pair range, when it does not depend on the j-leaf
+    const T Rc = P::RANGE_HJ ? T(0) : P::range(pa, tv, box, hmS, T(0)) + T(1e-6);
     walk_list<T, P, 64>(tv, pa, e0, e1, lane, keep_near,
                         [&](int js, int jc, uint32_t code, T hJ, T x, T y, T z,
                             const T *f) {
         int sx, sy, sz;
         decode_shift(code, sx, sy, sz);
-        if (nbuf + jc > CAP) {
-            sweep(nbuf);
+        if (nbuf + nnear + jc > CAP) {
+            if constexpr (P::FARNEAR) sweep(nbuf, nnear);
+            else sweep(nbuf);
             nbuf = 0;
+            nnear = 0;
         }
         // cull in raw coordinates against the sub-leaf box moved to this
         // image (its shifted bounds round by at most a few 1e-7: the range
         // gets an absolute 1e-6 on top of its relative widening)
-        const T R = P::range(pa, tv, box, hmS, hJ) + T(1e-6);
+        const T R = P::RANGE_HJ ? P::range(pa, tv, box, hmS, hJ) + T(1e-6) : Rc;
         const T R2 = R * R;
         const T clx = slx - T(sx), chx = shx - T(sx);
         const T cly = sly - T(sy), chy = shy - T(sy);
         const T clz = slz - T(sz), chz = shz - T(sz);
         bool keep = false;
+        T d2 = T(0);
         const int j = js + lane;
         if (lane < jc) {
             const T dx = fmax(fmax(clx - x, x - chx), T(0));
             const T dy = fmax(fmax(cly - y, y - chy), T(0));
             const T dz = fmax(fmax(clz - z, z - chz), T(0));
-            keep = dx * dx + dy * dy + dz * dz < R2;
+            d2 = dx * dx + dy * dy + dz * dz;
+            keep = d2 < R2;
         }
-        const uint64_t m = __ballot(keep);
-        if (keep) {
-            // recentred (exact for every pair in range)
-            const T fx = (x - rx) + T(sx), fy = (y - ry) + T(sy),
-                    fz = (z - rz) + T(sz);
-            const int pos = nbuf + __popcll(m & lt_mask);
-            P::store_j(&sj[pos * P::NJ], f, pa, tv, j, fx, fy, fz);
-            sjid[pos] = j;
+        if constexpr (P::FARNEAR) {
+            const bool far = keep && d2 >= Rf2;
+            const uint64_t mf = __ballot(far), mn = __ballot(keep && !far);
+            if (keep) {
+                const T fx = (x - rx) + T(sx), fy = (y - ry) + T(sy),
+                        fz = (z - rz) + T(sz);
+                const int pos = far ? nbuf + __popcll(mf & lt_mask)
+                                    : CAP - 1 - (nnear + __popcll(mn & lt_mask));
+                P::store_j(&sj[pos * P::NJ], f, pa, tv, j, fx, fy, fz);
+                sjid[pos] = j;
+            }
+            nbuf += __popcll(mf);
+            nnear += __popcll(mn);
+        } else {
+            const uint64_t m = __ballot(keep);
+            if (keep) {
+                // recentred (exact for every pair in range)
+                const T fx = (x - rx) + T(sx), fy = (y - ry) + T(sy),
+                        fz = (z - rz) + T(sz);
+                const int pos = nbuf + __popcll(m & lt_mask);
+                P::store_j(&sj[pos * P::NJ], f, pa, tv, j, fx, fy, fz);
+                sjid[pos] = j;
+            }
+            nbuf += __popcll(m);
         }
-        nbuf += __popcll(m);
     });
-    sweep(nbuf);
+    if constexpr (P::FARNEAR) sweep(nbuf, nnear);
+    else sweep(nbuf);
 }
 
 // Quad form: four lanes per particle.  Lane q of a particle's quad takes
@@ -637,17 +707,49 @@ __device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
         acc.fold(tile);
         __syncthreads();
     };
-    stage_subleaf<T, P>(tv, pa, I, slot, sj, sjid, sweep);
+    if constexpr (P::FARNEAR) {
+        // far candidates ([0, nf)) with the far pair body, near ones
+        // ([CAP - nn, CAP)) with the full one; the same quad sweep on each
+        const int CAP = split_cap<T, P>(tv);
+        auto sweep2 = [&](int nf, int nn) {
+            __syncthreads();
+            int k0 = 0;
+            for (; k0 + 16 <= nf; k0 += 16) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    P::pair_far(tile, is, &sj[(k0 + 4 * u + q) * P::NJ]);
+            }
+            for (int k = k0 + q; k < nf; k += 4) P::pair_far(tile, is, &sj[k * P::NJ]);
+            const int b0 = CAP - nn;
+            k0 = b0;
+            for (; k0 + 16 <= CAP; k0 += 16) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = k0 + 4 * u + q;
+                    P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+                }
+            }
+            for (int k = k0 + q; k < CAP; k += 4)
+                P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+            acc.fold(tile);
+            __syncthreads();
+        };
+        stage_subleaf<T, P>(tv, pa, I, slot, sj, sjid, sweep2);
+    } else {
+        stage_subleaf<T, P>(tv, pa, I, slot, sj, sjid, sweep);
+    }
     acc.quad_reduce();
     if (act && q == 0 && slot_active(tv, i)) P::finish(acc, is, pa, tv, i);
 }
 
 // One wavefront per sub-leaf: block b -> leaf b / 4, sub-leaf b % 4.
+// (the candidate buffer lives in dynamic LDS, sized at launch for the tile)
 template <typename T, typename P>
 __global__ __launch_bounds__(64) void pair_kernel_split(const TreeView<T> tv,
                                                         const typename P::Args pa) {
-    __shared__ __attribute__((aligned(16))) T sj[P::CAPF * 64 * P::NJ];
-    __shared__ int sjid[P::CAPF * 64];
+    extern __shared__ __attribute__((aligned(16))) unsigned char split_lds[];
+    T *sj = reinterpret_cast<T *>(split_lds);
+    int *sjid = reinterpret_cast<int *>(sj + split_cap<T, P>(tv) * P::NJ);
     const int n_items = *tv.n_items;
     if ((int)blockIdx.x >= 4 * n_items) return;
     const int b = tv.xcd_remap ? xcd_block(blockIdx.x, 4 * n_items)
@@ -663,6 +765,286 @@ __global__ __launch_bounds__(64) void pair_kernel_split(const TreeView<T> tv,
         if (__ballot(a) == 0) return;
     }
     process_subleaf<T, P>(tv, pa, I, g, sj, sjid);
+}
+
+// Persistent split form: each 64-thread workgroup pops sub-leaf slots from
+// an atomic counter (reset to 0 before the launch) until the queue is
+// exhausted; slot q is sub-leaf q % 4 of the leaf of rank q / 4 in
+// decreasing cost, so the longest items start first and the sub-leaves of
+// one leaf run side by side.  Every workgroup leaves the loop once the
+// counter passes the slot count.
+template <typename T, typename P>
+__global__ __launch_bounds__(64) void pair_kernel_split_queue(
+    const TreeView<T> tv, const typename P::Args pa,
+    const int32_t *__restrict__ order, int *__restrict__ head) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char split_lds[];
+    T *sj = reinterpret_cast<T *>(split_lds);
+    int *sjid = reinterpret_cast<int *>(sj + split_cap<T, P>(tv) * P::NJ);
+    const int n_slots = 4 * *tv.n_items;
+    while (true) {
+        int q = 0;
+        if (threadIdx.x == 0) q = atomicAdd(head, 1);
+        q = uni(__shfl(q, 0));
+        if (q >= n_slots) break;
+        const int I = order[q >> 2], g = q & 3;
+        if (g >= tv.nsub[I]) continue;
+        process_subleaf<T, P>(tv, pa, I, g, sj, sjid);
+    }
+}
+
+// Leaf form: one workgroup of four wavefronts per leaf, wavefront w owning
+// sub-leaf w.  The four wavefronts walk the leaf's list together, four
+// entries per round (entry e0 + 4 r + w by wavefront w), cull each j
+// particle against the leaf box widened by the pair range and stage the
+// survivors once, for all four sub-leaves, in a shared LDS buffer (in
+// round order, wavefront by wavefront).  A full buffer is swept: every
+// wavefront culls the staged candidates against its own sub-leaf box into an
+// index list (far and near lists with P::FARNEAR) and sweeps that list with
+// four lanes per particle as the split form does.  Staging once per leaf
+// reads each listed j-leaf from memory once per leaf instead of once per
+// sub-leaf.  Every wavefront reaches every barrier: the rounds and sweeps
+// are uniform over the workgroup.
+template <typename P> constexpr int leaf_cap() {
+    return (P::CAPF * 128 > 256) ? P::CAPF * 128 : 256;
+}
+
+template <typename T, typename P>
+__device__ __forceinline__ void process_leaf4(const TreeView<T> &tv,
+                                              const typename P::Args &pa,
+                                              const int I, T *sj, int *sjid,
+                                              unsigned short (*slist)[leaf_cap<P>()],
+                                              int *wcnt) {
+    constexpr int CAPL = leaf_cap<P>();
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int ns = tv.nsub[I];
+    const int64_t slot = 4 * (int64_t)I + (w < ns ? w : 0);
+    const int scnt = w < ns ? min(tv.scnt[slot], 16) : 0;
+    const int ii = lane >> 2, q = lane & 3;
+    const bool act = ii < scnt;
+    const int i = act ? tv.sst[slot] + ii : tv.sst[slot];
+    // a wavefront sweeps when its sub-leaf exists and, with an active
+    // subset, holds an active particle
+    bool sweeper = w < ns;
+    if (sweeper && tv.act) sweeper = __ballot(act && tv.act[i] != 0) != 0;
+    const int st = tv.leaf_start[I];
+    const T rx = tv.px[st], ry = tv.py[st], rz = tv.pz[st];
+    const int box = tv.leaf_box[I];
+    const T hmI = tv.hmax[I];
+    const int64_t lc = tv.lcap, sl = 4 * tv.lcap;
+    const T llx = tv.lo[I], lly = tv.lo[lc + I], llz = tv.lo[2 * lc + I];
+    const T lhx = tv.hi[I], lhy = tv.hi[lc + I], lhz = tv.hi[2 * lc + I];
+    // the sub-leaf box relative to the reference particle (the frame of the
+    // staged candidates; a few ulp of rounding, covered by the ranges'
+    // relative widening and an absolute 1e-6)
+    const T gl0 = tv.slo[slot] - rx, gl1 = tv.slo[sl + slot] - ry,
+            gl2 = tv.slo[2 * sl + slot] - rz;
+    const T gh0 = tv.shi[slot] - rx, gh1 = tv.shi[sl + slot] - ry,
+            gh2 = tv.shi[2 * sl + slot] - rz;
+    const T hg = tv.shm[slot];
+    typename P::I is;
+    P::load_i(is, pa, tv, i, tv.px[i] - rx, tv.py[i] - ry, tv.pz[i] - rz, box);
+    typename P::Tile tile;
+    tile.zero();
+    typename P::Acc acc;
+    acc.zero();
+    T Rf2 = T(0);
+    if constexpr (P::FARNEAR) {
+        const T Rf = P::far_range(tv, box);
+        Rf2 = Rf * Rf;
+    }
+    unsigned short *my = slist[w];
+    auto sweep = [&](int n) {
+        __syncthreads();  // the staged candidates are complete
+        int nf = 0, nn = 0;
+        if (sweeper) {
+            for (int base = 0; base < n; base += 64) {
+                const int k = base + lane;
+                bool keep = false, far = false;
+                if (k < n) {
+                    const T *jd = &sj[k * P::NJ];
+                    const T R = P::sub_range(pa, tv, box, hg, jd) + T(1e-6);
+                    const T dx = fmax(fmax(gl0 - jd[0], jd[0] - gh0), T(0));
+                    const T dy = fmax(fmax(gl1 - jd[1], jd[1] - gh1), T(0));
+                    const T dz = fmax(fmax(gl2 - jd[2], jd[2] - gh2), T(0));
+                    const T d2 = dx * dx + dy * dy + dz * dz;
+                    keep = d2 < R * R;
+                    if constexpr (P::FARNEAR) far = keep && d2 >= Rf2;
+                }
+                if constexpr (P::FARNEAR) {
+                    const uint64_t mf = __ballot(far), mn = __ballot(keep && !far);
+                    if (far) my[nf + __popcll(mf & lt_mask)] = (unsigned short)k;
+                    else if (keep)
+                        my[CAPL - 1 - (nn + __popcll(mn & lt_mask))] = (unsigned short)k;
+                    nf += __popcll(mf);
+                    nn += __popcll(mn);
+                } else {
+                    const uint64_t m = __ballot(keep);
+                    if (keep) my[nf + __popcll(m & lt_mask)] = (unsigned short)k;
+                    nf += __popcll(m);
+                }
+            }
+        }
+        __syncthreads();  // every list is complete
+        if (sweeper) {
+            if constexpr (P::FARNEAR) {
+                int u0 = 0;
+                for (; u0 + 16 <= nf; u0 += 16) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        P::pair_far(tile, is, &sj[my[u0 + 4 * u + q] * P::NJ]);
+                }
+                for (int u = u0 + q; u < nf; u += 4)
+                    P::pair_far(tile, is, &sj[my[u] * P::NJ]);
+                u0 = CAPL - nn;
+                for (; u0 + 16 <= CAPL; u0 += 16) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int k = my[u0 + 4 * u + q];
+                        P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+                    }
+                }
+                for (int u = u0 + q; u < CAPL; u += 4) {
+                    const int k = my[u];
+                    P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+                }
+            } else if constexpr (P::MASKED) {
+                // test, then pairs (the split form's two phases, over the list)
+                const int nt = (nf + 3) >> 2;
+                for (int t0 = 0; t0 < nt; t0 += 64) {
+                    const int tn = min(nt - t0, 64);
+                    uint64_t m = 0;
+                    for (int tt = 0; tt < tn; ++tt) {
+                        const int u = 4 * (t0 + tt) + q;
+                        const int k = my[u < nf ? u : 0];
+                        const bool c = P::test(is, &sj[k * P::NJ], sjid[k] == i);
+                        m |= uint64_t((u < nf) & c) << tt;
+                    }
+                    while (m) {
+                        const int b = __builtin_ctzll(m);
+                        m &= m - 1;
+                        const int k = my[4 * (t0 + b) + q];
+                        P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+                    }
+                }
+            } else {
+                int u0 = 0;
+                for (; u0 + 16 <= nf; u0 += 16) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int k = my[u0 + 4 * u + q];
+                        P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+                    }
+                }
+                for (int u = u0 + q; u < nf; u += 4) {
+                    const int k = my[u];
+                    P::pair(tile, is, &sj[k * P::NJ], sjid[k] == i);
+                }
+            }
+        }
+        acc.fold(tile);
+        __syncthreads();  // the buffer may be refilled
+    };
+    // after a capacity error (latched by the list builder) offsets may run
+    // past the allocation: clamp, and skip entries that were never written
+    const int64_t e0 = min(tv.list_off[I], tv.list_cap);
+    const int64_t e1 = min(tv.list_off[I + 1], tv.list_cap);
+    const int nl = *tv.n_leaves;
+    int nbuf = 0;
+    for (int64_t eb = e0; eb < e1; eb += 4) {
+        const int64_t e = eb + w;
+        int js = 0, jc = 0, sx = 0, sy = 0, sz = 0;
+        T hJ = T(0);
+        if (e < e1) {
+            const uint32_t ent = tv.list[e];
+            const int J = (int)(ent & LIST_LEAF_MASK);
+            if (J < nl) {
+                hJ = tv.hmax[J];
+                decode_shift(ent >> LIST_LEAF_BITS, sx, sy, sz);
+                js = tv.leaf_start[J];
+                jc = min(tv.leaf_count[J], 64);
+            }
+        }
+        js = uni(js);
+        jc = uni(jc);
+        bool keep = false;
+        T x = T(0), y = T(0), z = T(0);
+        T f[P::NP];
+#pragma unroll
+        for (int u = 0; u < P::NP; ++u) f[u] = T(0);
+        if (lane < jc) {
+            x = tv.px[js + lane];
+            y = tv.py[js + lane];
+            z = tv.pz[js + lane];
+            P::fetch_j(f, pa, tv, js + lane);
+            // cull in raw coordinates against the leaf box moved to this
+            // image (absolute 1e-6 for the rounding of its shifted bounds)
+            const T R = P::range(pa, tv, box, hmI, hJ) + T(1e-6);
+            const T dx = fmax(fmax((llx - T(sx)) - x, x - (lhx - T(sx))), T(0));
+            const T dy = fmax(fmax((lly - T(sy)) - y, y - (lhy - T(sy))), T(0));
+            const T dz = fmax(fmax((llz - T(sz)) - z, z - (lhz - T(sz))), T(0));
+            keep = dx * dx + dy * dy + dz * dz < R * R;
+        }
+        const uint64_t m = __ballot(keep);
+        if (lane == 0) wcnt[w] = __popcll(m);
+        __syncthreads();
+        const int c0 = wcnt[0], c1 = wcnt[1], c2 = wcnt[2], c3 = wcnt[3];
+        const int tot = c0 + c1 + c2 + c3;
+        if (nbuf + tot > CAPL) {
+            sweep(nbuf);
+            nbuf = 0;
+        }
+        if (keep) {
+            const int pos = nbuf + (w > 0 ? c0 : 0) + (w > 1 ? c1 : 0) +
+                            (w > 2 ? c2 : 0) + __popcll(m & lt_mask);
+            const T fx = (x - rx) + T(sx), fy = (y - ry) + T(sy),
+                    fz = (z - rz) + T(sz);
+            P::store_j(&sj[pos * P::NJ], f, pa, tv, js + lane, fx, fy, fz);
+            sjid[pos] = js + lane;
+        }
+        nbuf += tot;
+        __syncthreads();  // wcnt is rewritten by the next round
+    }
+    sweep(nbuf);
+    acc.quad_reduce();
+    if (sweeper && act && q == 0 && slot_active(tv, i)) P::finish(acc, is, pa, tv, i);
+}
+
+template <typename T, typename P>
+__global__ __launch_bounds__(256) void pair_kernel_leaf(const TreeView<T> tv,
+                                                       const typename P::Args pa) {
+    constexpr int CAPL = leaf_cap<P>();
+    __shared__ __attribute__((aligned(16))) T sj[CAPL * P::NJ];
+    __shared__ int sjid[CAPL];
+    __shared__ unsigned short slist[4][CAPL];
+    __shared__ int wcnt[4];
+    const int n_items = *tv.n_items;
+    if ((int)blockIdx.x >= n_items) return;
+    const int bi = tv.xcd_remap ? xcd_block(blockIdx.x, n_items) : (int)blockIdx.x;
+    process_leaf4<T, P>(tv, pa, item_leaf(tv, bi), sj, sjid, slist, wcnt);
+}
+
+// Persistent leaf form: each four-wavefront workgroup pops leaves in
+// decreasing cost from an atomic counter until the queue is exhausted.
+template <typename T, typename P>
+__global__ __launch_bounds__(256) void pair_kernel_leaf_queue(
+    const TreeView<T> tv, const typename P::Args pa,
+    const int32_t *__restrict__ order, int *__restrict__ head) {
+    constexpr int CAPL = leaf_cap<P>();
+    __shared__ __attribute__((aligned(16))) T sj[CAPL * P::NJ];
+    __shared__ int sjid[CAPL];
+    __shared__ unsigned short slist[4][CAPL];
+    __shared__ int wcnt[4];
+    __shared__ int slot;
+    const int n_items = *tv.n_items;
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) slot = atomicAdd(head, 1);
+        __syncthreads();
+        const int q = slot;
+        if (q >= n_items) break;
+        process_leaf4<T, P>(tv, pa, order[q], sj, sjid, slist, wcnt);
+    }
 }
 
 // Persistent grid: each workgroup pops queue slots from an atomic counter
@@ -711,6 +1093,9 @@ template <typename T> struct DensityPass {
     static constexpr int ID = 0;    // bit in the walk mask
     // split sweep: one phase (the pair body is about as cheap as its test)
     static constexpr bool MASKED = false;
+    static constexpr bool FARNEAR = false;
+    static constexpr bool PK = false;
+    static constexpr bool RANGE_HJ = false;
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
         return widen<T>(2.0 * (double)hI);
     }
@@ -805,6 +1190,9 @@ template <typename T> struct CoeffPass {
     static constexpr int CAPF = 4;
     static constexpr int ID = 1;
     static constexpr bool MASKED = true;  // split sweep: test, then pairs
+    static constexpr bool FARNEAR = false;
+    static constexpr bool PK = false;
+    static constexpr bool RANGE_HJ = false;
     static constexpr int NS = 33;
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
         return widen<T>(2.0 * (double)hI);
@@ -1013,7 +1401,9 @@ template <typename T> struct CoeffPass {
 // --------------------------------------------------------------------------
 // hydro forces
 // --------------------------------------------------------------------------
-// Per-particle fields, precomputed by hydro_gather_kernel (tree order):
+// Per-particle fields, precomputed by hydro_gather_kernel (tree order), one
+// contiguous record of hydro_stride(w) floats per particle (w fields, the
+// stride a multiple of four so that records load as 16-byte units):
 //   0 vx 1 vy 2 vz 3 ih2=1/h^2 4 a=A N 5..7 da=dA N 8..10 B
 //   11..13 ab=A N B  14..22 adb=A N dB [g][x]  23 h  24 V  25 P  26 rho
 //   27 cs   (N = 1/(pi h^3))
@@ -1027,6 +1417,21 @@ template <typename T> struct CoeffPass {
 constexpr int HF = 28;
 constexpr int HF_RECON = HF + 6;
 constexpr int HF_MAX = HF_RECON + 3;
+__host__ __device__ constexpr int hydro_stride(int w) { return (w + 3) / 4 * 4; }
+
+// n fields (n % 4 == 0 for the vector form) of a record into dst
+template <typename T, int N>
+__device__ __forceinline__ void copy_fields(T *dst, const T *src) {
+    if constexpr (std::is_same<T, float>::value && N % 4 == 0) {
+        const float4 *s4 = reinterpret_cast<const float4 *>(src);
+        float4 *d4 = reinterpret_cast<float4 *>(dst);
+#pragma unroll
+        for (int k = 0; k < N / 4; ++k) d4[k] = s4[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) dst[k] = src[k];
+    }
+}
 
 // optional inputs of the hydro field gather
 template <typename T> struct GatherExtra {
@@ -1046,7 +1451,7 @@ template <typename T> struct GatherExtra {
 // energy update)
 template <typename T, bool RECON = false, bool WORK = false> struct HydroPass {
     struct Args {
-        const T *f;       // HFN planes of n_gas, tree order
+        const T *f;       // records of RS floats (HFN fields), tree order
         int64_t n_gas;
         T *ax, *ay, *az, *dudt;  // caller order
         const T *m;       // tree order
@@ -1062,12 +1467,16 @@ template <typename T, bool RECON = false, bool WORK = false> struct HydroPass {
     static constexpr int FO = 4;
     static constexpr int NJ = (((FO + HFN + 3) / 4) | 1) * 4;
     static_assert(NJ == (RECON ? 44 : 36), "hydro record layout");
+    static constexpr int RS = hydro_stride(HFN);  // record stride in memory
     static constexpr int CAPF = 1;
     static constexpr int ID = 2;
     // split sweep: one phase.  The in-range candidates of one buffer are
     // clustered in space, so the per-lane counts of a two-phase sweep are
     // uneven and its longest lane costs more than the plain sweep.
     static constexpr bool MASKED = false;
+    static constexpr bool FARNEAR = false;
+    static constexpr bool PK = false;
+    static constexpr bool RANGE_HJ = true;  // 2 max(h_i, h_j)
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T hJ) {
         return widen<T>(2.0 * (double)(hI > hJ ? hI : hJ));
     }
@@ -1101,8 +1510,7 @@ template <typename T, bool RECON = false, bool WORK = false> struct HydroPass {
         is.epsQ = a.epsQ;
         is.eta_c = a.eta_c;
         is.ieta_f = a.ieta_f;
-#pragma unroll
-        for (int k = 0; k < HFN; ++k) is.f[k] = a.f[k * a.n_gas + i];
+        copy_fields<T, HFN>(is.f, a.f + (int64_t)i * RS);
     }
     // the fields are many: loaded for the culling survivors only
     static constexpr int NP = 1;
@@ -1115,10 +1523,10 @@ template <typename T, bool RECON = false, bool WORK = false> struct HydroPass {
         d[1] = fy;
         d[2] = fz;
         d[3] = T(0);
+        // whole 16-byte units of the record (its padding included)
+        copy_fields<T, RS>(d + FO, a.f + (int64_t)j * RS);
 #pragma unroll
-        for (int k = 0; k < HFN; ++k) d[FO + k] = a.f[k * a.n_gas + j];
-#pragma unroll
-        for (int k = FO + HFN; k < NJ; ++k) d[k] = T(0);
+        for (int k = FO + RS; k < NJ; ++k) d[k] = T(0);
     }
     // gradient of the corrected kernel of particle with fields f at y (and
     // q = r / h of that particle)
@@ -1226,14 +1634,18 @@ template <typename T, bool RECON = false, bool WORK = false> struct HydroPass {
 // (planes 0..22 and 24 of the hydro gather); j = i adds zero.
 template <typename T> struct VGradPass {
     struct Args {
-        const T *f;   // hydro field planes of n_gas, tree order
+        const T *f;   // hydro field records (stride hydro_stride(HF)), tree order
         int64_t n_gas;
         T *dv;        // 9 planes [a][b] of n_gas, caller order
     };
+    static constexpr int RS = hydro_stride(HF);
     static constexpr int NJ = 8;  // fx fy fz V vx vy vz pad
     static constexpr int CAPF = 4;
     static constexpr int ID = 6;
     static constexpr bool MASKED = false;
+    static constexpr bool FARNEAR = false;
+    static constexpr bool PK = false;
+    static constexpr bool RANGE_HJ = false;
     static constexpr int NI = 23;  // i fields: v, 1/h^2, coefficients
     __device__ static T range(const Args &, const TreeView<T> &, int, T hI, T) {
         return widen<T>(2.0 * (double)hI);
@@ -1244,7 +1656,7 @@ template <typename T> struct VGradPass {
     }
     struct I {
         T ex, ey, ez;
-        T f[NI];
+        T f[24];  // NI used
     };
     struct Tile {
         T s[9];
@@ -1264,16 +1676,16 @@ template <typename T> struct VGradPass {
         is.ex = ex;
         is.ey = ey;
         is.ez = ez;
-#pragma unroll
-        for (int k = 0; k < NI; ++k) is.f[k] = a.f[k * a.n_gas + i];
+        copy_fields<T, 24>(is.f, a.f + (int64_t)i * RS);  // (the first NI used)
     }
     static constexpr int NP = 4;  // prefetched with the position: V, v
     __device__ static void fetch_j(T *f, const Args &a, const TreeView<T> &,
                                    int j) {
-        f[0] = a.f[24 * a.n_gas + j];
-        f[1] = a.f[0 * a.n_gas + j];
-        f[2] = a.f[1 * a.n_gas + j];
-        f[3] = a.f[2 * a.n_gas + j];
+        const T *r = a.f + (int64_t)j * RS;
+        f[0] = r[24];
+        f[1] = r[0];
+        f[2] = r[1];
+        f[3] = r[2];
     }
     __device__ static void store_j(T *d, const T *f, const Args &,
                                    const TreeView<T> &, int, T fx, T fy, T fz) {
@@ -1333,11 +1745,19 @@ template <typename T> struct GravityPass {
         const T *m;  // tree order, times G
         T *ax_g, *ay_g, *az_g, *ax_d, *ay_d, *az_d;  // caller order
         int64_t n_gas;
+        const float4 *pk;  // float: (x, y, z, G m) per slot, tree order
     };
     static constexpr int NJ = 4;  // fx fy fz Gm
     static constexpr int CAPF = 4;
     static constexpr int ID = 3;
     static constexpr bool MASKED = false;  // (as for the hydro forces)
+    // float: the split sweep stages candidates that are at least far_range
+    // from the sub-leaf box apart and sweeps them with pair_far
+    static constexpr bool FARNEAR = std::is_same<T, float>::value;
+    // float: position and G m of every slot packed in one 16-byte record
+    static constexpr bool PK = std::is_same<T, float>::value;
+    static constexpr bool RANGE_HJ = false;
+    __device__ static const float4 *packed(const Args &a) { return a.pk; }
     __device__ static T range(const Args &, const TreeView<T> &tv, int box, T, T) {
         return widen<T>(tv.rc[box]);
     }
@@ -1421,6 +1841,42 @@ template <typename T> struct GravityPass {
         tl.s[1] = fma(-w, dy, tl.s[1]);
         tl.s[2] = fma(-w, dz, tl.s[2]);
     }
+    // Candidates at least this far from the sub-leaf box are far from every
+    // particle of it: r >= r_c / 2 (the outer branch of the S2 split) and
+    // r >= 15 eps (so (eps / r)^2 <= 1/225).  Relative margin against the
+    // float32 branch decision, absolute margin for the rounding of the
+    // shifted box bounds.
+    __device__ static T far_range(const TreeView<T> &tv, int box) {
+        const double rc = tv.rc[box], eps = tv.eps[box];
+        return (T)(fmax(0.5 * rc, 15.0 * eps) * (1.0 + 1e-4) + 2e-6);
+    }
+    // pair of a far candidate: only the outer S2 branch, and the Plummer
+    // factor (r^2 + eps^2)^(-3/2) = r^-3 (1 + e)^(-3/2), e = (eps/r)^2 <=
+    // 1/225, from its binomial series to e^3 (truncation below 1e-9
+    // relative): one reciprocal square root per pair instead of two
+    __device__ static void pair_far(Tile &tl, const I &is, const T *jd) {
+        const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        if (!(r2 < is.rc2)) return;
+        const T rs = rsq(r2);
+        const T rs2 = rs * rs;
+        const T rs3 = rs2 * rs;
+        const T xi = (r2 * rs) * is.two_rc;
+        const T u = T(2) - xi;
+        const T u2 = u * u;
+        const T u5 = u2 * u2 * u;
+        T po = fma(T(7), xi, T(22));
+        po = fma(po, xi, T(10));
+        po = fma(po, xi, T(4));
+        const T e = is.eps2 * rs2;
+        T q = fma(e, T(-35.0 / 16.0), T(15.0 / 8.0));
+        q = fma(q, e, T(-1.5));
+        const T t = fma(u5 * po, T(1.0 / 140.0), e * q);
+        const T w = jd[3] * (rs3 * t);
+        tl.s[0] = fma(-w, dx, tl.s[0]);
+        tl.s[1] = fma(-w, dy, tl.s[1]);
+        tl.s[2] = fma(-w, dz, tl.s[2]);
+    }
     __device__ static void finish(const Acc &ac, const I &, const Args &a,
                                   const TreeView<T> &tv, int i) {
         const int c = tv.perm[i];
@@ -1455,6 +1911,9 @@ template <typename T> struct CountPass {
     static constexpr int CAPF = 4;
     static constexpr int ID = 4;
     static constexpr bool MASKED = false;
+    static constexpr bool FARNEAR = false;
+    static constexpr bool PK = false;
+    static constexpr bool RANGE_HJ = true;  // 2 max(h_i, h_j)
     __device__ static T range(const Args &a, const TreeView<T> &tv, int box, T hI,
                               T hJ) {
         const int m = a.mode % 3;
@@ -1578,6 +2037,9 @@ template <typename T> struct FofPass {
     static constexpr int CAPF = 4;
     static constexpr int ID = 5;
     static constexpr bool MASKED = false;
+    static constexpr bool FARNEAR = false;
+    static constexpr bool PK = false;
+    static constexpr bool RANGE_HJ = false;
     __device__ static T range(const Args &a, const TreeView<T> &, int, T, T) {
         return widen<T>(a.b);
     }
@@ -1708,6 +2170,22 @@ __global__ void gather1_kernel(const int32_t *__restrict__ perm,
 }
 
 // masses of all tree slots (gas, then dm), times G
+// (x, y, z, G m) per slot in tree order, for the float gravity pass
+__global__ void gather_grav_packed_kernel(const int32_t *__restrict__ perm,
+                                          const float *__restrict__ px,
+                                          const float *__restrict__ py,
+                                          const float *__restrict__ pz,
+                                          const float *__restrict__ mg,
+                                          const float *__restrict__ md,
+                                          int64_t n_gas, int64_t n, float G,
+                                          float4 *__restrict__ out) {
+    GRID_STRIDE(p, n) {
+        const int c = perm[p];
+        out[p] = make_float4(px[p], py[p], pz[p],
+                             G * (c < n_gas ? mg[c] : md[c - n_gas]));
+    }
+}
+
 template <typename T>
 __global__ void gather_mass_kernel(const int32_t *__restrict__ perm,
                                    const T *__restrict__ mg,
@@ -1727,42 +2205,43 @@ __global__ void hydro_gather_kernel(
     const T *__restrict__ rho, const T *__restrict__ P,
     const T *__restrict__ cs, const T *__restrict__ A,
     const T *__restrict__ B, const T *__restrict__ gA,
-    const T *__restrict__ gB, const GatherExtra<T> ex, T *__restrict__ f,
-    T *__restrict__ mt) {
+    const T *__restrict__ gB, const GatherExtra<T> ex, int S,
+    T *__restrict__ f, T *__restrict__ mt) {
     GRID_STRIDE(p, n) {
+        T *r = f + (int64_t)p * S;  // this particle's record
         const int c = perm[p];
         const T hh = h[p];
         const T N = (T)(1.0 / (PI_D * (double)hh * (double)hh * (double)hh));
         const T a = A[c] * N;
-        f[0 * n + p] = vx[c];
-        f[1 * n + p] = vy[c];
-        f[2 * n + p] = vz[c];
-        f[3 * n + p] = T(1) / (hh * hh);
-        f[4 * n + p] = a;
+        r[0] = vx[c];
+        r[1] = vy[c];
+        r[2] = vz[c];
+        r[3] = T(1) / (hh * hh);
+        r[4] = a;
         for (int g = 0; g < 3; ++g) {
-            f[(5 + g) * n + p] = gA[g * n + c] * N;
-            f[(8 + g) * n + p] = B[g * n + c];
-            f[(11 + g) * n + p] = a * B[g * n + c];
+            r[(5 + g)] = gA[g * n + c] * N;
+            r[(8 + g)] = B[g * n + c];
+            r[(11 + g)] = a * B[g * n + c];
             for (int x = 0; x < 3; ++x)
-                f[(14 + 3 * g + x) * n + p] = a * gB[(3 * g + x) * n + c];
+                r[(14 + 3 * g + x)] = a * gB[(3 * g + x) * n + c];
         }
-        f[23 * n + p] = hh;
-        f[24 * n + p] = V[c];
+        r[23] = hh;
+        r[24] = V[c];
         // (the velocity-gradient pass needs neither the state nor the mass)
         if (P) {
-            f[25 * n + p] = P[c];
-            f[26 * n + p] = rho[c];
-            f[27 * n + p] = cs[c];
+            r[25] = P[c];
+            r[26] = rho[c];
+            r[27] = cs[c];
             mt[p] = m[c];
         }
         if (ex.dv) {
             const T *d = ex.dv + c;
-            f[(HF + 0) * n + p] = d[0];
-            f[(HF + 1) * n + p] = d[4 * n];
-            f[(HF + 2) * n + p] = d[8 * n];
-            f[(HF + 3) * n + p] = d[1 * n] + d[3 * n];
-            f[(HF + 4) * n + p] = d[2 * n] + d[6 * n];
-            f[(HF + 5) * n + p] = d[5 * n] + d[7 * n];
+            r[(HF + 0)] = d[0];
+            r[(HF + 1)] = d[4 * n];
+            r[(HF + 2)] = d[8 * n];
+            r[(HF + 3)] = d[1 * n] + d[3 * n];
+            r[(HF + 4)] = d[2 * n] + d[6 * n];
+            r[(HF + 5)] = d[5 * n] + d[7 * n];
         }
         if (ex.ag[0]) {
             const T *vv[3] = {vx, vy, vz};
@@ -1770,7 +2249,7 @@ __global__ void hydro_gather_kernel(
             for (int a = 0; a < 3; ++a) {
                 double acc = (double)ex.ag[a][c];
                 if (ex.ah[a]) acc += (double)ex.ah[a][c];
-                f[(ex.w0 + a) * n + p] = (T)((double)vv[a][c] + ex.dt * acc);
+                r[(ex.w0 + a)] = (T)((double)vv[a][c] + ex.dt * acc);
             }
         }
     }
@@ -1802,6 +2281,7 @@ TreeView<T> tree_view(crk_tree *t, bool hydro, const int32_t *n_items) {
     tv.hmax = t->leaf_hmax.as<T>();
     tv.lcap = t->leaf_cap;
     tv.xcd_remap = t->owner->tuning.xcd_remap;
+    tv.tile = t->owner->tuning.tile;
     tv.walk_mask = t->owner->tuning.walk_mask;
     tv.groups = t->has_sub ? t->owner->tuning.sub_sweep : 0;
     tv.nsub = t->sub_nsub.as<int32_t>();
@@ -1845,15 +2325,32 @@ int launch_pair(crk_ctx *ctx, crk_tree *t, const TreeView<T> &tv,
     else                                                                        \
         hipLaunchKernelGGL((pair_kernel<T, P, B, SWEEP_BROADCAST>), dim3(grid), \
                            dim3(B), 0, ctx->stream, tv, pa);
-    // the walk and group forms: one workgroup per leaf of <= 64 only
-    const int mode = (queue || L > 64) ? SWEEP_BROADCAST
+    // the sub-leaf forms (split, leaf) have persistent queue forms of their
+    // own; the walk and group forms run one workgroup per leaf only
+    const int mode = L > 64 ? SWEEP_BROADCAST
+                     : tv.groups == 2 ? SWEEP_SPLIT
+                     : tv.groups == 3 ? SWEEP_LEAF
+                     : queue ? SWEEP_BROADCAST
                      : ((ctx->tuning.walk_mask >> P::ID) & 1) ? SWEEP_WALK
-                     : tv.groups == 1 ? SWEEP_GROUPED
-                     : tv.groups == 2 ? SWEEP_SPLIT : SWEEP_BROADCAST;
-    if (mode == SWEEP_SPLIT) {
-        const unsigned g4 = (unsigned)std::max<int64_t>(1, 4 * n_items_bound);
-        hipLaunchKernelGGL((pair_kernel_split<T, P>), dim3(g4), dim3(64), 0,
+                     : tv.groups == 1 ? SWEEP_GROUPED : SWEEP_BROADCAST;
+    const size_t split_lds =
+        (size_t)split_cap_of<T, P>(ctx->tuning.tile) * (P::NJ * sizeof(T) + 4);
+    if (mode == SWEEP_LEAF && queue) {
+        hipLaunchKernelGGL((pair_kernel_leaf_queue<T, P>), dim3(grid), dim3(256),
+                           0, ctx->stream, tv, pa, order, head);
+    } else if (mode == SWEEP_LEAF) {
+        hipLaunchKernelGGL((pair_kernel_leaf<T, P>), dim3(grid), dim3(256), 0,
                            ctx->stream, tv, pa);
+    } else if (mode == SWEEP_SPLIT && queue) {
+        const unsigned g4 = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>(4 * n_items_bound,
+                                 (int64_t)ctx->tuning.grid_mult * ctx->n_cu * 4));
+        hipLaunchKernelGGL((pair_kernel_split_queue<T, P>), dim3(g4), dim3(64),
+                           split_lds, ctx->stream, tv, pa, order, head);
+    } else if (mode == SWEEP_SPLIT) {
+        const unsigned g4 = (unsigned)std::max<int64_t>(1, 4 * n_items_bound);
+        hipLaunchKernelGGL((pair_kernel_split<T, P>), dim3(g4), dim3(64),
+                           split_lds, ctx->stream, tv, pa);
     } else if (mode == SWEEP_WALK) {
         hipLaunchKernelGGL((pair_kernel<T, P, 64, SWEEP_WALK>), dim3(grid),
                            dim3(64), 0, ctx->stream, tv, pa);
@@ -1941,7 +2438,7 @@ int coeff_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *V,
                                         pa, gas_bound(ctx, t), P_COEFF, true);
 }
 
-// the hydro field planes of every gas particle in tree order (pf[7]);
+// the hydro field records of every gas particle in tree order (pf[7]);
 // P == nullptr: the kinematic and coefficient planes only (no state, no
 // masses); dv != nullptr: also the reconstruction planes
 template <typename T>
@@ -1951,7 +2448,12 @@ int hydro_fields(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                  const void *gA, const void *gB, const GatherExtra<T> &ex) {
     const int64_t ng = t->n_gas;
     const size_t n1 = std::max<int64_t>(ng, 1);
-    CRK_TRY(t->pf[7].ensure(n1 * HF_MAX * sizeof(T), ctx->capturing));
+    CRK_TRY(t->pf[7].ensure(n1 * hydro_stride(HF_MAX) * sizeof(T),
+                            ctx->capturing));
+    // the record stride of the fields this call writes (the passes read
+    // records of the same stride: hydro_stride of their field count)
+    const int S = hydro_stride((P ? HF : HF) + (ex.dv ? 6 : 0) +
+                               (ex.ag[0] ? 3 : 0));
     CRK_TRY(t->pf[4].ensure(n1 * sizeof(T), ctx->capturing));
     hipLaunchKernelGGL((hydro_gather_kernel<T>), dim3(grid_for(ng)), dim3(256),
                        0, ctx->stream, t->perm.as<int32_t>(), ng, t->hsm.as<T>(),
@@ -1961,7 +2463,7 @@ int hydro_fields(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                        static_cast<const T *>(P), static_cast<const T *>(cs),
                        static_cast<const T *>(A), static_cast<const T *>(B),
                        static_cast<const T *>(gA), static_cast<const T *>(gB),
-                       ex, t->pf[7].as<T>(), t->pf[4].as<T>());
+                       ex, S, t->pf[7].as<T>(), t->pf[4].as<T>());
     CRK_HIP(hipGetLastError());
     return CRK_OK;
 }
@@ -2057,12 +2559,24 @@ int gravity_impl(crk_ctx *ctx, crk_tree *t, const void *mg, const void *md,
                        ctx->stream, t->perm.as<int32_t>(),
                        static_cast<const T *>(mg), static_cast<const T *>(md),
                        t->n_gas, n, (T)ctx->params.G, mt);
+    const float4 *pk = nullptr;
+    if constexpr (std::is_same<T, float>::value) {
+        CRK_TRY(t->pf[11].ensure(std::max<int64_t>(n, 1) * sizeof(float4),
+                                 ctx->capturing));
+        hipLaunchKernelGGL(gather_grav_packed_kernel, dim3(grid_for(n)), dim3(256),
+                           0, ctx->stream, t->perm.as<int32_t>(),
+                           t->pos[0].as<float>(), t->pos[1].as<float>(),
+                           t->pos[2].as<float>(), static_cast<const float *>(mg),
+                           static_cast<const float *>(md), t->n_gas, n,
+                           (float)ctx->params.G, t->pf[11].as<float4>());
+        pk = t->pf[11].as<float4>();
+    }
     CRK_HIP(hipGetLastError());
     typename GravityPass<T>::Args pa{mt,
                                      static_cast<T *>(axg), static_cast<T *>(ayg),
                                      static_cast<T *>(azg), static_cast<T *>(axd),
                                      static_cast<T *>(ayd), static_cast<T *>(azd),
-                                     t->n_gas};
+                                     t->n_gas, pk};
     return launch_pair<T, GravityPass<T>>(ctx, t, tree_view<T>(t, false, all_leaf_count(t)),
                                           pa, all_bound(ctx, t), P_GRAV, false);
 }

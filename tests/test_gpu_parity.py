@@ -397,24 +397,27 @@ def test_graph_refuses_launch_after_buffers_are_freed(step_cls):
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_sub_leaf_sweeps_match_whole_leaf_sweep(orc, step_cls, precision):
     """Sub-leaf sweeps (lane groups; one wavefront per sub-leaf with four
-    lanes per particle) only drop candidates that are out of range of every
+    lanes per particle; four wavefronts per leaf sharing one staging of the
+    leaf's candidates) only drop candidates that are out of range of every
     particle of the sub-leaf.  The sub-leaf split reorders the slots inside
-    each leaf and the split form sums each particle's candidates in four
-    interleaved streams, so sums agree with the whole-leaf sweep up to
-    rounding order, and all agree with the oracle."""
+    each leaf and the split forms sum each particle's candidates in four
+    interleaved streams (and, in float, far gravity candidates with the
+    series form of the softening), so sums agree with the whole-leaf sweep
+    up to rounding, and all agree with the oracle."""
     print(f"case sub-leaf sweeps vs whole-leaf sweep {precision}", flush=True)
     wl = W.random_uniform(6000, 5000, 1301, n_ngb=48.0, clustered=True)
     outs = []
-    for ss in (0, 1, 2):
+    for ss in (0, 1, 2, 3):
         st, o = run(step_cls, wl, precision,
                     tuning=dict(leaf_max=64, sub_sweep=ss))
         outs.append(o)
         st.close()
     tol_same = 2e-6 if precision == "fp32" else 1e-12
-    compare(outs[1], outs[0], tol_same)
-    compare(outs[2], outs[0], tol_same)
+    for k in (1, 2, 3):
+        compare(outs[k], outs[0], tol_same)
     ref = orc.step(wl)
-    compare(outs[2], ref, FP32_TOL if precision == "fp32" else FP64_TOL)
+    for k in (2, 3):
+        compare(outs[k], ref, FP32_TOL if precision == "fp32" else FP64_TOL)
 
 
 @pytest.mark.parametrize("tuning", [dict(grid_mult=16), dict(xcd_remap=1),
@@ -435,6 +438,37 @@ def test_launch_shapes_are_bitwise_identical(step_cls, tuning):
     st.close()
     for k in KEYS:
         assert np.array_equal(ref[k], got[k]), k
+
+
+@pytest.mark.parametrize("form", [dict(sub_sweep=2), dict(sub_sweep=3)])
+def test_sub_leaf_queue_forms(orc, step_cls, form):
+    """The persistent cost-ordered queue of each sub-leaf form (64-thread
+    workgroups popping sub-leaves; four-wavefront workgroups popping
+    leaves) runs every item exactly as the one-workgroup-per-item launch
+    does, so the outputs are bitwise the same; and they match the oracle."""
+    print(f"case queue form {form}", flush=True)
+    wl = W.random_uniform(6000, 5000, 1511, n_ngb=48.0, clustered=True)
+    base = dict(leaf_max=64, **form)
+    st, ref = run(step_cls, wl, "fp32", tuning=base)
+    st.close()
+    for gm in (1, 16):
+        st, got = run(step_cls, wl, "fp32", tuning=dict(base, grid_mult=gm))
+        st.close()
+        for k in KEYS:
+            assert np.array_equal(ref[k], got[k]), (gm, k)
+    compare(got, orc.step(wl), FP32_TOL)
+
+
+@pytest.mark.parametrize("tile", [1, 2, 8])
+def test_tile_widths_match_oracle(orc, step_cls, tile):
+    """The j-tile width (candidate buffer of the split form) only moves the
+    points where partial sums are folded: every width matches the oracle."""
+    print(f"case tile {tile}", flush=True)
+    wl = W.random_uniform(5000, 4000, 1521, n_ngb=48.0, clustered=True)
+    st, got = run(step_cls, wl, "fp32",
+                  tuning=dict(leaf_max=64, sub_sweep=2, tile=tile))
+    st.close()
+    compare(got, orc.step(wl), FP32_TOL)
 
 
 @pytest.mark.parametrize("precision,L,cm", [("fp32", 64, 0.0), ("fp64", 32, 0.0),

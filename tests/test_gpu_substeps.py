@@ -106,13 +106,16 @@ def _bins_case(orc, ctx, n, dt, L, eps, c_cfl, eta, ag, ah, h, cs):
 # one pass over active leaves writes exactly the active particles
 # ---------------------------------------------------------------------------
 
-def test_active_passes_write_active_particles_only(step_cls):
+@pytest.mark.parametrize("sub_sweep", [2, 3])
+def test_active_passes_write_active_particles_only(step_cls, sub_sweep):
     """After crk_tree_set_active, each pass writes, for the active particles,
     bitwise the values of the full pass (their leaves are swept the same
-    way) and leaves every other output untouched."""
-    print("case active passes random_uniform(6000, 5000)", flush=True)
+    way) and leaves every other output untouched; in both sub-leaf forms
+    (one wavefront per sub-leaf, or four per leaf sharing the staging)."""
+    print(f"case active passes random_uniform(6000, 5000) sub_sweep "
+          f"{sub_sweep}", flush=True)
     wl = W.random_uniform(6000, 5000, 401, n_ngb=48.0, h_spread=0.15)
-    st = step_cls(wl, "fp32")
+    st = step_cls(wl, "fp32", tuning=dict(leaf_max=64, sub_sweep=sub_sweep))
     st.run()
     full = st.outputs()
     rng = np.random.default_rng(5)
@@ -201,6 +204,24 @@ def _cycle_errors(wl, got, ref):
     return errs
 
 
+def _close_pair_members(ref, eps, factor=3.0):
+    """Masks (gas, dm) of the particles with another particle closer than
+    factor * eps in the oracle's final state.  Their softened forces change
+    by up to ~1e-4 for a one-ulp change of their separation, so float32
+    trajectories that agree to 1e-7 can still give final forces that differ
+    by more than 1e-5 for them alone: the final outputs are compared over
+    the other particles (the trajectories over all)."""
+    from scipy.spatial import cKDTree
+    x = np.concatenate([ref["xg"], ref["xd"]], axis=1).T - 1.0
+    x = np.mod(x, 1.0)
+    tree = cKDTree(x, boxsize=1.0)
+    pairs = tree.query_pairs(factor * eps, output_type="ndarray")
+    close = np.zeros(x.shape[0], bool)
+    close[pairs.ravel()] = True
+    ng = ref["xg"].shape[1]
+    return close[:ng], close[ng:]
+
+
 # The clustered set is asserted on the float64 path only: there a random
 # one-ulp change of the float32 positions alone moves B, grad B and a_hydro
 # by ~3e-5 (relative RMS; ill-conditioned moment matrices between the
@@ -226,8 +247,20 @@ def test_substep_cycle_matches_oracle(orc, step_cls, precision, clustered, L,
         "float32" if precision == "fp32" else "float64"))
     tol = FP32_TOL if precision == "fp32" else FP64_TOL
     errs = _cycle_errors(wl, got, ref)
-    errs.update({k: rel_rms(outs[k], ref[k]) for k in KEYS})
-    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    if precision == "fp32":
+        cg, cd = _close_pair_members(ref, float(wl.eps[0]))
+    else:
+        cg, cd = np.zeros(wl.gas.n, bool), np.zeros(wl.dm.n, bool)
+    for k in KEYS:
+        keep = ~cd if k == "a_grav_dm" else ~cg
+        g, r = outs[k], ref[k]
+        if k.startswith("a_"):
+            errs[k] = rel_rms(g[:, keep], r[:, keep])
+        else:
+            errs[k] = rel_rms(g[keep], r[keep])
+    print({k: f"{v:.2e}" for k, v in errs.items()},
+          f"(final outputs without {int(cg.sum())} gas and {int(cd.sum())} "
+          "dm particles in close pairs)", flush=True)
     bad = {k: v for k, v in errs.items() if not v <= tol}
     assert not bad, bad
     # positions wrapped back into [1, 2)
