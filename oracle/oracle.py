@@ -470,7 +470,7 @@ def _wrap(x):
 
 def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
                   counts=None, forces_at="float64", pm_mesh=None,
-                  recon=False):
+                  recon=False, compatible=False):
     """One interval dt of hierarchical block steps (kick-drift-kick) with
     2^max_level substeps of dt / 2^max_level.  A particle of bin b takes
     steps tau_b = dt / 2^b, starting at substeps s with s % 2^(L-b) == 0
@@ -498,7 +498,18 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
     number of evaluations of every particle.  recon: the hydro forces use
     the viscosity on the limited midpoint reconstruction, with the velocity
     gradients evaluated with the coefficients (latest values of inactive
-    neighbours, like every other field)."""
+    neighbours, like every other field).
+
+    compatible: every half-kick of the gas takes the compatible energy
+    update of CRKSPH (its energy conservation, Sec. IV-A) in place of the
+    plain rate: a kick of the set K by widths w_i = tau_i / 2 changes u_i
+    by w_i du_i/dt, where du_i/dt comes from the pair forces of i's latest
+    evaluation (the velocities of that evaluation included) with the pair
+    work taken at the kick's centred velocities c = v + w a / 2 for the
+    particles of K and c = v for every other particle.  With one bin, or
+    bins that differ only between particles that do not interact, and G = 0,
+    sum m (v^2/2 + u) is then conserved to rounding; the returned dudt is
+    the rate of each particle's final closing kick."""
     f32 = forces_at == "float32"
 
     def q(a):
@@ -521,10 +532,12 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
               dv=np.zeros((ng, 3, 3)))
     ev_g = np.zeros(ng, np.int64)
     ev_d = np.zeros(nd, np.int64)
+    v_eval = vg.copy()      # gas velocities at each particle's latest evaluation
 
     def evaluate(act_g, act_d):
         ev_g[act_g] += 1
         ev_d[act_d] += 1
+        v_eval[:] = vg
         for b, gs, ds in _box_slices(wl):
             n = gs.stop - gs.start
             X = _wrap(q(xg[:, gs]))
@@ -565,11 +578,41 @@ def substep_cycle(wl, bins_gas, bins_dm, dt, max_level, params=PARAMS,
                 st["a_grav_gas"][:, gs.start + Tg] = (ax[:k], ay[:k], az[:k])
                 st["a_grav_dm"][:, ds.start + Td] = (ax[k:], ay[k:], az[k:])
 
+    def compatible_rate(act_g, w):
+        """du/dt of the gas of the kick set act_g with kick widths w (n_gas,
+        zero outside the set): the latest pair forces, whose velocities are
+        v_eval, with the pair work at the centred velocities c, passed to
+        hydro() as the velocities 2 c - v_eval after a kick from v_eval."""
+        c = vg + 0.5 * w * (st["a_grav_gas"] + st["a_hydro"])
+        v1 = 2.0 * c - v_eval
+        rate = st["dudt"].copy()
+        for b, gs, ds in _box_slices(wl):
+            Tg = np.nonzero(act_g[gs])[0]
+            if not Tg.size:
+                continue
+            X = _wrap(q(xg[:, gs]))
+            V3 = q(v_eval[:, gs])
+            _, _, _, du = hydro(
+                X[0], X[1], X[2], V3[0], V3[1], V3[2], g.h[gs], g.m[gs],
+                st["V"][gs], st["rho"][gs], st["P"][gs], st["cs"][gs],
+                st["A"][gs], st["B"][gs], st["gradA"][gs], st["gradB"][gs],
+                params["Cl"], params["Cq"], params["epsQ"], targets=Tg,
+                dv=st["dv"][gs] if recon else None, v1=v1[:, gs])
+            rate[gs.start + Tg] = du
+        return rate
+
     def kick(act_g, act_d):
         tg = dt * 2.0 ** (-bg[act_g].astype(np.float64)) * 0.5
         td = dt * 2.0 ** (-bd[act_d].astype(np.float64)) * 0.5
+        if compatible and ng:
+            w = np.zeros(ng)
+            w[act_g] = tg
+            rate = compatible_rate(act_g, w)
+            u[act_g] += rate[act_g] * tg
+            st["dudt"][act_g] = rate[act_g]
+        else:
+            u[act_g] += st["dudt"][act_g] * tg
         vg[:, act_g] += (st["a_grav_gas"][:, act_g] + st["a_hydro"][:, act_g]) * tg
-        u[act_g] += st["dudt"][act_g] * tg
         vd[:, act_d] += st["a_grav_dm"][:, act_d] * td
 
     def long_kick():
