@@ -120,6 +120,7 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
     active leaves only)."""
     import numpy as np
     import torch
+    from paper_2510_03557_amd import binding
     from paper_2510_03557_amd.step import ShortRangeStep
     c_cfl, eta = 0.25, 0.025
     st = ShortRangeStep(wl, precision="fp32", tuning=tuning)
@@ -143,16 +144,29 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
                                     + wl.dm.vy.astype(np.float64) ** 2
                                     + wl.dm.vz.astype(np.float64) ** 2))))
     dt = min(4.0 * tmed, 0.25 * float(wl.r_c[0]) / max(vmax, 1e-30))
-    levels = int(min(max(np.ceil(np.log2(dt / tmin)), 1), max_levels))
-    bg, bd = st.timestep_bins(dt, levels, c_cfl=c_cfl, eta=eta)
+    # where the chaining-mesh bins leave less margin than that, the refit
+    # reports CRK_ESTALE: the interval is then halved (fresh state)
+    for attempt in range(4):
+        levels = int(min(max(np.ceil(np.log2(dt / tmin)), 1), max_levels))
+        bg, bd = st.timestep_bins(dt, levels, c_cfl=c_cfl, eta=eta)
+        log(f"[bench] substep cycle: {levels} levels, dt {dt:.3g} (median "
+            f"tau {tmed:.3g}, min {tmin:.3g}), bins gas "
+            f"{np.bincount(bg, minlength=levels + 1).tolist()} dm "
+            f"{np.bincount(bd, minlength=levels + 1).tolist()}")
+        try:
+            st.substep_cycle(dt, levels)  # warm-up (sizes)
+            st.sync()
+            break
+        except binding.CrkError as e:
+            if e.status != binding.CRK_ESTALE or attempt == 3:
+                raise
+            log("[bench] the tree went stale inside the interval: halving dt")
+            st.close()
+            st = ShortRangeStep(wl, precision="fp32", tuning=tuning)
+            st.run()
+            dt *= 0.5
     steps = int(np.sum(2 ** bg.astype(np.int64)) + np.sum(2 ** bd.astype(np.int64)))
     n = wl.n_total
-    log(f"[bench] substep cycle: {levels} levels, dt {dt:.3g} (median tau "
-        f"{tmed:.3g}, min {tmin:.3g}), bins gas "
-        f"{np.bincount(bg, minlength=levels + 1).tolist()} dm "
-        f"{np.bincount(bd, minlength=levels + 1).tolist()}")
-    st.substep_cycle(dt, levels)  # warm-up (sizes)
-    st.sync()
     st.ctx.timing(True)
     sec = time_steps(lambda: st.substep_cycle(dt, levels),
                      lambda: (torch.cuda.synchronize(),
@@ -161,6 +175,33 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
     st.ctx.timing(False)
     st.sync()
     st.close()
+
+    def variant(label, tuning_change=None, **kw):
+        """The same cycle (same bins and dt) with one option changed."""
+        log(f"[bench] substep cycle, {label}")
+        v = ShortRangeStep(wl, precision="fp32",
+                           tuning=dict(tuning, **(tuning_change or {})), **kw)
+        v.run()
+        v.set_bins(bg, bd)
+        v.substep_cycle(dt, levels)  # warm-up
+        v.sync()
+        v.ctx.timing(True)
+        s2 = time_steps(lambda: v.substep_cycle(dt, levels),
+                        lambda: (torch.cuda.synchronize(),
+                                 v.ctx.stream.synchronize()), cycles, 0)
+        pm, _, _ = v.ctx.pass_times()
+        v.ctx.timing(False)
+        v.sync()
+        v.close()
+        return {"ms_per_cycle": s2 * 1e3,
+                "pass_ms_per_cycle": {k: round(x / cycles, 3)
+                                      for k, x in pm.items()}}
+
+    groups = int(tuning.get("act_groups", 1))
+    other = variant("active particles on the tree's sub-leaves" if groups
+                    else "dense active groups",
+                    {"act_groups": 0 if groups else 1})
+    comp = variant("compatible energy update in every kick", compatible=True)
     flat = (2 ** levels) * ms_per_step if ms_per_step else None
     return {"levels": levels, "substeps": 2 ** levels, "dt": dt,
             "tau_median": tmed, "tau_min": tmin, "v_max": vmax,
@@ -174,6 +215,9 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
                                   for k, v in pass_ms.items()},
             "flat_deepest_ms": flat,
             "speedup_vs_flat": (flat / (sec * 1e3)) if flat else None,
+            "act_groups": groups,
+            ("sub_leaves" if groups else "dense_groups"): other,
+            "compatible_energy": comp,
             "launch": "eager"}
 
 
@@ -568,6 +612,7 @@ def main():
     ap.add_argument("--sub-sweep", type=int, default=2)
     ap.add_argument("--tree-lds", type=int, default=1)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--act-groups", type=int, default=1)
     ap.add_argument("--tune", action="store_true",
                     help="tune the launch shape of the headline workload")
     ap.add_argument("--tuned-workload", default="uneven_boxes512",
@@ -626,7 +671,7 @@ def main():
     tuning = dict(leaf_max=args.leaf_max, grid_mult=args.grid_mult,
                   xcd_remap=args.xcd_remap, walk_mask=args.walk_mask,
                   sub_sweep=args.sub_sweep, tree_lds=args.tree_lds,
-                  tile=args.tile)
+                  tile=args.tile, act_groups=args.act_groups)
 
     if args.fof_only or args.pm_only or args.cycle_only:
         log(f"[bench] generating {args.workload}")

@@ -128,6 +128,14 @@ typedef struct {
                            LDS candidate buffer holds tile x 64 records
                            (capped per pass at 64 KiB); 0: the pass's own
                            width (default); 1, 2, 4 or 8                    */
+    int32_t act_groups; /* with an active subset (crk_tree_set_active) and
+                           sub-leaves: 1, the sub-leaf sweeps take dense
+                           groups of <= 16 active particles of each leaf (in
+                           slot order, boxed at their current positions), so
+                           a sub-leaf with few active particles no longer
+                           costs a whole sweep (default); 0, the tree's
+                           sub-leaves, skipping those without an active
+                           particle                                          */
 } crk_tuning;
 
 /* ------------------------------------------------------------------------ */
@@ -309,6 +317,36 @@ int crk_hydro_energy_compatible(crk_ctx *ctx, crk_tree *tree, const void *m,
                                 const void *const a_grav[3],
                                 const void *const a_hydro[3], void *dudt);
 
+/* The compatible energy update inside the block kicks of a hierarchical
+ * cycle (CRKSPH's energy conservation, Sec. IV-A, under the adaptive
+ * integration of that section; the split of the kicks is this library's
+ * reading).  The kick after substep `substep` of a cycle of 2^max_level
+ * substeps moves each gas particle i by a width w_i from its bin b
+ * (tau_b = dt / 2^b): substep -1, the opening half-kick of every particle
+ * at the start of the interval, w = tau_b / 2; a particle ending a step
+ * after `substep`, w = tau_b (its closing half-kick and the opening
+ * half-kick of its next step, made with the same forces, as one kick), or
+ * tau_b / 2 after the last substep; any other particle w = 0.  With
+ * v1 = v + w (a_grav + a_hydro), the rate is that of
+ * crk_hydro_energy_compatible with the pair work at (v + v1)/2, written for
+ * the particles crk_tree_set_active selected; the caller's two half-kicks
+ * (crk_kick phases 1 and 0) both apply it, so u gains w du/dt in all.
+ * With one bin (or bins that differ only between particles that do not
+ * interact) the hydro kicks conserve sum m (v^2/2 + u) to rounding.
+ * The selection must be that of crk_tree_set_active(bins, max_level,
+ * substep), or everything for substep -1 (CRK_ESTATE otherwise).
+ * dt > 0 is the interval; bins_gas: n_gas int32 levels (device, caller
+ * order, clamped to [0, max_level]); other arguments as
+ * crk_hydro_energy_compatible.  Timed as index 8 of crk_pass_times. */
+int crk_hydro_energy_compatible_block(
+    crk_ctx *ctx, crk_tree *tree, const void *m, const void *vx,
+    const void *vy, const void *vz, const void *V, const void *rho,
+    const void *P, const void *cs, const void *A, const void *B,
+    const void *gradA, const void *gradB, const void *dv, double eta_crit,
+    double eta_fold, double dt, int32_t max_level, const int32_t *bins_gas,
+    int64_t substep, const void *const a_grav[3], const void *const a_hydro[3],
+    void *dudt);
+
 /* Short-range gravity inside the handover scale (Sec. IV-A, with the
  * long-range part left to a spectral particle-mesh solver):
  *   a_i = -G sum_{j != i, r_ij < r_c} m_j g(r_ij) x_ij / r_ij,
@@ -373,7 +411,10 @@ int crk_timestep_bins(crk_ctx *ctx, int64_t n, double dt, int32_t max_level,
  * only.  substep < 0 selects everything (the state after build_tree).
  * The lists must be rebuilt after every call (build_interaction_lists then
  * lists the active leaves only; the passes report CRK_ESTATE until then).
- * Synchronises (reads the active leaf counts back). */
+ * With tuning act_groups and sub-leaves, the call also cuts the active
+ * particles of every active leaf into dense groups of <= 16, boxed at the
+ * tree's current positions, which the sub-leaf sweeps then take as their
+ * i-sets.  Synchronises (reads the active leaf counts back). */
 int crk_tree_set_active(crk_ctx *ctx, crk_tree *tree, const int32_t *bins_gas,
                         const int32_t *bins_dm, int32_t max_level,
                         int64_t substep);
@@ -384,7 +425,10 @@ int crk_tree_set_active(crk_ctx *ctx, crk_tree *tree, const int32_t *bins_gas,
  * smoothing lengths stay those of build_tree.  Returns CRK_ESTALE when a
  * leaf box reaches so far out of its chaining-mesh bin (by d) that the
  * 27-bin stencil could miss a pair (2 d + range > bin width): the tree must
- * then be rebuilt.  Synchronises. */
+ * then be rebuilt.  The lists must be rebuilt after a refit (the passes
+ * report CRK_ESTATE until then), and an active subset's dense groups
+ * (tuning act_groups) are dropped until the next crk_tree_set_active (the
+ * passes then sweep the tree's sub-leaves).  Synchronises. */
 int crk_tree_refit(crk_ctx *ctx, crk_tree *tree, const void *gx,
                    const void *gy, const void *gz, const void *dx,
                    const void *dy, const void *dz);

@@ -35,7 +35,8 @@ EXPORTS = (
     "crk_pass_times", "crk_timestep_bins", "crk_tree_set_active",
     "crk_tree_refit", "crk_kick", "crk_drift", "crk_pm_gravity", "crk_fof",
     "crk_velocity_gradient", "crk_hydro_forces_limited",
-    "crk_hydro_energy_compatible", "crk_fof_properties",
+    "crk_hydro_energy_compatible", "crk_hydro_energy_compatible_block",
+    "crk_fof_properties",
 )
 
 
@@ -64,7 +65,8 @@ class crk_tuning(ctypes.Structure):
     _fields_ = [("leaf_max", ctypes.c_int32), ("cm_factor", ctypes.c_double),
                 ("grid_mult", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("walk_mask", ctypes.c_int32), ("sub_sweep", ctypes.c_int32),
-                ("tree_lds", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("tree_lds", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("act_groups", ctypes.c_int32)]
 
 
 class crk_tree_info(ctypes.Structure):
@@ -132,6 +134,9 @@ def load(path: Path | str | None = None):
         + [vp] * 4
     lib.crk_hydro_energy_compatible.argtypes = [vp] * 15 + \
         [ctypes.c_double] * 3 + [ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.crk_hydro_energy_compatible_block.argtypes = [vp] * 15 + \
+        [ctypes.c_double] * 3 + [ctypes.c_int32, vp, ctypes.c_int64,
+                                 ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.shortrange_gravity.argtypes = [vp] * 10
     lib.crk_integrate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp, vp,
                                   vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -251,11 +256,12 @@ class Context:
             pass
 
     def set_tuning(self, leaf_max=64, cm_factor=0.0, grid_mult=0, xcd_remap=1,
-                   walk_mask=0, sub_sweep=2, tree_lds=1, tile=0):
+                   walk_mask=0, sub_sweep=2, tree_lds=1, tile=0,
+                   act_groups=1):
         check(self.lib.crk_set_tuning(self.handle, ctypes.byref(
             crk_tuning(int(leaf_max), float(cm_factor), int(grid_mult),
                        int(xcd_remap), int(walk_mask), int(sub_sweep),
-                       int(tree_lds), int(tile)))))
+                       int(tree_lds), int(tile), int(act_groups)))))
 
     def get_tuning(self) -> dict:
         t = crk_tuning()
@@ -377,6 +383,21 @@ class Context:
             g(dv, 9, "dv"), float(eta_crit), float(eta_fold), float(dt),
             self._p3(a_grav, n, "a_grav"), self._p3(a_hydro, n, "a_hydro"),
             g(dudt, 1, "dudt")))
+
+    def hydro_energy_compatible_block(self, tree, m, vx, vy, vz, V, rho, P,
+                                      cs, A, B, gA, gB, dv, eta_crit,
+                                      eta_fold, dt, max_level, bins_gas,
+                                      substep, a_grav, a_hydro, dudt):
+        import torch
+        g = lambda t, k, nm: self._g(tree, t, k, nm)
+        n = tree.n_gas
+        check(self.lib.crk_hydro_energy_compatible_block(
+            self.handle, tree.handle,
+            *self._hydro_in(tree, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB),
+            g(dv, 9, "dv"), float(eta_crit), float(eta_fold), float(dt),
+            int(max_level), _dev(bins_gas, torch.int32, n, "bins_gas"),
+            int(substep), self._p3(a_grav, n, "a_grav"),
+            self._p3(a_hydro, n, "a_hydro"), g(dudt, 1, "dudt")))
 
     def shortrange_gravity(self, tree, m_gas, m_dm, axg, ayg, azg, axd, ayd,
                            azd):

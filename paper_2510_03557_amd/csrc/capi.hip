@@ -237,6 +237,7 @@ int crk_ctx_create(crk_ctx **out, int precision, void *stream,
     c->tuning.sub_sweep = 2;
     c->tuning.tree_lds = 1;
     c->tuning.tile = 0;
+    c->tuning.act_groups = 1;
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount,
@@ -302,6 +303,8 @@ int crk_set_tuning(crk_ctx *ctx, const crk_tuning *t) {
     if (!(t->tile == 0 || t->tile == 1 || t->tile == 2 || t->tile == 4 ||
           t->tile == 8))
         return set_error(CRK_EINVAL, "tile must be 0, 1, 2, 4 or 8");
+    if (t->act_groups != 0 && t->act_groups != 1)
+        return set_error(CRK_EINVAL, "act_groups must be 0 or 1");
     if (ctx->capturing) return set_error(CRK_ESTATE, "tuning change during capture");
     ctx->tuning = *t;
     return CRK_OK;
@@ -388,6 +391,7 @@ int build_tree(crk_ctx *ctx, const crk_boxes *boxes, const void *gx,
     }
     PassSpan sp(ctx, P_TREE);
     t->act_on = false;  // a new tree starts with every leaf active
+    t->grp_on = false;
     return tree_build(ctx, t, boxes, gx, gy, gz, gh, dx, dy, dz);
 }
 
@@ -470,16 +474,19 @@ int crk_hydro_forces(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                       nullptr, 0.0, 1.0, ax, ay, az, dudt);
 }
 
-int crk_hydro_energy_compatible(crk_ctx *ctx, crk_tree *t, const void *m,
-                                const void *vx, const void *vy, const void *vz,
-                                const void *V, const void *rho, const void *P,
-                                const void *cs, const void *A, const void *B,
-                                const void *gradA, const void *gradB,
-                                const void *dv, double eta_crit,
-                                double eta_fold, double dt,
-                                const void *const a_grav[3],
-                                const void *const a_hydro[3], void *dudt) {
-    CRK_TRY(check_tree_ready(ctx, t, true));
+namespace {
+
+// the checks and the launch of both compatible-energy entry points; bins
+// (caller order) selects per-particle kick widths, nullptr the width dt
+int energy_compatible(crk_ctx *ctx, crk_tree *t, const void *m,
+                      const void *vx, const void *vy, const void *vz,
+                      const void *V, const void *rho, const void *P,
+                      const void *cs, const void *A, const void *B,
+                      const void *gradA, const void *gradB, const void *dv,
+                      double eta_crit, double eta_fold, double dt,
+                      const int32_t *bins, int max_level, int64_t substep,
+                      const void *const a_grav[3],
+                      const void *const a_hydro[3], void *dudt) {
     const size_t el = ctx->elem();
     const bool g = t->n_gas > 0;
     const void *ins[] = {m, vx, vy, vz, V, rho, P, cs, A, B, gradA, gradB};
@@ -504,7 +511,53 @@ int crk_hydro_energy_compatible(crk_ctx *ctx, crk_tree *t, const void *m,
     PassSpan sp(ctx, P_ENERGY);
     return pass_energy_compatible(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B,
                                   gradA, gradB, dv, eta_crit, eta_fold, dt,
-                                  a_grav, a_hydro, dudt);
+                                  bins, max_level, substep, a_grav, a_hydro,
+                                  dudt);
+}
+
+}  // namespace
+
+int crk_hydro_energy_compatible(crk_ctx *ctx, crk_tree *t, const void *m,
+                                const void *vx, const void *vy, const void *vz,
+                                const void *V, const void *rho, const void *P,
+                                const void *cs, const void *A, const void *B,
+                                const void *gradA, const void *gradB,
+                                const void *dv, double eta_crit,
+                                double eta_fold, double dt,
+                                const void *const a_grav[3],
+                                const void *const a_hydro[3], void *dudt) {
+    CRK_TRY(check_tree_ready(ctx, t, true));
+    return energy_compatible(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gradA,
+                             gradB, dv, eta_crit, eta_fold, dt, nullptr, 0, -1,
+                             a_grav, a_hydro, dudt);
+}
+
+int crk_hydro_energy_compatible_block(
+    crk_ctx *ctx, crk_tree *t, const void *m, const void *vx, const void *vy,
+    const void *vz, const void *V, const void *rho, const void *P,
+    const void *cs, const void *A, const void *B, const void *gradA,
+    const void *gradB, const void *dv, double eta_crit, double eta_fold,
+    double dt, int32_t max_level, const int32_t *bins_gas, int64_t substep,
+    const void *const a_grav[3], const void *const a_hydro[3], void *dudt) {
+    CRK_TRY(check_tree_ready(ctx, t, true));
+    if (max_level < 0 || max_level > 30)
+        return set_error(CRK_EINVAL, "max_level must be in [0, 30]");
+    if (substep < -1 || substep >= ((int64_t)1 << max_level))
+        return set_error(CRK_EINVAL, "substep must be in [-1, 2^max_level)");
+    if (!(dt > 0.0) || !std::isfinite(dt))
+        return set_error(CRK_EINVAL, "dt must be finite and > 0");
+    CRK_TRY(check_ptr(bins_gas, 4, "bins_gas", t->n_gas > 0));
+    // the pass writes the particles crk_tree_set_active selected: they must
+    // be the ones this kick moves
+    if (substep < 0 ? t->act_on
+                    : (!t->act_on || t->act_substep != substep ||
+                       t->act_level != max_level))
+        return set_error(CRK_ESTATE,
+                         "crk_tree_set_active must select the same substep "
+                         "and max_level (everything for substep -1)");
+    return energy_compatible(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gradA,
+                             gradB, dv, eta_crit, eta_fold, dt, bins_gas,
+                             max_level, substep, a_grav, a_hydro, dudt);
 }
 
 int crk_velocity_gradient(crk_ctx *ctx, crk_tree *t, const void *vx,

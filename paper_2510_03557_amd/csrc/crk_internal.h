@@ -214,11 +214,22 @@ struct crk_tree {
     // per-slot flags, active leaves in leaf order (gas leaves first), device
     // counts {all, gas} and their host copies
     bool act_on = false;
+    int64_t act_substep = -1;          // the selection's substep and levels
+    int act_level = 0;
     crk::DevBuf act_flags;             // uint8 per slot
     crk::DevBuf act_leaf;              // int32 per leaf (flag, then scan)
     crk::DevBuf act_items;             // int32 per active leaf
     crk::DevBuf act_count;             // int32 [2]
     int64_t act_nall = 0, act_ngas = 0;
+    // dense groups of the active particles of every active leaf (tuning
+    // act_groups, trees with sub-leaves): the sub-leaf tables of the
+    // subset, group g of leaf I in slot 4 I + g
+    bool grp_on = false;
+    crk::DevBuf grp_nsub;              // int32 per leaf
+    crk::DevBuf grp_cnt;               // int32 per slot
+    crk::DevBuf grp_idx;               // int32 [16] per slot: tree slots
+    crk::DevBuf grp_lo, grp_hi;        // T [3][4*leaf_cap]
+    crk::DevBuf grp_hmax;              // T per slot
     crk::DevBuf overhang;              // int flag: a leaf left the stencil (refit)
 };
 
@@ -279,6 +290,7 @@ int pass_energy_compatible(crk_ctx *ctx, crk_tree *t, const void *m,
                            const void *cs, const void *A, const void *B,
                            const void *gradA, const void *gradB, const void *dv,
                            double eta_crit, double eta_fold, double dt,
+                           const int32_t *bins, int max_level, int64_t substep,
                            const void *const a_grav[3],
                            const void *const a_hydro[3], void *dudt);
 int pass_velocity_gradient(crk_ctx *ctx, crk_tree *t, const void *vx,

@@ -130,6 +130,9 @@ template <typename T> struct TreeView {
     int groups;               // sub-leaf sweep: 1 lane groups, 2 split
     const int32_t *nsub, *sst, *scnt;  // sub-leaves (slots 4*leaf + k)
     const T *slo, *shi, *shm;          // their boxes (3 planes of 4*lcap), h_max
+    // dense active groups in place of the sub-leaves: particle k of slot
+    // 4*leaf + g is tree slot sidx[16 (4*leaf + g) + k] (NULL: sst + k)
+    const int32_t *sidx;
     const double *rc, *eps;
     int64_t n_gas;
     // active subset (hierarchical time steps): work item k is leaf items[k]
@@ -144,6 +147,11 @@ template <typename T> __device__ inline int item_leaf(const TreeView<T> &tv, int
 }
 template <typename T> __device__ inline bool slot_active(const TreeView<T> &tv, int i) {
     return !tv.act || tv.act[i] != 0;
+}
+// tree slot of particle k of sub-leaf (or active group) `slot`
+template <typename T>
+__device__ inline int sub_slot(const TreeView<T> &tv, int64_t slot, int k) {
+    return tv.sidx ? tv.sidx[16 * slot + k] : tv.sst[slot] + k;
 }
 
 // a wave-uniform value moved to a scalar register
@@ -301,7 +309,7 @@ __device__ __forceinline__ void process_leaf(const TreeView<T> &tv,
     const int64_t slot = 4 * (int64_t)I + g;
     const bool act = grouped ? (g < ns && (t & 15) < tv.scnt[g < ns ? slot : 4 * (int64_t)I])
                              : (t < cnt);
-    const int i = act ? (grouped ? tv.sst[slot] + (t & 15) : st + t) : st;
+    const int i = act ? (grouped ? sub_slot(tv, slot, t & 15) : st + t) : st;
     const T rx = tv.px[st], ry = tv.py[st], rz = tv.pz[st];
     const int box = tv.leaf_box[I];
     // i-leaf box relative to the reference particle (exact in float32)
@@ -640,11 +648,10 @@ __device__ __forceinline__ void process_subleaf(const TreeView<T> &tv,
                                                 T *sj, int *sjid) {
     const int lane = threadIdx.x;
     const int64_t slot = 4 * (int64_t)I + g;
-    const int sst = tv.sst[slot];
     const int scnt = min(tv.scnt[slot], 16);
     const int ii = lane >> 2, q = lane & 3;
     const bool act = ii < scnt;
-    const int i = act ? sst + ii : sst;
+    const int i = sub_slot(tv, slot, act ? ii : 0);
     const int st = tv.leaf_start[I];
     const T rx = tv.px[st], ry = tv.py[st], rz = tv.pz[st];
     const int box = tv.leaf_box[I];
@@ -761,7 +768,7 @@ __global__ __launch_bounds__(64) void pair_kernel_split(const TreeView<T> tv,
         // to write (the whole wavefront leaves together)
         const int64_t sl = 4 * (int64_t)I + g;
         const int lane = threadIdx.x;
-        const bool a = lane < min(tv.scnt[sl], 16) && tv.act[tv.sst[sl] + lane];
+        const bool a = lane < min(tv.scnt[sl], 16) && tv.act[sub_slot(tv, sl, lane)];
         if (__ballot(a) == 0) return;
     }
     process_subleaf<T, P>(tv, pa, I, g, sj, sjid);
@@ -822,7 +829,7 @@ __device__ __forceinline__ void process_leaf4(const TreeView<T> &tv,
     const int scnt = w < ns ? min(tv.scnt[slot], 16) : 0;
     const int ii = lane >> 2, q = lane & 3;
     const bool act = ii < scnt;
-    const int i = act ? tv.sst[slot] + ii : tv.sst[slot];
+    const int i = sub_slot(tv, slot, act ? ii : 0);
     // a wavefront sweeps when its sub-leaf exists and, with an active
     // subset, holds an active particle
     bool sweeper = w < ns;
@@ -1440,7 +1447,26 @@ template <typename T> struct GatherExtra {
     const T *ah[3] = {nullptr, nullptr, nullptr};
     double dt = 0.0;
     int w0 = HF;                     // first plane of v1
+    // block kicks: with bins (caller order), the kick width of each
+    // particle follows its bin and the substep (kick_width); dt otherwise
+    const int32_t *bins = nullptr;
+    int L = 0;
+    int64_t substep = -1;
 };
+
+// Width of the kick at the boundary after substep s of a cycle of 2^L
+// substeps for a particle of bin b (tau_b = dt / 2^b): s < 0, the opening
+// half-kick of the interval, tau_b / 2; a particle ending a step after s,
+// tau_b (its closing half-kick and the opening half-kick of its next step,
+// one kick with the same forces), or tau_b / 2 after the last substep; any
+// other particle 0.
+__device__ inline double kick_width(double dt, int L, int64_t s, int b) {
+    b = b < 0 ? 0 : (b > L ? L : b);
+    const double tau = ldexp(dt, -b);
+    if (s < 0) return 0.5 * tau;
+    if ((s + 1) % ((int64_t)1 << (L - b)) != 0) return 0.0;
+    return (s + 1 == ((int64_t)1 << L)) ? 0.5 * tau : tau;
+}
 
 // RECON: the viscosity acts on both velocities extrapolated linearly to the
 // pair midpoint, v~_ij = v_ij - phi/2 (dv_i + dv_j) x_ij, with the limiter
@@ -2245,11 +2271,13 @@ __global__ void hydro_gather_kernel(
         }
         if (ex.ag[0]) {
             const T *vv[3] = {vx, vy, vz};
+            const double w =
+                ex.bins ? kick_width(ex.dt, ex.L, ex.substep, ex.bins[c]) : ex.dt;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 double acc = (double)ex.ag[a][c];
                 if (ex.ah[a]) acc += (double)ex.ah[a][c];
-                r[(ex.w0 + a)] = (T)((double)vv[a][c] + ex.dt * acc);
+                r[(ex.w0 + a)] = (T)((double)vv[a][c] + w * acc);
             }
         }
     }
@@ -2290,6 +2318,15 @@ TreeView<T> tree_view(crk_tree *t, bool hydro, const int32_t *n_items) {
     tv.slo = t->sub_lo.as<T>();
     tv.shi = t->sub_hi.as<T>();
     tv.shm = t->sub_hmax.as<T>();
+    tv.sidx = nullptr;
+    if (t->act_on && t->grp_on) {
+        tv.nsub = t->grp_nsub.as<int32_t>();
+        tv.scnt = t->grp_cnt.as<int32_t>();
+        tv.sidx = t->grp_idx.as<int32_t>();
+        tv.slo = t->grp_lo.as<T>();
+        tv.shi = t->grp_hi.as<T>();
+        tv.shm = t->grp_hmax.as<T>();
+    }
     tv.rc = t->d_rc.as<double>();
     tv.eps = t->d_eps.as<double>();
     tv.n_gas = t->n_gas;
@@ -2504,7 +2541,8 @@ int energy_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                 const void *vy, const void *vz, const void *V, const void *rho,
                 const void *P, const void *cs, const void *A, const void *B,
                 const void *gA, const void *gB, const void *dv, double eta_c,
-                double eta_f, double dt, const void *const ag[3],
+                double eta_f, double dt, const int32_t *bins, int L,
+                int64_t substep, const void *const ag[3],
                 const void *const ah[3], void *dudt) {
     GatherExtra<T> ex;
     ex.dv = static_cast<const T *>(dv);
@@ -2513,6 +2551,9 @@ int energy_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
         ex.ah[a] = ah ? static_cast<const T *>(ah[a]) : nullptr;
     }
     ex.dt = dt;
+    ex.bins = bins;
+    ex.L = L;
+    ex.substep = substep;
     ex.w0 = dv ? HF_RECON : HF;
     CRK_TRY(hydro_fields<T>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB,
                             ex));
@@ -2675,15 +2716,17 @@ int pass_energy_compatible(crk_ctx *ctx, crk_tree *t, const void *m,
                            const void *cs, const void *A, const void *B,
                            const void *gradA, const void *gradB, const void *dv,
                            double eta_crit, double eta_fold, double dt,
+                           const int32_t *bins, int max_level, int64_t substep,
                            const void *const a_grav[3],
                            const void *const a_hydro[3], void *dudt) {
     if (ctx->precision == CRK_FP64)
         return energy_impl<double>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B,
                                    gradA, gradB, dv, eta_crit, eta_fold, dt,
-                                   a_grav, a_hydro, dudt);
+                                   bins, max_level, substep, a_grav, a_hydro,
+                                   dudt);
     return energy_impl<float>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gradA,
-                              gradB, dv, eta_crit, eta_fold, dt, a_grav,
-                              a_hydro, dudt);
+                              gradB, dv, eta_crit, eta_fold, dt, bins,
+                              max_level, substep, a_grav, a_hydro, dudt);
 }
 
 int pass_velocity_gradient(crk_ctx *ctx, crk_tree *t, const void *vx,

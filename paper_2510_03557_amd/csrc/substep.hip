@@ -7,6 +7,7 @@
 // Elementwise or per-leaf work, HBM/latency-bound.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 
 #include "crk_internal.h"
 
@@ -160,6 +161,59 @@ template <typename T> __device__ inline T wmin(T v, int width) {
 template <typename T> __device__ inline T wmax(T v, int width) {
     for (int off = width >> 1; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
     return v;
+}
+
+// Dense groups of the active particles: one wavefront per active leaf
+// (<= 64 slots, one per lane).  The active slots, in slot order (so the
+// groups follow the sub-leaf order of the k-d split), are cut into groups of
+// at most 16: group g of leaf I takes the active slots of ranks 16 g ..
+// 16 g + 15 into grp_idx[16 (4 I + g) ...], with their count, the bounding
+// box of their current positions and their largest h.
+template <typename T>
+__global__ __launch_bounds__(64) void act_groups_kernel(
+    const int32_t *__restrict__ items, int64_t n_items,
+    const int32_t *__restrict__ lstart, const int32_t *__restrict__ lcount,
+    const uint8_t *__restrict__ act, const T *__restrict__ px,
+    const T *__restrict__ py, const T *__restrict__ pz,
+    const T *__restrict__ h, int64_t lcap, int32_t *__restrict__ gnsub,
+    int32_t *__restrict__ gcnt, int32_t *__restrict__ gidx,
+    T *__restrict__ glo, T *__restrict__ ghi, T *__restrict__ ghm) {
+    const int64_t k = blockIdx.x;
+    if (k >= n_items) return;
+    const int I = items[k];
+    const int lane = threadIdx.x;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int st = lstart[I], cnt = min(lcount[I], 64);
+    const int s = st + lane;
+    const bool a = lane < cnt && act[s] != 0;
+    const uint64_t m = __ballot(a);
+    const int rank = __popcll(m & lt_mask);
+    const int nact = __popcll(m);
+    const int ng = (nact + 15) >> 4;
+    const int g = rank >> 4;
+    if (lane == 0) gnsub[I] = ng;
+    if (a) gidx[(4 * (int64_t)I + g) * 16 + (rank & 15)] = s;
+    const T big = std::numeric_limits<T>::max();
+    const int64_t sl = 4 * lcap;
+    for (int q = 0; q < ng; ++q) {
+        const bool in = a && g == q;
+        const T x = in ? px[s] : big, y = in ? py[s] : big, z = in ? pz[s] : big;
+        const T lx = wmin(x, 64), ly = wmin(y, 64), lz = wmin(z, 64);
+        const T hx = wmax(in ? x : -big, 64), hy = wmax(in ? y : -big, 64),
+                hz = wmax(in ? z : -big, 64);
+        const T hm = wmax(in ? h[s] : T(0), 64);
+        if (lane == 0) {
+            const int64_t slot = 4 * (int64_t)I + q;
+            gcnt[slot] = min(16, nact - 16 * q);
+            glo[slot] = lx;
+            glo[sl + slot] = ly;
+            glo[2 * sl + slot] = lz;
+            ghi[slot] = hx;
+            ghi[sl + slot] = hy;
+            ghi[2 * sl + slot] = hz;
+            ghm[slot] = hm;
+        }
+    }
 }
 
 // One wavefront per leaf (four per workgroup): grow the leaf box and its
@@ -346,6 +400,9 @@ int refit_impl(crk_ctx *ctx, crk_tree *t, const void *gx, const void *gy,
                const void *gz, const void *dx, const void *dy, const void *dz) {
     hipStream_t s = ctx->stream;
     const int64_t n = t->n;
+    // grown leaf boxes need new lists, moved particles new active groups
+    t->lists_built = false;
+    t->grp_on = false;
     hipLaunchKernelGGL((refit_pos_kernel<T>), dim3(grid_n(n)), dim3(256), 0, s,
                        n, t->n_gas, t->perm.as<int32_t>(), cp<T>(gx), cp<T>(gy),
                        cp<T>(gz), cp<T>(dx), cp<T>(dy), cp<T>(dz),
@@ -417,11 +474,35 @@ int timestep_bins(crk_ctx *ctx, int64_t n, double dt, int max_level, double eps,
                             a_hydro, h, cs, bins);
 }
 
+template <typename T> int act_groups(crk_ctx *ctx, crk_tree *t) {
+    const int64_t lcap = t->leaf_cap, sl = 4 * lcap;
+    CRK_TRY(t->grp_nsub.ensure((size_t)(lcap + 1) * 4, false));
+    CRK_TRY(t->grp_cnt.ensure((size_t)sl * 4, false));
+    CRK_TRY(t->grp_idx.ensure((size_t)sl * 16 * 4, false));
+    CRK_TRY(t->grp_lo.ensure((size_t)3 * sl * sizeof(T), false));
+    CRK_TRY(t->grp_hi.ensure((size_t)3 * sl * sizeof(T), false));
+    CRK_TRY(t->grp_hmax.ensure((size_t)sl * sizeof(T), false));
+    const int cur = t->cur_nodes;
+    hipLaunchKernelGGL((act_groups_kernel<T>), dim3((unsigned)t->act_nall),
+                       dim3(64), 0, ctx->stream, t->act_items.as<int32_t>(),
+                       t->act_nall, t->nd_start[cur].as<int32_t>(),
+                       t->nd_count[cur].as<int32_t>(), t->act_flags.as<uint8_t>(),
+                       t->pos[0].as<T>(), t->pos[1].as<T>(), t->pos[2].as<T>(),
+                       t->hsm.as<T>(), lcap, t->grp_nsub.as<int32_t>(),
+                       t->grp_cnt.as<int32_t>(), t->grp_idx.as<int32_t>(),
+                       t->grp_lo.as<T>(), t->grp_hi.as<T>(), t->grp_hmax.as<T>());
+    CRK_HIP(hipGetLastError());
+    return CRK_OK;
+}
+
 int tree_set_active(crk_ctx *ctx, crk_tree *t, const int32_t *bins_gas,
                     const int32_t *bins_dm, int max_level, int64_t substep) {
     hipStream_t s = ctx->stream;
     // lists belong to one subset: the next passes need a list build
     t->lists_built = false;
+    t->act_substep = substep < 0 ? -1 : substep;
+    t->act_level = max_level;
+    t->grp_on = false;
     if (substep < 0) {
         t->act_on = false;
         return CRK_OK;
@@ -460,6 +541,12 @@ int tree_set_active(crk_ctx *ctx, crk_tree *t, const int32_t *bins_gas,
     t->act_nall = hc[0];
     t->act_ngas = hc[1];
     t->act_on = true;
+    t->grp_on = false;
+    if (t->has_sub && ctx->tuning.act_groups && t->act_nall > 0) {
+        if (ctx->precision == CRK_FP64) CRK_TRY(act_groups<double>(ctx, t));
+        else CRK_TRY(act_groups<float>(ctx, t));
+        t->grp_on = true;
+    }
     return CRK_OK;
 }
 

@@ -21,7 +21,8 @@ class ShortRangeStep:
     gradient and the viscosity on the limited midpoint reconstruction
     (crk_velocity_gradient, then crk_hydro_forces_limited).  With
     ``compatible`` the integration's energy update takes the compatible rate
-    (crk_hydro_energy_compatible before crk_integrate; flat steps only)."""
+    (crk_hydro_energy_compatible before crk_integrate; in substep_cycle,
+    crk_hydro_energy_compatible_block at every kick)."""
 
     def __init__(self, wl, precision: str = "fp32", tuning: dict | None = None,
                  dt: float = 0.0, device: str = "cuda", params=None,
@@ -235,10 +236,11 @@ class ShortRangeStep:
         positions are wrapped at the end.  Bins come from set_bins or
         timestep_bins.  With pm_mesh (single box), the long-range mesh
         force brackets the interval: a half-kick of every particle before
-        the first substep and after the last one (positions wrapped)."""
-        if self.compatible:
-            raise ValueError("the compatible energy update is built for flat "
-                             "steps only")
+        the first substep and after the last one (positions wrapped).
+        With ``compatible`` every gas kick takes the compatible energy rate
+        (crk_hydro_energy_compatible_block): once for the opening half-kick
+        of the interval and once after each evaluation, for the closing
+        half-kick and the next opening one together."""
         c, t, wl = self.ctx, self.tree, self.wl
         L = int(max_level)
         if pm_mesh:
@@ -247,6 +249,7 @@ class ShortRangeStep:
                      self.gx, self.gy, self.gz, self.gh, self.dx, self.dy,
                      self.dz)
         self._passes()
+        self._compatible_block(dt, L, -1)
         delta = dt / 2 ** L
         for s in range(2 ** L):
             self._kick(dt, L, s, 0)
@@ -255,11 +258,22 @@ class ShortRangeStep:
                          self.dz)
             c.tree_set_active(t, self.bins_g, self.bins_d, L, s)
             self._passes()
+            self._compatible_block(dt, L, s)
             self._kick(dt, L, s, 1)
         c.tree_set_active(t, None, None, 0, -1)
         self._drift(0.0, True)
         if pm_mesh:
             self._long_kick(dt, pm_mesh)
+
+    def _compatible_block(self, dt, L, s):
+        if not (self.compatible and self.ng):
+            return
+        self.ctx.hydro_energy_compatible_block(
+            self.tree, self.gm, self.gvx, self.gvy, self.gvz, self.V,
+            self.rho, self.P, self.cs, self.A, self.B, self.gA, self.gB,
+            self.dv if self.recon else None, self.eta_crit, self.eta_fold,
+            dt, L, self.bins_g, s, (self.agx, self.agy, self.agz),
+            (self.ahx, self.ahy, self.ahz), self.dudt)
 
     def state(self) -> dict:
         """The double-precision state (numpy, (3, n) / n)."""

@@ -39,6 +39,9 @@ int main() {
         b = t;
         b.sub_sweep = 9;
         expect("tuning sub_sweep", crk_set_tuning(c, &b), E);
+        b = t;
+        b.act_groups = 2;
+        expect("tuning act_groups", crk_set_tuning(c, &b), E);
         expect("density null tree", crk_density(c, nullptr, nullptr, nullptr, nullptr), E);
         expect("graph launch without capture", crk_graph_launch(c), CRK_ESTATE);
         expect("ctx_destroy", crk_ctx_destroy(c), CRK_OK);
@@ -53,6 +56,14 @@ int main() {
     expect("lists", build_interaction_lists(nullptr, nullptr), E);
     expect("density", crk_density(nullptr, nullptr, nullptr, nullptr, nullptr), E);
     expect("density_noalloc", crk_density_noalloc(nullptr, nullptr, nullptr, nullptr, nullptr), E);
+    expect("energy_compatible", crk_hydro_energy_compatible(
+        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.8, 0.2, 0.01, nullptr,
+        nullptr, nullptr), E);
+    expect("energy_compatible_block", crk_hydro_energy_compatible_block(
+        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.8, 0.2, 0.01, 2, nullptr,
+        0, nullptr, nullptr, nullptr), E);
     expect("coefficients", crk_coefficients(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr), E);
     expect("hydro", crk_hydro_forces(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,

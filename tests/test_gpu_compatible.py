@@ -219,10 +219,14 @@ def test_compatible_argument_errors(step_cls):
                 c.hydro_energy_compatible(*base, dv, ec, ef, dt, a, None,
                                           st.dudt)
             assert e.value.status == CRK_EINVAL
-        with pytest.raises(ValueError):
-            st.compatible = True
-            st.substep_cycle(0.01, 1)
-        st.compatible = False
+        # the block form: bins required, dt > 0, substep in [-1, 2^L)
+        bins = torch.zeros(wl.gas.n, dtype=torch.int32, device="cuda")
+        for L, s, dt, b in ((1, 0, 1e-3, None), (1, -1, 0.0, bins),
+                            (1, 2, 1e-3, bins), (31, 0, 1e-3, bins)):
+            with pytest.raises(CrkError) as e:
+                c.hydro_energy_compatible_block(*base, None, 0.8, 0.2, dt, L,
+                                                b, s, ag, None, st.dudt)
+            assert e.value.status == CRK_EINVAL
         st.sync()
     finally:
         st.close()
