@@ -169,6 +169,7 @@ struct crk_tree {
     crk::DevBuf f_pos, f_scan;         // int32 per slot
     crk::DevBuf elem_node, elem_node2; // int32 per slot
     crk::DevBuf perm;                  // int32 caller index per slot
+    crk::DevBuf iperm;                 // int32 slot per caller index
     crk::DevBuf pos[3];                // T, tree-order positions
     crk::DevBuf hsm;                   // T, tree-order smoothing lengths (gas slots)
 

@@ -1446,7 +1446,6 @@ template <typename T> struct GatherExtra {
     const T *ag[3] = {nullptr, nullptr, nullptr};  // kick accelerations
     const T *ah[3] = {nullptr, nullptr, nullptr};
     double dt = 0.0;
-    int w0 = HF;                     // first plane of v1
     // block kicks: with bins (caller order), the kick width of each
     // particle follows its bin and the substep (kick_width); dt otherwise
     const int32_t *bins = nullptr;
@@ -2223,19 +2222,26 @@ __global__ void gather_mass_kernel(const int32_t *__restrict__ perm,
     }
 }
 
-template <typename T>
+// The hydro field records, one thread per gas particle in caller order: the
+// field planes are read with consecutive threads on consecutive particles
+// (coalesced), the record is assembled in registers and stored whole, in
+// 16-byte units, at the particle's slot iperm[c] (a record of S values per
+// slot; entries past the fields written are zero).
+template <typename T, int S>
 __global__ void hydro_gather_kernel(
-    const int32_t *__restrict__ perm, int64_t n, const T *__restrict__ h,
-    const T *__restrict__ m, const T *__restrict__ vx, const T *__restrict__ vy,
+    const int32_t *__restrict__ iperm, int64_t n, const T *__restrict__ h,
+    const T *__restrict__ vx, const T *__restrict__ vy,
     const T *__restrict__ vz, const T *__restrict__ V,
     const T *__restrict__ rho, const T *__restrict__ P,
     const T *__restrict__ cs, const T *__restrict__ A,
     const T *__restrict__ B, const T *__restrict__ gA,
-    const T *__restrict__ gB, const GatherExtra<T> ex, int S,
-    T *__restrict__ f, T *__restrict__ mt) {
-    GRID_STRIDE(p, n) {
-        T *r = f + (int64_t)p * S;  // this particle's record
-        const int c = perm[p];
+    const T *__restrict__ gB, const GatherExtra<T> ex, T *__restrict__ f) {
+    static_assert((S * sizeof(T)) % 16 == 0, "records of whole 16-byte units");
+    GRID_STRIDE(c, n) {
+        const int p = iperm[c];
+        T r[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) r[k] = T(0);
         const T hh = h[p];
         const T N = (T)(1.0 / (PI_D * (double)hh * (double)hh * (double)hh));
         const T a = A[c] * N;
@@ -2244,12 +2250,13 @@ __global__ void hydro_gather_kernel(
         r[2] = vz[c];
         r[3] = T(1) / (hh * hh);
         r[4] = a;
+#pragma unroll
         for (int g = 0; g < 3; ++g) {
-            r[(5 + g)] = gA[g * n + c] * N;
-            r[(8 + g)] = B[g * n + c];
-            r[(11 + g)] = a * B[g * n + c];
-            for (int x = 0; x < 3; ++x)
-                r[(14 + 3 * g + x)] = a * gB[(3 * g + x) * n + c];
+            r[5 + g] = gA[g * n + c] * N;
+            r[8 + g] = B[g * n + c];
+            r[11 + g] = a * B[g * n + c];
+#pragma unroll
+            for (int x = 0; x < 3; ++x) r[14 + 3 * g + x] = a * gB[(3 * g + x) * n + c];
         }
         r[23] = hh;
         r[24] = V[c];
@@ -2258,28 +2265,37 @@ __global__ void hydro_gather_kernel(
             r[25] = P[c];
             r[26] = rho[c];
             r[27] = cs[c];
-            mt[p] = m[c];
         }
-        if (ex.dv) {
-            const T *d = ex.dv + c;
-            r[(HF + 0)] = d[0];
-            r[(HF + 1)] = d[4 * n];
-            r[(HF + 2)] = d[8 * n];
-            r[(HF + 3)] = d[1 * n] + d[3 * n];
-            r[(HF + 4)] = d[2 * n] + d[6 * n];
-            r[(HF + 5)] = d[5 * n] + d[7 * n];
+        if constexpr (S >= HF_RECON) {
+            if (ex.dv) {
+                const T *d = ex.dv + c;
+                r[HF + 0] = d[0];
+                r[HF + 1] = d[4 * n];
+                r[HF + 2] = d[8 * n];
+                r[HF + 3] = d[1 * n] + d[3 * n];
+                r[HF + 4] = d[2 * n] + d[6 * n];
+                r[HF + 5] = d[5 * n] + d[7 * n];
+            }
         }
-        if (ex.ag[0]) {
+        // the kick's velocities: records of stride hydro_stride(HF + 3)
+        // (after the plain fields) or hydro_stride(HF_MAX) (after the
+        // reconstruction's)
+        if constexpr (S == hydro_stride(HF + 3) || S == hydro_stride(HF_MAX)) {
+            constexpr int W0 = S == hydro_stride(HF_MAX) ? HF_RECON : HF;
             const T *vv[3] = {vx, vy, vz};
             const double w =
                 ex.bins ? kick_width(ex.dt, ex.L, ex.substep, ex.bins[c]) : ex.dt;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                double acc = (double)ex.ag[a][c];
-                if (ex.ah[a]) acc += (double)ex.ah[a][c];
-                r[(ex.w0 + a)] = (T)((double)vv[a][c] + w * acc);
+            for (int q = 0; q < 3; ++q) {
+                double acc = (double)ex.ag[q][c];
+                if (ex.ah[q]) acc += (double)ex.ah[q][c];
+                r[W0 + q] = (T)((double)vv[q][c] + w * acc);
             }
         }
+        uint4 *dst = reinterpret_cast<uint4 *>(f + (int64_t)p * S);
+        const uint4 *src = reinterpret_cast<const uint4 *>(r);
+#pragma unroll
+        for (int k = 0; k < (int)(S * sizeof(T) / 16); ++k) dst[k] = src[k];
     }
 }
 
@@ -2489,19 +2505,48 @@ int hydro_fields(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
                             ctx->capturing));
     // the record stride of the fields this call writes (the passes read
     // records of the same stride: hydro_stride of their field count)
-    const int S = hydro_stride((P ? HF : HF) + (ex.dv ? 6 : 0) +
-                               (ex.ag[0] ? 3 : 0));
+    const int S = hydro_stride(HF + (ex.dv ? 6 : 0) + (ex.ag[0] ? 3 : 0));
     CRK_TRY(t->pf[4].ensure(n1 * sizeof(T), ctx->capturing));
-    hipLaunchKernelGGL((hydro_gather_kernel<T>), dim3(grid_for(ng)), dim3(256),
-                       0, ctx->stream, t->perm.as<int32_t>(), ng, t->hsm.as<T>(),
-                       static_cast<const T *>(m), static_cast<const T *>(vx),
-                       static_cast<const T *>(vy), static_cast<const T *>(vz),
-                       static_cast<const T *>(V), static_cast<const T *>(rho),
-                       static_cast<const T *>(P), static_cast<const T *>(cs),
-                       static_cast<const T *>(A), static_cast<const T *>(B),
-                       static_cast<const T *>(gA), static_cast<const T *>(gB),
-                       ex, S, t->pf[7].as<T>(), t->pf[4].as<T>());
+    const int32_t *ip = t->iperm.as<int32_t>();
+    const T *hs = t->hsm.as<T>();
+    const T *cvx = static_cast<const T *>(vx), *cvy = static_cast<const T *>(vy),
+            *cvz = static_cast<const T *>(vz), *cV = static_cast<const T *>(V),
+            *crho = static_cast<const T *>(rho), *cP = static_cast<const T *>(P),
+            *ccs = static_cast<const T *>(cs), *cA = static_cast<const T *>(A),
+            *cB = static_cast<const T *>(B), *cgA = static_cast<const T *>(gA),
+            *cgB = static_cast<const T *>(gB);
+    T *f = t->pf[7].as<T>();
+    const dim3 g(grid_for(ng)), b(256);
+    switch (S) {
+    case hydro_stride(HF):
+        hipLaunchKernelGGL((hydro_gather_kernel<T, hydro_stride(HF)>), g, b, 0,
+                           ctx->stream, ip, ng, hs, cvx, cvy, cvz, cV, crho, cP,
+                           ccs, cA, cB, cgA, cgB, ex, f);
+        break;
+    case hydro_stride(HF + 3):
+        hipLaunchKernelGGL((hydro_gather_kernel<T, hydro_stride(HF + 3)>), g, b,
+                           0, ctx->stream, ip, ng, hs, cvx, cvy, cvz, cV, crho,
+                           cP, ccs, cA, cB, cgA, cgB, ex, f);
+        break;
+    case hydro_stride(HF_RECON):
+        hipLaunchKernelGGL((hydro_gather_kernel<T, hydro_stride(HF_RECON)>), g, b,
+                           0, ctx->stream, ip, ng, hs, cvx, cvy, cvz, cV, crho,
+                           cP, ccs, cA, cB, cgA, cgB, ex, f);
+        break;
+    default:
+        hipLaunchKernelGGL((hydro_gather_kernel<T, hydro_stride(HF_MAX)>), g, b,
+                           0, ctx->stream, ip, ng, hs, cvx, cvy, cvz, cV, crho,
+                           cP, ccs, cA, cB, cgA, cgB, ex, f);
+        break;
+    }
     CRK_HIP(hipGetLastError());
+    // the masses in tree order (the force passes divide by them)
+    if (P) {
+        hipLaunchKernelGGL((gather1_kernel<T>), g, b, 0, ctx->stream,
+                           t->perm.as<int32_t>(), static_cast<const T *>(m), ng,
+                           t->pf[4].as<T>());
+        CRK_HIP(hipGetLastError());
+    }
     return CRK_OK;
 }
 
@@ -2554,7 +2599,6 @@ int energy_impl(crk_ctx *ctx, crk_tree *t, const void *m, const void *vx,
     ex.bins = bins;
     ex.L = L;
     ex.substep = substep;
-    ex.w0 = dv ? HF_RECON : HF;
     CRK_TRY(hydro_fields<T>(ctx, t, m, vx, vy, vz, V, rho, P, cs, A, B, gA, gB,
                             ex));
     const int64_t ng = t->n_gas;

@@ -164,20 +164,25 @@ template <typename T> __device__ inline T wmax(T v, int width) {
 }
 
 // Dense groups of the active particles: one wavefront per active leaf
-// (<= 64 slots, one per lane).  The active slots, in slot order (so the
-// groups follow the sub-leaf order of the k-d split), are cut into groups of
-// at most 16: group g of leaf I takes the active slots of ranks 16 g ..
-// 16 g + 15 into grp_idx[16 (4 I + g) ...], with their count, the bounding
-// box of their current positions and their largest h.
+// (<= 64 slots, one per lane).  The active particles of a leaf's sub-leaves
+// (k-d siblings 0, 1 and 2, 3) are merged where they fit one group of 16:
+// all of them when the leaf holds at most 16, else each sibling pair whose
+// actives fit, else each sub-leaf's own.  A group g of leaf I lists its
+// active slots in slot order at grp_idx[16 (4 I + g) ...], with their count,
+// the bounding box of their current positions and their largest h, so the
+// sweeps take only active i-particles, culled against a box no larger than
+// their sub-leaf's.
 template <typename T>
 __global__ __launch_bounds__(64) void act_groups_kernel(
     const int32_t *__restrict__ items, int64_t n_items,
     const int32_t *__restrict__ lstart, const int32_t *__restrict__ lcount,
-    const uint8_t *__restrict__ act, const T *__restrict__ px,
-    const T *__restrict__ py, const T *__restrict__ pz,
-    const T *__restrict__ h, int64_t lcap, int32_t *__restrict__ gnsub,
-    int32_t *__restrict__ gcnt, int32_t *__restrict__ gidx,
-    T *__restrict__ glo, T *__restrict__ ghi, T *__restrict__ ghm) {
+    const int32_t *__restrict__ nsub, const int32_t *__restrict__ sst,
+    const int32_t *__restrict__ scnt, const uint8_t *__restrict__ act,
+    const T *__restrict__ px, const T *__restrict__ py,
+    const T *__restrict__ pz, const T *__restrict__ h, int64_t lcap,
+    int32_t *__restrict__ gnsub, int32_t *__restrict__ gcnt,
+    int32_t *__restrict__ gidx, T *__restrict__ glo, T *__restrict__ ghi,
+    T *__restrict__ ghm) {
     const int64_t k = blockIdx.x;
     if (k >= n_items) return;
     const int I = items[k];
@@ -187,16 +192,60 @@ __global__ __launch_bounds__(64) void act_groups_kernel(
     const int s = st + lane;
     const bool a = lane < cnt && act[s] != 0;
     const uint64_t m = __ballot(a);
-    const int rank = __popcll(m & lt_mask);
-    const int nact = __popcll(m);
-    const int ng = (nact + 15) >> 4;
-    const int g = rank >> 4;
+    // lanes of each sub-leaf (contiguous slot ranges) and their actives
+    const int ns = min(nsub[I], 4);
+    auto lanes_of = [&](int q) -> uint64_t {
+        if (q >= ns) return 0ull;
+        const int lo = sst[4 * (int64_t)I + q] - st;
+        const int c = scnt[4 * (int64_t)I + q];
+        return (c >= 64 ? ~0ull : ((1ull << c) - 1)) << lo;
+    };
+    const uint64_t s0 = lanes_of(0), s1 = lanes_of(1), s2 = lanes_of(2),
+                   s3 = lanes_of(3);
+    const int n0 = __popcll(m & s0), n1 = __popcll(m & s1),
+              n2 = __popcll(m & s2), n3 = __popcll(m & s3);
+    // groups as unions of consecutive sub-leaves (wave-uniform lane masks);
+    // empty ones are dropped below
+    uint64_t c0, c1, c2, c3;
+    if (n0 + n1 + n2 + n3 <= 16) {
+        c0 = s0 | s1 | s2 | s3;
+        c1 = c2 = c3 = 0;
+    } else {
+        const bool p01 = n0 + n1 <= 16, p23 = n2 + n3 <= 16;
+        c0 = p01 ? (s0 | s1) : s0;
+        c1 = p01 ? 0 : s1;
+        c2 = p23 ? (s2 | s3) : s2;
+        c3 = p23 ? 0 : s3;
+    }
+    c0 &= (m & c0) ? ~0ull : 0ull;
+    c1 &= (m & c1) ? ~0ull : 0ull;
+    c2 &= (m & c2) ? ~0ull : 0ull;
+    c3 &= (m & c3) ? ~0ull : 0ull;
+    const int ng = (c0 != 0) + (c1 != 0) + (c2 != 0) + (c3 != 0);
+    // group q is the q-th non-empty candidate
+    auto gmask = [&](int q) -> uint64_t {
+        int seen = 0;
+        if (c0) { if (seen == q) return c0; ++seen; }
+        if (c1) { if (seen == q) return c1; ++seen; }
+        if (c2) { if (seen == q) return c2; ++seen; }
+        if (c3 && seen == q) return c3;
+        return 0ull;
+    };
     if (lane == 0) gnsub[I] = ng;
-    if (a) gidx[(4 * (int64_t)I + g) * 16 + (rank & 15)] = s;
+    int g = 0;
+    for (int q = 1; q < 4; ++q)
+        if ((gmask(q) >> lane) & 1ull) g = q;
+    if (a) {
+        // < 16 by construction (sub-leaves hold <= 16); the bound keeps every
+        // write inside the group's 16 entries regardless
+        const int rank = __popcll(m & gmask(g) & lt_mask);
+        if (rank < 16) gidx[(4 * (int64_t)I + g) * 16 + rank] = s;
+    }
     const T big = std::numeric_limits<T>::max();
     const int64_t sl = 4 * lcap;
     for (int q = 0; q < ng; ++q) {
-        const bool in = a && g == q;
+        const uint64_t gq = gmask(q);
+        const bool in = a && ((gq >> lane) & 1ull);
         const T x = in ? px[s] : big, y = in ? py[s] : big, z = in ? pz[s] : big;
         const T lx = wmin(x, 64), ly = wmin(y, 64), lz = wmin(z, 64);
         const T hx = wmax(in ? x : -big, 64), hy = wmax(in ? y : -big, 64),
@@ -204,7 +253,7 @@ __global__ __launch_bounds__(64) void act_groups_kernel(
         const T hm = wmax(in ? h[s] : T(0), 64);
         if (lane == 0) {
             const int64_t slot = 4 * (int64_t)I + q;
-            gcnt[slot] = min(16, nact - 16 * q);
+            gcnt[slot] = __popcll(m & gq);
             glo[slot] = lx;
             glo[sl + slot] = ly;
             glo[2 * sl + slot] = lz;
@@ -486,7 +535,9 @@ template <typename T> int act_groups(crk_ctx *ctx, crk_tree *t) {
     hipLaunchKernelGGL((act_groups_kernel<T>), dim3((unsigned)t->act_nall),
                        dim3(64), 0, ctx->stream, t->act_items.as<int32_t>(),
                        t->act_nall, t->nd_start[cur].as<int32_t>(),
-                       t->nd_count[cur].as<int32_t>(), t->act_flags.as<uint8_t>(),
+                       t->nd_count[cur].as<int32_t>(), t->sub_nsub.as<int32_t>(),
+                       t->sub_start.as<int32_t>(), t->sub_count.as<int32_t>(),
+                       t->act_flags.as<uint8_t>(),
                        t->pos[0].as<T>(), t->pos[1].as<T>(), t->pos[2].as<T>(),
                        t->hsm.as<T>(), lcap, t->grp_nsub.as<int32_t>(),
                        t->grp_cnt.as<int32_t>(), t->grp_idx.as<int32_t>(),

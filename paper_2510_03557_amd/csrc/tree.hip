@@ -20,6 +20,7 @@
 // Positions and h are copied to tree order; S_0 gives the tree permutation.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 
 #include "crk_internal.h"
 
@@ -333,6 +334,12 @@ __global__ void bound_clamp_kernel(int32_t *__restrict__ nn, int64_t bound,
 __global__ void bound_check_kernel(const int32_t *__restrict__ nn,
                                    int64_t bound, int *__restrict__ err) {
     if (*nn > bound) atomicOr(err, DEV_ERR_CAPACITY);
+}
+
+// slot of every caller index (the inverse of perm)
+__global__ void iperm_kernel(const int32_t *__restrict__ perm, int64_t n,
+                             int32_t *__restrict__ iperm) {
+    GRID_STRIDE(p, n) iperm[perm[p]] = (int32_t)p;
 }
 
 template <typename T>
@@ -672,8 +679,9 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
     const int32_t *__restrict__ seg_count, const int32_t *__restrict__ seg_key,
     const int32_t *__restrict__ leaf_off, const int32_t *__restrict__ V,
     const T *__restrict__ px, const T *__restrict__ py,
-    const T *__restrict__ pz, int L, int SEG, int64_t lcap, int sub,
-    int32_t *__restrict__ S0g, int32_t *__restrict__ lf_start,
+    const T *__restrict__ pz, int L, int SEG, int cmin, int cmax,
+    int64_t lcap, int sub, int32_t *__restrict__ S0g,
+    int32_t *__restrict__ lf_start,
     int32_t *__restrict__ lf_count, int32_t *__restrict__ lf_key,
     int32_t *__restrict__ sub_n, int32_t *__restrict__ sub_st,
     int32_t *__restrict__ sub_c, int *__restrict__ err) {
@@ -682,6 +690,8 @@ __global__ __launch_bounds__(SEG_TB) void seg_build_kernel(
     if (sg >= *nn_ptr) return;
     const int t = threadIdx.x;
     const int s0 = seg_start[sg], cnt = seg_count[sg], key = seg_key[sg];
+    // this launch builds the segments of one size class, cmin < cnt <= cmax
+    if (cnt <= cmin || cnt > cmax) return;
     const int loff = leaf_off[sg];
     const int nlv = seg_leaves(cnt, L);
     if ((int64_t)loff + nlv > lcap || cnt > SEG) {
@@ -1113,6 +1123,7 @@ int ensure_all(crk_tree *t, int64_t n, int64_t leaf_cap, size_t elem,
     CRK_TRY(t->elem_node.ensure(n1 * 4, cap));
     CRK_TRY(t->elem_node2.ensure(n1 * 4, cap));
     CRK_TRY(t->perm.ensure(n1 * 4, cap));
+    CRK_TRY(t->iperm.ensure(n1 * 4, cap));
     // caller-order combined positions and h live in pass-field slots 0..3
     for (int a = 0; a < 4; ++a) CRK_TRY(t->pf[a].ensure(n1 * elem, cap));
     for (int i = 0; i < 2; ++i) {
@@ -1234,23 +1245,36 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
             t->lds_tree = use_lds;
         }
         if (use_lds) {
-            // 3. sorts and k-d levels of every segment in LDS
+            // 3. sorts and k-d levels of every segment in LDS, one launch per
+            //    size class (padded sizes 128, 256, ... up to the largest):
+            //    a segment is sorted at the padded size of its class, with
+            //    that class's LDS, instead of at the size of the largest
+            //    segment (the same leaves either way: the keys are distinct)
             const int SEG = t->seg_size;
-            hipLaunchKernelGGL((seg_build_kernel<T>),
-                               dim3((unsigned)std::max<int64_t>(1, seg_cap)),
-                               dim3(SEG_TB), seg_lds_bytes(SEG), s, cnt + C_NN,
-                               t->nd_start[0].as<int32_t>(),
-                               t->nd_count[0].as<int32_t>(),
-                               t->nd_key[0].as<int32_t>(),
-                               t->nd_child.as<int32_t>(), Vv[r], px, py, pz, L,
-                               SEG, lcap, t->has_sub ? 1 : 0, S[0],
-                               t->nd_start[1].as<int32_t>(),
-                               t->nd_count[1].as<int32_t>(),
-                               t->nd_key[1].as<int32_t>(),
-                               t->sub_nsub.as<int32_t>(),
-                               t->sub_start.as<int32_t>(),
-                               t->sub_count.as<int32_t>(), err);
-            CRK_HIP(hipGetLastError());
+            int cmin = 0;
+            for (int c = 128;; c <<= 1) {
+                const bool last = c >= SEG;
+                const int seg_c = last ? SEG : c;
+                hipLaunchKernelGGL((seg_build_kernel<T>),
+                                   dim3((unsigned)std::max<int64_t>(1, seg_cap)),
+                                   dim3(SEG_TB), seg_lds_bytes(seg_c), s,
+                                   cnt + C_NN, t->nd_start[0].as<int32_t>(),
+                                   t->nd_count[0].as<int32_t>(),
+                                   t->nd_key[0].as<int32_t>(),
+                                   t->nd_child.as<int32_t>(), Vv[r], px, py, pz,
+                                   L, seg_c, cmin,
+                                   last ? std::numeric_limits<int>::max() : c,
+                                   lcap, t->has_sub ? 1 : 0, S[0],
+                                   t->nd_start[1].as<int32_t>(),
+                                   t->nd_count[1].as<int32_t>(),
+                                   t->nd_key[1].as<int32_t>(),
+                                   t->sub_nsub.as<int32_t>(),
+                                   t->sub_start.as<int32_t>(),
+                                   t->sub_count.as<int32_t>(), err);
+                CRK_HIP(hipGetLastError());
+                if (last) break;
+                cmin = c;
+            }
             sub_done = t->has_sub;
             hipLaunchKernelGGL(next_count_kernel, dim3(1), dim3(1), 0, s,
                                cnt + C_NN_NEXT, lcap, cnt + C_NN, err);
@@ -1425,6 +1449,9 @@ int build_impl(crk_ctx *ctx, crk_tree *t, const void *gx_, const void *gy_,
                            t->sub_hi.as<T>(), t->sub_hmax.as<T>());
         CRK_HIP(hipGetLastError());
     }
+    hipLaunchKernelGGL(iperm_kernel, dim3(grid_for(n)), dim3(TB), 0, s,
+                       t->perm.as<int32_t>(), n, t->iperm.as<int32_t>());
+    CRK_HIP(hipGetLastError());
     int32_t *gas_nl = t->bin_leaf.as<int32_t>() + t->total_bins;
     if (!cap) {
         // gas leaves for the host
