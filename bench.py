@@ -91,7 +91,12 @@ def measured_traffic(pass_name: str, kname: str, workload: str):
         return None
     with open(path) as f:
         d = json.load(f)
-    if (d.get("source_hash") != source_hash() or d.get("kernel_name") != kname
+    def bare(name):  # the trace may or may not print the return type
+        name = (name or "").strip()
+        return name[5:] if name.startswith("void ") else name
+
+    if (d.get("source_hash") != source_hash()
+            or bare(d.get("kernel_name")) != bare(kname)
             or d.get("workload") != workload):
         return None
     return d.get("hbm_bytes_per_launch")
