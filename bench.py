@@ -122,7 +122,9 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
     (at most max_levels) whose deepest step resolves the smallest tau_i;
     bins from crk_timestep_bins.  Then timed block kick-drift-kick cycles
     (tree built once per cycle, refitted every substep, passes over the
-    active leaves only)."""
+    active leaves only), each from the same starting state; the same cycle
+    with the other grouping of the active particles and with the
+    compatible energy update are timed after it."""
     import numpy as np
     import torch
     from paper_2510_03557_amd import binding
@@ -149,6 +151,28 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
                                     + wl.dm.vy.astype(np.float64) ** 2
                                     + wl.dm.vz.astype(np.float64) ** 2))))
     dt = min(4.0 * tmed, 0.25 * float(wl.r_c[0]) / max(vmax, 1e-30))
+    def timed_cycles(s):
+        """Every timed cycle starts from the state the step was made with
+        (restored outside the timed region), so each one does the same work
+        and none drifts further than the first."""
+        snap = s.snapshot()
+        s.substep_cycle(dt, levels)  # warm-up (sizes)
+        s.sync()
+        s.ctx.timing(True)
+        sec = 0.0
+        for _ in range(cycles):
+            s.restore(snap)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.substep_cycle(dt, levels)
+            torch.cuda.synchronize()
+            s.ctx.stream.synchronize()
+            sec += time.perf_counter() - t0
+        pm, _, _ = s.ctx.pass_times()
+        s.ctx.timing(False)
+        s.sync()
+        return sec / cycles, pm
+
     # where the chaining-mesh bins leave less margin than that, the refit
     # reports CRK_ESTALE: the interval is then halved (fresh state)
     for attempt in range(4):
@@ -159,8 +183,7 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
             f"{np.bincount(bg, minlength=levels + 1).tolist()} dm "
             f"{np.bincount(bd, minlength=levels + 1).tolist()}")
         try:
-            st.substep_cycle(dt, levels)  # warm-up (sizes)
-            st.sync()
+            sec, pass_ms = timed_cycles(st)
             break
         except binding.CrkError as e:
             if e.status != binding.CRK_ESTALE or attempt == 3:
@@ -172,13 +195,6 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
             dt *= 0.5
     steps = int(np.sum(2 ** bg.astype(np.int64)) + np.sum(2 ** bd.astype(np.int64)))
     n = wl.n_total
-    st.ctx.timing(True)
-    sec = time_steps(lambda: st.substep_cycle(dt, levels),
-                     lambda: (torch.cuda.synchronize(),
-                              st.ctx.stream.synchronize()), cycles, 0)
-    pass_ms, _, _ = st.ctx.pass_times()
-    st.ctx.timing(False)
-    st.sync()
     st.close()
 
     def variant(label, tuning_change=None, **kw):
@@ -188,15 +204,7 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
                            tuning=dict(tuning, **(tuning_change or {})), **kw)
         v.run()
         v.set_bins(bg, bd)
-        v.substep_cycle(dt, levels)  # warm-up
-        v.sync()
-        v.ctx.timing(True)
-        s2 = time_steps(lambda: v.substep_cycle(dt, levels),
-                        lambda: (torch.cuda.synchronize(),
-                                 v.ctx.stream.synchronize()), cycles, 0)
-        pm, _, _ = v.ctx.pass_times()
-        v.ctx.timing(False)
-        v.sync()
+        s2, pm = timed_cycles(v)
         v.close()
         return {"ms_per_cycle": s2 * 1e3,
                 "pass_ms_per_cycle": {k: round(x / cycles, 3)

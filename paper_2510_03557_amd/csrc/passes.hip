@@ -598,18 +598,16 @@ __device__ __forceinline__ void stage_subleaf(const TreeView<T> &tv,
         const T clx = slx - T(sx), chx = shx - T(sx);
         const T cly = sly - T(sy), chy = shy - T(sy);
         const T clz = slz - T(sz), chz = shz - T(sz);
-        bool keep = false;
-        T d2 = T(0);
+        // every lane computes the distance (lanes past jc hold stale or zero
+        // coordinates: arithmetic only, no access), the lane mask decides
         const int j = js + lane;
-        if (lane < jc) {
-            const T dx = fmax(fmax(clx - x, x - chx), T(0));
-            const T dy = fmax(fmax(cly - y, y - chy), T(0));
-            const T dz = fmax(fmax(clz - z, z - chz), T(0));
-            d2 = dx * dx + dy * dy + dz * dz;
-            keep = d2 < R2;
-        }
+        const T dx = fmax(fmax(clx - x, x - chx), T(0));
+        const T dy = fmax(fmax(cly - y, y - chy), T(0));
+        const T dz = fmax(fmax(clz - z, z - chz), T(0));
+        const T d2 = dx * dx + dy * dy + dz * dz;
+        const bool keep = (lane < jc) & (d2 < R2);
         if constexpr (P::FARNEAR) {
-            const bool far = keep && d2 >= Rf2;
+            const bool far = keep & (d2 >= Rf2);
             const uint64_t mf = __ballot(far), mn = __ballot(keep && !far);
             if (keep) {
                 const T fx = (x - rx) + T(sx), fy = (y - ry) + T(sy),

@@ -275,6 +275,24 @@ class ShortRangeStep:
             dt, L, self.bins_g, s, (self.agx, self.agy, self.agz),
             (self.ahx, self.ahy, self.ahz), self.dudt)
 
+    _STATE = ("gx64", "gv64", "gu64", "dx64", "dv64", "gx", "gy", "gz",
+              "gvx", "gvy", "gvz", "gu", "dx", "dy", "dz", "dvx", "dvy", "dvz")
+
+    def snapshot(self) -> dict:
+        """Device copies of the state a cycle or an integration changes
+        (positions, velocities, energies and their working copies)."""
+        with self.torch.cuda.stream(self.ctx.stream):
+            snap = {k: getattr(self, k).clone() for k in self._STATE}
+        self.ctx.stream.synchronize()
+        return snap
+
+    def restore(self, snap: dict):
+        """Puts back a snapshot's state (device to device)."""
+        with self.torch.cuda.stream(self.ctx.stream):
+            for k, t in snap.items():
+                getattr(self, k).copy_(t)
+        self.ctx.stream.synchronize()
+
     def state(self) -> dict:
         """The double-precision state (numpy, (3, n) / n)."""
         self.ctx.sync()

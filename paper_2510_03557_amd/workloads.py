@@ -532,5 +532,14 @@ CONFIGS = {
 }
 
 
+# smaller sets of the same kinds, for measurements that need many steps
+# (hierarchical cycles on clustered matter)
+EXTRA = {
+    "plummer4M": lambda: plummer_spheres(2 ** 22, seed=6),
+}
+
+
 def make(name: str) -> Workload:
+    if name in EXTRA:
+        return EXTRA[name]()
     return CONFIGS[name]()
