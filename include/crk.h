@@ -129,14 +129,12 @@ typedef struct {
                            (capped per pass at 64 KiB); 0: the pass's own
                            width (default); 1, 2, 4 or 8                    */
     int32_t act_groups; /* with an active subset (crk_tree_set_active) and
-                           sub-leaves: 1, the sub-leaf sweeps take groups of
-                           the active particles only, boxed at their current
-                           positions: a leaf's actives as one group when they
-                           are <= 16, else sibling sub-leaves merged where
-                           their actives fit 16, else one group per sub-leaf
-                           (default); 0, the tree's sub-leaves with their
-                           grown boxes, skipping those without an active
-                           particle                                          */
+                           sub-leaves: 1, the sub-leaf sweeps take, for each
+                           sub-leaf holding an active particle, its active
+                           particles only, boxed at their current positions
+                           (default); 0, the tree's sub-leaves with all
+                           their particles and their grown boxes, skipping
+                           those without an active particle                  */
 } crk_tuning;
 
 /* ------------------------------------------------------------------------ */
@@ -413,9 +411,9 @@ int crk_timestep_bins(crk_ctx *ctx, int64_t n, double dt, int32_t max_level,
  * The lists must be rebuilt after every call (build_interaction_lists then
  * lists the active leaves only; the passes report CRK_ESTATE until then).
  * With tuning act_groups and sub-leaves, the call also gathers the active
- * particles of every active leaf into groups of <= 16 (see crk_tuning),
- * boxed at the tree's current positions, which the sub-leaf sweeps then
- * take as their i-sets.  Synchronises (reads the active leaf counts back). */
+ * particles of every sub-leaf into a group (see crk_tuning), boxed at the
+ * tree's current positions, which the sub-leaf sweeps then take as their
+ * i-sets.  Synchronises (reads the active leaf counts back). */
 int crk_tree_set_active(crk_ctx *ctx, crk_tree *tree, const int32_t *bins_gas,
                         const int32_t *bins_dm, int32_t max_level,
                         int64_t substep);

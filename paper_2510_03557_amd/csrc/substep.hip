@@ -163,15 +163,15 @@ template <typename T> __device__ inline T wmax(T v, int width) {
     return v;
 }
 
-// Dense groups of the active particles: one wavefront per active leaf
-// (<= 64 slots, one per lane).  The active particles of a leaf's sub-leaves
-// (k-d siblings 0, 1 and 2, 3) are merged where they fit one group of 16:
-// all of them when the leaf holds at most 16, else each sibling pair whose
-// actives fit, else each sub-leaf's own.  A group g of leaf I lists its
-// active slots in slot order at grp_idx[16 (4 I + g) ...], with their count,
-// the bounding box of their current positions and their largest h, so the
-// sweeps take only active i-particles, culled against a box no larger than
-// their sub-leaf's.
+// Groups of the active particles: one wavefront per active leaf (<= 64
+// slots, one per lane).  Group g of leaf I holds the active particles of
+// one of its sub-leaves, in slot order (sub-leaves without an active
+// particle make no group), at grp_idx[16 (4 I + g) ...], with their count,
+// the bounding box of their current positions and their largest h: the
+// sweeps take only active i-particles, culled against a box no larger
+// than their sub-leaf's.  (Merging sibling sub-leaves whose actives fit one
+// group of 16 gives fewer, larger groups and measured slower: their boxes
+// take in many more candidates.)
 template <typename T>
 __global__ __launch_bounds__(64) void act_groups_kernel(
     const int32_t *__restrict__ items, int64_t n_items,
@@ -202,25 +202,9 @@ __global__ __launch_bounds__(64) void act_groups_kernel(
     };
     const uint64_t s0 = lanes_of(0), s1 = lanes_of(1), s2 = lanes_of(2),
                    s3 = lanes_of(3);
-    const int n0 = __popcll(m & s0), n1 = __popcll(m & s1),
-              n2 = __popcll(m & s2), n3 = __popcll(m & s3);
-    // groups as unions of consecutive sub-leaves (wave-uniform lane masks);
-    // empty ones are dropped below
-    uint64_t c0, c1, c2, c3;
-    if (n0 + n1 + n2 + n3 <= 16) {
-        c0 = s0 | s1 | s2 | s3;
-        c1 = c2 = c3 = 0;
-    } else {
-        const bool p01 = n0 + n1 <= 16, p23 = n2 + n3 <= 16;
-        c0 = p01 ? (s0 | s1) : s0;
-        c1 = p01 ? 0 : s1;
-        c2 = p23 ? (s2 | s3) : s2;
-        c3 = p23 ? 0 : s3;
-    }
-    c0 &= (m & c0) ? ~0ull : 0ull;
-    c1 &= (m & c1) ? ~0ull : 0ull;
-    c2 &= (m & c2) ? ~0ull : 0ull;
-    c3 &= (m & c3) ? ~0ull : 0ull;
+    // one group per sub-leaf holding an active particle
+    const uint64_t c0 = (m & s0) ? s0 : 0ull, c1 = (m & s1) ? s1 : 0ull,
+                   c2 = (m & s2) ? s2 : 0ull, c3 = (m & s3) ? s3 : 0ull;
     const int ng = (c0 != 0) + (c1 != 0) + (c2 != 0) + (c3 != 0);
     // group q is the q-th non-empty candidate
     auto gmask = [&](int q) -> uint64_t {
