@@ -195,6 +195,7 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
             dt *= 0.5
     steps = int(np.sum(2 ** bg.astype(np.int64)) + np.sum(2 ** bd.astype(np.int64)))
     n = wl.n_total
+    subsets = list(st.cycle_subsets)
     st.close()
 
     def variant(label, tuning_change=None, **kw):
@@ -211,9 +212,13 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
                                       for k, x in pm.items()}}
 
     groups = int(tuning.get("act_groups", 1))
-    other = variant("active particles on the tree's sub-leaves" if groups
-                    else "dense active groups",
-                    {"act_groups": 0 if groups else 1})
+    # the two fixed choices beside the default threshold
+    others = {}
+    for k, label in ((1, "active groups at every substep"),
+                     (0, "active particles on the tree's sub-leaves")):
+        if k != groups:
+            others[f"act_groups_{k}"] = variant(label, {"act_groups": k})
+    per_leaf = [p / max(lv, 1) for lv, p, _ in subsets]
     comp = variant("compatible energy update in every kick", compatible=True)
     flat = (2 ** levels) * ms_per_step if ms_per_step else None
     return {"levels": levels, "substeps": 2 ** levels, "dt": dt,
@@ -229,7 +234,11 @@ def measure_cycle(wl, tuning, max_levels, cycles, ms_per_step, log):
             "flat_deepest_ms": flat,
             "speedup_vs_flat": (flat / (sec * 1e3)) if flat else None,
             "act_groups": groups,
-            ("sub_leaves" if groups else "dense_groups"): other,
+            "grouped_substeps": int(sum(g for _, _, g in subsets)),
+            "active_per_leaf": ([round(float(q), 2) for q in
+                                 np.percentile(per_leaf, [0, 50, 100])]
+                                if per_leaf else None),
+            **others,
             "compatible_energy": comp,
             "launch": "eager"}
 

@@ -129,12 +129,18 @@ typedef struct {
                            (capped per pass at 64 KiB); 0: the pass's own
                            width (default); 1, 2, 4 or 8                    */
     int32_t act_groups; /* with an active subset (crk_tree_set_active) and
-                           sub-leaves: 1, the sub-leaf sweeps take, for each
-                           sub-leaf holding an active particle, its active
-                           particles only, boxed at their current positions
-                           (default); 0, the tree's sub-leaves with all
-                           their particles and their grown boxes, skipping
-                           those without an active particle                  */
+                           sub-leaves, k > 0: when the active leaves hold on
+                           average at least k active particles each, the
+                           sub-leaf sweeps take, for each sub-leaf holding
+                           an active particle, its active particles only,
+                           boxed at their current positions (an active
+                           group); otherwise, and with k = 0, the tree's
+                           sub-leaves with all their particles and their
+                           grown boxes, skipping those without an active
+                           particle.  In [0, 4096]; default 1, groups
+                           for every subset (with the sub-leaf sweep of one
+                           wavefront per listed sub-leaf they measured
+                           faster at every activity tried)                   */
 } crk_tuning;
 
 /* ------------------------------------------------------------------------ */
@@ -501,6 +507,11 @@ typedef struct {
     int64_t n_bins;                 /* chaining-mesh bins over all boxes     */
     int64_t grav_entries, hydro_entries; /* list lengths (leaf pairs)        */
     int32_t kd_levels;              /* k-d levels run                        */
+    /* the subset of the last crk_tree_set_active (0 after build_tree and
+     * for substep < 0): its leaves and particles, and 1 when the sub-leaf
+     * sweeps take active groups (tuning act_groups) */
+    int64_t act_leaves, act_particles;
+    int32_t act_grouped;
 } crk_tree_info;
 int crk_tree_get_info(const crk_tree *tree, crk_tree_info *info);
 

@@ -73,7 +73,9 @@ class crk_tree_info(ctypes.Structure):
     _fields_ = [("n_gas", ctypes.c_int64), ("n_dm", ctypes.c_int64),
                 ("n_leaves", ctypes.c_int64), ("n_gas_leaves", ctypes.c_int64),
                 ("n_bins", ctypes.c_int64), ("grav_entries", ctypes.c_int64),
-                ("hydro_entries", ctypes.c_int64), ("kd_levels", ctypes.c_int32)]
+                ("hydro_entries", ctypes.c_int64), ("kd_levels", ctypes.c_int32),
+                ("act_leaves", ctypes.c_int64), ("act_particles", ctypes.c_int64),
+                ("act_grouped", ctypes.c_int32)]
 
 
 _lib = None

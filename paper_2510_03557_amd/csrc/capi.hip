@@ -303,8 +303,8 @@ int crk_set_tuning(crk_ctx *ctx, const crk_tuning *t) {
     if (!(t->tile == 0 || t->tile == 1 || t->tile == 2 || t->tile == 4 ||
           t->tile == 8))
         return set_error(CRK_EINVAL, "tile must be 0, 1, 2, 4 or 8");
-    if (t->act_groups != 0 && t->act_groups != 1)
-        return set_error(CRK_EINVAL, "act_groups must be 0 or 1");
+    if (t->act_groups < 0 || t->act_groups > 4096)
+        return set_error(CRK_EINVAL, "act_groups must be in [0, 4096]");
     if (ctx->capturing) return set_error(CRK_ESTATE, "tuning change during capture");
     ctx->tuning = *t;
     return CRK_OK;
@@ -392,6 +392,7 @@ int build_tree(crk_ctx *ctx, const crk_boxes *boxes, const void *gx,
     PassSpan sp(ctx, P_TREE);
     t->act_on = false;  // a new tree starts with every leaf active
     t->grp_on = false;
+    t->slist_on = false;
     return tree_build(ctx, t, boxes, gx, gy, gz, gh, dx, dy, dz);
 }
 
@@ -855,6 +856,9 @@ int crk_tree_get_info(const crk_tree *t, crk_tree_info *info) {
     info->grav_entries = t->grav_entries;
     info->hydro_entries = t->hydro_entries;
     info->kd_levels = t->kd_levels;
+    info->act_leaves = t->act_on ? t->act_nall : 0;
+    info->act_particles = t->act_on ? t->act_npart : 0;
+    info->act_grouped = t->act_on && t->grp_on ? 1 : 0;
     return CRK_OK;
 }
 

@@ -220,8 +220,17 @@ struct crk_tree {
     crk::DevBuf act_flags;             // uint8 per slot
     crk::DevBuf act_leaf;              // int32 per leaf (flag, then scan)
     crk::DevBuf act_items;             // int32 per active leaf
-    crk::DevBuf act_count;             // int32 [2]
-    int64_t act_nall = 0, act_ngas = 0;
+    // int32 {active leaves, active gas leaves, scan total, active slots,
+    //        sub-leaf entries, gas sub-leaf entries}
+    crk::DevBuf act_count;
+    int64_t act_nall = 0, act_ngas = 0, act_npart = 0;
+    // the sub-leaves of the active leaves that hold an active particle (or,
+    // with groups, their groups), one entry 4 leaf + g each, in leaf order
+    // (gas leaves' entries first): the split sweeps launch one wavefront per
+    // entry.  Valid while slist_on (set with the subset, dropped by refit)
+    bool slist_on = false;
+    crk::DevBuf act_sub;               // int32 [3][leaf_cap + 1]: mask, count, offset
+    crk::DevBuf act_slist;             // int32 [4 * leaf_cap]
     // dense groups of the active particles of every active leaf (tuning
     // act_groups, trees with sub-leaves): the sub-leaf tables of the
     // subset, group g of leaf I in slot 4 I + g

@@ -139,6 +139,10 @@ template <typename T> struct TreeView {
     // and only slots with act[i] != 0 write outputs; both NULL: all leaves
     const int32_t *items;
     const uint8_t *act;
+    // with an active subset and sub-leaves: the sub-leaves (or groups)
+    // holding an active particle, entries 4*leaf + g, and their device
+    // count for the pass's items (NULL: every sub-leaf of every item)
+    const int32_t *slist, *n_slist;
 };
 
 // leaf of work item k, and whether slot i writes its outputs
@@ -755,13 +759,27 @@ __global__ __launch_bounds__(64) void pair_kernel_split(const TreeView<T> tv,
     extern __shared__ __attribute__((aligned(16))) unsigned char split_lds[];
     T *sj = reinterpret_cast<T *>(split_lds);
     int *sjid = reinterpret_cast<int *>(sj + split_cap<T, P>(tv) * P::NJ);
-    const int n_items = *tv.n_items;
-    if ((int)blockIdx.x >= 4 * n_items) return;
-    const int b = tv.xcd_remap ? xcd_block(blockIdx.x, 4 * n_items)
-                               : (int)blockIdx.x;
-    const int I = item_leaf(tv, b >> 2), g = b & 3;
-    if (g >= tv.nsub[I]) return;
-    if (tv.act) {
+    int I, g;
+    if (tv.slist) {
+        // active subset: one wavefront per listed sub-leaf, every one of
+        // which holds an active particle (no idle workgroups in the grid,
+        // whose regular pattern would leave CUs without work)
+        const int n = *tv.n_slist;
+        if ((int)blockIdx.x >= n) return;
+        const int e = tv.slist[tv.xcd_remap ? xcd_block(blockIdx.x, n)
+                                            : (int)blockIdx.x];
+        I = e >> 2;
+        g = e & 3;
+    } else {
+        const int n_items = *tv.n_items;
+        if ((int)blockIdx.x >= 4 * n_items) return;
+        const int b = tv.xcd_remap ? xcd_block(blockIdx.x, 4 * n_items)
+                                   : (int)blockIdx.x;
+        I = item_leaf(tv, b >> 2);
+        g = b & 3;
+        if (g >= tv.nsub[I]) return;
+    }
+    if (tv.act && !tv.slist) {
         // active subset: a sub-leaf without active particles has nothing
         // to write (the whole wavefront leaves together)
         const int64_t sl = 4 * (int64_t)I + g;
@@ -2346,6 +2364,14 @@ TreeView<T> tree_view(crk_tree *t, bool hydro, const int32_t *n_items) {
     tv.n_gas = t->n_gas;
     tv.items = t->act_on ? t->act_items.as<int32_t>() : nullptr;
     tv.act = t->act_on ? t->act_flags.as<uint8_t>() : nullptr;
+    tv.slist = tv.n_slist = nullptr;
+    if (t->act_on && t->slist_on) {
+        // n_items is the count of all active leaves (act_count[0]) or of
+        // the active gas leaves ([1]); their entries are counted at [4], [5]
+        const int32_t *c = t->act_count.as<int32_t>();
+        tv.slist = t->act_slist.as<int32_t>();
+        tv.n_slist = n_items == c ? c + 4 : c + 5;
+    }
     return tv;
 }
 

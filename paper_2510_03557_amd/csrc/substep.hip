@@ -75,12 +75,15 @@ __device__ inline int slot_bin(const int32_t *perm, int64_t n_gas,
     return b < 0 ? 0 : (b > L ? L : b);
 }
 
-// s < 0: every slot; else the slots ending a step after substep s
+// s < 0: every slot; else the slots ending a step after substep s.  Adds
+// the number of active slots to *count (cleared by the caller).
 __global__ void act_flags_kernel(int64_t n, int64_t n_gas,
                                  const int32_t *__restrict__ perm,
                                  const int32_t *__restrict__ bg,
                                  const int32_t *__restrict__ bd, int L, int64_t s,
-                                 uint8_t *__restrict__ act) {
+                                 uint8_t *__restrict__ act,
+                                 int32_t *__restrict__ count) {
+    int c = 0;
     GRID_LOOP(p, n) {
         bool a = true;
         if (s >= 0) {
@@ -88,7 +91,10 @@ __global__ void act_flags_kernel(int64_t n, int64_t n_gas,
             a = ((s + 1) % per) == 0;
         }
         act[p] = a ? 1 : 0;
+        c += a ? 1 : 0;
     }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
 }
 
 // per leaf: 1 when any of its slots is active
@@ -129,6 +135,60 @@ __global__ void act_count_kernel(const int32_t *__restrict__ nn_ptr,
     const int nn = *nn_ptr, ngl = *ngl_ptr;
     out[0] = *total;
     out[1] = ngl < nn ? pos[ngl] : *total;
+}
+
+// Sub-leaves of every active leaf holding an active particle: a mask of
+// bits q < nsub (sub-leaf q) and its population per item, one wavefront
+// per item (lanes = the leaf's slots, <= 64)
+__global__ __launch_bounds__(64) void act_submask_kernel(
+    const int32_t *__restrict__ items, int64_t n_items,
+    const int32_t *__restrict__ lstart, const int32_t *__restrict__ lcount,
+    const int32_t *__restrict__ nsub, const int32_t *__restrict__ sst,
+    const int32_t *__restrict__ scnt, const uint8_t *__restrict__ act,
+    int32_t *__restrict__ mask, int32_t *__restrict__ count) {
+    const int64_t k = blockIdx.x;
+    if (k >= n_items) return;
+    const int I = items[k];
+    const int lane = threadIdx.x;
+    const int st = lstart[I], cnt = min(lcount[I], 64);
+    const uint64_t m = __ballot(lane < cnt && act[st + lane] != 0);
+    const int ns = min(nsub[I], 4);
+    int bits = 0;
+    for (int q = 0; q < ns; ++q) {
+        const int lo = sst[4 * (int64_t)I + q] - st;
+        const int c = scnt[4 * (int64_t)I + q];
+        const uint64_t sm = (c >= 64 ? ~0ull : ((1ull << c) - 1)) << lo;
+        if (m & sm) bits |= 1 << q;
+    }
+    if (lane == 0) {
+        mask[k] = bits;
+        count[k] = __popc(bits);
+    }
+}
+
+// Entries 4 I + g of item k at off[k]: g = the sub-leaf, or with groups
+// (compressed) its rank among the item's sub-leaves holding an active
+// particle, which is the group index.  Thread k == n_items also writes the
+// entries of the gas items (items [0, n_gas_items)) to cnt[5].
+__global__ void act_sublist_kernel(const int32_t *__restrict__ items,
+                                   int64_t n_items, int64_t n_gas_items,
+                                   const int32_t *__restrict__ mask,
+                                   const int32_t *__restrict__ off, int groups,
+                                   int32_t *__restrict__ list,
+                                   int32_t *__restrict__ cnt) {
+    GRID_LOOP(k, n_items + 1) {
+        if (k == n_gas_items) cnt[5] = k < n_items ? off[k] : cnt[4];
+        if (k < n_items) {
+            const int I = items[k], m = mask[k];
+            int p = off[k], r = 0;
+            for (int q = 0; q < 4; ++q) {
+                if ((m >> q) & 1) {
+                    list[p++] = 4 * I + (groups ? r : q);
+                    ++r;
+                }
+            }
+        }
+    }
 }
 
 // new positions into tree order
@@ -434,8 +494,10 @@ int refit_impl(crk_ctx *ctx, crk_tree *t, const void *gx, const void *gy,
     hipStream_t s = ctx->stream;
     const int64_t n = t->n;
     // grown leaf boxes need new lists, moved particles new active groups
+    // (and the sub-leaf entries, which name groups when those are on)
     t->lists_built = false;
     t->grp_on = false;
+    t->slist_on = false;
     hipLaunchKernelGGL((refit_pos_kernel<T>), dim3(grid_n(n)), dim3(256), 0, s,
                        n, t->n_gas, t->perm.as<int32_t>(), cp<T>(gx), cp<T>(gy),
                        cp<T>(gz), cp<T>(dx), cp<T>(dy), cp<T>(dz),
@@ -530,6 +592,33 @@ template <typename T> int act_groups(crk_ctx *ctx, crk_tree *t) {
     return CRK_OK;
 }
 
+// the sub-leaf entries of the active subset (act_count[4], [5]: their
+// counts, all and gas; left at 0 by the caller for an empty subset)
+int act_sublist(crk_ctx *ctx, crk_tree *t) {
+    const int64_t lcap = t->leaf_cap, na = t->act_nall;
+    hipStream_t s = ctx->stream;
+    CRK_TRY(t->act_sub.ensure((size_t)3 * (lcap + 1) * 4, false));
+    CRK_TRY(t->act_slist.ensure((size_t)4 * lcap * 4, false));
+    int32_t *mask = t->act_sub.as<int32_t>();
+    int32_t *count = mask + (lcap + 1);
+    int32_t *off = count + (lcap + 1);
+    int32_t *cnt = t->act_count.as<int32_t>();
+    const int cur = t->cur_nodes;
+    hipLaunchKernelGGL(act_submask_kernel, dim3((unsigned)na), dim3(64), 0, s,
+                       t->act_items.as<int32_t>(), na,
+                       t->nd_start[cur].as<int32_t>(), t->nd_count[cur].as<int32_t>(),
+                       t->sub_nsub.as<int32_t>(), t->sub_start.as<int32_t>(),
+                       t->sub_count.as<int32_t>(), t->act_flags.as<uint8_t>(),
+                       mask, count);
+    CRK_HIP(hipGetLastError());
+    CRK_HIP(exclusive_scan_i32(count, off, na, cnt + 4, ctx->scratch.p, s));
+    hipLaunchKernelGGL(act_sublist_kernel, dim3(grid_n(na + 1)), dim3(256), 0, s,
+                       t->act_items.as<int32_t>(), na, t->act_ngas, mask, off,
+                       t->grp_on ? 1 : 0, t->act_slist.as<int32_t>(), cnt);
+    CRK_HIP(hipGetLastError());
+    return CRK_OK;
+}
+
 int tree_set_active(crk_ctx *ctx, crk_tree *t, const int32_t *bins_gas,
                     const int32_t *bins_dm, int max_level, int64_t substep) {
     hipStream_t s = ctx->stream;
@@ -538,6 +627,7 @@ int tree_set_active(crk_ctx *ctx, crk_tree *t, const int32_t *bins_gas,
     t->act_substep = substep < 0 ? -1 : substep;
     t->act_level = max_level;
     t->grp_on = false;
+    t->slist_on = false;
     if (substep < 0) {
         t->act_on = false;
         return CRK_OK;
@@ -546,16 +636,18 @@ int tree_set_active(crk_ctx *ctx, crk_tree *t, const int32_t *bins_gas,
     CRK_TRY(t->act_flags.ensure((size_t)std::max<int64_t>(n, 1), false));
     CRK_TRY(t->act_leaf.ensure((size_t)(lcap + 1) * 2 * 4, false));
     CRK_TRY(t->act_items.ensure((size_t)(lcap + 1) * 4, false));
-    CRK_TRY(t->act_count.ensure(4 * 4, false));
+    CRK_TRY(t->act_count.ensure(8 * 4, false));
     CRK_TRY(ctx->scratch.ensure(scan_tmp_bytes(lcap + 1), false));
+    // cnt: {active leaves, active gas leaves, scan total, active slots}
+    int32_t *cnt = t->act_count.as<int32_t>();
+    CRK_HIP(hipMemsetAsync(cnt + 3, 0, 3 * 4, s));
     hipLaunchKernelGGL(act_flags_kernel, dim3(grid_n(n)), dim3(256), 0, s, n,
                        t->n_gas, t->perm.as<int32_t>(), bins_gas, bins_dm,
-                       max_level, substep, t->act_flags.as<uint8_t>());
+                       max_level, substep, t->act_flags.as<uint8_t>(), cnt + 3);
     CRK_HIP(hipGetLastError());
     const int cur = t->cur_nodes;
     int32_t *flag = t->act_leaf.as<int32_t>();
     int32_t *pos = flag + (lcap + 1);
-    int32_t *cnt = t->act_count.as<int32_t>();
     hipLaunchKernelGGL(act_leaf_kernel, dim3(grid_n(lcap)), dim3(256), 0, s,
                        t->counters.as<int32_t>() + C_NN, lcap,
                        t->nd_start[cur].as<int32_t>(), t->nd_count[cur].as<int32_t>(),
@@ -570,18 +662,24 @@ int tree_set_active(crk_ctx *ctx, crk_tree *t, const int32_t *bins_gas,
                        t->counters.as<int32_t>() + C_NN,
                        t->bin_leaf.as<int32_t>() + t->total_bins, pos, cnt + 2, cnt);
     CRK_HIP(hipGetLastError());
-    int32_t hc[2];
-    CRK_HIP(hipMemcpyAsync(hc, cnt, 8, hipMemcpyDeviceToHost, s));
+    int32_t hc[4];
+    CRK_HIP(hipMemcpyAsync(hc, cnt, 16, hipMemcpyDeviceToHost, s));
     CRK_HIP(hipStreamSynchronize(s));
     t->act_nall = hc[0];
     t->act_ngas = hc[1];
+    t->act_npart = hc[3];
     t->act_on = true;
     t->grp_on = false;
-    if (t->has_sub && ctx->tuning.act_groups && t->act_nall > 0) {
+    // groups when the active leaves hold at least k active particles each
+    // on average (k = 1: always; 0: never)
+    const int64_t k = ctx->tuning.act_groups;
+    if (t->has_sub && k > 0 && t->act_nall > 0 && t->act_npart >= k * t->act_nall) {
         if (ctx->precision == CRK_FP64) CRK_TRY(act_groups<double>(ctx, t));
         else CRK_TRY(act_groups<float>(ctx, t));
         t->grp_on = true;
     }
+    if (t->has_sub && t->act_nall > 0) CRK_TRY(act_sublist(ctx, t));
+    t->slist_on = t->has_sub;
     return CRK_OK;
 }
 

@@ -240,8 +240,11 @@ class ShortRangeStep:
         With ``compatible`` every gas kick takes the compatible energy rate
         (crk_hydro_energy_compatible_block): once for the opening half-kick
         of the interval and once after each evaluation, for the closing
-        half-kick and the next opening one together."""
+        half-kick and the next opening one together.  ``cycle_subsets``
+        keeps, per substep, the active leaves and particles and whether the
+        sweeps took active groups."""
         c, t, wl = self.ctx, self.tree, self.wl
+        self.cycle_subsets = []
         L = int(max_level)
         if pm_mesh:
             self._long_kick(dt, pm_mesh)
@@ -257,6 +260,9 @@ class ShortRangeStep:
             c.tree_refit(t, self.gx, self.gy, self.gz, self.dx, self.dy,
                          self.dz)
             c.tree_set_active(t, self.bins_g, self.bins_d, L, s)
+            i = t.info()
+            self.cycle_subsets.append((i["act_leaves"], i["act_particles"],
+                                       i["act_grouped"]))
             self._passes()
             self._compatible_block(dt, L, s)
             self._kick(dt, L, s, 1)

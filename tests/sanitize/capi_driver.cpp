@@ -40,7 +40,7 @@ int main() {
         b.sub_sweep = 9;
         expect("tuning sub_sweep", crk_set_tuning(c, &b), E);
         b = t;
-        b.act_groups = 2;
+        b.act_groups = -1;
         expect("tuning act_groups", crk_set_tuning(c, &b), E);
         expect("density null tree", crk_density(c, nullptr, nullptr, nullptr, nullptr), E);
         expect("graph launch without capture", crk_graph_launch(c), CRK_ESTATE);

@@ -115,7 +115,7 @@ def _agree(g, f, rel):
 
 
 @pytest.mark.parametrize("sub_sweep,act_groups", [(2, 0), (3, 0), (2, 1),
-                                                  (3, 1)])
+                                                  (3, 1), (2, 4096)])
 def test_active_passes_write_active_particles_only(step_cls, sub_sweep,
                                                    act_groups):
     """After crk_tree_set_active, each pass writes, for the active particles,
@@ -125,7 +125,9 @@ def test_active_passes_write_active_particles_only(step_cls, sub_sweep,
     active particles' leaves are swept as in the full pass: bitwise.  On the
     dense active groups (act_groups 1) each active particle sweeps the same
     pairs with candidates culled against another box, so the compensated
-    sums group differently: to 2e-6 of |value| + RMS per value."""
+    sums group differently: to 2e-6 of |value| + RMS per value.  A
+    threshold above the active particles per active leaf (4096) keeps the
+    tree's sub-leaves."""
     print(f"case active passes random_uniform(6000, 5000) sub_sweep "
           f"{sub_sweep} act_groups {act_groups}", flush=True)
     wl = W.random_uniform(6000, 5000, 401, n_ngb=48.0, h_spread=0.15)
@@ -144,6 +146,11 @@ def test_active_passes_write_active_particles_only(step_cls, sub_sweep,
     act_d = ((s + 1) % (2 ** (L - bd))) == 0
     assert 0 < act_g.sum() < st.ng and 0 < act_d.sum() < st.nd
     c.tree_set_active(t, st.bins_g, st.bins_d, L, s)
+    info = t.info()
+    assert info["act_particles"] == act_g.sum() + act_d.sum()
+    assert 0 < info["act_leaves"] <= info["n_leaves"]
+    grouped = info["act_grouped"] == 1
+    assert grouped == (act_groups == 1), info
     c.build_interaction_lists(t)
     sentinel = -7.25
     groups = {
@@ -179,7 +186,7 @@ def test_active_passes_write_active_particles_only(step_cls, sub_sweep,
             ga = g[..., act] if k.startswith("a_") else g[act]
             fa = f[..., act] if k.startswith("a_") else f[act]
             gi = g[..., ~act] if k.startswith("a_") else g[~act]
-            if act_groups:
+            if grouped:
                 assert _agree(ga, fa, 2e-6), (name, k)
             else:
                 assert np.array_equal(ga, fa), (name, k)
@@ -190,6 +197,9 @@ def test_active_passes_write_active_particles_only(step_cls, sub_sweep,
                 getattr(st, k).copy_(saved[k])
     # a new subset invalidates the lists until they are rebuilt
     c.tree_set_active(t, None, None, 0, -1)
+    info = t.info()
+    assert (info["act_leaves"], info["act_particles"],
+            info["act_grouped"]) == (0, 0, 0)
     from paper_2510_03557_amd.binding import CrkError, CRK_ESTATE
     with pytest.raises(CrkError) as e:
         c.density(t, st.gm, st.V, st.rho_t)
