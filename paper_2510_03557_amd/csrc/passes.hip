@@ -133,6 +133,9 @@ template <typename T> struct TreeView {
     // dense active groups in place of the sub-leaves: particle k of slot
     // 4*leaf + g is tree slot sidx[16 (4*leaf + g) + k] (NULL: sst + k)
     const int32_t *sidx;
+    // the tree's sub-leaves as j-sets (the tables above may hold groups)
+    const int32_t *jns, *jst, *jcn;
+    const T *jlo, *jhi, *jhm;
     const double *rc, *eps;
     int64_t n_gas;
     // active subset (hierarchical time steps): work item k is leaf items[k]
@@ -532,11 +535,17 @@ template <typename T, typename P> __device__ inline int split_cap(const TreeView
 }
 
 // Split forms: one wavefront per sub-leaf (<= 16 particles).  The wave
-// walks the parent leaf's list, skips j-leaves out of range of the
-// sub-leaf's box, culls every j particle against that box (smaller than the
-// leaf's, so fewer candidates survive) and stages the survivors, recentred
-// on the parent leaf's first particle as in the other forms, in an LDS
-// buffer of P::CAPF * 64 candidates; sweep(n) consumes a full buffer.
+// walks the parent leaf's list sixteen entries at a time: lane l tests
+// sub-leaf l % 4 of the j-leaf of entry l / 4 (the tree's sub-leaves, in
+// the entry's periodic image) against this sub-leaf's box widened by the
+// pair range, so that only j sub-leaves in range are read.  The survivors
+// are then taken four at a time, sixteen lanes each (lane 16 g + p reads
+// particle p of the g-th), while the next four are being loaded; every j
+// particle is culled against the box and the survivors are staged,
+// recentred on the parent leaf's first particle as in the other forms, in
+// an LDS buffer of P::CAPF * 64 candidates; sweep(n) consumes a full
+// buffer.  Packing sub-leaves of different j-leaves into one round cuts
+// the rounds to about two thirds of one per j-leaf.
 template <typename T, typename P, typename Sweep>
 __device__ __forceinline__ void stage_subleaf(const TreeView<T> &tv,
                                               const typename P::Args &pa,
@@ -552,70 +561,78 @@ __device__ __forceinline__ void stage_subleaf(const TreeView<T> &tv,
     const T hmS = tv.shm[slot];
     const int64_t e0 = min(tv.list_off[I], tv.list_cap);
     const int64_t e1 = min(tv.list_off[I + 1], tv.list_cap);
-    int nbuf = 0;
-    // j-leaves of the parent's list out of range of this sub-leaf's box are
-    // skipped before their particles are loaded.  The box gap is computed in
-    // T from coordinates in [1, 2) shifted by at most one box (a few ulp of
-    // error at most), against the pair range widened by 1e-4 relative plus
-    // 1e-6 absolute, so nothing in range is dropped.
+    const int nl = *tv.n_leaves;
     const T slx = tv.slo[slot], sly = tv.slo[sl + slot], slz = tv.slo[2 * sl + slot];
     const T shx = tv.shi[slot], shy = tv.shi[sl + slot], shz = tv.shi[2 * sl + slot];
-    auto keep_near = [&](int J, uint32_t code, T hJ) {
-        int sx, sy, sz;
-        decode_shift(code, sx, sy, sz);
-        const int64_t lc = tv.lcap;
-        const T gx = fmax(T(0), fmax((tv.lo[J] + T(sx)) - shx, slx - (tv.hi[J] + T(sx))));
-        const T gy = fmax(T(0), fmax((tv.lo[lc + J] + T(sy)) - shy,
-                                     sly - (tv.hi[lc + J] + T(sy))));
-        const T gz = fmax(T(0), fmax((tv.lo[2 * lc + J] + T(sz)) - shz,
-                                     slz - (tv.hi[2 * lc + J] + T(sz))));
-        const T R = P::range(pa, tv, box, hmS, hJ) * T(1.0001) + T(1e-6);
-        return gx * gx + gy * gy + gz * gz < R * R;
-    };
     // with P::FARNEAR, candidates at least P::far_range from the box go to
     // the front of the buffer ([0, nbuf)), the others to its back
     // ([CAP - nnear, CAP)), and sweep(nbuf, nnear) takes both ranges
-    int nnear = 0;
+    int nbuf = 0, nnear = 0;
     T Rf2 = T(0);
     if constexpr (P::FARNEAR) {
         const T Rf = P::far_range(tv, box);
         Rf2 = Rf * Rf;
     }
-    // the pair range, when it does not depend on the j-leaf
+    // the pair range, when it does not depend on the j side
     const T Rc = P::RANGE_HJ ? T(0) : P::range(pa, tv, box, hmS, T(0)) + T(1e-6);
-    walk_list<T, P, 64>(tv, pa, e0, e1, lane, keep_near,
-                        [&](int js, int jc, uint32_t code, T hJ, T x, T y, T z,
-                            const T *f) {
-        int sx, sy, sz;
-        decode_shift(code, sx, sy, sz);
-        if (nbuf + nnear + jc > CAP) {
-            if constexpr (P::FARNEAR) sweep(nbuf, nnear);
-            else sweep(nbuf);
-            nbuf = 0;
-            nnear = 0;
+    const int g = lane >> 4, p = lane & 15;
+
+    // the next four surviving sub-leaves of mask `rem` (wave-uniform, lanes
+    // of the entry-side values js, jc, code, hJ): group g of the wavefront
+    // takes the g-th and loads its particle p
+    auto fetch = [&](uint64_t &rem, int js, int jc, int code, T hJ, int &gjs,
+                     int &gjc, int &gcode, T &ghJ, T &x, T &y, T &z, T *f) {
+        int src[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            src[k] = rem ? __builtin_ctzll(rem) : -1;
+            rem &= rem - 1;  // (0 stays 0)
         }
-        // cull in raw coordinates against the sub-leaf box moved to this
-        // image (its shifted bounds round by at most a few 1e-7: the range
-        // gets an absolute 1e-6 on top of its relative widening)
-        const T R = P::RANGE_HJ ? P::range(pa, tv, box, hmS, hJ) + T(1e-6) : Rc;
+        const int s = g == 0 ? src[0] : g == 1 ? src[1] : g == 2 ? src[2] : src[3];
+        const int sr = s < 0 ? 0 : s;
+        // every lane takes part in every shuffle (a shuffle under a
+        // condition reads nothing from the lanes the condition leaves out)
+        const int vjs = __shfl(js, sr);
+        const int vjc = __shfl(jc, sr);
+        const int vcode = __shfl(code, sr);
+        T vhJ = T(0);
+        if constexpr (P::RANGE_HJ) vhJ = __shfl(hJ, sr);
+        gjs = vjs;
+        gjc = s < 0 ? 0 : vjc;
+        gcode = vcode;
+        ghJ = vhJ;
+        x = y = z = T(0);
+#pragma unroll
+        for (int u = 0; u < P::NP; ++u) f[u] = T(0);
+        if (p < gjc) load_j<T, P>(x, y, z, f, pa, tv, gjs + p);
+    };
+    // cull one round's particles against the box moved to their images
+    // (the shifted bounds round by at most a few 1e-7: the range gets an
+    // absolute 1e-6 on top of its relative widening) and stage survivors
+    auto stage = [&](int cjs, int cjc, int ccode, T chJ, T x, T y, T z,
+                     const T *f) {
+        int sx, sy, sz;
+        decode_shift((uint32_t)ccode, sx, sy, sz);
+        const T R = P::RANGE_HJ ? P::range(pa, tv, box, hmS, chJ) + T(1e-6) : Rc;
         const T R2 = R * R;
-        const T clx = slx - T(sx), chx = shx - T(sx);
-        const T cly = sly - T(sy), chy = shy - T(sy);
-        const T clz = slz - T(sz), chz = shz - T(sz);
-        // every lane computes the distance (lanes past jc hold stale or zero
-        // coordinates: arithmetic only, no access), the lane mask decides
-        const int j = js + lane;
-        const T dx = fmax(fmax(clx - x, x - chx), T(0));
-        const T dy = fmax(fmax(cly - y, y - chy), T(0));
-        const T dz = fmax(fmax(clz - z, z - chz), T(0));
+        // every lane computes the distance (lanes past the sub-leaf's count
+        // hold zero coordinates: arithmetic only, no access)
+        const T dx = fmax(fmax((slx - T(sx)) - x, x - (shx - T(sx))), T(0));
+        const T dy = fmax(fmax((sly - T(sy)) - y, y - (shy - T(sy))), T(0));
+        const T dz = fmax(fmax((slz - T(sz)) - z, z - (shz - T(sz))), T(0));
         const T d2 = dx * dx + dy * dy + dz * dz;
-        const bool keep = (lane < jc) & (d2 < R2);
+        const bool keep = (p < cjc) & (d2 < R2);
+        const int j = cjs + p;
+        const T fx = (x - rx) + T(sx), fy = (y - ry) + T(sy), fz = (z - rz) + T(sz);
         if constexpr (P::FARNEAR) {
             const bool far = keep & (d2 >= Rf2);
             const uint64_t mf = __ballot(far), mn = __ballot(keep && !far);
+            if (nbuf + nnear + __popcll(mf) + __popcll(mn) > CAP) {
+                sweep(nbuf, nnear);
+                nbuf = 0;
+                nnear = 0;
+            }
             if (keep) {
-                const T fx = (x - rx) + T(sx), fy = (y - ry) + T(sy),
-                        fz = (z - rz) + T(sz);
                 const int pos = far ? nbuf + __popcll(mf & lt_mask)
                                     : CAP - 1 - (nnear + __popcll(mn & lt_mask));
                 P::store_j(&sj[pos * P::NJ], f, pa, tv, j, fx, fy, fz);
@@ -625,17 +642,80 @@ __device__ __forceinline__ void stage_subleaf(const TreeView<T> &tv,
             nnear += __popcll(mn);
         } else {
             const uint64_t m = __ballot(keep);
+            if (nbuf + __popcll(m) > CAP) {
+                sweep(nbuf);
+                nbuf = 0;
+            }
             if (keep) {
                 // recentred (exact for every pair in range)
-                const T fx = (x - rx) + T(sx), fy = (y - ry) + T(sy),
-                        fz = (z - rz) + T(sz);
                 const int pos = nbuf + __popcll(m & lt_mask);
                 P::store_j(&sj[pos * P::NJ], f, pa, tv, j, fx, fy, fz);
                 sjid[pos] = j;
             }
             nbuf += __popcll(m);
         }
-    });
+    };
+
+    for (int64_t eb = e0; eb < e1; eb += 16) {
+        // lane l: sub-leaf l % 4 of entry eb + l / 4.  Entries never written
+        // (after a capacity error) name no leaf below the leaf count and are
+        // skipped.  The box gap is computed in T from coordinates in [1, 2)
+        // shifted by at most one box (a few ulp of error at most), against
+        // the pair range widened by 1e-4 relative plus 1e-6 absolute, so
+        // nothing in range is dropped.
+        const int64_t e = eb + (lane >> 2);
+        const int s = lane & 3;
+        int js = 0, jc = 0, code = 0;
+        T hJ = T(0);
+        bool in = false;
+        if (e < e1) {
+            const uint32_t ent = tv.list[e];
+            const int J = (int)(ent & LIST_LEAF_MASK);
+            if (J < nl && s < tv.jns[J]) {
+                code = (int)(ent >> LIST_LEAF_BITS);
+                int sx, sy, sz;
+                decode_shift((uint32_t)code, sx, sy, sz);
+                const int64_t q = 4 * (int64_t)J + s;
+                hJ = tv.jhm[q];
+                const T gx = fmax(T(0), fmax((tv.jlo[q] + T(sx)) - shx,
+                                             slx - (tv.jhi[q] + T(sx))));
+                const T gy = fmax(T(0), fmax((tv.jlo[sl + q] + T(sy)) - shy,
+                                             sly - (tv.jhi[sl + q] + T(sy))));
+                const T gz = fmax(T(0), fmax((tv.jlo[2 * sl + q] + T(sz)) - shz,
+                                             slz - (tv.jhi[2 * sl + q] + T(sz))));
+                const T R = P::range(pa, tv, box, hmS, hJ) * T(1.0001) + T(1e-6);
+                if (gx * gx + gy * gy + gz * gz < R * R) {
+                    js = tv.jst[q];
+                    jc = min(tv.jcn[q], 16);
+                    in = jc > 0;
+                }
+            }
+        }
+        uint64_t rem = __ballot(in);
+        if (rem == 0) continue;
+        int cjs, cjc, ccode;
+        T chJ, cx, cy, cz, cf[P::NP];
+        fetch(rem, js, jc, code, hJ, cjs, cjc, ccode, chJ, cx, cy, cz, cf);
+        while (true) {
+            const bool more = rem != 0;
+            int njs = 0, njc = 0, ncode = 0;
+            T nhJ = T(0), nx = T(0), ny = T(0), nz = T(0), nf[P::NP];
+#pragma unroll
+            for (int u = 0; u < P::NP; ++u) nf[u] = T(0);
+            if (more) fetch(rem, js, jc, code, hJ, njs, njc, ncode, nhJ, nx, ny, nz, nf);
+            stage(cjs, cjc, ccode, chJ, cx, cy, cz, cf);
+            if (!more) break;
+            cjs = njs;
+            cjc = njc;
+            ccode = ncode;
+            chJ = nhJ;
+            cx = nx;
+            cy = ny;
+            cz = nz;
+#pragma unroll
+            for (int u = 0; u < P::NP; ++u) cf[u] = nf[u];
+        }
+    }
     if constexpr (P::FARNEAR) sweep(nbuf, nnear);
     else sweep(nbuf);
 }
@@ -2351,6 +2431,12 @@ TreeView<T> tree_view(crk_tree *t, bool hydro, const int32_t *n_items) {
     tv.shi = t->sub_hi.as<T>();
     tv.shm = t->sub_hmax.as<T>();
     tv.sidx = nullptr;
+    tv.jns = tv.nsub;
+    tv.jst = tv.sst;
+    tv.jcn = tv.scnt;
+    tv.jlo = tv.slo;
+    tv.jhi = tv.shi;
+    tv.jhm = tv.shm;
     if (t->act_on && t->grp_on) {
         tv.nsub = t->grp_nsub.as<int32_t>();
         tv.scnt = t->grp_cnt.as<int32_t>();
