@@ -416,10 +416,13 @@ int crk_timestep_bins(crk_ctx *ctx, int64_t n, double dt, int32_t max_level,
  * only.  substep < 0 selects everything (the state after build_tree).
  * The lists must be rebuilt after every call (build_interaction_lists then
  * lists the active leaves only; the passes report CRK_ESTATE until then).
- * With tuning act_groups and sub-leaves, the call also gathers the active
- * particles of every sub-leaf into a group (see crk_tuning), boxed at the
- * tree's current positions, which the sub-leaf sweeps then take as their
- * i-sets.  Synchronises (reads the active leaf counts back). */
+ * With sub-leaves, the call also lists the sub-leaves that hold an active
+ * particle (the split sweep then runs one wavefront per listed sub-leaf)
+ * and, as tuning act_groups decides, gathers the active particles of each
+ * into a group (see crk_tuning), boxed at the tree's current positions,
+ * which the sub-leaf sweeps then take as their i-sets.  The subset's sizes
+ * are reported by crk_tree_get_info.  Synchronises (reads the active leaf
+ * and particle counts back). */
 int crk_tree_set_active(crk_ctx *ctx, crk_tree *tree, const int32_t *bins_gas,
                         const int32_t *bins_dm, int32_t max_level,
                         int64_t substep);
