@@ -1964,10 +1964,11 @@ template <typename T> struct GravityPass {
         const T u = T(2) - xi;
         const T u2 = u * u;
         const T u5 = u2 * u2 * u;
-        T po = fma(T(7), xi, T(22));
-        po = fma(po, xi, T(10));
-        po = fma(po, xi, T(4));
-        const T val = fma(u5 * po, T(1.0 / 140.0), T(-1));
+        // (7 xi^3 + 22 xi^2 + 10 xi + 4) / 140
+        T po = fma(T(7.0 / 140.0), xi, T(22.0 / 140.0));
+        po = fma(po, xi, T(10.0 / 140.0));
+        po = fma(po, xi, T(4.0 / 140.0));
+        const T val = fma(u5, po, T(-1));
         const T rs3 = rs * rs * rs;
         const T gout = fma(rs3, val, plum);
         const T gr = xi < T(1) ? gin : gout;
@@ -1987,8 +1988,9 @@ template <typename T> struct GravityPass {
     }
     // pair of a far candidate: only the outer S2 branch, and the Plummer
     // factor (r^2 + eps^2)^(-3/2) = r^-3 (1 + e)^(-3/2), e = (eps/r)^2 <=
-    // 1/225, from its binomial series to e^3 (truncation below 1e-9
-    // relative): one reciprocal square root per pair instead of two
+    // 1/225, from its binomial series to e^2 (the first term left out,
+    // 35/16 e^3, is below 2e-7 of r^-3, and below 3e-9 where r_c/2 >= 30
+    // eps): one reciprocal square root per pair instead of two
     __device__ static void pair_far(Tile &tl, const I &is, const T *jd) {
         const T dx = is.ex - jd[0], dy = is.ey - jd[1], dz = is.ez - jd[2];
         const T r2 = dx * dx + dy * dy + dz * dz;
@@ -2000,13 +2002,12 @@ template <typename T> struct GravityPass {
         const T u = T(2) - xi;
         const T u2 = u * u;
         const T u5 = u2 * u2 * u;
-        T po = fma(T(7), xi, T(22));
-        po = fma(po, xi, T(10));
-        po = fma(po, xi, T(4));
+        T po = fma(T(7.0 / 140.0), xi, T(22.0 / 140.0));
+        po = fma(po, xi, T(10.0 / 140.0));
+        po = fma(po, xi, T(4.0 / 140.0));
         const T e = is.eps2 * rs2;
-        T q = fma(e, T(-35.0 / 16.0), T(15.0 / 8.0));
-        q = fma(q, e, T(-1.5));
-        const T t = fma(u5 * po, T(1.0 / 140.0), e * q);
+        const T q = fma(e, T(15.0 / 8.0), T(-1.5));
+        const T t = fma(u5, po, e * q);
         const T w = jd[3] * (rs3 * t);
         tl.s[0] = fma(-w, dx, tl.s[0]);
         tl.s[1] = fma(-w, dy, tl.s[1]);
