@@ -1998,15 +1998,13 @@ template <typename T> struct GravityPass {
         const T rs = rsq(r2);
         const T rs2 = rs * rs;
         const T rs3 = rs2 * rs;
-        // u = 2 - xi (xi = 2 r / r_c in [1, 2) here)
-        const T u = fma(-(r2 * rs), is.two_rc, T(2));
+        const T xi = (r2 * rs) * is.two_rc;
+        const T u = T(2) - xi;
         const T u2 = u * u;
         const T u5 = u2 * u2 * u;
-        // (7 xi^3 + 22 xi^2 + 10 xi + 4) / 140 written in u (xi itself is
-        // then never formed)
-        T po = fma(T(-7.0 / 140.0), u, T(64.0 / 140.0));
-        po = fma(po, u, T(-182.0 / 140.0));
-        po = fma(po, u, T(168.0 / 140.0));
+        T po = fma(T(7.0 / 140.0), xi, T(22.0 / 140.0));
+        po = fma(po, xi, T(10.0 / 140.0));
+        po = fma(po, xi, T(4.0 / 140.0));
         const T e = is.eps2 * rs2;
         const T q = fma(e, T(15.0 / 8.0), T(-1.5));
         const T t = fma(u5, po, e * q);
