@@ -125,3 +125,34 @@ def test_context_checks_plane_triples_before_the_library():
         ctx._p3(planes, 5, "a")
     assert "device" in str(e.value)
     assert ctx._p3(None, 5, "a") is None
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (a C program built against include/crk.h prints them)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = [binding.crk_params, binding.crk_boxes, binding.crk_tuning,
+               binding.crk_tree_info]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "crk.h"',
+             "int main(void) {"]
+    for cls in structs:
+        n = cls.__name__
+        lines.append(f'    printf("{n} %zu\\n", sizeof({n}));')
+        for f, _ in cls._fields_:
+            lines.append(f'    printf("{n}.{f} %zu\\n", offsetof({n}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", str(ROOT / "include"), str(src),
+                    "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run(
+        [str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    for cls in structs:
+        n = cls.__name__
+        assert int(got[n]) == ctypes.sizeof(cls), n
+        for f, _ in cls._fields_:
+            assert int(got[f"{n}.{f}"]) == getattr(cls, f).offset, (n, f)
